@@ -1,0 +1,91 @@
+"""Cross sections and efficiencies from a solved polarization P.
+
+§3.1 "What Does It Calculate?" defines the efficiencies
+Q = C / (pi a_eff^2) for extinction, absorption and scattering.  The sums
+that give C from the dipole moments are cited (Draine 1988; Draine & Flatau
+1994), not printed.  Reading, with |E_0| = 1 and d = 1:
+
+    C_ext = 4 pi k sum_j Im( conj(E_inc,j) . P_j )
+    C_abs = 4 pi k sum_j [ Im( P_j . conj(1/alpha_j) conj(P_j) ) - (2/3) k^3 |P_j|^2 ]
+    C_sca = k^4 * integral dOmega | sum_j (I - n n) P_j e^{-i k n.r_j} |^2
+          = 4 pi k^4 sum_j sum_l conj(P_j) . K(k R_jl) . P_l
+
+with R_jl = r_j - r_l and, using the angular integral
+integral dOmega (I - n n) e^{i k n.R} = 4 pi K(kR),
+
+    K(x) = (j0(x) - j1(x)/x) I + j2(x) Rhat Rhat,    K(0) = (2/3) I
+
+(spherical Bessel functions j_n).  ``c_sca_quadrature`` evaluates the same
+far-field integral by brute-force angular quadrature, as an independent check
+of ``c_sca_exact``.
+"""
+
+import math
+
+import numpy as np
+import scipy.special as ssp
+
+
+def c_ext(kd, E_inc, P):
+    return 4.0 * math.pi * kd * float(np.sum(np.imag(np.conj(E_inc) * P)))
+
+
+def c_abs(kd, alpha_inv_sites, P):
+    ai = np.asarray(alpha_inv_sites, dtype=complex)
+    p2 = np.sum(np.abs(P) ** 2, axis=-1)
+    term = np.imag(np.conj(ai)) * p2 - (2.0 / 3.0) * kd ** 3 * p2
+    return 4.0 * math.pi * kd * float(np.sum(term))
+
+
+def _k_tensor(x, Rhat):
+    """K(x) of the module docstring for arrays x[...] > 0, Rhat[..., 3]."""
+    j0 = ssp.spherical_jn(0, x)
+    j1 = ssp.spherical_jn(1, x)
+    j2 = ssp.spherical_jn(2, x)
+    a = j0 - j1 / x
+    return a[..., None, None] * np.eye(3) + j2[..., None, None] * (Rhat[..., :, None] * Rhat[..., None, :])
+
+
+def c_sca_exact(sites, kd, P, block=512):
+    """Exact C_sca of the dipole array by the O(N^2) double sum."""
+    sites = np.asarray(sites, dtype=float)
+    P = np.asarray(P, dtype=complex)
+    n = sites.shape[0]
+    total = (2.0 / 3.0) * float(np.sum(np.abs(P) ** 2))        # j == l terms
+    for j0 in range(0, n, block):
+        j1 = min(n, j0 + block)
+        R = sites[j0:j1, None, :] - sites[None, :, :]
+        r = np.sqrt(np.sum(R * R, axis=-1))
+        same = r == 0
+        r_safe = np.where(same, 1.0, r)
+        K = _k_tensor(kd * r_safe, R / r_safe[..., None])
+        K[same] = 0.0
+        total += float(np.real(np.einsum("ja,jlab,lb->", np.conj(P[j0:j1]), K, P)))
+    return 4.0 * math.pi * kd ** 4 * total
+
+
+def c_sca_quadrature(sites, kd, P, n_theta=96, n_phi=192):
+    """C_sca by Gauss-Legendre (cos theta) x trapezoid (phi) quadrature."""
+    sites = np.asarray(sites, dtype=float)
+    P = np.asarray(P, dtype=complex)
+    mu, w = np.polynomial.legendre.leggauss(n_theta)
+    phi = 2.0 * math.pi * np.arange(n_phi) / n_phi
+    st = np.sqrt(1.0 - mu * mu)
+    n = np.stack([np.outer(st, np.cos(phi)), np.outer(st, np.sin(phi)),
+                  np.outer(mu, np.ones_like(phi))], axis=-1)            # [T, F, 3]
+    phase = np.exp(-1j * kd * np.einsum("tfc,jc->tfj", n, sites))
+    F = np.einsum("tfj,ja->tfa", phase, P)
+    F = F - n * np.sum(n * F, axis=-1, keepdims=True)
+    integrand = np.sum(np.abs(F) ** 2, axis=-1)
+    total = np.sum(w[:, None] * integrand) * (2.0 * math.pi / n_phi)
+    return kd ** 4 * float(total)
+
+
+def efficiencies(n_sites, kd, E_inc, alpha_inv_sites, P, sites=None, exact_sca=False):
+    """Dict of Q_ext, Q_abs, Q_sca (= Q_ext - Q_abs unless exact_sca) and a_eff."""
+    aeff = (3.0 * n_sites / (4.0 * math.pi)) ** (1.0 / 3.0)
+    geo = math.pi * aeff * aeff
+    ce = c_ext(kd, E_inc, P)
+    ca = c_abs(kd, alpha_inv_sites, P)
+    cs = c_sca_exact(sites, kd, P) if exact_sca else ce - ca
+    return dict(qext=ce / geo, qabs=ca / geo, qsca=cs / geo, aeff=aeff)
