@@ -1,0 +1,225 @@
+/*
+ * dda.h -- C ABI of the MI355X discrete-dipole-approximation (DDA) solver.
+ *
+ * The library solves A P = E for the polarizations P of N point dipoles on a
+ * cubic lattice (DDSCAT 7.3 user guide, Draine & Flatau 2013, §12 "Choice of
+ * Iterative Algorithm", eq. AP=E), with
+ *
+ *     (A P)_j = P_j / alpha_j - sum_{l != j} G(r_j - r_l) P_l ,
+ *
+ * G the free-space dipole field tensor (cited in §1 and §12 from Draine 1988
+ * and Draine & Flatau 1994) and alpha_j the dipole polarizability (§14).  The
+ * sum is a discrete convolution evaluated with zero-padded 3-D FFTs of the six
+ * independent tensor components (Goodman, Draine & Flatau 1990; §13 "Choice
+ * of FFT Algorithm" for the 2/3/5-smooth grid extents).  The solver is
+ * BiCGSTAB (van der Vorst 1992; the PBCGST option of §12), started from P = 0,
+ * stopped on the true relative residual |E - A P| / |E| <= tol.  Cross sections
+ * follow the efficiencies Q = C / (pi a_eff^2) of §3.1.
+ *
+ * Units: lattice spacing d = 1; Gaussian units; time dependence exp(-i w t)
+ * (an absorbing material has Im m > 0).
+ *
+ * Conventions for every entry point:
+ *   - Return value: DDA_OK (0) on success, a negative DDA_E* code on error, a
+ *     positive DDA_W* code for a completed call with a warning.  No C++
+ *     exception crosses this interface.  dda_last_error() returns a message
+ *     for the last failing call on the calling thread.
+ *   - Host pointers ("host") are read during the call only; the caller owns
+ *     them.  Device pointers ("device") are HIP device addresses on the
+ *     target's device; the caller owns them and they must stay valid until
+ *     the work queued on the given stream has finished.
+ *   - A stream argument is a hipStream_t passed as void*; NULL means the
+ *     target's own stream.  Calls on one handle must not overlap in time
+ *     (one thread, one stream per handle); distinct handles may run
+ *     concurrently on distinct streams.
+ *   - Complex numbers are dda_c64 {re, im} (16 bytes, FP64).
+ *   - Polarization / field vectors are laid out [nrhs][n_sites][3] dda_c64,
+ *     site order as given to dda_setup_target, component order (x, y, z) of
+ *     the Target Frame.
+ */
+#ifndef DDA_H
+#define DDA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define DDA_OK 0
+#define DDA_EINVAL (-1)       /* invalid argument (message via dda_last_error) */
+#define DDA_ENOMEM (-2)       /* device allocation failed or footprint too large */
+#define DDA_EDEVICE (-3)      /* HIP runtime error */
+#define DDA_ENOTSUP (-4)      /* valid but unsupported (e.g. grid extent > 512) */
+#define DDA_NOT_CONVERGED 1   /* dda_solve: some RHS stopped at max_iter or broke down */
+#define DDA_WVALIDITY 2       /* dda_setup_target: |m|kd >= 1 or |m-1| > 2 (§2) */
+
+/* ---- enumerations ------------------------------------------------------ */
+/* Polarizability prescription (§14). */
+#define DDA_ALPHA_LDR 0       /* LATTDR: lattice dispersion relation (Draine & Goodman 1993) */
+#define DDA_ALPHA_CMRR 1      /* Clausius-Mossotti with radiative reaction */
+#define DDA_ALPHA_FCD 2       /* FLTRCD polarizability (requires kd < pi) */
+
+/* Arithmetic of the FFT product inside the Krylov iteration. */
+#define DDA_FP64 0            /* complex FP64 throughout */
+#define DDA_MIXED 1           /* complex FP32 FFT product; FP64 Krylov vectors,
+                                 inner products, residual refinement and sums */
+
+/* Built-in target shapes (§21, SHPAR conventions of the guide). */
+#define DDA_SHAPE_ELLIPSOID 1 /* shpar = diameters along x, y, z (a sphere: all equal) */
+#define DDA_SHAPE_RCTGLPRSM 2 /* shpar = x, y, z extents in dipoles */
+#define DDA_SHAPE_CYLINDER1 3 /* shpar = length, diameter, axis (1 = x, 2 = y, 3 = z) */
+#define DDA_SHAPE_HEX_PRISM 4 /* shpar = length, vertex-to-vertex width, orientation 1..6 */
+
+/* ---- types --------------------------------------------------------------- */
+typedef struct { double re, im; } dda_c64;
+
+typedef struct {
+  int32_t nx, ny, nz;      /* bounding box in lattice units; every site inside */
+  int64_t n_sites;         /* N >= 1 */
+  const int32_t *ijk;      /* host [N][3] site indices, 0 <= i < nx etc., unique */
+  const uint8_t *comp;     /* host [N] composition index, or NULL (all 0) */
+  int32_t n_comp;          /* number of compositions, 1..255 */
+  const dda_c64 *m;        /* host [n_comp] refractive index relative to the medium (§3.2) */
+  double kd;               /* k d > 0 (wavenumber in the medium times lattice spacing) */
+  int32_t alpha_kind;      /* DDA_ALPHA_* */
+  int32_t device;          /* HIP device ordinal */
+} dda_target_desc;
+
+typedef struct dda_target dda_target;   /* opaque handle; owns its device memory */
+
+/* One right-hand side: incident direction and polarization in the Target Frame. */
+typedef struct {
+  double khat[3];          /* unit propagation direction (|khat| = 1 within 1e-12) */
+  dda_c64 e[3];            /* polarization, normalised by the library; khat.e = 0 */
+} dda_rhs;
+
+typedef struct {
+  double tol;              /* stop when |E - A P| / |E| <= tol (FP64 residual), e.g. 1e-5 */
+  int32_t max_iter;        /* BiCGSTAB iteration cap per RHS (the guide's MXITER, §9) */
+  int32_t precision;       /* DDA_FP64 or DDA_MIXED */
+  double inner_tol;        /* MIXED: inner recursive-residual target relative to the
+                              current true residual; 0 => tol (one refinement pass) */
+  int32_t max_outer;       /* cap on true-residual checks / refinement passes per RHS */
+  int32_t check_every;     /* iterations between host convergence checks (>= 1; 0 => 8) */
+} dda_solve_opts;
+
+typedef struct {
+  int32_t status;          /* 0 converged, 1 max_iter, 2 breakdown without recovery */
+  int32_t iters;           /* BiCGSTAB iterations */
+  int32_t matvecs;         /* FFT products in the iteration precision */
+  int32_t outer;           /* true-residual evaluations (FP64 products) */
+  double rel_resid;        /* final true relative residual |E - A P| / |E| (FP64) */
+} dda_solve_stats;
+
+typedef struct {
+  double qext, qabs, qsca; /* efficiencies Q = C / (pi a_eff^2) (§3.1); qsca = qext - qabs */
+  double aeff;             /* effective radius in lattice units (§2) */
+} dda_q;
+
+typedef struct {
+  int32_t box[3];          /* nx, ny, nz */
+  int32_t grid[3];         /* padded FFT extents Mx, My, Mz (2/3/5-smooth, >= 2n-1) */
+  int64_t n_sites;
+  double kd, aeff;
+  uint64_t device_bytes;   /* device memory currently held by the handle */
+} dda_target_info;
+
+/* ---- target geometry (host arithmetic) ------------------------------- */
+
+/* Occupied sites of a built-in shape (§21).  Sites are centred lattice points
+ * of n = nearest-integer(extent) per axis that satisfy the shape's inequality
+ * (boundary included), shifted so the smallest index on each axis is 0, in
+ * raster order (x fastest).  Call with ijk = NULL to get *n_sites and box;
+ * then call again with ijk of capacity >= *n_sites triples.
+ * Errors: DDA_EINVAL for an unknown shape, a non-positive extent or a bad
+ * orientation code; DDA_EINVAL if capacity is too small. */
+int dda_make_sites(int32_t shape, const double shpar[3], int64_t *n_sites,
+                   int32_t box[3], int32_t *ijk, int64_t capacity);
+
+/* a_eff = (3N/4pi)^(1/3) and kd = x / a_eff (§2). */
+double dda_aeff(int64_t n_sites);
+double dda_kd_from_x(double x, int64_t n_sites);
+
+/* Incident direction and polarization in the Target Frame for target
+ * orientation (beta, theta, phi) (radians, §19) and Lab-Frame polarization
+ * e01 (normalised; x component must be 0).  which = 1 gives e01, which = 2 the
+ * orthogonal state e02 = x_LF x conj(e01) (§24).  The target axes a1, a2 are
+ * taken along x_TF, y_TF.  Errors: DDA_EINVAL for which not in {1,2} or a
+ * zero / non-transverse e01. */
+int dda_orient_rhs(double beta, double theta, double phi, const dda_c64 e01_lf[3],
+                   int32_t which, dda_rhs *out);
+
+/* ---- target handle ------------------------------------------------------- */
+
+/* Validate the description, copy sites to the device, pick the padded grid
+ * and build the Fourier transforms of the six Green-tensor components
+ * (FP64 and FP32 copies).  Errors: DDA_EINVAL (N < 1, site outside the box or
+ * duplicated, n_comp out of range, non-finite m, m^2 = -2, kd <= 0, FCD with
+ * kd >= pi); DDA_ENOTSUP (padded extent > 512); DDA_ENOMEM; DDA_EDEVICE.
+ * Returns DDA_WVALIDITY (with a valid handle) when |m|kd >= 1 or |m - 1| > 2
+ * for some composition, the guide's validity criteria (§2). */
+int dda_setup_target(const dda_target_desc *desc, dda_target **out);
+
+/* Device bytes a target plus a solve of nrhs right-hand sides would hold
+ * (setup transient included).  Same validation as dda_setup_target except
+ * that sites are not read (ijk may be NULL). */
+int dda_footprint_bytes(const dda_target_desc *desc, int32_t nrhs,
+                        const dda_solve_opts *opts, uint64_t *bytes);
+
+int dda_target_get_info(const dda_target *t, dda_target_info *info);
+
+/* Solve A P = E for nrhs right-hand sides as one block (shared FFT grid and
+ * Green transform, per-RHS polarizabilities, scalars and convergence).
+ * p_dev: device [nrhs][N][3] dda_c64 receiving P, or NULL for a
+ *   library-owned buffer (then read P back through p_host).
+ * p_host: host [nrhs][N][3] copy of P, or NULL.
+ * stats: host [nrhs], or NULL.
+ * Returns DDA_OK when every RHS reached tol, DDA_NOT_CONVERGED when some did
+ * not (per-RHS status in stats), or an error.  The call is synchronous: P is
+ * complete on return.  Errors: DDA_EINVAL (nrhs < 1, |khat| != 1, khat.e != 0,
+ * e = 0, tol <= 0, max_iter < 1, bad precision); DDA_ENOMEM; DDA_EDEVICE. */
+int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_opts *opts,
+              void *p_dev, dda_c64 *p_host, void *stream, dda_solve_stats *stats);
+
+/* Q_ext, Q_abs, Q_sca (= Q_ext - Q_abs) of solved polarizations P, from FP64
+ * sums over the sites (cross sections of Draine 1988 / Draine & Flatau 1994,
+ * efficiencies of §3.1).  P is read from p_dev (device) if non-NULL, else from
+ * p_host (host).  out: host [nrhs].  Synchronous. */
+int dda_cross_sections(dda_target *t, const dda_rhs *rhs, int32_t nrhs,
+                       const void *p_dev, const dda_c64 *p_host, void *stream, dda_q *out);
+
+/* The product AP = A P for nrhs vectors (device [nrhs][N][3] in and out, may
+ * not alias), in DDA_FP64 or DDA_MIXED (FP32 FFT convolution, FP64 diagonal
+ * and output).  The polarizabilities are those of the given RHS.  Queued on
+ * the stream; not synchronous. */
+int dda_apply(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t precision,
+              const void *p_dev, void *ap_dev, void *stream);
+
+/* Incident field E_j = e exp(i kd khat . r_j) at the sites (eq. AP=E),
+ * device [nrhs][N][3] out.  Queued on the stream. */
+int dda_incident_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, void *e_dev, void *stream);
+
+void dda_free_target(dda_target *t);
+
+/* ---- diagnostics --------------------------------------------------------- */
+
+/* Batched in-place-free 1-D complex FFT of length n (2/3/5-smooth, <= 512) on
+ * the device: out[b][k] = scale * sum_j in[b][j] exp(sign * 2 pi i j k / n),
+ * sign = -1 (forward) or +1 (inverse).  precision DDA_FP64 (dda_c64 data) or
+ * DDA_MIXED (interleaved float pairs).  This is the FFT engine of the product
+ * exposed for testing.  Queued on the stream. */
+int dda_fft_pencils(int32_t n, int64_t batch, int32_t sign, int32_t precision, double scale,
+                    const void *in_dev, void *out_dev, void *stream, int32_t device);
+
+/* Smallest 2/3/5-smooth integer >= n (the grid-extension rule of §13). */
+int32_t dda_next_smooth(int32_t n);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *dda_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDA_H */

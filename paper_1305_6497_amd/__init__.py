@@ -1,0 +1,182 @@
+"""MI355X-native DDA solver: Python binding of the C ABI in include/dda.h.
+
+Every step of the computation runs in libdda.so (HIP kernels for gfx950 and
+its host code); this module only marshals arguments.  PyTorch supplies device
+memory and streams.  If the library is missing, importing the API raises.
+
+Typical use::
+
+    import paper_1305_6497_amd as dda
+    sites, box = dda.make_sites("ELLIPSOID", (20, 20, 20))
+    kd = dda.kd_from_x(1.0, len(sites))
+    t = dda.Target(sites, box, m=1.33 + 0.01j, kd=kd)
+    rhs = [dda.orient_rhs(0, 0, 0, which=1), dda.orient_rhs(0, 0, 0, which=2)]
+    P, stats = t.solve(rhs, tol=1e-5)
+    q = t.cross_sections(rhs, P)
+"""
+
+import ctypes
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import DDAError  # noqa: F401
+
+SHAPES = {"ELLIPSOID": L.DDA_SHAPE_ELLIPSOID, "RCTGLPRSM": L.DDA_SHAPE_RCTGLPRSM,
+          "CYLINDER1": L.DDA_SHAPE_CYLINDER1, "HEX_PRISM": L.DDA_SHAPE_HEX_PRISM}
+ALPHA = {"LATTDR": L.DDA_ALPHA_LDR, "LDR": L.DDA_ALPHA_LDR, "CMRR": L.DDA_ALPHA_CMRR,
+         "FLTRCD": L.DDA_ALPHA_FCD, "FCD": L.DDA_ALPHA_FCD}
+PRECISION = {"fp64": L.DDA_FP64, "mixed": L.DDA_MIXED}
+
+
+def make_sites(shape, shpar):
+    """Sites of a built-in shape: (int32 [N, 3] array, (nx, ny, nz))."""
+    lib = L.lib()
+    sp = (ctypes.c_double * 3)(*[float(v) for v in (tuple(shpar) + (1.0, 1.0, 1.0))[:3]])
+    n = ctypes.c_int64()
+    box = (ctypes.c_int32 * 3)()
+    L.check(lib.dda_make_sites(SHAPES[shape], sp, ctypes.byref(n), box, None, 0))
+    out = np.empty((n.value, 3), dtype=np.int32)
+    L.check(lib.dda_make_sites(SHAPES[shape], sp, ctypes.byref(n), box,
+                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n.value))
+    return out, tuple(box)
+
+
+def aeff(n_sites):
+    return L.lib().dda_aeff(int(n_sites))
+
+
+def kd_from_x(x, n_sites):
+    return L.lib().dda_kd_from_x(float(x), int(n_sites))
+
+
+def next_smooth(n):
+    return int(L.lib().dda_next_smooth(int(n)))
+
+
+def orient_rhs(beta, theta, phi, e01=(0.0, 1.0, 0.0), which=1):
+    """(khat, e) in the Target Frame for orientation (beta, theta, phi)."""
+    e = (L.C64 * 3)(*[L.C64(complex(v).real, complex(v).imag) for v in e01])
+    out = L.Rhs()
+    L.check(L.lib().dda_orient_rhs(float(beta), float(theta), float(phi), e, int(which), ctypes.byref(out)))
+    khat = np.array(list(out.khat))
+    ev = np.array([complex(out.e[a].re, out.e[a].im) for a in range(3)])
+    return khat, ev
+
+
+def _rhs_array(rhs):
+    arr = (L.Rhs * len(rhs))()
+    for i, (khat, e) in enumerate(rhs):
+        for a in range(3):
+            arr[i].khat[a] = float(khat[a])
+            c = complex(e[a])
+            arr[i].e[a] = L.C64(c.real, c.imag)
+    return arr
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def fft_pencils(x, sign=-1, scale=1.0, stream=None):
+    """Batched 1-D FFT of the last axis of a contiguous complex CUDA tensor."""
+    import torch
+    assert x.is_cuda and x.is_contiguous()
+    prec = L.DDA_FP64 if x.dtype == torch.complex128 else L.DDA_MIXED
+    assert x.dtype in (torch.complex128, torch.complex64)
+    out = torch.empty_like(x)
+    n = x.shape[-1]
+    batch = x.numel() // n if n else 0
+    L.check(L.lib().dda_fft_pencils(n, batch, int(sign), prec, float(scale), ctypes.c_void_p(x.data_ptr()),
+                                    ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream), x.device.index or 0))
+    return out
+
+
+def footprint_bytes(box, n_sites, m=1.5, kd=0.5, nrhs=1, alpha="LATTDR"):
+    """Device bytes a target and a solve of nrhs right-hand sides would hold."""
+    mlist = m if isinstance(m, (list, tuple)) else [m]
+    marr = (L.C64 * len(mlist))(*[L.C64(complex(v).real, complex(v).imag) for v in mlist])
+    d = L.TargetDesc(nx=box[0], ny=box[1], nz=box[2], n_sites=int(n_sites), ijk=None, comp=None,
+                     n_comp=len(mlist), m=marr, kd=float(kd), alpha_kind=ALPHA[alpha], device=0)
+    out = ctypes.c_uint64()
+    L.check(L.lib().dda_footprint_bytes(ctypes.byref(d), int(nrhs), None, ctypes.byref(out)))
+    return out.value
+
+
+class Target:
+    """A target handle: sites, refractive indices and wavenumber on one GPU."""
+
+    def __init__(self, sites, box, m, kd, alpha="LATTDR", comp=None, device=0):
+        self._lib = L.lib()
+        self.sites = np.ascontiguousarray(sites, dtype=np.int32)
+        self.n = self.sites.shape[0]
+        mlist = list(m) if isinstance(m, (list, tuple, np.ndarray)) else [m]
+        self._m = (L.C64 * len(mlist))(*[L.C64(complex(v).real, complex(v).imag) for v in mlist])
+        self._comp = None if comp is None else np.ascontiguousarray(comp, dtype=np.uint8)
+        self.device = device
+        d = L.TargetDesc(nx=int(box[0]), ny=int(box[1]), nz=int(box[2]), n_sites=self.n,
+                         ijk=self.sites.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                         comp=None if self._comp is None else self._comp.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                         n_comp=len(mlist), m=self._m, kd=float(kd), alpha_kind=ALPHA[alpha], device=device)
+        h = ctypes.c_void_p()
+        self.setup_status = L.check(self._lib.dda_setup_target(ctypes.byref(d), ctypes.byref(h)),
+                                    ok=(L.DDA_OK, L.DDA_WVALIDITY))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.dda_free_target(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        i = L.TargetInfo()
+        L.check(self._lib.dda_target_get_info(self._h, ctypes.byref(i)))
+        return dict(box=tuple(i.box), grid=tuple(i.grid), n_sites=i.n_sites, kd=i.kd, aeff=i.aeff,
+                    device_bytes=i.device_bytes)
+
+    def _vec(self, nrhs):
+        import torch
+        return torch.empty((nrhs, self.n, 3), dtype=torch.complex128, device=f"cuda:{self.device}")
+
+    def solve(self, rhs, tol=1e-5, max_iter=1000, precision="fp64", inner_tol=0.0, max_outer=20, check_every=8,
+              out=None, stream=None):
+        """Solve A P = E for every (khat, e) in rhs.  Returns (P, stats)."""
+        nrhs = len(rhs)
+        P = self._vec(nrhs) if out is None else out
+        opts = L.SolveOpts(tol=tol, max_iter=max_iter, precision=PRECISION[precision], inner_tol=inner_tol,
+                           max_outer=max_outer, check_every=check_every)
+        st = (L.SolveStats * nrhs)()
+        code = L.check(self._lib.dda_solve(self._h, _rhs_array(rhs), nrhs, ctypes.byref(opts),
+                                           ctypes.c_void_p(P.data_ptr()), None, _stream_ptr(stream), st),
+                       ok=(L.DDA_OK, L.DDA_NOT_CONVERGED))
+        stats = [dict(status=s.status, iters=s.iters, matvecs=s.matvecs, outer=s.outer, rel_resid=s.rel_resid)
+                 for s in st]
+        return P, stats
+
+    def cross_sections(self, rhs, P, stream=None):
+        nrhs = len(rhs)
+        q = (L.Q * nrhs)()
+        L.check(self._lib.dda_cross_sections(self._h, _rhs_array(rhs), nrhs, ctypes.c_void_p(P.data_ptr()), None,
+                                             _stream_ptr(stream), q))
+        return [dict(qext=v.qext, qabs=v.qabs, qsca=v.qsca, aeff=v.aeff) for v in q]
+
+    def apply(self, rhs, P, precision="fp64", stream=None):
+        out = self._vec(len(rhs))
+        L.check(self._lib.dda_apply(self._h, _rhs_array(rhs), len(rhs), PRECISION[precision],
+                                    ctypes.c_void_p(P.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                    _stream_ptr(stream)))
+        return out
+
+    def incident_field(self, rhs, stream=None):
+        out = self._vec(len(rhs))
+        L.check(self._lib.dda_incident_field(self._h, _rhs_array(rhs), len(rhs), ctypes.c_void_p(out.data_ptr()),
+                                             _stream_ptr(stream)))
+        return out

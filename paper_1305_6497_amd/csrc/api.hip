@@ -1,0 +1,640 @@
+// The C ABI (include/dda.h): target handles, the BiCGSTAB driver with FP64
+// true-residual refinement, cross sections and diagnostics.
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dda_internal.hpp"
+
+using namespace dda;
+
+namespace dda {
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+}  // namespace dda
+
+struct dda_target {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  Geometry g{};
+  double kd = 0, aeff = 0;
+  int alpha_kind = 0;
+  int ncomp = 1;
+  std::vector<c64> m;
+  AxisPlan px{}, py{}, pz{};
+  Twiddles tx, ty, tz;
+  int32_t *d_ijk = nullptr;
+  uint8_t *d_comp = nullptr;
+  int *d_cell_site = nullptr;
+  c64 *d_ghat64 = nullptr;
+  c32 *d_ghat32 = nullptr;
+  // workspace, grown on demand
+  int ws_nrhs = 0;
+  void *d_bufA = nullptr, *d_bufB = nullptr;
+  // Krylov state, grown on demand
+  int kr_nrhs = 0;
+  KrylovState k;
+  c64 *d_ainv = nullptr;
+  RhsDev *d_rhs = nullptr;
+  double *d_sums = nullptr;
+  int *d_restart = nullptr;
+  uint64_t bytes = 0;
+  std::vector<std::pair<void *, size_t>> allocs;
+
+  template <typename P>
+  P *alloc(size_t bytes_) {
+    void *p = nullptr;
+    DDA_HIP(hipMalloc(&p, std::max<size_t>(bytes_, 16)));
+    allocs.push_back({p, bytes_});
+    bytes += bytes_;
+    return static_cast<P *>(p);
+  }
+  void release(void *p) {
+    if (!p) return;
+    for (size_t i = 0; i < allocs.size(); ++i)
+      if (allocs[i].first == p) {
+        bytes -= allocs[i].second;
+        (void)hipFree(p);
+        allocs.erase(allocs.begin() + i);
+        return;
+      }
+  }
+  ~dda_target() {
+    (void)hipSetDevice(device);
+    for (auto &a : allocs) (void)hipFree(a.first);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+namespace {
+
+template <typename F>
+int guarded(F &&f) {
+  try {
+    return f();
+  } catch (const Error &e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    set_error("host allocation failed");
+    return DDA_ENOMEM;
+  } catch (const std::exception &e) {
+    set_error(e.what());
+    return DDA_EDEVICE;
+  } catch (...) {
+    set_error("unknown error");
+    return DDA_EDEVICE;
+  }
+}
+
+int grid_extent(int n) { return std::max(2, next_smooth(2 * n - 1)); }
+
+Geometry make_geometry(int nx, int ny, int nz, int64_t n) {
+  Geometry g{};
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  g.Mx = grid_extent(nx);
+  g.My = grid_extent(ny);
+  g.Mz = grid_extent(nz);
+  if (g.Mx > kMaxLen || g.My > kMaxLen || g.Mz > kMaxLen)
+    throw Error{DDA_ENOTSUP, "padded FFT extent exceeds 512 (box extent > 256)"};
+  g.Mxh = g.Mx / 2 + 1;
+  g.Myh = g.My / 2 + 1;
+  g.Mzh = g.Mz / 2 + 1;
+  g.n_sites = n;
+  return g;
+}
+
+void validate_desc(const dda_target_desc *d, bool need_sites) {
+  DDA_REQUIRE(d != nullptr, "desc is NULL");
+  DDA_REQUIRE(d->nx >= 1 && d->ny >= 1 && d->nz >= 1, "box extents must be >= 1");
+  DDA_REQUIRE(d->n_sites >= 1, "n_sites must be >= 1");
+  DDA_REQUIRE(d->n_sites <= (int64_t)d->nx * d->ny * d->nz, "more sites than box cells");
+  DDA_REQUIRE(d->n_sites < (int64_t)INT32_MAX / 3, "too many sites");
+  DDA_REQUIRE(d->n_comp >= 1 && d->n_comp <= 255, "n_comp must be in 1..255");
+  DDA_REQUIRE(d->m != nullptr, "m is NULL");
+  DDA_REQUIRE(std::isfinite(d->kd) && d->kd > 0.0, "kd must be finite and > 0");
+  DDA_REQUIRE(d->alpha_kind == DDA_ALPHA_LDR || d->alpha_kind == DDA_ALPHA_CMRR || d->alpha_kind == DDA_ALPHA_FCD,
+              "unknown alpha_kind");
+  if (d->alpha_kind == DDA_ALPHA_FCD) DDA_REQUIRE(d->kd < 3.14159265358979323846, "FCD requires kd < pi");
+  for (int c = 0; c < d->n_comp; ++c) {
+    const std::complex<double> m(d->m[c].re, d->m[c].im);
+    DDA_REQUIRE(std::isfinite(m.real()) && std::isfinite(m.imag()), "refractive index must be finite");
+    DDA_REQUIRE(std::abs(m * m + 2.0) > 1e-12, "m^2 = -2: Clausius-Mossotti polarizability is singular");
+    DDA_REQUIRE(std::abs(m * m - 1.0) > 1e-300, "m = 1: target has no polarizability");
+  }
+  if (need_sites) DDA_REQUIRE(d->ijk != nullptr, "ijk is NULL");
+}
+
+bool validity_warning(const dda_target_desc *d) {
+  bool w = false;
+  for (int c = 0; c < d->n_comp; ++c) {
+    const std::complex<double> m(d->m[c].re, d->m[c].im);
+    if (std::abs(m) * d->kd >= 1.0 || std::abs(m - 1.0) > 2.0) w = true;     // §2
+  }
+  return w;
+}
+
+void make_twiddles(dda_target *t, Twiddles &tw, int L) {
+  std::vector<c64> h64(L);
+  std::vector<c32> h32(L);
+  const double pi = 3.14159265358979323846;
+  for (int n = 0; n < L; ++n) {
+    const double a = 2.0 * pi * double(n) / double(L);
+    h64[n] = c64{std::cos(a), -std::sin(a)};
+    h32[n] = c32{float(h64[n].x), float(h64[n].y)};
+  }
+  tw.L = L;
+  tw.d64 = t->alloc<c64>(sizeof(c64) * L);
+  tw.d32 = t->alloc<c32>(sizeof(c32) * L);
+  DDA_HIP(hipMemcpy(tw.d64, h64.data(), sizeof(c64) * L, hipMemcpyHostToDevice));
+  DDA_HIP(hipMemcpy(tw.d32, h32.data(), sizeof(c32) * L, hipMemcpyHostToDevice));
+}
+
+size_t workspace_bytes(const Geometry &g, int nrhs) {
+  const size_t a = std::max(g.a_elems(true) * sizeof(c32), g.a_elems(false) * sizeof(c64));
+  const size_t b = std::max(g.b_elems(true) * sizeof(c32), g.b_elems(false) * sizeof(c64));
+  return (a + b) * (size_t)nrhs;
+}
+
+size_t krylov_bytes(const Geometry &g, int nrhs) {
+  const int64_t n3 = 3 * g.n_sites;
+  const size_t vec = (size_t)n3 * sizeof(c64) * nrhs;
+  const int nblk = krylov_blocks(n3);
+  return 8 * vec + (size_t)nrhs * nblk * 4 * sizeof(double) + (size_t)nrhs * kScal * sizeof(c64) +
+         4 * (size_t)nrhs * sizeof(int) + (size_t)nrhs * (sizeof(RhsDev) + 2 * sizeof(double)) +
+         (size_t)nrhs * 255 * sizeof(c64);
+}
+
+void ensure_workspace(dda_target *t, int nrhs) {
+  if (t->ws_nrhs >= nrhs) return;
+  t->release(t->d_bufA);
+  t->release(t->d_bufB);
+  t->d_bufA = t->d_bufB = nullptr;
+  const Geometry &g = t->g;
+  const size_t a = std::max(g.a_elems(true) * sizeof(c32), g.a_elems(false) * sizeof(c64)) * nrhs;
+  const size_t b = std::max(g.b_elems(true) * sizeof(c32), g.b_elems(false) * sizeof(c64)) * nrhs;
+  t->d_bufA = t->alloc<void>(a);
+  t->d_bufB = t->alloc<void>(b);
+  t->ws_nrhs = nrhs;
+}
+
+void ensure_krylov(dda_target *t, int nrhs) {
+  if (t->kr_nrhs >= nrhs) {
+    t->k.nrhs = nrhs;
+    return;
+  }
+  KrylovState &k = t->k;
+  for (c64 *p : {k.x, k.r, k.rh, k.p, k.v, k.s, k.t, k.b}) t->release(p);
+  t->release(k.partial);
+  t->release(k.scal);
+  t->release(k.active);
+  t->release(k.status);
+  t->release(k.check);
+  t->release(t->d_ainv);
+  t->release(t->d_rhs);
+  t->release(t->d_sums);
+  t->release(t->d_restart);
+  const int64_t n3 = 3 * t->g.n_sites;
+  const size_t vec = (size_t)n3 * sizeof(c64) * nrhs;
+  k.n3 = n3;
+  k.nblk = krylov_blocks(n3);
+  k.x = t->alloc<c64>(vec);
+  k.r = t->alloc<c64>(vec);
+  k.rh = t->alloc<c64>(vec);
+  k.p = t->alloc<c64>(vec);
+  k.v = t->alloc<c64>(vec);
+  k.s = t->alloc<c64>(vec);
+  k.t = t->alloc<c64>(vec);
+  k.b = t->alloc<c64>(vec);
+  k.partial = t->alloc<double>((size_t)nrhs * k.nblk * 4 * sizeof(double));
+  k.scal = t->alloc<c64>((size_t)nrhs * kScal * sizeof(c64));
+  k.active = t->alloc<int>(nrhs * sizeof(int));
+  k.status = t->alloc<int>(nrhs * sizeof(int));
+  k.check = t->alloc<int>(nrhs * sizeof(int));
+  t->d_restart = t->alloc<int>(nrhs * sizeof(int));
+  t->d_ainv = t->alloc<c64>((size_t)nrhs * t->ncomp * sizeof(c64));
+  t->d_rhs = t->alloc<RhsDev>(nrhs * sizeof(RhsDev));
+  t->d_sums = t->alloc<double>(2 * nrhs * sizeof(double));
+  t->kr_nrhs = nrhs;
+  k.nrhs = nrhs;
+}
+
+// Validate and normalise the RHS; fill per-RHS descriptions and 1/alpha.
+void prepare_rhs(dda_target *t, const dda_rhs *rhs, int nrhs, std::vector<RhsDev> &rd, std::vector<c64> &ainv) {
+  DDA_REQUIRE(rhs != nullptr, "rhs is NULL");
+  rd.resize(nrhs);
+  ainv.resize((size_t)nrhs * t->ncomp);
+  for (int r = 0; r < nrhs; ++r) {
+    const dda_rhs &q = rhs[r];
+    const double kn = std::sqrt(q.khat[0] * q.khat[0] + q.khat[1] * q.khat[1] + q.khat[2] * q.khat[2]);
+    DDA_REQUIRE(std::fabs(kn - 1.0) <= 1e-12, "khat must be a unit vector");
+    double en = 0.0;
+    for (int a = 0; a < 3; ++a) en += q.e[a].re * q.e[a].re + q.e[a].im * q.e[a].im;
+    en = std::sqrt(en);
+    DDA_REQUIRE(en > 0.0 && std::isfinite(en), "polarization must be non-zero and finite");
+    std::complex<double> dot = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      rd[r].khat[a] = q.khat[a];
+      rd[r].e[a] = c64{q.e[a].re / en, q.e[a].im / en};
+      dot += q.khat[a] * std::complex<double>(rd[r].e[a].x, rd[r].e[a].y);
+    }
+    DDA_REQUIRE(std::abs(dot) <= 1e-9, "polarization must be transverse (khat . e = 0)");
+    for (int c = 0; c < t->ncomp; ++c) ainv[(size_t)r * t->ncomp + c] = alpha_inverse(t->alpha_kind, t->m[c], t->kd, rd[r].khat, rd[r].e);
+  }
+}
+
+void upload_rhs(dda_target *t, const std::vector<RhsDev> &rd, const std::vector<c64> &ainv, hipStream_t s) {
+  DDA_HIP(hipMemcpyAsync(t->d_rhs, rd.data(), rd.size() * sizeof(RhsDev), hipMemcpyHostToDevice, s));
+  DDA_HIP(hipMemcpyAsync(t->d_ainv, ainv.data(), ainv.size() * sizeof(c64), hipMemcpyHostToDevice, s));
+}
+
+void matvec(dda_target *t, int precision, const c64 *in, c64 *out, int nrhs, const int *mask, hipStream_t s) {
+  MatvecArgs a{};
+  a.in = in;
+  a.out = out;
+  a.nrhs = nrhs;
+  a.mask = mask;
+  a.ainv = t->d_ainv;
+  a.ncomp = t->ncomp;
+  a.comp = t->d_comp;
+  a.cell_site = t->d_cell_site;
+  a.bufA = t->d_bufA;
+  a.bufB = t->d_bufB;
+  a.px = t->px;
+  a.py = t->py;
+  a.pz = t->pz;
+  if (precision == DDA_MIXED) {
+    a.ghat = t->d_ghat32;
+    a.twx = t->tx.d32;
+    a.twy = t->ty.d32;
+    a.twz = t->tz.d32;
+    launch_matvec<float>(t->g, a, s);
+  } else {
+    a.ghat = t->d_ghat64;
+    a.twx = t->tx.d64;
+    a.twy = t->ty.d64;
+    a.twz = t->tz.d64;
+    launch_matvec<double>(t->g, a, s);
+  }
+}
+
+void iteration(dda_target *t, int precision, hipStream_t s) {
+  KrylovState &k = t->k;
+  k_update_p(k, s);
+  matvec(t, precision, k.p, k.v, k.nrhs, k.active, s);
+  k_dot_rv(k, s);
+  k_scalar_alpha(k, s);
+  k_update_s(k, s);
+  matvec(t, precision, k.s, k.t, k.nrhs, k.active, s);
+  k_dot_ts(k, s);
+  k_scalar_omega(k, s);
+  k_update_xr(k, s);
+  k_scalar_rho(k, s);
+}
+
+}  // namespace
+
+// ========================================================================= ABI
+
+extern "C" {
+
+const char *dda_last_error(void) { return g_last_error.c_str(); }
+
+int32_t dda_next_smooth(int32_t n) { return next_smooth(n); }
+
+double dda_aeff(int64_t n) { return std::cbrt(3.0 * double(n) / (4.0 * 3.14159265358979323846)); }
+
+double dda_kd_from_x(double x, int64_t n) { return x / dda_aeff(n); }
+
+int dda_make_sites(int32_t shape, const double shpar[3], int64_t *n_sites, int32_t box[3], int32_t *ijk,
+                   int64_t capacity) {
+  return guarded([&]() -> int {
+    DDA_REQUIRE(shpar && n_sites && box, "NULL argument");
+    for (int a = 0; a < 3; ++a) DDA_REQUIRE(std::isfinite(shpar[a]), "shape parameters must be finite");
+    DDA_REQUIRE(shpar[0] <= 4096 && shpar[1] <= 4096 && shpar[2] <= 4096, "shape parameter too large");
+    std::vector<int32_t> s = make_sites(shape, shpar, box);
+    *n_sites = (int64_t)(s.size() / 3);
+    if (ijk) {
+      DDA_REQUIRE(capacity >= *n_sites, "ijk capacity too small");
+      std::memcpy(ijk, s.data(), s.size() * sizeof(int32_t));
+    }
+    return DDA_OK;
+  });
+}
+
+int dda_orient_rhs(double beta, double theta, double phi, const dda_c64 e01_lf[3], int32_t which, dda_rhs *out) {
+  return guarded([&]() -> int {
+    DDA_REQUIRE(e01_lf && out, "NULL argument");
+    c64 e[3];
+    for (int a = 0; a < 3; ++a) e[a] = c64{e01_lf[a].re, e01_lf[a].im};
+    RhsDev rd;
+    orient_rhs(beta, theta, phi, e, which, rd);
+    for (int a = 0; a < 3; ++a) {
+      out->khat[a] = rd.khat[a];
+      out->e[a].re = rd.e[a].x;
+      out->e[a].im = rd.e[a].y;
+    }
+    return DDA_OK;
+  });
+}
+
+int dda_footprint_bytes(const dda_target_desc *desc, int32_t nrhs, const dda_solve_opts *opts, uint64_t *bytes) {
+  return guarded([&]() -> int {
+    validate_desc(desc, false);
+    DDA_REQUIRE(bytes != nullptr, "bytes is NULL");
+    DDA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    (void)opts;
+    const Geometry g = make_geometry(desc->nx, desc->ny, desc->nz, desc->n_sites);
+    const size_t M = (size_t)g.Mx * g.My * g.Mz;
+    const size_t fixed = (size_t)desc->n_sites * (3 * sizeof(int32_t) + 1) + (size_t)g.nx * g.ny * g.nz * sizeof(int) +
+                         6 * g.oct_elems() * (sizeof(c64) + sizeof(c32)) +
+                         (size_t)(g.Mx + g.My + g.Mz) * (sizeof(c64) + sizeof(c32));
+    const size_t setup_transient = 6 * M * sizeof(c64);
+    const size_t solve = workspace_bytes(g, nrhs) + krylov_bytes(g, nrhs);
+    *bytes = fixed + std::max(setup_transient, solve);
+    return DDA_OK;
+  });
+}
+
+int dda_setup_target(const dda_target_desc *desc, dda_target **out) {
+  return guarded([&]() -> int {
+    DDA_REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    validate_desc(desc, true);
+    const int nx = desc->nx, ny = desc->ny, nz = desc->nz;
+    const int64_t n = desc->n_sites;
+    // cell -> site map; rejects sites outside the box and duplicates
+    std::vector<int> cell((size_t)nx * ny * nz, -1);
+    for (int64_t j = 0; j < n; ++j) {
+      const int32_t x = desc->ijk[3 * j], y = desc->ijk[3 * j + 1], z = desc->ijk[3 * j + 2];
+      DDA_REQUIRE(x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz, "site outside the box");
+      int &c = cell[((size_t)z * ny + y) * nx + x];
+      DDA_REQUIRE(c < 0, "duplicate site");
+      c = (int)j;
+    }
+    if (desc->comp)
+      for (int64_t j = 0; j < n; ++j) DDA_REQUIRE(desc->comp[j] < desc->n_comp, "composition index >= n_comp");
+    std::unique_ptr<dda_target> t(new dda_target());
+    t->device = desc->device;
+    DDA_HIP(hipSetDevice(t->device));
+    DDA_HIP(hipStreamCreateWithFlags(&t->stream, hipStreamNonBlocking));
+    t->g = make_geometry(nx, ny, nz, n);
+    t->kd = desc->kd;
+    t->aeff = dda_aeff(n);
+    t->alpha_kind = desc->alpha_kind;
+    t->ncomp = desc->n_comp;
+    t->m.resize(t->ncomp);
+    for (int c = 0; c < t->ncomp; ++c) t->m[c] = c64{desc->m[c].re, desc->m[c].im};
+    t->px = make_axis_plan(t->g.Mx);
+    t->py = make_axis_plan(t->g.My);
+    t->pz = make_axis_plan(t->g.Mz);
+    make_twiddles(t.get(), t->tx, t->g.Mx);
+    make_twiddles(t.get(), t->ty, t->g.My);
+    make_twiddles(t.get(), t->tz, t->g.Mz);
+    t->d_ijk = t->alloc<int32_t>((size_t)n * 3 * sizeof(int32_t));
+    DDA_HIP(hipMemcpy(t->d_ijk, desc->ijk, (size_t)n * 3 * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (desc->comp && t->ncomp > 1) {
+      t->d_comp = t->alloc<uint8_t>((size_t)n);
+      DDA_HIP(hipMemcpy(t->d_comp, desc->comp, (size_t)n, hipMemcpyHostToDevice));
+    }
+    t->d_cell_site = t->alloc<int>(cell.size() * sizeof(int));
+    DDA_HIP(hipMemcpy(t->d_cell_site, cell.data(), cell.size() * sizeof(int), hipMemcpyHostToDevice));
+    const Geometry &g = t->g;
+    const size_t M = (size_t)g.Mx * g.My * g.Mz;
+    t->d_ghat64 = t->alloc<c64>(6 * g.oct_elems() * sizeof(c64));
+    t->d_ghat32 = t->alloc<c32>(6 * g.oct_elems() * sizeof(c32));
+    c64 *full = t->alloc<c64>(6 * M * sizeof(c64));
+    launch_green_build(g, t->kd, full, t->d_ghat64, t->d_ghat32, t->tx, t->ty, t->tz, t->px, t->py, t->pz,
+                       t->stream);
+    DDA_HIP(hipStreamSynchronize(t->stream));
+    t->release(full);
+    const bool warn = validity_warning(desc);
+    *out = t.release();
+    if (warn) {
+      set_error("validity warning: |m|kd >= 1 or |m-1| > 2 for some composition");
+      return DDA_WVALIDITY;
+    }
+    return DDA_OK;
+  });
+}
+
+int dda_target_get_info(const dda_target *t, dda_target_info *info) {
+  return guarded([&]() -> int {
+    DDA_REQUIRE(t && info, "NULL argument");
+    info->box[0] = t->g.nx;
+    info->box[1] = t->g.ny;
+    info->box[2] = t->g.nz;
+    info->grid[0] = t->g.Mx;
+    info->grid[1] = t->g.My;
+    info->grid[2] = t->g.Mz;
+    info->n_sites = t->g.n_sites;
+    info->kd = t->kd;
+    info->aeff = t->aeff;
+    info->device_bytes = t->bytes;
+    return DDA_OK;
+  });
+}
+
+void dda_free_target(dda_target *t) { delete t; }
+
+int dda_incident_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, void *e_dev, void *stream) {
+  return guarded([&]() -> int {
+    DDA_REQUIRE(t && e_dev, "NULL argument");
+    DDA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    DDA_HIP(hipSetDevice(t->device));
+    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : t->stream;
+    std::vector<RhsDev> rd;
+    std::vector<c64> ai;
+    prepare_rhs(t, rhs, nrhs, rd, ai);
+    ensure_krylov(t, nrhs);
+    upload_rhs(t, rd, ai, s);
+    launch_incident(t->g, t->d_ijk, t->d_rhs, nrhs, t->kd, static_cast<c64 *>(e_dev), s);
+    return DDA_OK;
+  });
+}
+
+int dda_apply(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t precision, const void *p_dev, void *ap_dev,
+              void *stream) {
+  return guarded([&]() -> int {
+    DDA_REQUIRE(t && p_dev && ap_dev, "NULL argument");
+    DDA_REQUIRE(p_dev != ap_dev, "p_dev and ap_dev must not alias");
+    DDA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    DDA_REQUIRE(precision == DDA_FP64 || precision == DDA_MIXED, "unknown precision");
+    DDA_HIP(hipSetDevice(t->device));
+    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : t->stream;
+    std::vector<RhsDev> rd;
+    std::vector<c64> ai;
+    prepare_rhs(t, rhs, nrhs, rd, ai);
+    ensure_krylov(t, nrhs);
+    ensure_workspace(t, nrhs);
+    upload_rhs(t, rd, ai, s);
+    matvec(t, precision, static_cast<const c64 *>(p_dev), static_cast<c64 *>(ap_dev), nrhs, nullptr, s);
+    return DDA_OK;
+  });
+}
+
+int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_opts *opts, void *p_dev,
+              dda_c64 *p_host, void *stream, dda_solve_stats *stats) {
+  return guarded([&]() -> int {
+    DDA_REQUIRE(t && opts, "NULL argument");
+    DDA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    DDA_REQUIRE(std::isfinite(opts->tol) && opts->tol > 0.0, "tol must be > 0");
+    DDA_REQUIRE(opts->max_iter >= 1, "max_iter must be >= 1");
+    DDA_REQUIRE(opts->precision == DDA_FP64 || opts->precision == DDA_MIXED, "unknown precision");
+    DDA_REQUIRE(opts->inner_tol >= 0.0 && opts->inner_tol < 1.0, "inner_tol must be in [0, 1)");
+    DDA_HIP(hipSetDevice(t->device));
+    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : t->stream;
+    const int K = opts->check_every > 0 ? opts->check_every : 8;
+    const int max_outer = opts->max_outer > 0 ? opts->max_outer : 20;
+    std::vector<RhsDev> rd;
+    std::vector<c64> ai;
+    prepare_rhs(t, rhs, nrhs, rd, ai);
+    ensure_krylov(t, nrhs);
+    ensure_workspace(t, nrhs);
+    KrylovState &k = t->k;
+    upload_rhs(t, rd, ai, s);
+    launch_incident(t->g, t->d_ijk, t->d_rhs, nrhs, t->kd, k.b, s);
+    k_init_state(k, opts->tol, opts->max_iter, s);
+
+    std::vector<int> status(nrhs), check(nrhs), restart(nrhs), outer(nrhs, 0), final_status(nrhs, -1);
+    std::vector<c64> scal((size_t)nrhs * kScal);
+    std::vector<double> rel(nrhs, 0.0);
+    const double tol = opts->tol;
+    const double inner = opts->precision == DDA_MIXED ? opts->inner_tol : 0.0;
+    // P = 0 start: an RHS with E = 0 is already solved.
+    while (true) {
+      DDA_HIP(hipMemcpyAsync(status.data(), k.status, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
+      DDA_HIP(hipStreamSynchronize(s));
+      bool any_run = false, any_check = false;
+      for (int r = 0; r < nrhs; ++r) {
+        check[r] = 0;
+        if (final_status[r] >= 0) continue;
+        if (status[r] == ST_RUN) any_run = true;
+        else {
+          check[r] = 1;
+          any_check = true;
+        }
+      }
+      if (any_check) {
+        // FP64 true residual r = E - A x for the stopped RHS
+        DDA_HIP(hipMemcpyAsync(k.check, check.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+        matvec(t, DDA_FP64, k.x, k.t, nrhs, k.check, s);
+        k_true_residual(k, k.t, s);
+        DDA_HIP(hipMemcpyAsync(scal.data(), k.scal, scal.size() * sizeof(c64), hipMemcpyDeviceToHost, s));
+        DDA_HIP(hipStreamSynchronize(s));
+        bool any_restart = false;
+        for (int r = 0; r < nrhs; ++r) {
+          restart[r] = 0;
+          if (!check[r]) continue;
+          const double b2 = scal[(size_t)r * kScal + S_BNORM2].x;
+          const double t2 = scal[(size_t)r * kScal + S_TRUE2].x;
+          rel[r] = b2 > 0.0 ? std::sqrt(t2 / b2) : 0.0;
+          ++outer[r];
+          if (b2 == 0.0 || rel[r] <= tol) final_status[r] = 0;
+          else if (status[r] == ST_MAXIT) final_status[r] = 1;
+          else if (outer[r] >= max_outer || !(rel[r] == rel[r])) final_status[r] = status[r] == ST_BREAK ? 2 : 1;
+          else {
+            restart[r] = 1;
+            any_restart = true;
+          }
+        }
+        if (any_restart) {
+          DDA_HIP(hipMemcpyAsync(t->d_restart, restart.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+          k_restart(k, t->d_restart, tol, inner, s);
+          any_run = true;
+        }
+      }
+      if (!any_run) break;
+      for (int it = 0; it < K; ++it) iteration(t, opts->precision, s);
+    }
+    DDA_HIP(hipMemcpyAsync(scal.data(), k.scal, scal.size() * sizeof(c64), hipMemcpyDeviceToHost, s));
+    const size_t vec = (size_t)k.n3 * nrhs * sizeof(c64);
+    if (p_dev) DDA_HIP(hipMemcpyAsync(p_dev, k.x, vec, hipMemcpyDeviceToDevice, s));
+    if (p_host) DDA_HIP(hipMemcpyAsync(p_host, k.x, vec, hipMemcpyDeviceToHost, s));
+    DDA_HIP(hipStreamSynchronize(s));
+    bool all_ok = true;
+    for (int r = 0; r < nrhs; ++r) {
+      if (final_status[r] != 0) all_ok = false;
+      if (stats) {
+        stats[r].status = final_status[r];
+        stats[r].iters = (int)scal[(size_t)r * kScal + S_ITERS].x;
+        stats[r].matvecs = 2 * stats[r].iters;
+        stats[r].outer = outer[r];
+        stats[r].rel_resid = rel[r];
+      }
+    }
+    return all_ok ? DDA_OK : DDA_NOT_CONVERGED;
+  });
+}
+
+int dda_cross_sections(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const void *p_dev, const dda_c64 *p_host,
+                       void *stream, dda_q *out) {
+  return guarded([&]() -> int {
+    DDA_REQUIRE(t && out, "NULL argument");
+    DDA_REQUIRE(p_dev || p_host, "need p_dev or p_host");
+    DDA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    DDA_HIP(hipSetDevice(t->device));
+    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : t->stream;
+    std::vector<RhsDev> rd;
+    std::vector<c64> ai;
+    prepare_rhs(t, rhs, nrhs, rd, ai);
+    ensure_krylov(t, nrhs);
+    upload_rhs(t, rd, ai, s);
+    const c64 *P = static_cast<const c64 *>(p_dev);
+    if (!P) {
+      DDA_HIP(hipMemcpyAsync(t->k.t, p_host, (size_t)t->k.n3 * nrhs * sizeof(c64), hipMemcpyHostToDevice, s));
+      P = t->k.t;
+    }
+    launch_cross_sums(t->g, t->d_ijk, t->d_rhs, nrhs, t->kd, P, t->d_ainv, t->ncomp, t->d_comp, t->k.partial,
+                      t->d_sums, s);
+    std::vector<double> sums(2 * nrhs);
+    DDA_HIP(hipMemcpyAsync(sums.data(), t->d_sums, sums.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    DDA_HIP(hipStreamSynchronize(s));
+    const double pi = 3.14159265358979323846;
+    const double geo = pi * t->aeff * t->aeff;
+    for (int r = 0; r < nrhs; ++r) {
+      const double cext = 4.0 * pi * t->kd * sums[2 * r];
+      const double cabs = 4.0 * pi * t->kd * sums[2 * r + 1];
+      out[r].qext = cext / geo;
+      out[r].qabs = cabs / geo;
+      out[r].qsca = (cext - cabs) / geo;
+      out[r].aeff = t->aeff;
+    }
+    return DDA_OK;
+  });
+}
+
+int dda_fft_pencils(int32_t n, int64_t batch, int32_t sign, int32_t precision, double scale, const void *in_dev,
+                    void *out_dev, void *stream, int32_t device) {
+  return guarded([&]() -> int {
+    DDA_REQUIRE(in_dev && out_dev, "NULL argument");
+    DDA_REQUIRE(sign == -1 || sign == 1, "sign must be -1 or +1");
+    DDA_REQUIRE(batch >= 0, "batch must be >= 0");
+    DDA_REQUIRE(precision == DDA_FP64 || precision == DDA_MIXED, "unknown precision");
+    DDA_REQUIRE(n >= 1 && n <= kMaxLen && next_smooth(n) == n, "n must be 2/3/5-smooth and <= 512");
+    DDA_HIP(hipSetDevice(device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const AxisPlan p = make_axis_plan(n);
+    dda_target tmp;         // owns the temporary twiddle tables
+    tmp.device = device;
+    make_twiddles(&tmp, tmp.tx, n);
+    if (precision == DDA_FP64)
+      launch_fft_rows<double>(static_cast<const c64 *>(in_dev), static_cast<c64 *>(out_dev), batch, p, tmp.tx.d64,
+                              sign, scale, s);
+    else
+      launch_fft_rows<float>(static_cast<const c32 *>(in_dev), static_cast<c32 *>(out_dev), batch, p, tmp.tx.d32,
+                             sign, float(scale), s);
+    DDA_HIP(hipStreamSynchronize(s));
+    return DDA_OK;
+  });
+}
+
+}  // extern "C"

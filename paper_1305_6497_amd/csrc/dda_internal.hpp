@@ -1,0 +1,193 @@
+// Internal declarations shared by the HIP sources of the DDA library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dda.h"
+
+namespace dda {
+
+// ------------------------------------------------------------------ errors --
+void set_error(const std::string &msg);
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define DDA_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw ::dda::Error{(e_ == hipErrorOutOfMemory) ? DDA_ENOMEM : DDA_EDEVICE,       \
+                         std::string(#call) + ": " + hipGetErrorString(e_)};           \
+  } while (0)
+
+#define DDA_REQUIRE(cond, msg)                                                         \
+  do {                                                                                 \
+    if (!(cond)) throw ::dda::Error{DDA_EINVAL, (msg)};                                \
+  } while (0)
+
+// ----------------------------------------------------------------- complex --
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+  T x, y;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> mk(T a, T b) { return cpx<T>{a, b}; }
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator*(cpx<T> a, cpx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator*(T s, cpx<T> a) { return {s * a.x, s * a.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> conj(cpx<T> a) { return {a.x, -a.y}; }
+// conj(a) * b
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
+  return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+}
+
+using c64 = cpx<double>;
+using c32 = cpx<float>;
+
+// ---------------------------------------------------------------- FFT plan --
+constexpr int kMaxStages = 12;
+constexpr int kMaxLen = 512;      // largest supported padded extent
+
+struct AxisPlan {
+  int L;                          // transform length
+  int nstages;
+  int radix[kMaxStages];          // radices in execution order (each 2, 3, 4, 5 or 8)
+};
+
+AxisPlan make_axis_plan(int L);   // throws for non-smooth L or L > kMaxLen
+int next_smooth(int n);
+
+// Twiddle tables exp(-2 pi i n / L), n = 0..L-1, in both precisions.
+struct Twiddles {
+  c64 *d64 = nullptr;
+  c32 *d32 = nullptr;
+  int L = 0;
+};
+
+// Threads per block of every FFT kernel.
+constexpr int kNT = 256;
+
+// ----------------------------------------------------------- grid geometry --
+// Layouts of the two intermediate buffers of the convolution (per RHS):
+//   A: [3][nz][nxt][ny][W]   x-transformed rows, tiled in x by W
+//   B: [My][nxt][3][nz][W]   x- and y-transformed, tiled in x by W
+// W = 16 (FP32) or 8 (FP64) so that a tile row is 128 bytes; nxt = ceil(Mx/W).
+struct Geometry {
+  int nx, ny, nz;
+  int Mx, My, Mz;
+  int Mxh, Myh, Mzh;              // octant extents M/2 + 1
+  int64_t n_sites;
+  int W(bool fp32) const { return fp32 ? 16 : 8; }
+  int nxt(bool fp32) const { return (Mx + W(fp32) - 1) / W(fp32); }
+  size_t a_elems(bool fp32) const { return (size_t)3 * nz * nxt(fp32) * ny * W(fp32); }
+  size_t b_elems(bool fp32) const { return (size_t)My * nxt(fp32) * 3 * nz * W(fp32); }
+  size_t oct_elems() const { return (size_t)Mxh * Myh * Mzh; }
+};
+
+// Per-RHS device description used by the field and diagonal kernels.
+struct RhsDev {
+  double khat[3];
+  c64 e[3];
+};
+
+// ------------------------------------------------------------ kernel API --
+// Convolution + diagonal:  out_r = ainv_r[comp] * in_r - (G * in_r)   (r < nrhs)
+// in/out are FP64 [nrhs][N][3]; the FFT pipeline runs in T.
+struct MatvecArgs {
+  const c64 *in;
+  c64 *out;
+  int nrhs;
+  const int *mask;                // device [nrhs] (nonzero = process) or nullptr
+  const c64 *ainv;                // device [nrhs][ncomp]
+  int ncomp;
+  const uint8_t *comp;            // device [N] or nullptr
+  const int *cell_site;           // device [nz][ny][nx], -1 = empty
+  void *bufA, *bufB;              // workspaces (sized for nrhs in FP64)
+  const void *ghat;               // octant Green transform [6][Mzh][Myh][Mxh] (scaled by 1/M)
+  const void *twx, *twy, *twz;    // twiddles of the T precision
+  AxisPlan px, py, pz;
+};
+
+template <typename T>
+void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s);
+
+// Green-tensor transform: fills `full` [6][Mz][My][Mx] (FP64), transforms it in
+// place and writes the octant copies (scaled by 1/M) in FP64 and FP32.
+void launch_green_build(const Geometry &g, double kd, c64 *full, c64 *oct64, c32 *oct32,
+                        const Twiddles &tx, const Twiddles &ty, const Twiddles &tz,
+                        const AxisPlan &px, const AxisPlan &py, const AxisPlan &pz, hipStream_t s);
+
+// Batched 1-D FFT of contiguous pencils (diagnostic and setup helper).
+template <typename T>
+void launch_fft_rows(const cpx<T> *in, cpx<T> *out, int64_t batch, const AxisPlan &p,
+                     const cpx<T> *tw, int dir, T scale, hipStream_t s);
+
+// ------------------------------------------------------ Krylov kernels --
+struct KrylovState {
+  int nrhs = 0;
+  int64_t n3 = 0;                 // 3N complex entries per RHS
+  c64 *x = nullptr, *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *s = nullptr,
+      *t = nullptr, *b = nullptr;
+  double *partial = nullptr;      // [nrhs][nblk][4]
+  c64 *scal = nullptr;            // [nrhs][kScal]
+  int *active = nullptr;          // [nrhs]
+  int *status = nullptr;          // [nrhs]
+  int *check = nullptr;           // [nrhs]
+  int nblk = 0;
+};
+
+// scalar slots per RHS
+enum : int { S_RHO = 0, S_ALPHA, S_OMEGA, S_BETA, S_RNORM2, S_BNORM2, S_THR2, S_ITERS, S_MAXIT, S_RH2, S_TRUE2, kScal };
+
+// status values kept on the device
+enum : int { ST_RUN = 0, ST_CONV = 1, ST_BREAK = 2, ST_MAXIT = 3, ST_DONE = 4, ST_IDLE = 5 };
+
+int krylov_blocks(int64_t n3);
+void k_init_state(const KrylovState &k, double tol, int max_iter, hipStream_t s);
+void k_update_p(const KrylovState &k, hipStream_t s);
+void k_dot_rv(const KrylovState &k, hipStream_t s);
+void k_scalar_alpha(const KrylovState &k, hipStream_t s);
+void k_update_s(const KrylovState &k, hipStream_t s);
+void k_dot_ts(const KrylovState &k, hipStream_t s);
+void k_scalar_omega(const KrylovState &k, hipStream_t s);
+void k_update_xr(const KrylovState &k, hipStream_t s);
+void k_scalar_rho(const KrylovState &k, hipStream_t s);
+// r_true = b - Ax (Ax given in `ax`) for RHS with check[r]; writes norms into partial/scal.
+void k_true_residual(const KrylovState &k, const c64 *ax, hipStream_t s);
+// Restart RHS with restart[r] from the current x: r holds the true residual;
+// rh = r, p = v = 0, fresh scalars, inner threshold max(tol |b|, inner_tol |r|).
+void k_restart(const KrylovState &k, const int *restart, double tol, double inner_tol, hipStream_t s);
+
+void launch_incident(const Geometry &g, const int32_t *ijk, const RhsDev *rhs, int nrhs, double kd,
+                     c64 *e, hipStream_t s);
+// Sums per RHS: [0] = sum Im(conj(E) . P), [1] = sum (-Im(ainv) - (2/3) kd^3) |P|^2
+void launch_cross_sums(const Geometry &g, const int32_t *ijk, const RhsDev *rhs, int nrhs, double kd,
+                       const c64 *P, const c64 *ainv, int ncomp, const uint8_t *comp, double *partial,
+                       double *sums, hipStream_t s);
+void copy_vec(c64 *dst, const c64 *src, int64_t n, hipStream_t s);
+void zero_vec(c64 *dst, int64_t n, hipStream_t s);
+
+// --------------------------------------------------------------- host side --
+std::vector<int32_t> make_sites(int shape, const double shpar[3], int32_t box[3]);
+void orient_rhs(double beta, double theta, double phi, const c64 e01[3], int which, RhsDev &out);
+c64 alpha_inverse(int kind, c64 m, double kd, const double khat[3], const c64 e[3]);
+
+}  // namespace dda

@@ -1,0 +1,472 @@
+// BiCGSTAB vector updates, FP64 reductions and per-RHS scalar logic; the
+// incident field and the cross-section sums.
+//
+// BiCGSTAB (van der Vorst 1992; the PBCGST option of §12 of the DDSCAT 7.3
+// guide), unpreconditioned, Hermitian inner products <a,b> = sum conj(a) b:
+//     rho' = <rh, r>;  beta = (rho'/rho)(alpha/omega);  p = r + beta (p - omega v)
+//     v = A p;  alpha = rho' / <rh, v>;  s = r - alpha v
+//     t = A s;  omega = <t, s> / <t, t>;  x += alpha p + omega s;  r = s - omega t
+// Every RHS of a block carries its own scalars on the device, so a block of
+// iterations can be queued without host round trips: each kernel returns
+// early for an RHS whose `active` flag is cleared, and the scalar kernels
+// clear it when the recursive residual passes the threshold, the iteration
+// cap is hit, or the recurrence breaks down.
+//
+// Reductions are deterministic: a fixed grid writes per-block partial sums
+// (wavefront shuffles, then LDS across the block's wavefronts) and one block
+// per RHS adds them in a fixed order.  Repeated solves are bit-identical.
+
+#include <algorithm>
+
+#include "dda_internal.hpp"
+
+namespace dda {
+
+constexpr int KNT = 256;
+constexpr int kPart = 4;     // doubles per partial-sum record
+
+int krylov_blocks(int64_t n3) {
+  int64_t b = (n3 + (int64_t)KNT * 8 - 1) / ((int64_t)KNT * 8);
+  if (b < 1) b = 1;
+  if (b > 1024) b = 1024;
+  return (int)b;
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *out) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += __shfl_down(v[k], off, 64);
+  __shared__ double sh[NV][KNT / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[k][wid] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < KNT / 64; ++w) s += sh[k][w];
+      out[k] = s;
+    }
+}
+
+// Sum the per-block partials of RHS r (fixed order), NV values.
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double *partial, int nblk, int r, double *out) {
+  double v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = 0.0;
+  for (int j = threadIdx.x; j < nblk; j += KNT)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += partial[((size_t)r * nblk + j) * kPart + k];
+  block_sum<NV>(v, out);
+}
+
+#define RHS_PREAMBLE                                       \
+  const int r = blockIdx.y;                                \
+  if (!active[r]) return;                                  \
+  const size_t off = (size_t)r * n3;
+
+// ------------------------------------------------------------- init/restart --
+__global__ void kk_init(c64 *x, c64 *rr, c64 *rh, c64 *p, c64 *v, const c64 *b, int64_t n3, double *partial,
+                        int nblk) {
+  const int r = blockIdx.y;
+  const size_t off = (size_t)r * n3;
+  double acc[1] = {0.0};
+  for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT) {
+    const c64 bv = b[off + i];
+    x[off + i] = {0, 0};
+    rr[off + i] = bv;
+    rh[off + i] = bv;
+    p[off + i] = {0, 0};
+    v[off + i] = {0, 0};
+    acc[0] += bv.x * bv.x + bv.y * bv.y;
+  }
+  double out[1];
+  block_sum<1>(acc, out);
+  if (threadIdx.x == 0) partial[((size_t)r * nblk + blockIdx.x) * kPart] = out[0];
+}
+
+__global__ void kk_init_scalars(const double *partial, int nblk, c64 *scal, int *active, int *status, double tol2,
+                                int max_iter) {
+  const int r = blockIdx.x;
+  double s[1];
+  sum_partials<1>(partial, nblk, r, s);
+  if (threadIdx.x == 0) {
+    c64 *sc = scal + (size_t)r * kScal;
+    const double b2 = s[0];
+    sc[S_RHO] = {b2, 0.0};
+    sc[S_ALPHA] = {1.0, 0.0};
+    sc[S_OMEGA] = {1.0, 0.0};
+    sc[S_BETA] = {0.0, 0.0};
+    sc[S_RNORM2] = {b2, 0.0};
+    sc[S_BNORM2] = {b2, 0.0};
+    sc[S_THR2] = {tol2 * b2, 0.0};
+    sc[S_ITERS] = {0.0, 0.0};
+    sc[S_MAXIT] = {double(max_iter), 0.0};
+    sc[S_RH2] = {b2, 0.0};
+    const bool go = b2 > 0.0;
+    active[r] = go ? 1 : 0;
+    status[r] = go ? ST_RUN : ST_CONV;
+  }
+}
+
+// p = r + beta (p - omega v)
+__global__ void kk_update_p(const int *active, const c64 *rr, c64 *p, const c64 *v, const c64 *scal, int64_t n3,
+                            int nblk) {
+  RHS_PREAMBLE
+  const c64 beta = scal[(size_t)r * kScal + S_BETA];
+  const c64 omega = scal[(size_t)r * kScal + S_OMEGA];
+  for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT) {
+    const c64 pv = p[off + i], vv = v[off + i];
+    p[off + i] = rr[off + i] + beta * (pv - omega * vv);
+  }
+}
+
+// partial <rh, v>
+__global__ void kk_dot_rv(const int *active, const c64 *rh, const c64 *v, int64_t n3, double *partial, int nblk) {
+  RHS_PREAMBLE
+  double acc[2] = {0.0, 0.0};
+  for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT) {
+    const c64 d = cmulc(rh[off + i], v[off + i]);
+    acc[0] += d.x;
+    acc[1] += d.y;
+  }
+  double out[2];
+  block_sum<2>(acc, out);
+  if (threadIdx.x == 0) {
+    double *o = partial + ((size_t)r * nblk + blockIdx.x) * kPart;
+    o[0] = out[0];
+    o[1] = out[1];
+  }
+}
+
+__device__ __forceinline__ c64 cdiv(c64 a, c64 b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return {(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
+}
+__device__ __forceinline__ double cabs2(c64 a) { return a.x * a.x + a.y * a.y; }
+
+__global__ void kk_scalar_alpha(const double *partial, int nblk, c64 *scal, int *active, int *status) {
+  const int r = blockIdx.x;
+  if (!active[r]) return;
+  double s[2];
+  sum_partials<2>(partial, nblk, r, s);
+  if (threadIdx.x == 0) {
+    c64 *sc = scal + (size_t)r * kScal;
+    const c64 den = {s[0], s[1]};
+    // <rh, v> ~ 0 relative to |rh| |r|: the recurrence cannot continue
+    if (cabs2(den) <= 1e-60 * sc[S_RH2].x * sc[S_RNORM2].x || !(cabs2(den) > 0.0)) {
+      active[r] = 0;
+      status[r] = ST_BREAK;
+    } else {
+      sc[S_ALPHA] = cdiv(sc[S_RHO], den);
+    }
+  }
+}
+
+// s = r - alpha v
+__global__ void kk_update_s(const int *active, const c64 *rr, const c64 *v, c64 *s, const c64 *scal, int64_t n3,
+                            int nblk) {
+  RHS_PREAMBLE
+  const c64 alpha = scal[(size_t)r * kScal + S_ALPHA];
+  for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT)
+    s[off + i] = rr[off + i] - alpha * v[off + i];
+}
+
+// partial <t, s>, <t, t>
+__global__ void kk_dot_ts(const int *active, const c64 *t, const c64 *s, int64_t n3, double *partial, int nblk) {
+  RHS_PREAMBLE
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT) {
+    const c64 tv = t[off + i];
+    const c64 d = cmulc(tv, s[off + i]);
+    acc[0] += d.x;
+    acc[1] += d.y;
+    acc[2] += tv.x * tv.x + tv.y * tv.y;
+  }
+  double out[3];
+  block_sum<3>(acc, out);
+  if (threadIdx.x == 0) {
+    double *o = partial + ((size_t)r * nblk + blockIdx.x) * kPart;
+    o[0] = out[0];
+    o[1] = out[1];
+    o[2] = out[2];
+  }
+}
+
+__global__ void kk_scalar_omega(const double *partial, int nblk, c64 *scal, const int *active) {
+  const int r = blockIdx.x;
+  if (!active[r]) return;
+  double s[3];
+  sum_partials<3>(partial, nblk, r, s);
+  if (threadIdx.x == 0) {
+    c64 *sc = scal + (size_t)r * kScal;
+    sc[S_OMEGA] = s[2] > 0.0 ? c64{s[0] / s[2], s[1] / s[2]} : c64{0.0, 0.0};
+  }
+}
+
+// x += alpha p + omega s;  r = s - omega t;  partial <rh, r>, |r|^2
+__global__ void kk_update_xr(const int *active, c64 *x, c64 *rr, const c64 *rh, const c64 *p, const c64 *s,
+                             const c64 *t, const c64 *scal, int64_t n3, double *partial, int nblk) {
+  RHS_PREAMBLE
+  const c64 alpha = scal[(size_t)r * kScal + S_ALPHA];
+  const c64 omega = scal[(size_t)r * kScal + S_OMEGA];
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT) {
+    const c64 sv = s[off + i];
+    x[off + i] = x[off + i] + alpha * p[off + i] + omega * sv;
+    const c64 rv = sv - omega * t[off + i];
+    rr[off + i] = rv;
+    const c64 d = cmulc(rh[off + i], rv);
+    acc[0] += d.x;
+    acc[1] += d.y;
+    acc[2] += rv.x * rv.x + rv.y * rv.y;
+  }
+  double out[3];
+  block_sum<3>(acc, out);
+  if (threadIdx.x == 0) {
+    double *o = partial + ((size_t)r * nblk + blockIdx.x) * kPart;
+    o[0] = out[0];
+    o[1] = out[1];
+    o[2] = out[2];
+  }
+}
+
+__global__ void kk_scalar_rho(const double *partial, int nblk, c64 *scal, int *active, int *status) {
+  const int r = blockIdx.x;
+  if (!active[r]) return;
+  double s[3];
+  sum_partials<3>(partial, nblk, r, s);
+  if (threadIdx.x == 0) {
+    c64 *sc = scal + (size_t)r * kScal;
+    const c64 rho_new = {s[0], s[1]};
+    const double rn2 = s[2];
+    sc[S_RNORM2] = {rn2, 0.0};
+    sc[S_ITERS].x += 1.0;
+    const c64 omega = sc[S_OMEGA];
+    if (!(rn2 == rn2)) {                                     // NaN
+      active[r] = 0;
+      status[r] = ST_BREAK;
+    } else if (rn2 <= sc[S_THR2].x) {
+      active[r] = 0;
+      status[r] = ST_CONV;
+    } else if (sc[S_ITERS].x >= sc[S_MAXIT].x) {
+      active[r] = 0;
+      status[r] = ST_MAXIT;
+    } else if (cabs2(rho_new) <= 1e-60 * sc[S_RH2].x * rn2 || cabs2(omega) == 0.0) {
+      active[r] = 0;
+      status[r] = ST_BREAK;
+    } else {
+      sc[S_BETA] = cdiv(rho_new, sc[S_RHO]) * cdiv(sc[S_ALPHA], omega);
+      sc[S_RHO] = rho_new;
+    }
+  }
+}
+
+// r = b - ax for checked RHS; partial |r|^2
+__global__ void kk_true_residual(const int *check, const c64 *b, const c64 *ax, c64 *rr, int64_t n3,
+                                 double *partial, int nblk) {
+  const int r = blockIdx.y;
+  if (!check[r]) return;
+  const size_t off = (size_t)r * n3;
+  double acc[1] = {0.0};
+  for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT) {
+    const c64 rv = b[off + i] - ax[off + i];
+    rr[off + i] = rv;
+    acc[0] += rv.x * rv.x + rv.y * rv.y;
+  }
+  double out[1];
+  block_sum<1>(acc, out);
+  if (threadIdx.x == 0) partial[((size_t)r * nblk + blockIdx.x) * kPart] = out[0];
+}
+
+__global__ void kk_scalar_true(const double *partial, int nblk, c64 *scal, const int *check) {
+  const int r = blockIdx.x;
+  if (!check[r]) return;
+  double s[1];
+  sum_partials<1>(partial, nblk, r, s);
+  if (threadIdx.x == 0) scal[(size_t)r * kScal + S_TRUE2] = {s[0], 0.0};
+}
+
+// Restart from the current x for RHS with restart[r]: r already holds the true
+// residual; rh = r, p = v = 0 and fresh scalars.
+__global__ void kk_restart(const int *restart, const c64 *rr, c64 *rh, c64 *p, c64 *v, int64_t n3, int nblk) {
+  const int r = blockIdx.y;
+  if (!restart[r]) return;
+  const size_t off = (size_t)r * n3;
+  for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT) {
+    rh[off + i] = rr[off + i];
+    p[off + i] = {0, 0};
+    v[off + i] = {0, 0};
+  }
+}
+
+__global__ void kk_restart_scalars(const int *restart, c64 *scal, int *active, int *status, int nrhs, double tol2,
+                                   double inner2) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs || !restart[r]) return;
+  c64 *sc = scal + (size_t)r * kScal;
+  const double t2 = sc[S_TRUE2].x;
+  sc[S_RHO] = {t2, 0.0};
+  sc[S_ALPHA] = {1.0, 0.0};
+  sc[S_OMEGA] = {1.0, 0.0};
+  sc[S_BETA] = {0.0, 0.0};
+  sc[S_RNORM2] = {t2, 0.0};
+  sc[S_RH2] = {t2, 0.0};
+  const double thr = tol2 * sc[S_BNORM2].x;
+  const double inner = inner2 * t2;
+  sc[S_THR2] = {thr > inner ? thr : inner, 0.0};
+  active[r] = 1;
+  status[r] = ST_RUN;
+}
+
+// ------------------------------------------------------------- host wrappers --
+static dim3 vgrid(const KrylovState &k) { return dim3(k.nblk, k.nrhs); }
+
+void k_init_state(const KrylovState &k, double tol, int max_iter, hipStream_t s) {
+  hipLaunchKernelGGL(kk_init, vgrid(k), dim3(KNT), 0, s, k.x, k.r, k.rh, k.p, k.v, k.b, k.n3, k.partial, k.nblk);
+  hipLaunchKernelGGL(kk_init_scalars, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, k.nblk, k.scal, k.active, k.status,
+                     tol * tol, max_iter);
+  DDA_HIP(hipGetLastError());
+}
+void k_update_p(const KrylovState &k, hipStream_t s) {
+  hipLaunchKernelGGL(kk_update_p, vgrid(k), dim3(KNT), 0, s, k.active, k.r, k.p, k.v, k.scal, k.n3, k.nblk);
+}
+void k_dot_rv(const KrylovState &k, hipStream_t s) {
+  hipLaunchKernelGGL(kk_dot_rv, vgrid(k), dim3(KNT), 0, s, k.active, k.rh, k.v, k.n3, k.partial, k.nblk);
+}
+void k_scalar_alpha(const KrylovState &k, hipStream_t s) {
+  hipLaunchKernelGGL(kk_scalar_alpha, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, k.nblk, k.scal, k.active, k.status);
+}
+void k_update_s(const KrylovState &k, hipStream_t s) {
+  hipLaunchKernelGGL(kk_update_s, vgrid(k), dim3(KNT), 0, s, k.active, k.r, k.v, k.s, k.scal, k.n3, k.nblk);
+}
+void k_dot_ts(const KrylovState &k, hipStream_t s) {
+  hipLaunchKernelGGL(kk_dot_ts, vgrid(k), dim3(KNT), 0, s, k.active, k.t, k.s, k.n3, k.partial, k.nblk);
+}
+void k_scalar_omega(const KrylovState &k, hipStream_t s) {
+  hipLaunchKernelGGL(kk_scalar_omega, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, k.nblk, k.scal, k.active);
+}
+void k_update_xr(const KrylovState &k, hipStream_t s) {
+  hipLaunchKernelGGL(kk_update_xr, vgrid(k), dim3(KNT), 0, s, k.active, k.x, k.r, k.rh, k.p, k.s, k.t, k.scal, k.n3,
+                     k.partial, k.nblk);
+}
+void k_scalar_rho(const KrylovState &k, hipStream_t s) {
+  hipLaunchKernelGGL(kk_scalar_rho, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, k.nblk, k.scal, k.active, k.status);
+}
+void k_true_residual(const KrylovState &k, const c64 *ax, hipStream_t s) {
+  hipLaunchKernelGGL(kk_true_residual, vgrid(k), dim3(KNT), 0, s, k.check, k.b, ax, k.r, k.n3, k.partial, k.nblk);
+  hipLaunchKernelGGL(kk_scalar_true, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, k.nblk, k.scal, k.check);
+  DDA_HIP(hipGetLastError());
+}
+void k_restart(const KrylovState &k, const int *restart, double tol, double inner_tol, hipStream_t s) {
+  hipLaunchKernelGGL(kk_restart, vgrid(k), dim3(KNT), 0, s, restart, k.r, k.rh, k.p, k.v, k.n3, k.nblk);
+  hipLaunchKernelGGL(kk_restart_scalars, dim3((k.nrhs + 63) / 64), dim3(64), 0, s, restart, k.scal, k.active,
+                     k.status, k.nrhs, tol * tol, inner_tol * inner_tol);
+  DDA_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------- incident field --
+// E_j = e exp(i kd khat . r_j)  (eq. AP=E with |E0| = 1)
+__global__ void kk_incident(const int32_t *ijk, int64_t n, const RhsDev *rhs, double kd, c64 *e) {
+  const int r = blockIdx.y;
+  const RhsDev R = rhs[r];
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    const double ph = kd * (R.khat[0] * ijk[3 * j] + R.khat[1] * ijk[3 * j + 1] + R.khat[2] * ijk[3 * j + 2]);
+    double sn, cs;
+    sincos(ph, &sn, &cs);
+    const c64 w = {cs, sn};
+    c64 *o = e + ((size_t)r * n + j) * 3;
+    o[0] = w * R.e[0];
+    o[1] = w * R.e[1];
+    o[2] = w * R.e[2];
+  }
+}
+
+void launch_incident(const Geometry &g, const int32_t *ijk, const RhsDev *rhs, int nrhs, double kd, c64 *e,
+                     hipStream_t s) {
+  const int64_t n = g.n_sites;
+  const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
+  hipLaunchKernelGGL(kk_incident, dim3(nb, nrhs), dim3(256), 0, s, ijk, n, rhs, kd, e);
+  DDA_HIP(hipGetLastError());
+}
+
+// --------------------------------------------------------- cross sections --
+// per site: Im(conj(E_j) . P_j)  and  (-Im(ainv_j) - (2/3) kd^3) |P_j|^2
+__global__ void kk_cross(const int32_t *ijk, int64_t n, const RhsDev *rhs, double kd, const c64 *P, const c64 *ainv,
+                         int ncomp, const uint8_t *comp, double *partial, int nblk) {
+  const int r = blockIdx.y;
+  const RhsDev R = rhs[r];
+  const double rr = (2.0 / 3.0) * kd * kd * kd;
+  double acc[2] = {0.0, 0.0};
+  for (int64_t j = blockIdx.x * (int64_t)KNT + threadIdx.x; j < n; j += (int64_t)nblk * KNT) {
+    const double ph = kd * (R.khat[0] * ijk[3 * j] + R.khat[1] * ijk[3 * j + 1] + R.khat[2] * ijk[3 * j + 2]);
+    double sn, cs;
+    sincos(ph, &sn, &cs);
+    const c64 w = {cs, sn};
+    const c64 *pj = P + ((size_t)r * n + j) * 3;
+    const c64 ai = ainv[(size_t)r * ncomp + (comp ? comp[j] : 0)];
+    double p2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const c64 ec = w * R.e[c];
+      const c64 pc = pj[c];
+      acc[0] += ec.x * pc.y - ec.y * pc.x;        // Im(conj(E) P)
+      p2 += pc.x * pc.x + pc.y * pc.y;
+    }
+    acc[1] += (-ai.y - rr) * p2;
+  }
+  double out[2];
+  block_sum<2>(acc, out);
+  if (threadIdx.x == 0) {
+    double *o = partial + ((size_t)r * nblk + blockIdx.x) * kPart;
+    o[0] = out[0];
+    o[1] = out[1];
+  }
+}
+
+__global__ void kk_cross_final(const double *partial, int nblk, double *sums) {
+  const int r = blockIdx.x;
+  double s[2];
+  sum_partials<2>(partial, nblk, r, s);
+  if (threadIdx.x == 0) {
+    sums[2 * r] = s[0];
+    sums[2 * r + 1] = s[1];
+  }
+}
+
+void launch_cross_sums(const Geometry &g, const int32_t *ijk, const RhsDev *rhs, int nrhs, double kd, const c64 *P,
+                       const c64 *ainv, int ncomp, const uint8_t *comp, double *partial, double *sums,
+                       hipStream_t s) {
+  const int nblk = krylov_blocks(3 * g.n_sites);
+  hipLaunchKernelGGL(kk_cross, dim3(nblk, nrhs), dim3(KNT), 0, s, ijk, g.n_sites, rhs, kd, P, ainv, ncomp, comp,
+                     partial, nblk);
+  hipLaunchKernelGGL(kk_cross_final, dim3(nrhs), dim3(KNT), 0, s, partial, nblk, sums);
+  DDA_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ misc vectors --
+__global__ void kk_copy(c64 *dst, const c64 *src, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+__global__ void kk_zero(c64 *dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = {0.0, 0.0};
+}
+void copy_vec(c64 *dst, const c64 *src, int64_t n, hipStream_t s) {
+  const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(kk_copy, dim3(nb), dim3(256), 0, s, dst, src, n);
+  DDA_HIP(hipGetLastError());
+}
+void zero_vec(c64 *dst, int64_t n, hipStream_t s) {
+  const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(kk_zero, dim3(nb), dim3(256), 0, s, dst, n);
+  DDA_HIP(hipGetLastError());
+}
+
+}  // namespace dda

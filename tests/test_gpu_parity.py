@@ -1,0 +1,281 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Tolerances:
+* FP64 FFT / product: 1e-12 relative to the largest output (rounding of
+  O(log M) stages of complex FP64 arithmetic, ~1e-15 each, with margin).
+* FP32 FFT: 2e-6 relative to the largest output (24-bit mantissa, ~log2 L
+  stages).  FP32 convolution product (MIXED): 5e-6 relative to the largest
+  output: three FP32 transforms with ~log2 M roundings of 6e-8 each, the
+  FP32-rounded Green transform and the cancellation between the diagonal and
+  the field term, which is O(1) for these refractive indices.
+* Solves: P against dense LU to 1e-8 relative when solved to tol 1e-10;
+  efficiencies to 1e-9 of Q_ext.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import inputs  # noqa: E402
+from oracle import cross_sections, incident, interaction, polarizability, solvers, targets  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def dda():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1305_6497_amd as m
+    m._lib.lib()
+    return m
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+# ------------------------------------------------------------------- FFT --
+def _smooth_list(limit):
+    out = []
+    for n in range(1, limit + 1):
+        v = n
+        for p in (2, 3, 5):
+            while v % p == 0:
+                v //= p
+        if v == 1:
+            out.append(n)
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fft_pencils_all_smooth_lengths(dda, prec):
+    rng = np.random.default_rng(11)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    for n in _smooth_list(512):
+        batch = 1 + (n * 7) % 13            # ragged batches
+        x = rng.standard_normal((batch, n)) + 1j * rng.standard_normal((batch, n))
+        xt = torch.tensor(x, dtype=dt, device="cuda")
+        f = dda.fft_pencils(xt, sign=-1).cpu().numpy()
+        b = dda.fft_pencils(xt, sign=+1, scale=1.0 / n).cpu().numpy()
+        assert _rel(f, np.fft.fft(x, axis=-1)) < tol, n
+        assert _rel(b, np.fft.ifft(x, axis=-1)) < tol, n
+
+
+def test_fft_pencils_empty_batch(dda):
+    x = torch.zeros((0, 40), dtype=torch.complex128, device="cuda")
+    assert dda.fft_pencils(x).shape == (0, 40)
+
+
+# --------------------------------------------------------------- products --
+def _oracle_ainv(m, kd, khat, e):
+    return polarizability.alpha_inv_ldr(m, kd, khat, e)
+
+
+SMALL_TARGETS = [
+    ("ELLIPSOID", (8.3, 8.3, 8.3)),
+    ("ELLIPSOID", (11, 6, 5)),
+    ("RCTGLPRSM", (7, 5, 3)),
+    ("CYLINDER1", (9, 7, 3)),
+    ("HEX_PRISM", (6, 9, 2)),
+    ("RCTGLPRSM", (1, 1, 1)),          # one dipole
+    ("RCTGLPRSM", (2, 1, 1)),          # two dipoles
+    ("RCTGLPRSM", (1, 1, 13)),         # a line: degenerate x and y extents
+    ("RCTGLPRSM", (23, 2, 1)),
+    ("ELLIPSOID", (21, 17, 14.5)),     # several FFT tiles in x, ragged
+]
+
+
+@pytest.mark.parametrize("shape,shpar", SMALL_TARGETS)
+def test_matvec_fp64_and_mixed_against_direct_sum(dda, shape, shpar):
+    sites, box = dda.make_sites(shape, shpar)
+    osites = targets.make(shape, shpar)
+    kd, m = 0.45, 1.6 + 0.05j
+    khat, e = dda.orient_rhs(0.3, 1.1, 2.0, which=1)
+    t = dda.Target(sites, box, m=m, kd=kd)
+    P = inputs.random_polarization(len(sites), 2, seed=5)
+    Pt = torch.tensor(P, dtype=torch.complex128, device="cuda")
+    rhs = [(khat, e), dda.orient_rhs(0.3, 1.1, 2.0, which=2)]
+    ref = np.stack([interaction.direct_matvec(osites, kd, _oracle_ainv(m, kd, *rhs[r]), P[r]) for r in range(2)])
+    a64 = t.apply(rhs, Pt, "fp64").cpu().numpy()
+    a32 = t.apply(rhs, Pt, "mixed").cpu().numpy()
+    t.close()
+    assert _rel(a64, ref) < 1e-12
+    assert _rel(a32, ref) < 5e-6
+
+
+def test_matvec_multi_composition(dda):
+    sites, box = dda.make_sites("ELLIPSOID", (12, 10, 9))
+    comp = (np.arange(len(sites)) % 3).astype(np.uint8)
+    ms = [1.5 + 0.1j, 1.33 + 0.0j, 2.0 + 0.5j]
+    kd = 0.3
+    rhs = [dda.orient_rhs(0, 0, 0)]
+    t = dda.Target(sites, box, m=ms, kd=kd, comp=comp)
+    P = inputs.random_polarization(len(sites), 1, seed=9)
+    out = t.apply(rhs, torch.tensor(P, device="cuda"), "fp64").cpu().numpy()[0]
+    t.close()
+    ai = np.array([_oracle_ainv(mm, kd, *rhs[0]) for mm in ms])[comp]
+    ref = interaction.direct_matvec(targets.ellipsoid(12, 10, 9), kd, ai, P[0])
+    assert _rel(out, ref) < 1e-12
+
+
+def test_incident_field(dda):
+    sites, box = dda.make_sites("ELLIPSOID", (15, 12, 9))
+    kd = 0.37
+    b, th, ph = inputs.orientation_angles(3, seed=2)
+    rhs = [dda.orient_rhs(b[i], th[i], ph[i], which=1 + i % 2) for i in range(3)]
+    t = dda.Target(sites, box, m=1.5, kd=kd)
+    E = t.incident_field(rhs).cpu().numpy()
+    t.close()
+    for i in range(3):
+        ref = incident.incident_field(targets.ellipsoid(15, 12, 9), kd, *rhs[i])
+        assert _rel(E[i], ref) < 1e-14
+
+
+# ------------------------------------------------------------------ solves --
+@pytest.mark.parametrize("m,alpha", [(1.33 + 0.01j, "LATTDR"), (1.7 + 0.3j, "LATTDR"), (2.5 + 0.5j, "CMRR"),
+                                     (1.5 + 0.0j, "FLTRCD")])
+def test_solve_matches_dense_lu(dda, m, alpha):
+    shpar = (9.5, 8.0, 6.5)
+    sites, box = dda.make_sites("ELLIPSOID", shpar)
+    osites = targets.ellipsoid(*shpar)
+    kd = 0.5
+    b, th, ph = inputs.orientation_angles(1, seed=3)
+    rhs = [dda.orient_rhs(b[0], th[0], ph[0], which=1), dda.orient_rhs(b[0], th[0], ph[0], which=2)]
+    t = dda.Target(sites, box, m=m, kd=kd, alpha=alpha)
+    P, stats = t.solve(rhs, tol=1e-11, precision="fp64", max_iter=2000)
+    q = t.cross_sections(rhs, P)
+    Pg = P.cpu().numpy()
+    t.close()
+    for r in range(2):
+        assert stats[r]["status"] == 0 and stats[r]["rel_resid"] <= 1e-11
+        ai = polarizability.alpha_inv(alpha, m, kd, *rhs[r])
+        E = incident.incident_field(osites, kd, *rhs[r])
+        A = interaction.dense_matrix(osites, kd, ai)
+        Po = solvers.lu_solve(A, E.ravel()).reshape(-1, 3)
+        assert _rel(Pg[r], Po) < 1e-8
+        qo = cross_sections.efficiencies(len(osites), kd, E, ai, Po)
+        for key in ("qext", "qabs", "qsca"):
+            assert abs(q[r][key] - qo[key]) <= 1e-9 * qo["qext"], key
+
+
+def test_solve_mixed_reaches_fp64_tolerance(dda):
+    sites, box = dda.make_sites("RCTGLPRSM", (16, 12, 10))
+    osites = targets.rctglprsm(16, 12, 10)
+    kd, m = 0.35, 1.5 + 0.1j
+    rhs = [dda.orient_rhs(0, 0, 0, which=1)]
+    t = dda.Target(sites, box, m=m, kd=kd)
+    P, st = t.solve(rhs, tol=1e-8, precision="mixed")
+    Pg = P.cpu().numpy()[0]
+    t.close()
+    assert st[0]["status"] == 0
+    ai = _oracle_ainv(m, kd, *rhs[0])
+    E = incident.incident_field(osites, kd, *rhs[0])
+    res = np.linalg.norm(E - interaction.FFTOperator(osites, kd, ai).matvec(Pg)) / np.linalg.norm(E)
+    assert res <= 1e-8
+
+
+def test_batched_block_equals_single_solves_bitwise(dda):
+    sites, box = dda.make_sites("ELLIPSOID", (14, 10, 8))
+    kd, m = 0.4, 1.7 + 0.05j
+    b, th, ph = inputs.orientation_angles(3, seed=4)
+    rhs = [dda.orient_rhs(b[i], th[i], ph[i], which=1 + (i % 2)) for i in range(3)]
+    t = dda.Target(sites, box, m=m, kd=kd)
+    for prec in ("fp64", "mixed"):
+        Pb, sb = t.solve(rhs, tol=1e-7, precision=prec)
+        Pb = Pb.cpu().numpy()
+        for i in range(3):
+            Ps, ss = t.solve([rhs[i]], tol=1e-7, precision=prec)
+            assert np.array_equal(Ps.cpu().numpy()[0], Pb[i]), (prec, i)
+            assert ss[0]["iters"] == sb[i]["iters"]
+    t.close()
+
+
+def test_repeat_solve_is_deterministic(dda):
+    sites, box = dda.make_sites("ELLIPSOID", (12, 12, 12))
+    t = dda.Target(sites, box, m=1.33 + 0.01j, kd=0.3)
+    rhs = [dda.orient_rhs(0, 0, 0)]
+    a, _ = t.solve(rhs, tol=1e-6, precision="mixed")
+    b, _ = t.solve(rhs, tol=1e-6, precision="mixed")
+    assert torch.equal(a, b)
+    t.close()
+
+
+def test_not_converged_and_zero_rhs(dda):
+    sites, box = dda.make_sites("ELLIPSOID", (10, 10, 10))
+    t = dda.Target(sites, box, m=1.7 + 0.1j, kd=0.4)
+    rhs = [dda.orient_rhs(0, 0, 0)]
+    P, st = t.solve(rhs, tol=1e-12, max_iter=1, max_outer=1)
+    assert st[0]["status"] == 1 and st[0]["iters"] == 1
+    with pytest.raises(dda.DDAError):
+        t.solve([(np.array([1.0, 0, 0]), np.array([1.0, 0, 0]))])      # khat . e != 0
+    with pytest.raises(dda.DDAError):
+        t.solve([(np.array([2.0, 0, 0]), np.array([0, 1.0, 0]))])      # |khat| != 1
+    t.close()
+
+
+def test_validity_warning_is_reported(dda):
+    sites, box = dda.make_sites("ELLIPSOID", (6, 6, 6))
+    t = dda.Target(sites, box, m=2.5 + 0.5j, kd=0.6)          # |m|kd > 1
+    assert t.setup_status == dda._lib.DDA_WVALIDITY
+    t.close()
+
+
+# ----------------------------------------------------- configuration sizes --
+def _sampled_rows_check(dda, shape, shpar, m, x, nrows=24, prec_tol=(("fp64", 1e-12), ("mixed", 5e-6))):
+    sites, box = dda.make_sites(shape, shpar)
+    n = len(sites)
+    kd = dda.kd_from_x(x, n)
+    rhs = [dda.orient_rhs(0, 0, 0)]
+    t = dda.Target(sites, box, m=m, kd=kd)
+    P = inputs.random_polarization(n, 1, seed=21)
+    Pt = torch.tensor(P, device="cuda")
+    rng = np.random.default_rng(0)
+    rows = np.unique(np.concatenate([[0, n - 1], rng.integers(0, n, nrows)]))
+    osites = sites.astype(np.int64)
+    ai = _oracle_ainv(m, kd, *rhs[0])
+    ref = ai * P[0][rows] - interaction.sampled_direct_field(osites, kd, P[0], rows)
+    for prec, tol in prec_tol:
+        out = t.apply(rhs, Pt, prec).cpu().numpy()[0][rows]
+        assert _rel(out, ref) < tol, prec
+    t.close()
+
+
+def test_matvec_full_size_block_64(dda):
+    _sampled_rows_check(dda, "RCTGLPRSM", (64, 64, 64), 1.5 + 0.1j, 10.0)
+
+
+def test_matvec_full_size_ellipsoid_96x64x48(dda):
+    _sampled_rows_check(dda, "ELLIPSOID", (96, 64, 48), 1.7 + 0.05j, 8.0)
+
+
+def test_matvec_full_size_sphere_133(dda):
+    _sampled_rows_check(dda, "ELLIPSOID", (133, 133, 133), 1.33 + 0.001j, 25.0, nrows=8)
+
+
+def test_sphere_d20_fp64_solve_against_oracle(dda):
+    w = inputs.WORKLOADS["sphere_d20"]
+    sites, box = dda.make_sites(w["shape"], w["shpar"])
+    osites = targets.make(w["shape"], w["shpar"])
+    n = len(sites)
+    kd = dda.kd_from_x(w["x"], n)
+    rhs = [dda.orient_rhs(0, 0, 0, which=1), dda.orient_rhs(0, 0, 0, which=2)]
+    t = dda.Target(sites, box, m=w["m"], kd=kd)
+    P, st = t.solve(rhs, tol=1e-5, precision="fp64")
+    q = t.cross_sections(rhs, P)
+    Pg = P.cpu().numpy()
+    t.close()
+    for r in range(2):
+        ai = _oracle_ainv(w["m"], kd, *rhs[r])
+        E = incident.incident_field(osites, kd, *rhs[r])
+        op = interaction.FFTOperator(osites, kd, ai)
+        res = np.linalg.norm(E - op.matvec(Pg[r])) / np.linalg.norm(E)
+        assert st[r]["status"] == 0 and res <= 1e-5
+        Po, info = solvers.bicgstab(op.matvec, E, tol=1e-10)
+        qo = cross_sections.efficiencies(n, kd, E, ai, Po)
+        for key in ("qext", "qabs", "qsca"):
+            assert abs(q[r][key] - qo[key]) <= 1e-5 * abs(qo[key]), (key, q[r][key], qo[key])

@@ -1,0 +1,140 @@
+"""CPU checks of the C ABI: library loads, exports every declared symbol, and its
+host-side arithmetic (site rules, orientation, grid extents, validation) agrees
+with the oracle.  No GPU work is launched here."""
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import incident, targets
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def dda():
+    import paper_1305_6497_amd as m
+    m._lib.lib()
+    return m
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "dda.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|double|int32_t|const char \*)\s*\*?\s*(dda_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_declared_symbol(dda):
+    names = _declared_symbols()
+    assert len(names) >= 15
+    lib = dda._lib.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    bound = {s[0] for s in dda._lib.SIGNATURES}
+    assert set(names) == bound
+
+
+@pytest.mark.parametrize("shape,shpar,fn", [
+    ("ELLIPSOID", (8.3, 8.3, 8.3), lambda: targets.sphere(8.3)),
+    ("ELLIPSOID", (20, 20, 20), lambda: targets.sphere(20)),
+    ("ELLIPSOID", (96, 64, 48), lambda: targets.ellipsoid(96, 64, 48)),
+    ("ELLIPSOID", (17.3, 9.6, 12.2), lambda: targets.ellipsoid(17.3, 9.6, 12.2)),
+    ("RCTGLPRSM", (16, 32, 32), lambda: targets.rctglprsm(16, 32, 32)),
+    ("CYLINDER1", (30, 21, 1), lambda: targets.cylinder1(30, 21, 1)),
+    ("CYLINDER1", (17, 24, 2), lambda: targets.cylinder1(17, 24, 2)),
+    ("CYLINDER1", (9, 13.5, 3), lambda: targets.cylinder1(9, 13.5, 3)),
+    ("HEX_PRISM", (19, 24, 1), lambda: targets.hex_prism(19, 24, 1)),
+    ("HEX_PRISM", (12, 31, 5), lambda: targets.hex_prism(12, 31, 5)),
+    ("HEX_PRISM", (40, 57, 4), lambda: targets.hex_prism(40, 57, 4)),
+])
+def test_site_rules_bit_exact_against_oracle(dda, shape, shpar, fn):
+    s, box = dda.make_sites(shape, shpar)
+    o = fn()
+    assert np.array_equal(s.astype(np.int64), o)
+    assert tuple(box) == targets.box_of(o)
+
+
+def test_serving_shapes_bit_exact_against_oracle(dda):
+    import inputs
+    reqs = inputs.serving_requests(n=40, seed=7)
+    for q in reqs:
+        s, box = dda.make_sites(q["shape"], q["shpar"])
+        o = targets.make(q["shape"], q["shpar"])
+        assert np.array_equal(s.astype(np.int64), o), q
+
+
+def test_scale(dda):
+    assert abs(dda.aeff(16384) - targets.aeff(16384)) < 1e-12
+    assert abs(dda.kd_from_x(3.093665, 16384) - targets.kd_from_x(3.093665, 16384)) < 1e-15
+
+
+def test_orientation_matches_oracle(dda):
+    import inputs
+    b, t, p = inputs.orientation_angles(16)
+    for i in range(16):
+        for which, e01 in ((1, (0, 1, 0)), (2, (0, 1, 0)), (1, (0, 1, 1j))):
+            k, e = dda.orient_rhs(b[i], t[i], p[i], e01=e01, which=which)
+            e1, e2 = incident.polarization_pair(e01)
+            ko, eo = incident.incident_in_tf(b[i], t[i], p[i], e1 if which == 1 else e2)
+            assert np.allclose(k, ko, atol=1e-14) and np.allclose(e, eo, atol=1e-14)
+            assert abs(np.dot(k, e)) < 1e-13
+
+
+def test_next_smooth(dda):
+    smooth = [n for n in range(1, 600) if all(p in (2, 3, 5) for p in _factors(n))]
+    for n in range(1, 520):
+        assert dda.next_smooth(n) == min(s for s in smooth if s >= n)
+
+
+def _factors(n):
+    out, p = [], 2
+    while n > 1:
+        while n % p == 0:
+            out.append(p)
+            n //= p
+        p += 1
+    return out
+
+
+def test_invalid_inputs_are_rejected_before_device_work(dda):
+    L = dda._lib
+    with pytest.raises(dda.DDAError) as ei:
+        dda.make_sites("ELLIPSOID", (0, 3, 3))
+    assert ei.value.code == L.DDA_EINVAL
+    with pytest.raises(dda.DDAError):
+        dda.orient_rhs(0, 0, 0, e01=(1, 0, 0))
+    with pytest.raises(dda.DDAError):
+        dda.orient_rhs(0, 0, 0, which=3)
+    # footprint validation (host only)
+    with pytest.raises(dda.DDAError) as ei:
+        dda.footprint_bytes((10, 10, 10), 0)
+    assert ei.value.code == L.DDA_EINVAL
+    with pytest.raises(dda.DDAError):
+        dda.footprint_bytes((10, 10, 10), 100, m=complex(0, math.sqrt(2)))    # m^2 = -2
+    with pytest.raises(dda.DDAError):
+        dda.footprint_bytes((10, 10, 10), 100, kd=-1.0)
+    with pytest.raises(dda.DDAError):
+        dda.footprint_bytes((10, 10, 10), 100, m=float("nan"))
+    with pytest.raises(dda.DDAError) as ei:
+        dda.footprint_bytes((300, 10, 10), 100)
+    assert ei.value.code == L.DDA_ENOTSUP
+
+
+def test_setup_rejects_bad_sites_without_device(dda):
+    with pytest.raises(dda.DDAError) as ei:
+        dda.Target(np.array([[0, 0, 0], [5, 0, 0]]), (3, 3, 3), m=1.5, kd=0.3)
+    assert "outside" in str(ei.value)
+    with pytest.raises(dda.DDAError) as ei:
+        dda.Target(np.array([[0, 0, 0], [0, 0, 0]]), (3, 3, 3), m=1.5, kd=0.3)
+    assert "duplicate" in str(ei.value)
+
+
+def test_footprint_grows_with_rhs_and_grid(dda):
+    a = dda.footprint_bytes((64, 64, 64), 262144, nrhs=1)
+    b = dda.footprint_bytes((64, 64, 64), 262144, nrhs=4)
+    c = dda.footprint_bytes((96, 64, 48), 154424, nrhs=64)
+    assert 0 < a < b < c
+    assert c < 288 * 2 ** 30
