@@ -28,9 +28,9 @@
  *     them.  Device pointers ("device") are HIP device addresses on the
  *     target's device; the caller owns them and they must stay valid until
  *     the work queued on the given stream has finished.
- *   - A stream argument is a hipStream_t passed as void*; NULL means the
- *     target's own stream.  Calls on one handle must not overlap in time
- *     (one thread, one stream per handle); distinct handles may run
+ *   - A stream argument is a hipStream_t passed as void*; NULL is the
+ *     device's default (null) stream.  Calls on one handle must not overlap
+ *     in time (one thread, one stream per handle); distinct handles may run
  *     concurrently on distinct streams.
  *   - Complex numbers are dda_c64 {re, im} (16 bytes, FP64).
  *   - Polarization / field vectors are laid out [nrhs][n_sites][3] dda_c64,
@@ -203,13 +203,22 @@ int dda_incident_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, void *e_
 
 void dda_free_target(dda_target *t);
 
+/* Time `reps` products AP = A P as dda_apply does, with HIP events recorded
+ * on the given stream around each of the five FFT passes (x-forward,
+ * y-forward, z-pass with the Green multiply, y-inverse, x-inverse).
+ * ms_per_pass (host [6]) receives the average milliseconds of each pass and,
+ * in [5], of the whole product.  Synchronous. */
+int dda_profile_matvec(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t precision, int32_t reps,
+                       const void *p_dev, void *ap_dev, void *stream, double ms_per_pass[6]);
+
 /* ---- diagnostics --------------------------------------------------------- */
 
-/* Batched in-place-free 1-D complex FFT of length n (2/3/5-smooth, <= 512) on
+/* Batched 1-D complex FFT (in_dev may equal out_dev) of length n (2/3/5-smooth, <= 512) on
  * the device: out[b][k] = scale * sum_j in[b][j] exp(sign * 2 pi i j k / n),
  * sign = -1 (forward) or +1 (inverse).  precision DDA_FP64 (dda_c64 data) or
  * DDA_MIXED (interleaved float pairs).  This is the FFT engine of the product
- * exposed for testing.  Queued on the stream. */
+ * exposed for testing.  batch = 0 is a no-op (pointers may then be NULL).
+ * Synchronous. */
 int dda_fft_pencils(int32_t n, int64_t batch, int32_t sign, int32_t precision, double scale,
                     const void *in_dev, void *out_dev, void *stream, int32_t device);
 

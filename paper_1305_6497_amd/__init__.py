@@ -175,6 +175,16 @@ class Target:
                                     _stream_ptr(stream)))
         return out
 
+    def profile_matvec(self, rhs, P, precision="mixed", reps=20, stream=None):
+        """Average ms of each FFT pass (and the whole product) over reps products."""
+        out = self._vec(len(rhs))
+        ms = (ctypes.c_double * 6)()
+        L.check(self._lib.dda_profile_matvec(self._h, _rhs_array(rhs), len(rhs), PRECISION[precision], int(reps),
+                                             ctypes.c_void_p(P.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                             _stream_ptr(stream), ms))
+        names = ("x_forward", "y_forward", "z_pass", "y_inverse", "x_inverse", "total")
+        return dict(zip(names, list(ms)))
+
     def incident_field(self, rhs, stream=None):
         out = self._vec(len(rhs))
         L.check(self._lib.dda_incident_field(self._h, _rhs_array(rhs), len(rhs), ctypes.c_void_p(out.data_ptr()),

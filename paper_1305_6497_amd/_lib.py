@@ -87,6 +87,8 @@ SIGNATURES = [
     ("dda_apply", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP]),
     ("dda_incident_field", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), ctypes.c_int32, _VP, _VP]),
     ("dda_free_target", None, [_VP]),
+    ("dda_profile_matvec", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          _VP, _VP, _VP, ctypes.POINTER(ctypes.c_double)]),
     ("dda_fft_pencils", ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_double, _VP, _VP, _VP, ctypes.c_int32]),
     ("dda_next_smooth", ctypes.c_int32, [ctypes.c_int32]),

@@ -44,6 +44,11 @@ struct dda_target {
   RhsDev *d_rhs = nullptr;
   double *d_sums = nullptr;
   int *d_restart = nullptr;
+  // host staging of the per-RHS uploads; kept alive until the copy that
+  // reads them has completed (upload_done)
+  std::vector<RhsDev> h_rhs;
+  std::vector<c64> h_ainv;
+  hipEvent_t upload_done = nullptr;
   uint64_t bytes = 0;
   std::vector<std::pair<void *, size_t>> allocs;
 
@@ -67,7 +72,9 @@ struct dda_target {
   }
   ~dda_target() {
     (void)hipSetDevice(device);
+    if (upload_done) (void)hipEventSynchronize(upload_done);
     for (auto &a : allocs) (void)hipFree(a.first);
+    if (upload_done) (void)hipEventDestroy(upload_done);
     if (stream) (void)hipStreamDestroy(stream);
   }
 };
@@ -252,11 +259,17 @@ void prepare_rhs(dda_target *t, const dda_rhs *rhs, int nrhs, std::vector<RhsDev
 }
 
 void upload_rhs(dda_target *t, const std::vector<RhsDev> &rd, const std::vector<c64> &ainv, hipStream_t s) {
-  DDA_HIP(hipMemcpyAsync(t->d_rhs, rd.data(), rd.size() * sizeof(RhsDev), hipMemcpyHostToDevice, s));
-  DDA_HIP(hipMemcpyAsync(t->d_ainv, ainv.data(), ainv.size() * sizeof(c64), hipMemcpyHostToDevice, s));
+  if (!t->upload_done) DDA_HIP(hipEventCreateWithFlags(&t->upload_done, hipEventDisableTiming));
+  DDA_HIP(hipEventSynchronize(t->upload_done));      // previous upload has read the staging
+  t->h_rhs = rd;
+  t->h_ainv = ainv;
+  DDA_HIP(hipMemcpyAsync(t->d_rhs, t->h_rhs.data(), rd.size() * sizeof(RhsDev), hipMemcpyHostToDevice, s));
+  DDA_HIP(hipMemcpyAsync(t->d_ainv, t->h_ainv.data(), ainv.size() * sizeof(c64), hipMemcpyHostToDevice, s));
+  DDA_HIP(hipEventRecord(t->upload_done, s));
 }
 
-void matvec(dda_target *t, int precision, const c64 *in, c64 *out, int nrhs, const int *mask, hipStream_t s) {
+void matvec(dda_target *t, int precision, const c64 *in, c64 *out, int nrhs, const int *mask, hipStream_t s,
+            const hipEvent_t *ev = nullptr) {
   MatvecArgs a{};
   a.in = in;
   a.out = out;
@@ -276,13 +289,13 @@ void matvec(dda_target *t, int precision, const c64 *in, c64 *out, int nrhs, con
     a.twx = t->tx.d32;
     a.twy = t->ty.d32;
     a.twz = t->tz.d32;
-    launch_matvec<float>(t->g, a, s);
+    launch_matvec<float>(t->g, a, s, ev);
   } else {
     a.ghat = t->d_ghat64;
     a.twx = t->tx.d64;
     a.twy = t->ty.d64;
     a.twz = t->tz.d64;
-    launch_matvec<double>(t->g, a, s);
+    launch_matvec<double>(t->g, a, s, ev);
   }
 }
 
@@ -450,7 +463,7 @@ int dda_incident_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, void *e_
     DDA_REQUIRE(t && e_dev, "NULL argument");
     DDA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
     DDA_HIP(hipSetDevice(t->device));
-    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : t->stream;
+    hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<RhsDev> rd;
     std::vector<c64> ai;
     prepare_rhs(t, rhs, nrhs, rd, ai);
@@ -469,7 +482,7 @@ int dda_apply(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t precision
     DDA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
     DDA_REQUIRE(precision == DDA_FP64 || precision == DDA_MIXED, "unknown precision");
     DDA_HIP(hipSetDevice(t->device));
-    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : t->stream;
+    hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<RhsDev> rd;
     std::vector<c64> ai;
     prepare_rhs(t, rhs, nrhs, rd, ai);
@@ -477,6 +490,40 @@ int dda_apply(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t precision
     ensure_workspace(t, nrhs);
     upload_rhs(t, rd, ai, s);
     matvec(t, precision, static_cast<const c64 *>(p_dev), static_cast<c64 *>(ap_dev), nrhs, nullptr, s);
+    return DDA_OK;
+  });
+}
+
+int dda_profile_matvec(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t precision, int32_t reps,
+                       const void *p_dev, void *ap_dev, void *stream, double ms_per_pass[6]) {
+  return guarded([&]() -> int {
+    DDA_REQUIRE(t && p_dev && ap_dev && ms_per_pass, "NULL argument");
+    DDA_REQUIRE(p_dev != ap_dev, "p_dev and ap_dev must not alias");
+    DDA_REQUIRE(nrhs >= 1 && reps >= 1, "nrhs and reps must be >= 1");
+    DDA_REQUIRE(precision == DDA_FP64 || precision == DDA_MIXED, "unknown precision");
+    DDA_HIP(hipSetDevice(t->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<RhsDev> rd;
+    std::vector<c64> ai;
+    prepare_rhs(t, rhs, nrhs, rd, ai);
+    ensure_krylov(t, nrhs);
+    ensure_workspace(t, nrhs);
+    upload_rhs(t, rd, ai, s);
+    std::vector<hipEvent_t> ev(6 * (size_t)reps);
+    for (auto &e : ev) DDA_HIP(hipEventCreate(&e));
+    for (int i = 0; i < reps; ++i)
+      matvec(t, precision, static_cast<const c64 *>(p_dev), static_cast<c64 *>(ap_dev), nrhs, nullptr, s,
+             ev.data() + 6 * (size_t)i);
+    DDA_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < 6; ++k) ms_per_pass[k] = 0.0;
+    for (int i = 0; i < reps; ++i)
+      for (int k = 0; k < 5; ++k) {
+        float ms = 0.f;
+        DDA_HIP(hipEventElapsedTime(&ms, ev[6 * (size_t)i + k], ev[6 * (size_t)i + k + 1]));
+        ms_per_pass[k] += ms / reps;
+        ms_per_pass[5] += ms / reps;
+      }
+    for (auto &e : ev) (void)hipEventDestroy(e);
     return DDA_OK;
   });
 }
@@ -491,7 +538,7 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     DDA_REQUIRE(opts->precision == DDA_FP64 || opts->precision == DDA_MIXED, "unknown precision");
     DDA_REQUIRE(opts->inner_tol >= 0.0 && opts->inner_tol < 1.0, "inner_tol must be in [0, 1)");
     DDA_HIP(hipSetDevice(t->device));
-    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : t->stream;
+    hipStream_t s = static_cast<hipStream_t>(stream);
     const int K = opts->check_every > 0 ? opts->check_every : 8;
     const int max_outer = opts->max_outer > 0 ? opts->max_outer : 20;
     std::vector<RhsDev> rd;
@@ -582,7 +629,7 @@ int dda_cross_sections(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const vo
     DDA_REQUIRE(p_dev || p_host, "need p_dev or p_host");
     DDA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
     DDA_HIP(hipSetDevice(t->device));
-    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : t->stream;
+    hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<RhsDev> rd;
     std::vector<c64> ai;
     prepare_rhs(t, rhs, nrhs, rd, ai);
@@ -615,9 +662,10 @@ int dda_cross_sections(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const vo
 int dda_fft_pencils(int32_t n, int64_t batch, int32_t sign, int32_t precision, double scale, const void *in_dev,
                     void *out_dev, void *stream, int32_t device) {
   return guarded([&]() -> int {
-    DDA_REQUIRE(in_dev && out_dev, "NULL argument");
     DDA_REQUIRE(sign == -1 || sign == 1, "sign must be -1 or +1");
     DDA_REQUIRE(batch >= 0, "batch must be >= 0");
+    if (batch == 0) return DDA_OK;
+    DDA_REQUIRE(in_dev && out_dev, "NULL argument");
     DDA_REQUIRE(precision == DDA_FP64 || precision == DDA_MIXED, "unknown precision");
     DDA_REQUIRE(n >= 1 && n <= kMaxLen && next_smooth(n) == n, "n must be 2/3/5-smooth and <= 512");
     DDA_HIP(hipSetDevice(device));

@@ -126,8 +126,9 @@ struct MatvecArgs {
   AxisPlan px, py, pz;
 };
 
+// ev: optional 6 events recorded before each of the five passes and after the last.
 template <typename T>
-void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s);
+void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const hipEvent_t *ev = nullptr);
 
 // Green-tensor transform: fills `full` [6][Mz][My][Mx] (FP64), transforms it in
 // place and writes the octant copies (scaled by 1/M) in FP64 and FP32.

@@ -413,7 +413,7 @@ template <typename T>
 static int rows_per_block(int Mx) { return std::max(1, row_budget<T>() / (3 * Mx)); }
 
 template <typename T>
-void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s) {
+void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const hipEvent_t *ev) {
   const bool f32 = sizeof(T) == 4;
   const int W = g.W(f32), nxt = g.nxt(f32);
   const size_t ae = g.a_elems(f32), be = g.b_elems(f32);
@@ -426,6 +426,10 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s) {
   const int nrows = rows_per_block<T>(g.Mx);
   const int nrowblk = (g.ny * g.nz + nrows - 1) / nrows;
   const size_t cs = sizeof(cpx<T>);
+  auto mark = [&](int i) {
+    if (ev) DDA_HIP(hipEventRecord(ev[i], s));
+  };
+  mark(0);
   {
     const size_t elems = (size_t)3 * nrows * g.Mx;
     const size_t lds = (elems + g.Mx) * cs;
@@ -435,6 +439,7 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s) {
                          ae, twx, a.px, g.nx, g.ny, g.nz, nxt, W, nrows);
     });
   }
+  mark(1);
   {
     const size_t elems = (size_t)g.My * W;
     const size_t lds = (elems + g.My) * cs;
@@ -444,6 +449,7 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s) {
                          a.py, g.ny, g.nz, nxt, W);
     });
   }
+  mark(2);
   {
     const size_t elems = (size_t)g.Mz * W;
     const size_t lds = (elems + g.Mz) * cs;
@@ -454,6 +460,7 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s) {
                          g.oct_elems());
     });
   }
+  mark(3);
   {
     const size_t elems = (size_t)g.My * W;
     const size_t lds = (elems + g.My) * cs;
@@ -463,6 +470,7 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s) {
                          a.py, g.ny, g.nz, nxt, W);
     });
   }
+  mark(4);
   {
     const size_t elems = (size_t)3 * nrows * g.Mx;
     const size_t lds = (elems + g.Mx) * cs;
@@ -472,11 +480,12 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s) {
                          a.ncomp, a.comp, a.cell_site, A, ae, twx, a.px, g.nx, g.ny, g.nz, nxt, W, nrows);
     });
   }
+  mark(5);
   DDA_HIP(hipGetLastError());
 }
 
-template void launch_matvec<float>(const Geometry &, const MatvecArgs &, hipStream_t);
-template void launch_matvec<double>(const Geometry &, const MatvecArgs &, hipStream_t);
+template void launch_matvec<float>(const Geometry &, const MatvecArgs &, hipStream_t, const hipEvent_t *);
+template void launch_matvec<double>(const Geometry &, const MatvecArgs &, hipStream_t, const hipEvent_t *);
 
 template <typename T>
 void launch_fft_rows(const cpx<T> *in, cpx<T> *out, int64_t batch, const AxisPlan &p, const cpx<T> *tw, int dir,
