@@ -203,11 +203,12 @@ int dda_incident_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, void *e_
 
 void dda_free_target(dda_target *t);
 
-/* Time `reps` products AP = A P as dda_apply does, with HIP events recorded
- * on the given stream around each of the five FFT passes (x-forward,
- * y-forward, z-pass with the Green multiply, y-inverse, x-inverse).
- * ms_per_pass (host [6]) receives the average milliseconds of each pass and,
- * in [5], of the whole product.  Synchronous. */
+/* Timing of the product AP = A P as dda_apply computes it, with HIP events
+ * recorded on the given stream.  ms_per_pass (host [6]): [0..4] the average
+ * milliseconds of one launch of each FFT pass (x-forward, y-forward, z-pass
+ * with the Green multiply, y-inverse, x-inverse), each pass launched `reps`
+ * times back to back on buffers a full product has just filled; [5] the
+ * average of `reps` whole products.  ap_dev receives A P.  Synchronous. */
 int dda_profile_matvec(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t precision, int32_t reps,
                        const void *p_dev, void *ap_dev, void *stream, double ms_per_pass[6]);
 

@@ -16,7 +16,9 @@ DEVICE_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                 "-Wno-unused-command-line-argument"]
 SOURCES = {
-    "matvec.hip": [],
+    "matvec_f32.hip": [],
+    "matvec_f64.hip": [],
+    "fft_generic.hip": [],
     "krylov.hip": [],
     "api.hip": [],
     "host.cpp": ["-ffp-contract=off"],
@@ -43,7 +45,7 @@ def build(verbose=False):
             raise RuntimeError("build failed:\n" + " ".join(cmd) + "\n" + r.stdout + r.stderr)
         return r.stderr
 
-    with cf.ThreadPoolExecutor(max_workers=min(4, len(cmds))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(max(1, (os.cpu_count() or 4)), len(cmds))) as ex:
         for msg in ex.map(run, cmds):
             if verbose and msg:
                 print(msg)

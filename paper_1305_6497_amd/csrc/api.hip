@@ -174,7 +174,7 @@ size_t workspace_bytes(const Geometry &g, int nrhs) {
 size_t krylov_bytes(const Geometry &g, int nrhs) {
   const int64_t n3 = 3 * g.n_sites;
   const size_t vec = (size_t)n3 * sizeof(c64) * nrhs;
-  const int nblk = krylov_blocks(n3);
+  const int nblk = std::max(krylov_blocks(n3), std::max(xpass_blocks(g, true), xpass_blocks(g, false)));
   return 8 * vec + (size_t)nrhs * nblk * 4 * sizeof(double) + (size_t)nrhs * kScal * sizeof(c64) +
          4 * (size_t)nrhs * sizeof(int) + (size_t)nrhs * (sizeof(RhsDev) + 2 * sizeof(double)) +
          (size_t)nrhs * 255 * sizeof(c64);
@@ -213,6 +213,7 @@ void ensure_krylov(dda_target *t, int nrhs) {
   const size_t vec = (size_t)n3 * sizeof(c64) * nrhs;
   k.n3 = n3;
   k.nblk = krylov_blocks(n3);
+  k.nrec = std::max(k.nblk, std::max(xpass_blocks(t->g, true), xpass_blocks(t->g, false)));
   k.x = t->alloc<c64>(vec);
   k.r = t->alloc<c64>(vec);
   k.rh = t->alloc<c64>(vec);
@@ -221,7 +222,7 @@ void ensure_krylov(dda_target *t, int nrhs) {
   k.s = t->alloc<c64>(vec);
   k.t = t->alloc<c64>(vec);
   k.b = t->alloc<c64>(vec);
-  k.partial = t->alloc<double>((size_t)nrhs * k.nblk * 4 * sizeof(double));
+  k.partial = t->alloc<double>((size_t)nrhs * k.nrec * 4 * sizeof(double));
   k.scal = t->alloc<c64>((size_t)nrhs * kScal * sizeof(c64));
   k.active = t->alloc<int>(nrhs * sizeof(int));
   k.status = t->alloc<int>(nrhs * sizeof(int));
@@ -269,8 +270,9 @@ void upload_rhs(dda_target *t, const std::vector<RhsDev> &rd, const std::vector<
 }
 
 void matvec(dda_target *t, int precision, const c64 *in, c64 *out, int nrhs, const int *mask, hipStream_t s,
-            const hipEvent_t *ev = nullptr) {
+            const hipEvent_t *ev = nullptr, int only_pass = -1, int reps = 1, const FuseArgs *fuse = nullptr) {
   MatvecArgs a{};
+  if (fuse) a.fuse = *fuse;
   a.in = in;
   a.out = out;
   a.nrhs = nrhs;
@@ -289,26 +291,44 @@ void matvec(dda_target *t, int precision, const c64 *in, c64 *out, int nrhs, con
     a.twx = t->tx.d32;
     a.twy = t->ty.d32;
     a.twz = t->tz.d32;
-    launch_matvec<float>(t->g, a, s, ev);
+    launch_matvec<float>(t->g, a, s, ev, only_pass, reps);
   } else {
     a.ghat = t->d_ghat64;
     a.twx = t->tx.d64;
     a.twy = t->ty.d64;
     a.twz = t->tz.d64;
-    launch_matvec<double>(t->g, a, s, ev);
+    launch_matvec<double>(t->g, a, s, ev, only_pass, reps);
   }
 }
 
+// One BiCGSTAB iteration for every active RHS of the block: 14 kernels.
+//   product 1: x-forward forms p = r + beta (p - omega v); x-inverse writes
+//              v = A p and partial sums of <rh, v>; alpha = rho / <rh, v>
+//   product 2: x-forward forms s = r - alpha v; x-inverse writes t = A s and
+//              partial sums of <t, s>, <t, t>; omega = <t, s> / <t, t>
+//   update:    x += alpha p + omega s, r = s - omega t with <rh, r>, |r|^2;
+//              rho, beta and the convergence status.
 void iteration(dda_target *t, int precision, hipStream_t s) {
   KrylovState &k = t->k;
-  k_update_p(k, s);
-  matvec(t, precision, k.p, k.v, k.nrhs, k.active, s);
-  k_dot_rv(k, s);
-  k_scalar_alpha(k, s);
-  k_update_s(k, s);
-  matvec(t, precision, k.s, k.t, k.nrhs, k.active, s);
-  k_dot_ts(k, s);
-  k_scalar_omega(k, s);
+  const int nrec = xpass_blocks(t->g, precision == DDA_MIXED);
+  FuseArgs f;
+  f.r = k.r;
+  f.v = k.v;
+  f.rh = k.rh;
+  f.scal = k.scal;
+  f.active = k.active;
+  f.status = k.status;
+  f.partial = k.partial;
+  f.in_mode = 1;
+  f.out_mode = 1;
+  f.w = k.p;
+  matvec(t, precision, k.p, k.v, k.nrhs, k.active, s, nullptr, -1, 1, &f);
+  k_scalar_alpha(k, s, nrec);
+  f.in_mode = 2;
+  f.out_mode = 2;
+  f.w = k.s;
+  matvec(t, precision, k.s, k.t, k.nrhs, k.active, s, nullptr, -1, 1, &f);
+  k_scalar_omega(k, s, nrec);
   k_update_xr(k, s);
   k_scalar_rho(k, s);
 }
@@ -509,20 +529,31 @@ int dda_profile_matvec(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t 
     ensure_krylov(t, nrhs);
     ensure_workspace(t, nrhs);
     upload_rhs(t, rd, ai, s);
-    std::vector<hipEvent_t> ev(6 * (size_t)reps);
+    hipEvent_t ev[6];
     for (auto &e : ev) DDA_HIP(hipEventCreate(&e));
-    for (int i = 0; i < reps; ++i)
-      matvec(t, precision, static_cast<const c64 *>(p_dev), static_cast<c64 *>(ap_dev), nrhs, nullptr, s,
-             ev.data() + 6 * (size_t)i);
-    DDA_HIP(hipStreamSynchronize(s));
-    for (int k = 0; k < 6; ++k) ms_per_pass[k] = 0.0;
-    for (int i = 0; i < reps; ++i)
-      for (int k = 0; k < 5; ++k) {
-        float ms = 0.f;
-        DDA_HIP(hipEventElapsedTime(&ms, ev[6 * (size_t)i + k], ev[6 * (size_t)i + k + 1]));
-        ms_per_pass[k] += ms / reps;
-        ms_per_pass[5] += ms / reps;
-      }
+    const c64 *in = static_cast<const c64 *>(p_dev);
+    c64 *out = static_cast<c64 *>(ap_dev);
+    // whole products, events between the passes
+    matvec(t, precision, in, out, nrhs, nullptr, s);        // warm-up
+    double whole = 0.0;
+    for (int i = 0; i < reps; ++i) {
+      matvec(t, precision, in, out, nrhs, nullptr, s, ev);
+      DDA_HIP(hipStreamSynchronize(s));
+      float ms = 0.f;
+      DDA_HIP(hipEventElapsedTime(&ms, ev[0], ev[5]));
+      whole += ms;
+    }
+    ms_per_pass[5] = whole / reps;
+    // each pass alone, launched `reps` times back to back on buffers that a
+    // full product has just filled
+    for (int k = 0; k < 5; ++k) {
+      matvec(t, precision, in, out, nrhs, nullptr, s);
+      matvec(t, precision, in, out, nrhs, nullptr, s, ev, k, reps);
+      DDA_HIP(hipStreamSynchronize(s));
+      float ms = 0.f;
+      DDA_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+      ms_per_pass[k] = ms / reps;
+    }
     for (auto &e : ev) (void)hipEventDestroy(e);
     return DDA_OK;
   });

@@ -109,6 +109,21 @@ struct RhsDev {
 };
 
 // ------------------------------------------------------------ kernel API --
+// BiCGSTAB work fused into the first and last pass of a product.
+struct FuseArgs {
+  int in_mode = 0;     // 0: transform `in` as given
+                       // 1: form p = r + beta (p - omega v), store it in w (= p), transform it
+                       // 2: form s = r - alpha v, store it in w (= s), transform it
+  int out_mode = 0;    // 0: nothing
+                       // 1: per-block partial sums of <rh, out>
+                       // 2: per-block partial sums of <out, in> and <out, out>
+  const c64 *r = nullptr, *v = nullptr, *rh = nullptr;
+  c64 *w = nullptr;
+  c64 *scal = nullptr;
+  int *active = nullptr, *status = nullptr;
+  double *partial = nullptr;      // [nrhs][x-pass blocks][4]
+};
+
 // Convolution + diagonal:  out_r = ainv_r[comp] * in_r - (G * in_r)   (r < nrhs)
 // in/out are FP64 [nrhs][N][3]; the FFT pipeline runs in T.
 struct MatvecArgs {
@@ -124,11 +139,23 @@ struct MatvecArgs {
   const void *ghat;               // octant Green transform [6][Mzh][Myh][Mxh] (scaled by 1/M)
   const void *twx, *twy, *twz;    // twiddles of the T precision
   AxisPlan px, py, pz;
+  FuseArgs fuse;
 };
 
-// ev: optional 6 events recorded before each of the five passes and after the last.
+// The x passes keep 3 * rows * Mx <= kXBudget elements per block (EPT <= 8):
+// more, lighter blocks keep more loads in flight than few heavy ones.
+constexpr int kXBudget = 1536;
+inline int xpass_rows(int Mx) { return 3 * Mx >= kXBudget ? 1 : kXBudget / (3 * Mx); }
+
+// Blocks of the x passes (= partial records an out_mode reduction writes).
+int xpass_blocks(const Geometry &g, bool fp32);
+
+// ev: optional events recorded before each of the five passes and after the
+// last (6 events).  only_pass >= 0 launches that pass alone `reps` times back to
+// back, between ev[0] and ev[1] (timing of one kernel).
 template <typename T>
-void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const hipEvent_t *ev = nullptr);
+void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const hipEvent_t *ev = nullptr,
+                   int only_pass = -1, int reps = 1);
 
 // Green-tensor transform: fills `full` [6][Mz][My][Mx] (FP64), transforms it in
 // place and writes the octant copies (scaled by 1/M) in FP64 and FP32.
@@ -153,6 +180,7 @@ struct KrylovState {
   int *status = nullptr;          // [nrhs]
   int *check = nullptr;           // [nrhs]
   int nblk = 0;
+  int nrec = 0;                   // records per RHS in `partial` (max of Krylov and x-pass blocks)
 };
 
 // scalar slots per RHS
@@ -165,12 +193,13 @@ int krylov_blocks(int64_t n3);
 void k_init_state(const KrylovState &k, double tol, int max_iter, hipStream_t s);
 void k_update_p(const KrylovState &k, hipStream_t s);
 void k_dot_rv(const KrylovState &k, hipStream_t s);
-void k_scalar_alpha(const KrylovState &k, hipStream_t s);
+void k_scalar_alpha(const KrylovState &k, hipStream_t s, int nrec);
 void k_update_s(const KrylovState &k, hipStream_t s);
 void k_dot_ts(const KrylovState &k, hipStream_t s);
-void k_scalar_omega(const KrylovState &k, hipStream_t s);
+void k_scalar_omega(const KrylovState &k, hipStream_t s, int nrec);
 void k_update_xr(const KrylovState &k, hipStream_t s);
 void k_scalar_rho(const KrylovState &k, hipStream_t s);
+
 // r_true = b - Ax (Ax given in `ax`) for RHS with check[r]; writes norms into partial/scal.
 void k_true_residual(const KrylovState &k, const c64 *ax, hipStream_t s);
 // Restart RHS with restart[r] from the current x: r holds the true residual;

@@ -3,6 +3,7 @@
 // contraction so the site rules give the same boundary decisions as a plain
 // IEEE evaluation of the same inequalities.
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -236,6 +237,8 @@ int next_smooth(int n) {
   }
 }
 
+// Radix plan of a transform: radix 8 while it divides, then 4, 2, 5, 3
+// (the radices fft_lds.hpp implements).
 AxisPlan make_axis_plan(int L) {
   DDA_REQUIRE(L >= 1 && L <= kMaxLen, "FFT length out of range");
   AxisPlan p{};

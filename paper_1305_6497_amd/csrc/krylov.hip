@@ -19,11 +19,11 @@
 #include <algorithm>
 
 #include "dda_internal.hpp"
+#include "reduce.hpp"
 
 namespace dda {
 
 constexpr int KNT = 256;
-constexpr int kPart = 4;     // doubles per partial-sum record
 
 int krylov_blocks(int64_t n3) {
   int64_t b = (n3 + (int64_t)KNT * 8 - 1) / ((int64_t)KNT * 8);
@@ -34,35 +34,11 @@ int krylov_blocks(int64_t n3) {
 
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double *out) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += __shfl_down(v[k], off, 64);
-  __shared__ double sh[NV][KNT / 64];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) sh[k][wid] = v[k];
-  __syncthreads();
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double s = 0.0;
-      for (int w = 0; w < KNT / 64; ++w) s += sh[k][w];
-      out[k] = s;
-    }
+  dda::block_sum<NV, KNT>(v, out);
 }
-
-// Sum the per-block partials of RHS r (fixed order), NV values.
 template <int NV>
 __device__ __forceinline__ void sum_partials(const double *partial, int nblk, int r, double *out) {
-  double v[NV];
-#pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = 0.0;
-  for (int j = threadIdx.x; j < nblk; j += KNT)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += partial[((size_t)r * nblk + j) * kPart + k];
-  block_sum<NV>(v, out);
+  sum_records<NV, KNT>(partial, nblk, r, out);
 }
 
 #define RHS_PREAMBLE                                       \
@@ -144,11 +120,6 @@ __global__ void kk_dot_rv(const int *active, const c64 *rh, const c64 *v, int64_
   }
 }
 
-__device__ __forceinline__ c64 cdiv(c64 a, c64 b) {
-  const double d = b.x * b.x + b.y * b.y;
-  return {(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
-}
-__device__ __forceinline__ double cabs2(c64 a) { return a.x * a.x + a.y * a.y; }
 
 __global__ void kk_scalar_alpha(const double *partial, int nblk, c64 *scal, int *active, int *status) {
   const int r = blockIdx.x;
@@ -339,8 +310,8 @@ void k_update_p(const KrylovState &k, hipStream_t s) {
 void k_dot_rv(const KrylovState &k, hipStream_t s) {
   hipLaunchKernelGGL(kk_dot_rv, vgrid(k), dim3(KNT), 0, s, k.active, k.rh, k.v, k.n3, k.partial, k.nblk);
 }
-void k_scalar_alpha(const KrylovState &k, hipStream_t s) {
-  hipLaunchKernelGGL(kk_scalar_alpha, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, k.nblk, k.scal, k.active, k.status);
+void k_scalar_alpha(const KrylovState &k, hipStream_t s, int nrec) {
+  hipLaunchKernelGGL(kk_scalar_alpha, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, nrec, k.scal, k.active, k.status);
 }
 void k_update_s(const KrylovState &k, hipStream_t s) {
   hipLaunchKernelGGL(kk_update_s, vgrid(k), dim3(KNT), 0, s, k.active, k.r, k.v, k.s, k.scal, k.n3, k.nblk);
@@ -348,8 +319,8 @@ void k_update_s(const KrylovState &k, hipStream_t s) {
 void k_dot_ts(const KrylovState &k, hipStream_t s) {
   hipLaunchKernelGGL(kk_dot_ts, vgrid(k), dim3(KNT), 0, s, k.active, k.t, k.s, k.n3, k.partial, k.nblk);
 }
-void k_scalar_omega(const KrylovState &k, hipStream_t s) {
-  hipLaunchKernelGGL(kk_scalar_omega, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, k.nblk, k.scal, k.active);
+void k_scalar_omega(const KrylovState &k, hipStream_t s, int nrec) {
+  hipLaunchKernelGGL(kk_scalar_omega, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, nrec, k.scal, k.active);
 }
 void k_update_xr(const KrylovState &k, hipStream_t s) {
   hipLaunchKernelGGL(kk_update_xr, vgrid(k), dim3(KNT), 0, s, k.active, k.x, k.r, k.rh, k.p, k.s, k.t, k.scal, k.n3,
