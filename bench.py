@@ -76,6 +76,127 @@ def cpu_baseline(sites, kd, m, rhs, gpu_fp64_iters, budget_s=20.0):
                 matvecs_per_s=2 * its / dt)
 
 
+def _reference(name):
+    """Oracle efficiencies stored by tests/golden/make_reference.py, if present."""
+    path = os.path.join(ROOT, "tests", "golden", f"reference_{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def _rel_err(q, ref):
+    return {k: abs(q[k] - ref[k]) / abs(ref[k]) for k in ("qext", "qabs", "qsca")}
+
+
+def _rhs_list(dda, inputs, w):
+    """(khat, e) of the workload: fixed incidence along x, or seeded SO(3) orientations."""
+    if w["orientations"] == 1:
+        return [dda.orient_rhs(0.0, 0.0, 0.0, which=k + 1) for k in range(w["polarizations"])]
+    b, t, p = inputs.orientation_angles(w["orientations"])
+    return [dda.orient_rhs(b[i], t[i], p[i], which=k + 1) for i in range(w["orientations"])
+            for k in range(w["polarizations"])]
+
+
+def extra_workloads(dda, inputs, torch, tol):
+    """The other configurations: latency-bound sphere, batched RHS, large sphere."""
+    import numpy as np
+    out = {}
+
+    # Sphere D = 20 (N = 4224), FP64, two polarizations solved separately.
+    w = inputs.WORKLOADS["sphere_d20"]
+    sites, box = dda.make_sites(w["shape"], w["shpar"])
+    kd = dda.kd_from_x(w["x"], len(sites))
+    rhs = _rhs_list(dda, inputs, w)
+    t = dda.Target(sites, box, m=w["m"], kd=kd)
+    res = {}
+    for graph in (False, True):
+        for r in rhs:
+            t.solve([r], tol=tol, precision="fp64", use_graph=graph)
+        lat = []
+        for _ in range(10):
+            for r in rhs:
+                s0 = time.perf_counter()
+                P, st = t.solve([r], tol=tol, precision="fp64", use_graph=graph)
+                torch.cuda.synchronize()
+                lat.append(time.perf_counter() - s0)
+        res["graph" if graph else "eager"] = {"solves_per_s": len(lat) / sum(lat),
+                                             "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                                             "p99_ms": float(np.percentile(lat, 99) * 1e3), "iters": st[0]["iters"]}
+    P, st = t.solve(rhs, tol=tol, precision="fp64")
+    q = t.cross_sections(rhs, P)
+    ref = _reference("sphere_d20")
+    res["q"] = q
+    res["q_rel_err_vs_oracle"] = [_rel_err(q[i], ref["results"][i]) for i in range(len(q))] if ref else None
+    res["mie"] = ref.get("mie") if ref else None
+    res["config"] = {"n_sites": len(sites), "fft_grid": list(t.info()["grid"]), "precision": "fp64", "nrhs": 1}
+    t.close()
+    out["sphere_d20"] = res
+
+    # Ellipsoid 96 x 64 x 48: 32 orientations x 2 polarizations = 64 RHS in one block (mixed) against the
+    # plain FP64 single-RHS solver on the same GPU.
+    w = inputs.WORKLOADS["ellipsoid_96x64x48"]
+    sites, box = dda.make_sites(w["shape"], w["shpar"])
+    kd = dda.kd_from_x(w["x"], len(sites))
+    rhs = _rhs_list(dda, inputs, w)
+    t = dda.Target(sites, box, m=w["m"], kd=kd)
+    P = torch.empty((len(rhs), len(sites), 3), dtype=torch.complex128, device="cuda")
+    t.solve(rhs, tol=tol, precision="mixed", out=P)
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    P, st = t.solve(rhs, tol=tol, precision="mixed", out=P)
+    q = t.cross_sections(rhs, P)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - s0
+    P1 = torch.empty((1, len(sites), 3), dtype=torch.complex128, device="cuda")
+    t.solve(rhs[:1], tol=tol, precision="fp64", out=P1)
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    iters64 = []
+    for r in rhs:
+        P1, s1 = t.solve([r], tol=tol, precision="fp64", out=P1)
+        t.cross_sections([r], P1)
+        iters64.append(s1[0]["iters"])
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - s0
+    ref = _reference("ellipsoid_96x64x48")
+    errs = [_rel_err(q[i], ref["results"][i]) for i in range(len(ref["results"]))] if ref else None
+    out["ellipsoid_96x64x48_batched"] = {
+        "nrhs": len(rhs), "solves_per_s": len(rhs) / tb, "block_seconds": tb,
+        "fp64_single_rhs_solves_per_s": len(rhs) / ts, "speedup_vs_fp64_single": ts / tb,
+        "iters_mean": float(np.mean([x["iters"] for x in st])), "iters_max": int(max(x["iters"] for x in st)),
+        "fp64_iters_mean": float(np.mean(iters64)), "max_rel_resid": float(max(x["rel_resid"] for x in st)),
+        "q_rel_err_vs_oracle_first_rhs": errs,
+        "config": {"n_sites": len(sites), "fft_grid": list(t.info()["grid"]), "precision": "mixed",
+                   "orientations": "PCG64 seed 1305, uniform on SO(3)"}}
+    t.close()
+
+    # Sphere D = 133 (N = 1,232,177, grid 270^3), 2 polarizations batched, mixed, against Mie.
+    w = inputs.WORKLOADS["sphere_d133"]
+    sites, box = dda.make_sites(w["shape"], w["shpar"])
+    kd = dda.kd_from_x(w["x"], len(sites))
+    rhs = _rhs_list(dda, inputs, w)
+    s0 = time.perf_counter()
+    t = dda.Target(sites, box, m=w["m"], kd=kd)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - s0
+    P = torch.empty((len(rhs), len(sites), 3), dtype=torch.complex128, device="cuda")
+    s0 = time.perf_counter()
+    P, st = t.solve(rhs, tol=tol, precision="mixed", out=P)
+    q = t.cross_sections(rhs, P)
+    torch.cuda.synchronize()
+    tsolve = time.perf_counter() - s0
+    ref = _reference("sphere_d133")
+    mie = ref.get("mie") if ref else None
+    out["sphere_d133"] = {
+        "nrhs": len(rhs), "solves_per_s": len(rhs) / tsolve, "solve_seconds": tsolve, "setup_seconds": setup,
+        "iters": [x["iters"] for x in st], "rel_resid": [x["rel_resid"] for x in st], "q": q,
+        "mie": mie, "q_rel_err_vs_mie": [_rel_err(v, mie) for v in q] if mie else None,
+        "config": {"n_sites": len(sites), "fft_grid": list(t.info()["grid"]), "precision": "mixed"}}
+    t.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +204,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--no-extras", action="store_true", help="only the block_64 workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not part of this "
@@ -150,6 +272,7 @@ def main():
                       x_inverse=a_b + 2 * 48 * n)
     achieved = pass_bytes[dom] / (prof[dom] * 1e-3) / 1e9
     ms_per_step = 1e3 * total / args.steps
+    extras = None if args.no_extras else extra_workloads(dda, inputs, torch, args.tol)
     cpu = None
     if not args.no_cpu:
         from oracle import targets
@@ -190,6 +313,8 @@ def main():
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": pass_bytes[dom]},
         "cpu_baseline": cpu,
+        "q_rel_err_vs_oracle": (_rel_err(q, _reference(WORKLOAD)["results"][0]) if _reference(WORKLOAD) else None),
+        "workloads": extras,
     }
     t.close()
     print(json.dumps(out))

@@ -103,6 +103,9 @@ typedef struct {
                               current true residual; 0 => tol (one refinement pass) */
   int32_t max_outer;       /* cap on true-residual checks / refinement passes per RHS */
   int32_t check_every;     /* iterations between host convergence checks (>= 1; 0 => 8) */
+  int32_t use_graph;       /* 1: the check_every iterations between host checks run as one
+                              captured HIP graph on a stream of the handle (ordered after and
+                              before the caller's stream); 0: kernels are launched directly */
 } dda_solve_opts;
 
 typedef struct {

@@ -147,12 +147,12 @@ class Target:
         return torch.empty((nrhs, self.n, 3), dtype=torch.complex128, device=f"cuda:{self.device}")
 
     def solve(self, rhs, tol=1e-5, max_iter=1000, precision="fp64", inner_tol=0.0, max_outer=20, check_every=8,
-              out=None, stream=None):
+              out=None, stream=None, use_graph=False):
         """Solve A P = E for every (khat, e) in rhs.  Returns (P, stats)."""
         nrhs = len(rhs)
         P = self._vec(nrhs) if out is None else out
         opts = L.SolveOpts(tol=tol, max_iter=max_iter, precision=PRECISION[precision], inner_tol=inner_tol,
-                           max_outer=max_outer, check_every=check_every)
+                           max_outer=max_outer, check_every=check_every, use_graph=int(bool(use_graph)))
         st = (L.SolveStats * nrhs)()
         code = L.check(self._lib.dda_solve(self._h, _rhs_array(rhs), nrhs, ctypes.byref(opts),
                                            ctypes.c_void_p(P.data_ptr()), None, _stream_ptr(stream), st),

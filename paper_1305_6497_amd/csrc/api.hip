@@ -49,6 +49,12 @@ struct dda_target {
   std::vector<RhsDev> h_rhs;
   std::vector<c64> h_ainv;
   hipEvent_t upload_done = nullptr;
+  // captured block of BiCGSTAB iterations (see run_iterations)
+  hipGraphExec_t graph = nullptr;
+  int graph_nrhs = 0, graph_prec = -1, graph_k = 0;
+  uint64_t graph_gen = 0;
+  uint64_t buffer_gen = 0;        // bumped whenever workspaces are reallocated
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
   uint64_t bytes = 0;
   std::vector<std::pair<void *, size_t>> allocs;
 
@@ -73,6 +79,10 @@ struct dda_target {
   ~dda_target() {
     (void)hipSetDevice(device);
     if (upload_done) (void)hipEventSynchronize(upload_done);
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (graph) (void)hipGraphExecDestroy(graph);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
     for (auto &a : allocs) (void)hipFree(a.first);
     if (upload_done) (void)hipEventDestroy(upload_done);
     if (stream) (void)hipStreamDestroy(stream);
@@ -190,7 +200,11 @@ void ensure_workspace(dda_target *t, int nrhs) {
   const size_t b = std::max(g.b_elems(true) * sizeof(c32), g.b_elems(false) * sizeof(c64)) * nrhs;
   t->d_bufA = t->alloc<void>(a);
   t->d_bufB = t->alloc<void>(b);
+  // zero once: tile columns beyond Mx are never written by the passes
+  DDA_HIP(hipMemset(t->d_bufA, 0, a));
+  DDA_HIP(hipMemset(t->d_bufB, 0, b));
   t->ws_nrhs = nrhs;
+  ++t->buffer_gen;
 }
 
 void ensure_krylov(dda_target *t, int nrhs) {
@@ -233,6 +247,7 @@ void ensure_krylov(dda_target *t, int nrhs) {
   t->d_sums = t->alloc<double>(2 * nrhs * sizeof(double));
   t->kr_nrhs = nrhs;
   k.nrhs = nrhs;
+  ++t->buffer_gen;
 }
 
 // Validate and normalise the RHS; fill per-RHS descriptions and 1/alpha.
@@ -331,6 +346,53 @@ void iteration(dda_target *t, int precision, hipStream_t s) {
   k_scalar_omega(k, s, nrec);
   k_update_xr(k, s);
   k_scalar_rho(k, s);
+}
+
+// K BiCGSTAB iterations on stream s.  With use_graph the block is captured
+// once into a HIP graph on the handle's own stream (capture needs a non-null
+// stream) and replayed; events order it after the work already queued on s
+// and make s wait for it.  Every kernel reads its scalars and flags from
+// device memory, so one captured block serves every replay; the graph is
+// captured again when the block shape or the buffers change.  The captured
+// kernels contain no memset nodes.
+void run_iterations(dda_target *t, int precision, int K, bool use_graph, hipStream_t s) {
+  if (!use_graph) {
+    for (int it = 0; it < K; ++it) iteration(t, precision, s);
+    return;
+  }
+  if (!t->ev_in) {
+    DDA_HIP(hipEventCreateWithFlags(&t->ev_in, hipEventDisableTiming));
+    DDA_HIP(hipEventCreateWithFlags(&t->ev_out, hipEventDisableTiming));
+  }
+  if (!t->graph || t->graph_nrhs != t->k.nrhs || t->graph_prec != precision || t->graph_k != K ||
+      t->graph_gen != t->buffer_gen) {
+    if (t->graph) {
+      DDA_HIP(hipGraphExecDestroy(t->graph));
+      t->graph = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    DDA_HIP(hipStreamBeginCapture(t->stream, hipStreamCaptureModeThreadLocal));
+    try {
+      for (int it = 0; it < K; ++it) iteration(t, precision, t->stream);
+    } catch (...) {
+      (void)hipStreamEndCapture(t->stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    DDA_HIP(hipStreamEndCapture(t->stream, &g));
+    hipError_t e = hipGraphInstantiate(&t->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    DDA_HIP(e);
+    t->graph_nrhs = t->k.nrhs;
+    t->graph_prec = precision;
+    t->graph_k = K;
+    t->graph_gen = t->buffer_gen;
+  }
+  DDA_HIP(hipEventRecord(t->ev_in, s));
+  DDA_HIP(hipStreamWaitEvent(t->stream, t->ev_in, 0));
+  DDA_HIP(hipGraphLaunch(t->graph, t->stream));
+  DDA_HIP(hipEventRecord(t->ev_out, t->stream));
+  DDA_HIP(hipStreamWaitEvent(s, t->ev_out, 0));
 }
 
 }  // namespace
@@ -631,7 +693,7 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
         }
       }
       if (!any_run) break;
-      for (int it = 0; it < K; ++it) iteration(t, opts->precision, s);
+      run_iterations(t, opts->precision, K, opts->use_graph != 0, s);
     }
     DDA_HIP(hipMemcpyAsync(scal.data(), k.scal, scal.size() * sizeof(c64), hipMemcpyDeviceToHost, s));
     const size_t vec = (size_t)k.n3 * nrhs * sizeof(c64);

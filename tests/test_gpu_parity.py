@@ -279,3 +279,21 @@ def test_sphere_d20_fp64_solve_against_oracle(dda):
         qo = cross_sections.efficiencies(n, kd, E, ai, Po)
         for key in ("qext", "qabs", "qsca"):
             assert abs(q[r][key] - qo[key]) <= 1e-5 * abs(qo[key]), (key, q[r][key], qo[key])
+
+
+def test_graph_replay_matches_eager_bitwise(dda):
+    # The iteration block is captured once and replayed several times per
+    # solve (host checks between replays); each solve also replays the graph
+    # captured by the previous one.  Every result must equal the eager path.
+    sites, box = dda.make_sites("ELLIPSOID", (18, 14, 11))
+    t = dda.Target(sites, box, m=1.6 + 0.08j, kd=0.35)
+    b, th, ph = inputs.orientation_angles(2, seed=8)
+    rhs = [dda.orient_rhs(b[i], th[i], ph[i], which=1 + i) for i in range(2)]
+    for prec in ("fp64", "mixed"):
+        ref, sr = t.solve(rhs, tol=1e-9, precision=prec, use_graph=False, check_every=3)
+        for rep in range(3):
+            got, sg = t.solve(rhs, tol=1e-9, precision=prec, use_graph=True, check_every=3)
+            assert torch.equal(got, ref), (prec, rep)
+            assert [s["iters"] for s in sg] == [s["iters"] for s in sr]
+        assert all(s["iters"] > 6 for s in sr)          # several replays per solve
+    t.close()
