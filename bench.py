@@ -188,12 +188,28 @@ def extra_workloads(dda, inputs, torch, tol):
     tsolve = time.perf_counter() - s0
     ref = _reference("sphere_d133")
     mie = ref.get("mie") if ref else None
-    out["sphere_d133"] = {
-        "nrhs": len(rhs), "solves_per_s": len(rhs) / tsolve, "solve_seconds": tsolve, "setup_seconds": setup,
-        "iters": [x["iters"] for x in st], "rel_resid": [x["rel_resid"] for x in st], "q": q,
-        "mie": mie, "q_rel_err_vs_mie": [_rel_err(v, mie) for v in q] if mie else None,
-        "config": {"n_sites": len(sites), "fft_grid": list(t.info()["grid"]), "precision": "mixed"}}
+    d133 = dict(nrhs=len(rhs), solves_per_s=len(rhs) / tsolve, solve_seconds=tsolve, setup_seconds=setup,
+                iters=[x["iters"] for x in st], rel_resid=[x["rel_resid"] for x in st], q=q, mie=mie)
+    d133["q_rel_err_vs_mie"] = [_rel_err(v, mie) for v in q] if mie else None
+    d133["config"] = {"n_sites": len(sites), "fft_grid": list(t.info()["grid"]), "precision": "mixed"}
+    out["sphere_d133"] = d133
     t.close()
+
+    # Serving mix (seeded, first 200 of the 1000-request stream): saturated, then Poisson arrivals at 0.8x.
+    from paper_1305_6497_amd import serving
+    ex = serving.GpuExecutor(tol=tol)
+    reqs = serving.make_requests(200, inputs.SERVING_SEED, 1.0, dda)
+    burst = [serving.Request(**{**r.__dict__, "arrival": 0.0}) for r in reqs]
+    s0 = time.perf_counter()
+    sat = serving.summarize(serving.Server(ex, slots=8).run(burst), time.perf_counter() - s0)
+    rate = 0.8 * sat["requests_per_s"]
+    reqs = serving.make_requests(200, inputs.SERVING_SEED, rate, dda)
+    s0 = time.perf_counter()
+    poi = serving.summarize(serving.Server(ex, slots=8).run(reqs), time.perf_counter() - s0)
+    poi["arrival_rate_per_s"] = rate
+    out["serving_mix_200"] = {"saturated": sat, "poisson_0.8": poi, "slots": 8,
+                              "note": "first 200 requests of the seeded 1000-request mix; 2 polarizations each; "
+                                      "mixed precision; admission by dda_footprint_bytes against 80% of free HBM"}
     return out
 
 

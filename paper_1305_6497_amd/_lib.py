@@ -106,9 +106,18 @@ class DDAError(RuntimeError):
 
 
 def lib():
-    """The loaded libdda.so.  Raises if it has not been built."""
+    """The loaded libdda.so.  Raises if it has not been built.
+
+    PyTorch (when installed) is imported first: it ships its own HIP runtime
+    with the same soname, and loading it before libdda.so makes both use that
+    one runtime (two HIP runtimes in one process do not share devices).
+    """
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing; build it with __graft_entry__.build()")
         L = ctypes.CDLL(LIB_PATH)

@@ -190,8 +190,13 @@ size_t krylov_bytes(const Geometry &g, int nrhs) {
          (size_t)nrhs * 255 * sizeof(c64);
 }
 
-void ensure_workspace(dda_target *t, int nrhs) {
+// Workspaces grow on demand.  Work already queued on s may still use the old
+// buffers, so s is drained before they are freed; the new buffers are zeroed
+// on s itself, ordered before the kernels that follow (a memset on the null
+// stream would not be ordered against a non-blocking caller stream).
+void ensure_workspace(dda_target *t, int nrhs, hipStream_t s) {
   if (t->ws_nrhs >= nrhs) return;
+  DDA_HIP(hipStreamSynchronize(s));
   t->release(t->d_bufA);
   t->release(t->d_bufB);
   t->d_bufA = t->d_bufB = nullptr;
@@ -201,17 +206,19 @@ void ensure_workspace(dda_target *t, int nrhs) {
   t->d_bufA = t->alloc<void>(a);
   t->d_bufB = t->alloc<void>(b);
   // zero once: tile columns beyond Mx are never written by the passes
-  DDA_HIP(hipMemset(t->d_bufA, 0, a));
-  DDA_HIP(hipMemset(t->d_bufB, 0, b));
+  DDA_HIP(hipMemsetAsync(t->d_bufA, 0, a, s));
+  DDA_HIP(hipMemsetAsync(t->d_bufB, 0, b, s));
   t->ws_nrhs = nrhs;
   ++t->buffer_gen;
 }
 
-void ensure_krylov(dda_target *t, int nrhs) {
+void ensure_krylov(dda_target *t, int nrhs, hipStream_t s) {
   if (t->kr_nrhs >= nrhs) {
     t->k.nrhs = nrhs;
     return;
   }
+  DDA_HIP(hipStreamSynchronize(s));
+  if (t->upload_done) DDA_HIP(hipEventSynchronize(t->upload_done));
   KrylovState &k = t->k;
   for (c64 *p : {k.x, k.r, k.rh, k.p, k.v, k.s, k.t, k.b}) t->release(p);
   t->release(k.partial);
@@ -549,7 +556,7 @@ int dda_incident_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, void *e_
     std::vector<RhsDev> rd;
     std::vector<c64> ai;
     prepare_rhs(t, rhs, nrhs, rd, ai);
-    ensure_krylov(t, nrhs);
+    ensure_krylov(t, nrhs, s);
     upload_rhs(t, rd, ai, s);
     launch_incident(t->g, t->d_ijk, t->d_rhs, nrhs, t->kd, static_cast<c64 *>(e_dev), s);
     return DDA_OK;
@@ -568,8 +575,8 @@ int dda_apply(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t precision
     std::vector<RhsDev> rd;
     std::vector<c64> ai;
     prepare_rhs(t, rhs, nrhs, rd, ai);
-    ensure_krylov(t, nrhs);
-    ensure_workspace(t, nrhs);
+    ensure_krylov(t, nrhs, s);
+    ensure_workspace(t, nrhs, s);
     upload_rhs(t, rd, ai, s);
     matvec(t, precision, static_cast<const c64 *>(p_dev), static_cast<c64 *>(ap_dev), nrhs, nullptr, s);
     return DDA_OK;
@@ -588,8 +595,8 @@ int dda_profile_matvec(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t 
     std::vector<RhsDev> rd;
     std::vector<c64> ai;
     prepare_rhs(t, rhs, nrhs, rd, ai);
-    ensure_krylov(t, nrhs);
-    ensure_workspace(t, nrhs);
+    ensure_krylov(t, nrhs, s);
+    ensure_workspace(t, nrhs, s);
     upload_rhs(t, rd, ai, s);
     hipEvent_t ev[6];
     for (auto &e : ev) DDA_HIP(hipEventCreate(&e));
@@ -637,8 +644,8 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     std::vector<RhsDev> rd;
     std::vector<c64> ai;
     prepare_rhs(t, rhs, nrhs, rd, ai);
-    ensure_krylov(t, nrhs);
-    ensure_workspace(t, nrhs);
+    ensure_krylov(t, nrhs, s);
+    ensure_workspace(t, nrhs, s);
     KrylovState &k = t->k;
     upload_rhs(t, rd, ai, s);
     launch_incident(t->g, t->d_ijk, t->d_rhs, nrhs, t->kd, k.b, s);
@@ -726,7 +733,7 @@ int dda_cross_sections(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const vo
     std::vector<RhsDev> rd;
     std::vector<c64> ai;
     prepare_rhs(t, rhs, nrhs, rd, ai);
-    ensure_krylov(t, nrhs);
+    ensure_krylov(t, nrhs, s);
     upload_rhs(t, rd, ai, s);
     const c64 *P = static_cast<const c64 *>(p_dev);
     if (!P) {

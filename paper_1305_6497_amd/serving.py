@@ -1,0 +1,228 @@
+"""Serving loop: a continuous-batching request scheduler over the C ABI.
+
+Requests (a target shape, refractive index and size parameter; two incident
+polarizations each) arrive over time.  A request is admitted when a slot is
+free and its device footprint (``dda_footprint_bytes`` plus its output
+buffer) fits in what is left of the HBM budget; admitted requests run
+concurrently, each on its own thread, HIP stream and target handle, so their
+kernels overlap on the GPU while their polarization and residual state stays
+in device memory.  Requests that arrive while others run are admitted as
+slots and memory free up (FIFO order, no head-of-line skipping).
+
+Latency is measured from arrival to result.  The clock, the footprint
+function and the executor are injectable, so the admission logic can be
+exercised on the CPU with a fake clock and a fake memory budget.
+"""
+
+import heapq
+import threading
+import time
+from dataclasses import dataclass, field
+
+
+@dataclass
+class Request:
+    id: int
+    arrival: float                  # seconds after the start of the run
+    shape: str
+    shpar: tuple
+    m: complex
+    x: float
+    redraws: int = 0
+
+
+@dataclass
+class Result:
+    id: int
+    arrival: float
+    admitted: float
+    done: float
+    q: list = field(default_factory=list)
+    stats: list = field(default_factory=list)
+    n_sites: int = 0
+    footprint: int = 0
+    error: str = ""
+
+    @property
+    def latency(self):
+        return self.done - self.arrival
+
+
+class GpuExecutor:
+    """Runs one request: target setup, two-polarization solve, cross sections."""
+
+    def __init__(self, device=0, tol=1e-5, precision="mixed", max_iter=2000):
+        import paper_1305_6497_amd as dda
+        self.dda = dda
+        self.device = device
+        self.tol = tol
+        self.precision = precision
+        self.max_iter = max_iter
+        self._local = threading.local()
+
+    def prepare(self, req):
+        """Host-side work: sites, kd and the footprint.  No device work."""
+        sites, box = self.dda.make_sites(req.shape, req.shpar)
+        kd = self.dda.kd_from_x(req.x, len(sites))
+        fp = self.dda.footprint_bytes(box, len(sites), m=req.m, kd=kd, nrhs=2)
+        fp += 2 * len(sites) * 3 * 16          # the P output buffer
+        return dict(sites=sites, box=box, kd=kd), fp
+
+    def _stream(self):
+        import torch
+        s = getattr(self._local, "stream", None)
+        if s is None:
+            s = torch.cuda.Stream(device=self.device)
+            self._local.stream = s
+        return s
+
+    def __call__(self, req, prep):
+        import torch
+        dda = self.dda
+        s = self._stream()
+        rhs = [dda.orient_rhs(0.0, 0.0, 0.0, which=1), dda.orient_rhs(0.0, 0.0, 0.0, which=2)]
+        with torch.cuda.stream(s):
+            t = dda.Target(prep["sites"], prep["box"], m=req.m, kd=prep["kd"], device=self.device)
+            try:
+                P, st = t.solve(rhs, tol=self.tol, precision=self.precision, max_iter=self.max_iter, stream=s)
+                q = t.cross_sections(rhs, P, stream=s)
+                s.synchronize()
+                del P
+            finally:
+                t.close()
+        return q, st
+
+
+class Server:
+    def __init__(self, executor, slots=8, hbm_budget=None, clock=time.perf_counter):
+        self.executor = executor
+        self.slots = slots
+        self.hbm_budget = hbm_budget
+        self.clock = clock
+
+    def run(self, requests, time_scale=1.0):
+        """Serve `requests` (arrival times scaled by time_scale).  Returns results by id."""
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        preps = {}
+        for r in reqs:
+            preps[r.id] = self.executor.prepare(r)
+        budget = self.hbm_budget
+        if budget is None:
+            import torch
+            free, _ = torch.cuda.mem_get_info()
+            budget = int(free * 0.8)
+        for r in reqs:
+            if preps[r.id][1] > budget:
+                raise ValueError(f"request {r.id} needs {preps[r.id][1]} bytes, more than the budget {budget}")
+        lock = threading.Condition()
+        state = dict(used=0, running=0)
+        results = {}
+        pending = []             # (arrival, id) of arrived, not admitted requests
+        t0 = self.clock()
+
+        def worker(req, prep, fp, admitted):
+            res = Result(id=req.id, arrival=req.arrival * time_scale, admitted=admitted, done=0.0,
+                         n_sites=len(prep["sites"]), footprint=fp)
+            try:
+                q, st = self.executor(req, prep)
+                res.q, res.stats = q, st
+            except Exception as e:          # reported per request
+                res.error = repr(e)
+            with lock:
+                res.done = self.clock() - t0
+                results[req.id] = res
+                state["used"] -= fp
+                state["running"] -= 1
+                lock.notify_all()
+
+        threads = []
+        i = 0
+        by_id = {r.id: r for r in reqs}
+        while len(results) < len(reqs):
+            now = self.clock() - t0
+            with lock:
+                while i < len(reqs) and reqs[i].arrival * time_scale <= now:
+                    heapq.heappush(pending, (reqs[i].arrival, reqs[i].id))
+                    i += 1
+                # admit in arrival order while a slot and memory are free
+                while pending and state["running"] < self.slots:
+                    arr, rid = pending[0]
+                    fp = preps[rid][1]
+                    if state["used"] + fp > budget:
+                        break
+                    heapq.heappop(pending)
+                    state["used"] += fp
+                    state["running"] += 1
+                    th = threading.Thread(target=worker, args=(by_id[rid], preps[rid][0], fp, now), daemon=True)
+                    threads.append(th)
+                    th.start()
+                if len(results) >= len(reqs):
+                    break
+                # sleep until the next arrival or a completion frees resources
+                next_arrival = reqs[i].arrival * time_scale if i < len(reqs) else None
+                wait = 0.05 if next_arrival is None else max(0.0, next_arrival - (self.clock() - t0))
+                lock.wait(timeout=min(wait, 0.05))
+        for th in threads:
+            th.join()
+        return results
+
+
+def summarize(results, wall):
+    import numpy as np
+    lat = np.array([r.latency for r in results.values()])
+    n = len(results)
+    ok = [r for r in results.values() if not r.error and all(s["status"] == 0 for s in r.stats)]
+    return dict(requests=n, solves=2 * n, wall_s=wall, requests_per_s=n / wall, solves_per_s=2 * n / wall,
+                p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+                mean_ms=float(lat.mean() * 1e3), converged=len(ok),
+                errors=[r.error for r in results.values() if r.error][:5])
+
+
+def make_requests(n, seed, rate, dda):
+    """The seeded serving mix, redrawing targets outside |m| kd < 1."""
+    import inputs
+
+    def accept(q):
+        sites, box = dda.make_sites(q["shape"], q["shpar"])
+        kd = dda.kd_from_x(q["x"], len(sites))
+        return abs(q["m"]) * kd < 1.0
+
+    raw = inputs.serving_requests(n=n, seed=seed, rate=rate, accept=accept)
+    return [Request(id=q["id"], arrival=q["arrival"], shape=q["shape"], shpar=q["shpar"], m=q["m"], x=q["x"],
+                    redraws=q["redraws"]) for q in raw]
+
+
+def main():
+    """Serve the seeded mix: saturated (all arrive at once), then Poisson arrivals
+    at `load` times the saturated rate.  Prints one JSON line."""
+    import argparse
+    import json
+
+    import paper_1305_6497_amd as dda
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=1000)
+    ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--load", type=float, default=0.8)
+    ap.add_argument("--seed", type=int, default=4242)
+    args = ap.parse_args()
+    ex = GpuExecutor()
+    reqs = make_requests(args.requests, args.seed, 1.0, dda)
+    burst = [Request(**{**r.__dict__, "arrival": 0.0}) for r in reqs]
+    t0 = time.perf_counter()
+    res = Server(ex, slots=args.slots).run(burst)
+    sat = summarize(res, time.perf_counter() - t0)
+    rate = args.load * sat["requests_per_s"]
+    reqs = make_requests(args.requests, args.seed, rate, dda)
+    t0 = time.perf_counter()
+    res2 = Server(ex, slots=args.slots).run(reqs)
+    poi = summarize(res2, time.perf_counter() - t0)
+    poi["arrival_rate_per_s"] = rate
+    sizes = sorted(r.n_sites for r in res.values())
+    print(json.dumps(dict(saturated=sat, poisson=poi, slots=args.slots, requests=args.requests,
+                          n_sites_p50=sizes[len(sizes) // 2], n_sites_max=sizes[-1],
+                          redraws=sum(r.redraws for r in reqs))))
+
+
+if __name__ == "__main__":
+    main()
