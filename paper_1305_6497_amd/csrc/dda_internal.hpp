@@ -63,13 +63,41 @@ using c64 = cpx<double>;
 using c32 = cpx<float>;
 
 // ---------------------------------------------------------------- FFT plan --
-constexpr int kMaxStages = 12;
+constexpr int kMaxStages = 8;     // a 2/3/5-smooth L <= 512 needs at most 6 stages
 constexpr int kMaxLen = 512;      // largest supported padded extent
 
+// Unsigned division by a divisor d >= 1 fixed at launch time, without a
+// divide instruction sequence.  For d = 2^sh it is a shift.  Otherwise, with
+// m = floor(2^32 / d) + 1 = 2^32 / d + e (0 < e < 1),
+//   umulhi(x, m) = floor(x / d + x e / 2^32),
+// and x e / 2^32 < 1 / d whenever x d < 2^32: the extra term never reaches the
+// next integer, so the quotient is exact for every x with x * d < 2^32.
+struct FastDiv {
+  uint32_t m = 0;
+  int32_t sh = 0;                 // >= 0: d = 2^sh
+  __host__ __device__ __forceinline__ uint32_t operator()(uint32_t x) const {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return sh >= 0 ? x >> sh : __umulhi(x, m);
+#else
+    return sh >= 0 ? x >> sh : (uint32_t)(((uint64_t)x * m) >> 32);
+#endif
+  }
+};
+FastDiv make_fastdiv(uint32_t d);
+
+// Stockham plan of one axis.  Stage s has radix R = radix[s] and sub-transform
+// length ns[s] = radix[0] * ... * radix[s-1]; it reads inputs lr[s] = L / R
+// apart and uses twiddle exponents that are multiples of twstep[s] =
+// L / (ns[s] R).
 struct AxisPlan {
   int L;                          // transform length
   int nstages;
   int radix[kMaxStages];          // radices in execution order (each 2, 3, 4, 5 or 8)
+  int ns[kMaxStages];
+  int lr[kMaxStages];
+  int twstep[kMaxStages];
+  FastDiv ns_div[kMaxStages];     // division by ns[s]
+  FastDiv lr_div[kMaxStages];     // division by lr[s]
 };
 
 AxisPlan make_axis_plan(int L);   // throws for non-smooth L or L > kMaxLen
@@ -145,7 +173,7 @@ struct MatvecArgs {
 // The x passes keep 3 * rows * Mx <= kXBudget elements per block (EPT <= 8):
 // more, lighter blocks keep more loads in flight than few heavy ones.
 constexpr int kXBudget = 1536;
-inline int xpass_rows(int Mx) { return 3 * Mx >= kXBudget ? 1 : kXBudget / (3 * Mx); }
+constexpr int xpass_rows(int Mx) { return 3 * Mx >= kXBudget ? 1 : kXBudget / (3 * Mx); }
 
 // Blocks of the x passes (= partial records an out_mode reduction writes).
 int xpass_blocks(const Geometry &g, bool fp32);

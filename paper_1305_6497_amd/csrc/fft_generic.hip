@@ -26,32 +26,33 @@ __global__ __launch_bounds__(kNT) void k_fft_rows(const cpx<T> *in, cpx<T> *out,
     buf[e] = q < nvalid ? in[row0 * L + e] : cpx<T>{0, 0};
   }
   __syncthreads();
-  fft_lds<T, EPT, DIR>(buf, tw, pl, np, L, 1, false);
+  fft_rows<T, EPT, DIR, 0>(buf, tw, pl, np);
   for (int e = threadIdx.x; e < nvalid * L; e += kNT) out[row0 * L + e] = scale * buf[e];
 }
 
 // Pencils of stride `inner` in an array viewed as [outer][L][inner]; a block
-// takes np consecutive inner indices of one outer index.  In place.
-template <typename T, int EPT, int DIR>
+// takes NP = 2^LOGP consecutive inner indices of one outer index.  In place.
+template <typename T, int EPT, int DIR, int LOGP>
 __global__ __launch_bounds__(kNT) void k_fft_strided(cpx<T> *data, AxisPlan pl, const cpx<T> *__restrict__ twg,
-                                                      int64_t inner, int np, int tiles) {
+                                                      int64_t inner, int tiles) {
+  constexpr int NP = 1 << LOGP;
   const int L = pl.L;
   cpx<T> *buf = reinterpret_cast<cpx<T> *>(dda_smem);
-  cpx<T> *tw = buf + np * L;
+  cpx<T> *tw = buf + NP * L;
   load_twiddles(tw, twg, L);
   const int64_t o = blockIdx.x / tiles;
-  const int64_t i0 = (int64_t)(blockIdx.x % tiles) * np;
+  const int64_t i0 = (int64_t)(blockIdx.x % tiles) * NP;
   const int64_t rem = inner - i0;
-  const int nvalid = rem < np ? (int)rem : np;
+  const int nvalid = rem < NP ? (int)rem : NP;
   cpx<T> *base = data + o * L * inner + i0;
-  for (int e = threadIdx.x; e < np * L; e += kNT) {
-    const int m = e / np, p = e - m * np;
+  for (int e = threadIdx.x; e < NP * L; e += kNT) {
+    const int m = e >> LOGP, p = e & (NP - 1);
     buf[e] = p < nvalid ? base[(int64_t)m * inner + p] : cpx<T>{0, 0};
   }
   __syncthreads();
-  fft_lds<T, EPT, DIR>(buf, tw, pl, np, 1, np, true);
-  for (int e = threadIdx.x; e < np * L; e += kNT) {
-    const int m = e / np, p = e - m * np;
+  fft_pen<T, EPT, DIR, LOGP, 0>(buf, tw, pl);
+  for (int e = threadIdx.x; e < NP * L; e += kNT) {
+    const int m = e >> LOGP, p = e & (NP - 1);
     if (p < nvalid) base[(int64_t)m * inner + p] = buf[e];
   }
 }
@@ -174,15 +175,22 @@ template void launch_fft_rows<double>(const c64 *, c64 *, int64_t, const AxisPla
 
 static void fft_strided_fwd64(c64 *data, const AxisPlan &p, const c64 *tw, int64_t outer, int64_t inner,
                               hipStream_t s) {
-  int np = (int)std::min<int64_t>(8, inner);
-  while (np > 1 && (size_t)np * p.L > (size_t)row_budget<double>()) np /= 2;
+  // 8 pencils per block, 4 for the longest axes (LDS budget of row_budget)
+  const bool wide = (size_t)8 * p.L <= (size_t)row_budget<double>();
+  const int np = wide ? 8 : 4;
   const int tiles = (int)((inner + np - 1) / np);
   const size_t elems = (size_t)np * p.L;
   const size_t lds = (elems + p.L) * sizeof(c64);
   DDA_EPT_SWITCH(pick_ept_gen(elems), {
-    allow_lds(k_fft_strided<double, E, -1>, lds);
-    hipLaunchKernelGGL((k_fft_strided<double, E, -1>), dim3((unsigned)(outer * tiles)), dim3(kNT), lds, s, data, p,
-                       tw, inner, np, tiles);
+    if (wide) {
+      allow_lds(k_fft_strided<double, E, -1, 3>, lds);
+      hipLaunchKernelGGL((k_fft_strided<double, E, -1, 3>), dim3((unsigned)(outer * tiles)), dim3(kNT), lds, s,
+                         data, p, tw, inner, tiles);
+    } else {
+      allow_lds(k_fft_strided<double, E, -1, 2>, lds);
+      hipLaunchKernelGGL((k_fft_strided<double, E, -1, 2>), dim3((unsigned)(outer * tiles)), dim3(kNT), lds, s,
+                         data, p, tw, inner, tiles);
+    }
   });
   DDA_HIP(hipGetLastError());
 }

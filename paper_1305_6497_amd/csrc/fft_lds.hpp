@@ -4,10 +4,18 @@
 // "Choice of FFT Algorithm": GPFA needs extents of the form 2^i 3^j 5^k).
 // The transform is a Stockham autosort FFT: every stage reads R inputs spaced
 // L/R apart, multiplies by twiddles, does a radix-R DFT and writes the outputs
-// to their sorted places, so no bit-reversal pass is needed.  A block of kNT
-// threads works on `npen` pencils of length L stored in LDS at
-// buf[p * ps + m * es]; each stage reads everything into registers, waits at a
-// barrier, and writes back in place.
+// to their sorted places, so no bit-reversal pass is needed.  Each stage reads
+// everything into registers, waits at a barrier, and writes back in place.
+//
+// Two layouts of a batch of npen pencils in LDS:
+//   pen   element m of pencil p at buf[m * NPEN + p], NPEN = 2^LOGP fixed at
+//         compile time (the tiled y and z passes: pencils are the W lanes of
+//         a 128-byte row);
+//   rows  element m of pencil p at buf[p * L + m] (the x passes).
+// The length is either a template constant LC (the whole plan, every stride
+// and every quotient folds into immediates and shifts) or, with LC = 0, read
+// from an AxisPlan whose per-stage strides and divisors were prepared on the
+// host (no divide sequences in the kernels).
 //
 // EPT (elements per thread) bounds npen * L <= EPT * kNT and sizes the
 // register arrays at compile time; every index into them is a compile-time
@@ -81,72 +89,203 @@ __device__ __forceinline__ void dft_small(cpx<T> *a) {
   }
 }
 
-// One Stockham stage of radix R over npen pencils (see file comment).
-template <typename T, int R, int EPT, int DIR>
-__device__ __forceinline__ void fft_stage(cpx<T> *buf, const cpx<T> *tw, int L, int Ns, int npen,
-                                          int ps, int es, bool pen_fastest) {
-  constexpr int NB = (EPT + R - 1) / R;
-  const int Lr = L / R;
-  const int nbf = npen * Lr;
-  const int tstride = L / (Ns * R);
-  const int tid = threadIdx.x;
+// v * w for the forward transform, v * conj(w) for the inverse: the table
+// holds exp(-2 pi i n / L), and the conjugate costs nothing extra.
+template <int DIR, typename T>
+__device__ __forceinline__ cpx<T> twmul(cpx<T> v, cpx<T> w) {
+  if (DIR < 0) return {v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x};
+  return {v.x * w.x + v.y * w.y, v.y * w.x - v.x * w.y};
+}
+
+// Division by a compile-time constant (strength-reduced by the compiler).
+template <int N>
+struct ConstDiv {
+  __device__ __forceinline__ uint32_t operator()(uint32_t x) const { return x / N; }
+};
+
+__device__ __forceinline__ int mul24(int a, int b) { return __mul24(a, b); }
+
+// Pen layout, one stage.  Butterfly b = j * NPEN + p reads buf[b + k * nbf],
+// nbf = (L / R) * NPEN; with j = q * Ns + jm its outputs go to
+// buf[b + q * Ns (R - 1) NPEN + k * Ns NPEN], which is the Stockham position
+// ((j - jm) R + jm + k Ns) * NPEN + p.
+template <typename T, int R, int NB, int DIR, int LOGP, typename DN>
+__device__ __forceinline__ void stage_pen(cpx<T> *buf, const cpx<T> *tw, int lr, int Ns, int twstep, DN nsd) {
+  const int nbf = lr << LOGP;
+  const int ostr = Ns << LOGP;
+  const int jump = mul24(Ns, R - 1) << LOGP;
   cpx<T> v[NB][R];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const int b = tid + i * kNT;
+    const int b = threadIdx.x + i * kNT;
     if (b < nbf) {
-      int p, j;
-      if (pen_fastest) { p = b % npen; j = b / npen; }
-      else { j = b % Lr; p = b / Lr; }
-      const cpx<T> *src = buf + p * ps + j * es;
 #pragma unroll
-      for (int k = 0; k < R; ++k) v[i][k] = src[k * Lr * es];
+      for (int k = 0; k < R; ++k) v[i][k] = buf[b + k * nbf];
     }
   }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const int b = tid + i * kNT;
+    const int b = threadIdx.x + i * kNT;
     if (b < nbf) {
-      int p, j;
-      if (pen_fastest) { p = b % npen; j = b / npen; }
-      else { j = b % Lr; p = b / Lr; }
-      const int jm = j % Ns;
-      if (jm != 0) {
+      const int j = b >> LOGP;
+      const int q = (int)nsd((uint32_t)j);
+      if (Ns > 1) {
+        const int st = mul24(j - mul24(q, Ns), twstep);
+        int ti = st;
 #pragma unroll
         for (int k = 1; k < R; ++k) {
-          cpx<T> w = tw[jm * k * tstride];
-          if (DIR > 0) w.y = -w.y;
-          v[i][k] = v[i][k] * w;
+          v[i][k] = twmul<DIR>(v[i][k], tw[ti]);
+          ti += st;
         }
       }
       dft_small<R, DIR>(v[i]);
-      cpx<T> *dst = buf + p * ps + ((j - jm) * R + jm) * es;
+      cpx<T> *dst = buf + b + mul24(q, jump);
 #pragma unroll
-      for (int k = 0; k < R; ++k) dst[k * Ns * es] = v[i][k];
+      for (int k = 0; k < R; ++k) dst[k * ostr] = v[i][k];
     }
   }
   __syncthreads();
 }
 
-// Full transform of npen pencils in LDS.  Data must be visible to all threads
-// on entry (callers put a barrier after filling buf); on exit a barrier has
-// been passed.
-template <typename T, int EPT, int DIR>
-__device__ __forceinline__ void fft_lds(cpx<T> *buf, const cpx<T> *tw, const AxisPlan &pl, int npen,
-                                        int ps, int es, bool pen_fastest) {
-  int Ns = 1;
-  for (int s = 0; s < pl.nstages; ++s) {
-    const int R = pl.radix[s];
-    switch (R) {
-      case 2: fft_stage<T, 2, EPT, DIR>(buf, tw, pl.L, Ns, npen, ps, es, pen_fastest); break;
-      case 3: fft_stage<T, 3, EPT, DIR>(buf, tw, pl.L, Ns, npen, ps, es, pen_fastest); break;
-      case 4: fft_stage<T, 4, EPT, DIR>(buf, tw, pl.L, Ns, npen, ps, es, pen_fastest); break;
-      case 5: fft_stage<T, 5, EPT, DIR>(buf, tw, pl.L, Ns, npen, ps, es, pen_fastest); break;
-      default: fft_stage<T, 8, EPT, DIR>(buf, tw, pl.L, Ns, npen, ps, es, pen_fastest); break;
+// Rows layout, one stage.  Butterfly b = p * (L / R) + j reads
+// buf[p L + j + k L / R] and writes buf[p L + (j - jm) R + jm + k Ns].
+template <typename T, int R, int NB, int DIR, typename DL, typename DN>
+__device__ __forceinline__ void stage_rows(cpx<T> *buf, const cpx<T> *tw, int L, int lr, int Ns, int twstep, DL lrd,
+                                           DN nsd, int npen) {
+  const int nbf = mul24(npen, lr);
+  const int gap = L - lr;
+  const int jump = mul24(Ns, R - 1);
+  cpx<T> v[NB][R];
+  int base[NB], jj[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = threadIdx.x + i * kNT;
+    if (b < nbf) {
+      const int p = (int)lrd((uint32_t)b);
+      jj[i] = b - mul24(p, lr);
+      base[i] = b + mul24(p, gap);
+#pragma unroll
+      for (int k = 0; k < R; ++k) v[i][k] = buf[base[i] + k * lr];
     }
-    Ns *= R;
   }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = threadIdx.x + i * kNT;
+    if (b < nbf) {
+      const int q = (int)nsd((uint32_t)jj[i]);
+      if (Ns > 1) {
+        const int st = mul24(jj[i] - mul24(q, Ns), twstep);
+        int ti = st;
+#pragma unroll
+        for (int k = 1; k < R; ++k) {
+          v[i][k] = twmul<DIR>(v[i][k], tw[ti]);
+          ti += st;
+        }
+      }
+      dft_small<R, DIR>(v[i]);
+      cpx<T> *dst = buf + base[i] + mul24(q, jump);
+#pragma unroll
+      for (int k = 0; k < R; ++k) dst[k * Ns] = v[i][k];
+    }
+  }
+  __syncthreads();
+}
+
+// The plan of a compile-time length: same radix order as make_axis_plan.
+struct StaticPlan {
+  int n;
+  int radix[kMaxStages];
+  int ns[kMaxStages];
+};
+
+constexpr StaticPlan static_plan(int L) {
+  StaticPlan p{};
+  const int order[5] = {8, 4, 2, 5, 3};
+  int n = L, ns = 1;
+  for (int o = 0; o < 5; ++o) {
+    while (n % order[o] == 0 && p.n < kMaxStages) {
+      p.radix[p.n] = order[o];
+      p.ns[p.n] = ns;
+      ++p.n;
+      ns *= order[o];
+      n /= order[o];
+    }
+  }
+  return p;
+}
+
+constexpr int cdiv_c(int a, int b) { return (a + b - 1) / b; }
+
+template <typename T, int DIR, int LOGP, int L, int S>
+__device__ __forceinline__ void fft_pen_c(cpx<T> *buf, const cpx<T> *tw) {
+  constexpr StaticPlan P = static_plan(L);
+  if constexpr (S < P.n) {
+    constexpr int R = P.radix[S], Ns = P.ns[S];
+    constexpr int NB = cdiv_c((L / R) << LOGP, kNT);
+    stage_pen<T, R, NB, DIR, LOGP>(buf, tw, L / R, Ns, L / (Ns * R), ConstDiv<Ns>{});
+    fft_pen_c<T, DIR, LOGP, L, S + 1>(buf, tw);
+  }
+}
+
+template <typename T, int EPT, int DIR, int LOGP>
+__device__ __forceinline__ void fft_pen_rt(cpx<T> *buf, const cpx<T> *tw, const AxisPlan &pl) {
+  for (int s = 0; s < pl.nstages; ++s) {
+    const int lr = pl.lr[s], Ns = pl.ns[s], ts = pl.twstep[s];
+    const FastDiv d = pl.ns_div[s];
+    switch (pl.radix[s]) {
+      case 2: stage_pen<T, 2, cdiv_c(EPT, 2), DIR, LOGP>(buf, tw, lr, Ns, ts, d); break;
+      case 3: stage_pen<T, 3, cdiv_c(EPT, 3), DIR, LOGP>(buf, tw, lr, Ns, ts, d); break;
+      case 4: stage_pen<T, 4, cdiv_c(EPT, 4), DIR, LOGP>(buf, tw, lr, Ns, ts, d); break;
+      case 5: stage_pen<T, 5, cdiv_c(EPT, 5), DIR, LOGP>(buf, tw, lr, Ns, ts, d); break;
+      default: stage_pen<T, 8, cdiv_c(EPT, 8), DIR, LOGP>(buf, tw, lr, Ns, ts, d); break;
+    }
+  }
+}
+
+// Transform the 2^LOGP interleaved pencils in buf (pen layout).  LC > 0: the
+// length is LC and `pl` is not read.  Data must be visible to all threads on
+// entry (callers put a barrier after filling buf); on exit a barrier has been
+// passed.
+template <typename T, int EPT, int DIR, int LOGP, int LC>
+__device__ __forceinline__ void fft_pen(cpx<T> *buf, const cpx<T> *tw, const AxisPlan &pl) {
+  if constexpr (LC > 0) fft_pen_c<T, DIR, LOGP, LC, 0>(buf, tw);
+  else fft_pen_rt<T, EPT, DIR, LOGP>(buf, tw, pl);
+}
+
+template <typename T, int EPT, int DIR, int L, int S>
+__device__ __forceinline__ void fft_rows_c(cpx<T> *buf, const cpx<T> *tw, int npen) {
+  constexpr StaticPlan P = static_plan(L);
+  if constexpr (S < P.n) {
+    constexpr int R = P.radix[S], Ns = P.ns[S];
+    stage_rows<T, R, cdiv_c(EPT, R), DIR>(buf, tw, L, L / R, Ns, L / (Ns * R), ConstDiv<L / R>{}, ConstDiv<Ns>{},
+                                          npen);
+    fft_rows_c<T, EPT, DIR, L, S + 1>(buf, tw, npen);
+  }
+}
+
+template <typename T, int EPT, int DIR>
+__device__ __forceinline__ void fft_rows_rt(cpx<T> *buf, const cpx<T> *tw, const AxisPlan &pl, int npen) {
+  const int L = pl.L;
+  for (int s = 0; s < pl.nstages; ++s) {
+    const int lr = pl.lr[s], Ns = pl.ns[s], ts = pl.twstep[s];
+    const FastDiv dl = pl.lr_div[s], dn = pl.ns_div[s];
+    switch (pl.radix[s]) {
+      case 2: stage_rows<T, 2, cdiv_c(EPT, 2), DIR>(buf, tw, L, lr, Ns, ts, dl, dn, npen); break;
+      case 3: stage_rows<T, 3, cdiv_c(EPT, 3), DIR>(buf, tw, L, lr, Ns, ts, dl, dn, npen); break;
+      case 4: stage_rows<T, 4, cdiv_c(EPT, 4), DIR>(buf, tw, L, lr, Ns, ts, dl, dn, npen); break;
+      case 5: stage_rows<T, 5, cdiv_c(EPT, 5), DIR>(buf, tw, L, lr, Ns, ts, dl, dn, npen); break;
+      default: stage_rows<T, 8, cdiv_c(EPT, 8), DIR>(buf, tw, L, lr, Ns, ts, dl, dn, npen); break;
+    }
+  }
+}
+
+// Transform npen contiguous pencils in buf (rows layout); npen * L <= EPT * kNT.
+template <typename T, int EPT, int DIR, int LC>
+__device__ __forceinline__ void fft_rows(cpx<T> *buf, const cpx<T> *tw, const AxisPlan &pl, int npen) {
+  if constexpr (LC > 0) fft_rows_c<T, EPT, DIR, LC, 0>(buf, tw, npen);
+  else fft_rows_rt<T, EPT, DIR>(buf, tw, pl, npen);
 }
 
 // Copy a twiddle table into LDS.

@@ -239,6 +239,20 @@ int next_smooth(int n) {
 
 // Radix plan of a transform: radix 8 while it divides, then 4, 2, 5, 3
 // (the radices fft_lds.hpp implements).
+FastDiv make_fastdiv(uint32_t d) {
+  DDA_REQUIRE(d >= 1, "division by zero");
+  FastDiv f;
+  if ((d & (d - 1)) == 0) {
+    f.sh = 0;
+    while ((1u << f.sh) < d) ++f.sh;
+    f.m = 0;
+  } else {
+    f.sh = -1;
+    f.m = (uint32_t)((uint64_t(1) << 32) / d + 1);
+  }
+  return f;
+}
+
 AxisPlan make_axis_plan(int L) {
   DDA_REQUIRE(L >= 1 && L <= kMaxLen, "FFT length out of range");
   AxisPlan p{};
@@ -258,6 +272,16 @@ AxisPlan make_axis_plan(int L) {
   take(5);
   take(3);
   if (n != 1) throw Error{DDA_EINVAL, "FFT length must be 2/3/5-smooth"};
+  int ns = 1;
+  for (int s = 0; s < p.nstages; ++s) {
+    const int R = p.radix[s];
+    p.ns[s] = ns;
+    p.lr[s] = L / R;
+    p.twstep[s] = L / (ns * R);
+    p.ns_div[s] = make_fastdiv((uint32_t)ns);
+    p.lr_div[s] = make_fastdiv((uint32_t)(L / R));
+    ns *= R;
+  }
   return p;
 }
 

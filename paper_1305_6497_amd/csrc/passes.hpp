@@ -24,6 +24,7 @@
 #pragma once
 
 #include <algorithm>
+#include <type_traits>
 
 #include "dda_internal.hpp"
 #include "fft_lds.hpp"
@@ -40,6 +41,19 @@ __device__ __forceinline__ cpx<T> to_t(c64 v) { return {T(v.x), T(v.y)}; }
 // Tile width in x of the intermediate layouts: 128 bytes of complex values.
 template <typename T>
 constexpr int kW = 128 / (int)sizeof(cpx<T>);
+template <typename T>
+constexpr int kLogW = sizeof(T) == 4 ? 4 : 3;
+
+// Sizes of the passes with their divisors prepared on the host.
+struct PassDims {
+  int nx, ny, nz;
+  int Mx, My;
+  int nxt;                        // x tiles of W
+  int nrows;                      // rows per block of the x passes
+  int Mxh, Myh;                   // octant extents M/2 + 1 (Green table)
+  int64_t moct;                   // Mxh * Myh * Mzh
+  FastDiv d_mx, d_nx, d_ny, d_nxt, d_nrows;
+};
 
 // Fill LDS from global memory: every global load of a thread is issued before
 // any LDS write, so each thread keeps up to EPT loads in flight.
@@ -58,35 +72,58 @@ __device__ __forceinline__ void stage_in(cpx<T> *buf, int n, F &&load) {
   }
 }
 
+// Offsets in A of the rows (component c, row q) of an x-pass block, or -1 for
+// rows past the end: rowoff[c * nrows + q] = ((c nz + z) nxt ny + y) W.
+template <typename T, int LC>
+__device__ __forceinline__ void x_row_offsets(int *rowoff, const PassDims &d, int nrows, int row0, int nrow) {
+  constexpr int W = kW<T>;
+  for (int pq = threadIdx.x; pq < 3 * nrows; pq += kNT) {
+    const int c = LC > 0 ? pq / nrows : (int)d.d_nrows((uint32_t)pq);
+    const int q = pq - c * nrows;
+    int off = -1;
+    if (q < nrow) {
+      const int row = row0 + q;
+      const int z = (int)d.d_ny((uint32_t)row), y = row - z * d.ny;
+      off = ((c * d.nz + z) * d.nxt * d.ny + y) * W;
+    }
+    rowoff[pq] = off;
+  }
+}
+
 // --------------------------------------------------------------- x-forward --
 // f.in_mode (see FuseArgs): 0 transforms `in`; 1 and 2 first form the BiCGSTAB
 // vector p or s from r, v (and the old p) and store it, so the vector update
-// costs no pass of its own.
-template <typename T, int EPT>
+// costs no pass of its own.  LC > 0: Mx = LC, known at compile time.
+template <typename T, int EPT, int LC>
 __global__ __launch_bounds__(kNT) void k_xfwd(const c64 *__restrict__ in, int64_t n3, const int *__restrict__ mask,
                                                const int *__restrict__ cell_site, cpx<T> *__restrict__ A,
                                                size_t a_elems, const cpx<T> *__restrict__ twx, AxisPlan px,
-                                               int nx, int ny, int nz, int nxt, int nrows, FuseArgs f) {
-  constexpr int W = kW<T>;
+                                               PassDims d, FuseArgs f) {
+  constexpr int W = kW<T>, LOGW = kLogW<T>;
   constexpr int NE = (EPT + 2) / 3;      // nrows * Mx <= EPT * kNT / 3
   const int r = blockIdx.y;
   if (mask && !mask[r]) return;
-  const int Mx = px.L;
+  const int Mx = LC > 0 ? LC : px.L;
+  const int nrows = LC > 0 ? xpass_rows(LC) : d.nrows;
+  const int nxt = LC > 0 ? (LC + W - 1) / W : d.nxt;
+  const int ne = nrows * Mx;
   cpx<T> *buf = reinterpret_cast<cpx<T> *>(dda_smem);
-  cpx<T> *tw = buf + 3 * nrows * Mx;
+  cpx<T> *tw = buf + 3 * ne;
+  int *rowoff = reinterpret_cast<int *>(tw + Mx);
   load_twiddles(tw, twx, Mx);
   const int row0 = blockIdx.x * nrows;
-  const int nrow = min(nrows, ny * nz - row0);
+  const int nrow = min(nrows, d.ny * d.nz - row0);
+  x_row_offsets<T, LC>(rowoff, d, nrows, row0, nrow);
   const size_t off = (size_t)r * n3;
-  const int ne = nrows * Mx;
   int site[NE];
 #pragma unroll
   for (int i = 0; i < NE; ++i) {
     const int e = threadIdx.x + i * kNT;
     site[i] = -1;
     if (e < ne) {
-      const int q = e / Mx, x = e - q * Mx;
-      if (q < nrow && x < nx) site[i] = cell_site[(size_t)(row0 + q) * nx + x];
+      const int q = LC > 0 ? e / LC : (int)d.d_mx((uint32_t)e);
+      const int x = e - q * Mx;
+      if (q < nrow && x < d.nx) site[i] = cell_site[(size_t)(row0 + q) * d.nx + x];
     }
   }
   c64 v[NE][3];
@@ -116,51 +153,51 @@ __global__ __launch_bounds__(kNT) void k_xfwd(const c64 *__restrict__ in, int64_
   for (int i = 0; i < NE; ++i) {
     const int e = threadIdx.x + i * kNT;
     if (e < ne) {
-      const int q = e / Mx, x = e - q * Mx;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) buf[(c * nrows + q) * Mx + x] = to_t<T>(v[i][c]);
+      for (int c = 0; c < 3; ++c) buf[c * ne + e] = to_t<T>(v[i][c]);
     }
   }
   __syncthreads();
-  fft_lds<T, EPT, -1>(buf, tw, px, 3 * nrows, Mx, 1, false);
-  const int nxtW = nxt * W;
+  fft_rows<T, EPT, -1, LC>(buf, tw, px, 3 * nrows);
   cpx<T> *Ar = A + (size_t)r * a_elems;
-  for (int e = threadIdx.x; e < 3 * nrows * nxtW; e += kNT) {
-    const int pq = e / nxtW, kx = e - pq * nxtW;
-    const int c = pq / nrows, q = pq - c * nrows;
-    if (q < nrow) {
-      const int row = row0 + q, z = row / ny, y = row - z * ny;
-      const int xt = kx / W, p = kx % W;
-      const cpx<T> val = kx < Mx ? buf[pq * Mx + kx] : cpx<T>{0, 0};
-      Ar[((((size_t)c * nz + z) * nxt + xt) * ny + y) * W + p] = val;
+  const int nyW = d.ny * W;
+  const int nseg = 3 * nrows * nxt;
+  for (int e = threadIdx.x; e < (nseg << LOGW); e += kNT) {
+    const int sg = e >> LOGW, p = e & (W - 1);
+    const int pq = LC > 0 ? sg / ((LC + W - 1) / W) : (int)d.d_nxt((uint32_t)sg);
+    const int xt = sg - pq * nxt;
+    const int ro = rowoff[pq];
+    if (ro >= 0) {
+      const int kx = (xt << LOGW) + p;
+      Ar[ro + xt * nyW + p] = kx < Mx ? buf[pq * Mx + kx] : cpx<T>{0, 0};
     }
   }
 }
 
 // --------------------------------------------------------------- y-forward --
-template <typename T, int EPT>
+template <typename T, int EPT, int LC>
 __global__ __launch_bounds__(kNT) void k_yfwd(const int *__restrict__ mask, const cpx<T> *__restrict__ A,
                                                size_t a_elems, cpx<T> *__restrict__ B, size_t b_elems,
-                                               const cpx<T> *__restrict__ twy, AxisPlan py, int ny, int nz,
-                                               int nxt) {
-  constexpr int W = kW<T>;
+                                               const cpx<T> *__restrict__ twy, AxisPlan py, PassDims d) {
+  constexpr int W = kW<T>, LOGW = kLogW<T>;
   const int r = blockIdx.y;
   if (mask && !mask[r]) return;
-  const int My = py.L;
+  const int My = LC > 0 ? LC : py.L;
+  const int n = My << LOGW;
   cpx<T> *buf = reinterpret_cast<cpx<T> *>(dda_smem);
-  cpx<T> *tw = buf + My * W;
+  cpx<T> *tw = buf + n;
   load_twiddles(tw, twy, My);
+  const int nxt = d.nxt, nz = d.nz;
   const int b = blockIdx.x;
-  const int xt = b % nxt, cz = b / nxt, c = cz / nz, z = cz - c * nz;
-  const cpx<T> *src = A + (size_t)r * a_elems + (((size_t)c * nz + z) * nxt + xt) * ny * W;
-  stage_in<T, EPT>(buf, My * W, [&](int e) { return e < ny * W ? src[e] : cpx<T>{0, 0}; });
+  const int cz = b / nxt, xt = b - cz * nxt, c = cz / nz, z = cz - c * nz;
+  const cpx<T> *src = A + (size_t)r * a_elems + (((size_t)c * nz + z) * nxt + xt) * d.ny * W;
+  const int nyW = d.ny << LOGW;
+  stage_in<T, EPT>(buf, n, [&](int e) { return e < nyW ? src[e] : cpx<T>{0, 0}; });
   __syncthreads();
-  fft_lds<T, EPT, -1>(buf, tw, py, W, 1, W, true);
-  cpx<T> *Br = B + (size_t)r * b_elems;
-  for (int e = threadIdx.x; e < My * W; e += kNT) {
-    const int ky = e / W, p = e % W;
-    Br[((((size_t)ky * nxt + xt) * 3 + c) * nz + z) * W + p] = buf[e];
-  }
+  fft_pen<T, EPT, -1, LOGW, LC>(buf, tw, py);
+  cpx<T> *dst = B + (size_t)r * b_elems + (((size_t)xt * 3 + c) * nz + z) * W;
+  const int kstr = nxt * 3 * nz * W;
+  for (int e = threadIdx.x; e < n; e += kNT) dst[(e >> LOGW) * kstr + (e & (W - 1))] = buf[e];
 }
 
 // ------------------------------------------------------------------ z-pass --
@@ -172,47 +209,63 @@ __device__ __forceinline__ int fold(int k, int M, int &sgn) {
   return M - k;
 }
 
-// One block per (ky, x tile); the three components are transformed one after
-// the other in an Mz x W LDS buffer (staged loads, in-place stages).  Each
-// thread owns octant cells (oz, p), oz <= Mz/2, and with them the mirror
-// frequency Mz - oz of the same pencil: one read of the six Green values
-// serves both, with the z-odd components (xz, yz) negated for the mirror.
-// Forward spectra of components 0 and 1 are parked in registers, component 2
-// stays in LDS.
-template <typename T, int EPT>
+// One block per (ky, x tile).  The three components are transformed one after
+// the other in an Mz x W LDS buffer (in-place stages); the nz data rows of the
+// next component are loaded into registers while the current one is
+// transformed.  Each thread owns
+// octant cells (oz, p), oz <= Mz/2, and with them the mirror frequency
+// Mz - oz of the same pencil: one read of the six Green values serves both,
+// with the z-odd components (xz, yz) negated for the mirror.  Forward spectra
+// of components 0 and 1 are parked in registers, component 2 stays in LDS.
+template <typename T, int EPT, int LC>
 __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx<T> *__restrict__ B, size_t b_elems,
                                                 const cpx<T> *__restrict__ ghat, const cpx<T> *__restrict__ twz,
-                                                AxisPlan pz, int Mx, int My, int nz, int nxt, int Mxh, int Myh,
-                                                size_t moct) {
-  constexpr int W = kW<T>;
-  constexpr int NQ = EPT / 2 + 1;
+                                                AxisPlan pz, PassDims d) {
+  constexpr int W = kW<T>, LOGW = kLogW<T>;
+  constexpr int NQ = EPT / 2 + 1;        // octant cells per thread: (Mz/2 + 1) W <= NQ kNT
+  constexpr int NL = EPT / 2 + 1;        // data rows per thread: nz W <= (Mz + 1) W / 2 <= NL kNT
   const int r = blockIdx.y;
   if (mask && !mask[r]) return;
-  const int Mz = pz.L;
-  const int n = Mz * W;
-  const int nq = (Mz / 2 + 1) * W;
+  const int Mz = LC > 0 ? LC : pz.L;
+  const int n = Mz << LOGW;
+  const int nq = ((Mz >> 1) + 1) << LOGW;
+  const int nzW = d.nz << LOGW;
   cpx<T> *buf = reinterpret_cast<cpx<T> *>(dda_smem);
   cpx<T> *tw = buf + n;
   load_twiddles(tw, twz, Mz);
   const int b = blockIdx.x;
-  const int xt = b % nxt, ky = b / nxt;
-  cpx<T> *tile = B + (size_t)r * b_elems + (((size_t)ky * nxt + xt) * 3) * nz * W;
+  const int ky = b / d.nxt, xt = b - ky * d.nxt;
+  cpx<T> *tile = B + (size_t)r * b_elems + (((size_t)ky * d.nxt + xt) * 3) * d.nz * W;
+  // two-slot ring: the rows of component c + 1 are in flight while c is transformed
+  cpx<T> pre[2][NL];
+  auto fetch = [&](int c, cpx<T>(&dst)[NL]) {
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const int e = threadIdx.x + i * kNT;
+      dst[i] = e < nzW ? tile[c * nzW + e] : cpx<T>{0, 0};
+    }
+  };
+  fetch(0, pre[0]);
   cpx<T> a0[NQ], b0[NQ], a1[NQ], b1[NQ];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const cpx<T> *src = tile + (size_t)c * nz * W;
-    stage_in<T, EPT>(buf, n, [&](int e) { return e < nz * W ? src[e] : cpx<T>{0, 0}; });
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * kNT;
+      if (e < n) buf[e] = (i < NL && e < nzW) ? pre[c & 1][i < NL ? i : 0] : cpx<T>{0, 0};
+    }
+    if (c < 2) fetch(c + 1, pre[(c + 1) & 1]);
     __syncthreads();
-    fft_lds<T, EPT, -1>(buf, tw, pz, W, 1, W, true);
+    fft_pen<T, EPT, -1, LOGW, LC>(buf, tw, pz);
     if (c < 2) {
 #pragma unroll
       for (int i = 0; i < NQ; ++i) {
         const int q = threadIdx.x + i * kNT;
         if (q < nq) {
-          const int oz = q / W, p = q % W;
+          const int oz = q >> LOGW, p = q & (W - 1);
           const bool mir = oz != 0 && 2 * oz != Mz;
           const cpx<T> va = buf[q];
-          const cpx<T> vb = mir ? buf[(Mz - oz) * W + p] : cpx<T>{0, 0};
+          const cpx<T> vb = mir ? buf[((Mz - oz) << LOGW) + p] : cpx<T>{0, 0};
           if (c == 0) { a0[i] = va; b0[i] = vb; }
           else { a1[i] = va; b1[i] = vb; }
         }
@@ -221,21 +274,21 @@ __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx
     }
   }
   int sy;
-  const int oy = fold(ky, My, sy);
+  const int oy = fold(ky, d.My, sy);
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     const int q = threadIdx.x + i * kNT;
     if (q < nq) {
-      const int oz = q / W, p = q % W, kx = xt * W + p;
+      const int oz = q >> LOGW, p = q & (W - 1), kx = (xt << LOGW) + p;
       const bool mir = oz != 0 && 2 * oz != Mz;
-      const int zb = (Mz - oz) * W + p;
+      const int zb = ((Mz - oz) << LOGW) + p;
       cpx<T> qa0 = {0, 0}, qa1 = {0, 0}, qa2 = {0, 0}, qb0 = {0, 0}, qb1 = {0, 0}, qb2 = {0, 0};
-      if (kx < Mx) {
+      if (kx < d.Mx) {
         int sx;
-        const int ox = fold(kx, Mx, sx);
-        const cpx<T> *g = ghat + ((size_t)oz * Myh + oy) * Mxh + ox;
-        const cpx<T> gxx = g[0], gyy = g[moct], gzz = g[2 * moct];
-        const cpx<T> gxy = T(sx * sy) * g[3 * moct], gxz = T(sx) * g[4 * moct], gyz = T(sy) * g[5 * moct];
+        const int ox = fold(kx, d.Mx, sx);
+        const cpx<T> *g = ghat + (size_t)(mul24(mul24(oz, d.Myh) + oy, d.Mxh) + ox);
+        const cpx<T> gxx = g[0], gyy = g[d.moct], gzz = g[2 * d.moct];
+        const cpx<T> gxy = T(sx * sy) * g[3 * d.moct], gxz = T(sx) * g[4 * d.moct], gyz = T(sy) * g[5 * d.moct];
         const cpx<T> a2 = buf[q];
         qa0 = gxx * a0[i] + gxy * a1[i] + gxz * a2;
         qa1 = gxy * a0[i] + gyy * a1[i] + gyz * a2;
@@ -266,91 +319,95 @@ __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx
       for (int i = 0; i < NQ; ++i) {
         const int q = threadIdx.x + i * kNT;
         if (q < nq) {
-          const int oz = q / W, p = q % W;
+          const int oz = q >> LOGW, p = q & (W - 1);
           buf[q] = c == 0 ? a0[i] : a1[i];
-          if (oz != 0 && 2 * oz != Mz) buf[(Mz - oz) * W + p] = c == 0 ? b0[i] : b1[i];
+          if (oz != 0 && 2 * oz != Mz) buf[((Mz - oz) << LOGW) + p] = c == 0 ? b0[i] : b1[i];
         }
       }
       __syncthreads();
     }
-    fft_lds<T, EPT, +1>(buf, tw, pz, W, 1, W, true);
-    cpx<T> *dst = tile + (size_t)c * nz * W;
-    for (int e = threadIdx.x; e < nz * W; e += kNT) dst[e] = buf[e];
+    fft_pen<T, EPT, +1, LOGW, LC>(buf, tw, pz);
+    cpx<T> *dst = tile + c * nzW;
+    for (int e = threadIdx.x; e < nzW; e += kNT) dst[e] = buf[e];
     __syncthreads();
   }
 }
 
 // --------------------------------------------------------------- y-inverse --
-template <typename T, int EPT>
+template <typename T, int EPT, int LC>
 __global__ __launch_bounds__(kNT) void k_yinv(const int *__restrict__ mask, const cpx<T> *__restrict__ B,
                                                size_t b_elems, cpx<T> *__restrict__ A, size_t a_elems,
-                                               const cpx<T> *__restrict__ twy, AxisPlan py, int ny, int nz,
-                                               int nxt) {
-  constexpr int W = kW<T>;
+                                               const cpx<T> *__restrict__ twy, AxisPlan py, PassDims d) {
+  constexpr int W = kW<T>, LOGW = kLogW<T>;
   const int r = blockIdx.y;
   if (mask && !mask[r]) return;
-  const int My = py.L;
+  const int My = LC > 0 ? LC : py.L;
+  const int n = My << LOGW;
   cpx<T> *buf = reinterpret_cast<cpx<T> *>(dda_smem);
-  cpx<T> *tw = buf + My * W;
+  cpx<T> *tw = buf + n;
   load_twiddles(tw, twy, My);
+  const int nxt = d.nxt, nz = d.nz;
   const int b = blockIdx.x;
-  const int xt = b % nxt, cz = b / nxt, c = cz / nz, z = cz - c * nz;
-  const cpx<T> *Br = B + (size_t)r * b_elems;
-  stage_in<T, EPT>(buf, My * W, [&](int e) {
-    const int ky = e / W, p = e % W;
-    return Br[((((size_t)ky * nxt + xt) * 3 + c) * nz + z) * W + p];
-  });
+  const int cz = b / nxt, xt = b - cz * nxt, c = cz / nz, z = cz - c * nz;
+  const cpx<T> *src = B + (size_t)r * b_elems + (((size_t)xt * 3 + c) * nz + z) * W;
+  const int kstr = nxt * 3 * nz * W;
+  stage_in<T, EPT>(buf, n, [&](int e) { return src[(e >> LOGW) * kstr + (e & (W - 1))]; });
   __syncthreads();
-  fft_lds<T, EPT, +1>(buf, tw, py, W, 1, W, true);
-  cpx<T> *dst = A + (size_t)r * a_elems + (((size_t)c * nz + z) * nxt + xt) * ny * W;
-  for (int e = threadIdx.x; e < ny * W; e += kNT) dst[e] = buf[e];
+  fft_pen<T, EPT, +1, LOGW, LC>(buf, tw, py);
+  cpx<T> *dst = A + (size_t)r * a_elems + (((size_t)c * nz + z) * nxt + xt) * d.ny * W;
+  const int nyW = d.ny << LOGW;
+  for (int e = threadIdx.x; e < nyW; e += kNT) dst[e] = buf[e];
 }
 
 // --------------------------------------------------------------- x-inverse --
 // f.out_mode (see FuseArgs): 0 only writes out = ainv * in - G*in; 1 and 2 also
 // write per-block partial sums of the BiCGSTAB inner products of `out`.
-template <typename T, int EPT>
+template <typename T, int EPT, int LC>
 __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *__restrict__ out, int64_t n3,
                                                const int *__restrict__ mask, const c64 *__restrict__ ainv,
                                                int ncomp, const uint8_t *__restrict__ comp,
                                                const int *__restrict__ cell_site, const cpx<T> *__restrict__ A,
                                                size_t a_elems, const cpx<T> *__restrict__ twx, AxisPlan px,
-                                               int nx, int ny, int nz, int nxt, int nrows, FuseArgs f) {
-  constexpr int W = kW<T>;
+                                               PassDims d, FuseArgs f) {
+  constexpr int W = kW<T>, LOGW = kLogW<T>;
   constexpr int NE = (EPT + 2) / 3;
   const int r = blockIdx.y;
   if (mask && !mask[r]) return;
-  const int Mx = px.L;
+  const int Mx = LC > 0 ? LC : px.L;
+  const int nrows = LC > 0 ? xpass_rows(LC) : d.nrows;
+  const int ne = nrows * Mx;
   cpx<T> *buf = reinterpret_cast<cpx<T> *>(dda_smem);
-  cpx<T> *tw = buf + 3 * nrows * Mx;
+  cpx<T> *tw = buf + 3 * ne;
+  int *rowoff = reinterpret_cast<int *>(tw + Mx);
   load_twiddles(tw, twx, Mx);
   const int row0 = blockIdx.x * nrows;
-  const int nrow = min(nrows, ny * nz - row0);
+  const int nrow = min(nrows, d.ny * d.nz - row0);
+  x_row_offsets<T, LC>(rowoff, d, nrows, row0, nrow);
+  __syncthreads();
   const cpx<T> *Ar = A + (size_t)r * a_elems;
-  stage_in<T, EPT>(buf, 3 * nrows * Mx, [&](int e) {
-    const int pq = e / Mx, kx = e - pq * Mx;
-    const int c = pq / nrows, q = pq - c * nrows;
-    cpx<T> v = {0, 0};
-    if (q < nrow) {
-      const int row = row0 + q, z = row / ny, y = row - z * ny;
-      const int xt = kx / W, p = kx % W;
-      v = Ar[((((size_t)c * nz + z) * nxt + xt) * ny + y) * W + p];
-    }
-    return v;
+  const int nyW = d.ny * W;
+  stage_in<T, EPT>(buf, 3 * ne, [&](int e) {
+    const int pq = LC > 0 ? e / LC : (int)d.d_mx((uint32_t)e);
+    const int kx = e - pq * Mx;
+    const int ro = rowoff[pq];
+    return ro >= 0 ? Ar[ro + (kx >> LOGW) * nyW + (kx & (W - 1))] : cpx<T>{0, 0};
   });
   __syncthreads();
-  fft_lds<T, EPT, +1>(buf, tw, px, 3 * nrows, Mx, 1, false);
+  fft_rows<T, EPT, +1, LC>(buf, tw, px, 3 * nrows);
   const size_t off = (size_t)r * n3;
   const c64 *ai = ainv + (size_t)r * ncomp;
-  const int ne = nrow * nx;
-  int site[NE];
+  const int nsite = nrow * d.nx;
+  const int *cs = cell_site + (size_t)row0 * d.nx;
+  int site[NE], bi[NE];
 #pragma unroll
   for (int i = 0; i < NE; ++i) {
     const int e = threadIdx.x + i * kNT;
     site[i] = -1;
-    if (e < ne) {
-      const int q = e / nx, x = e - q * nx;
-      site[i] = cell_site[(size_t)(row0 + q) * nx + x];
+    bi[i] = 0;
+    if (e < nsite) {
+      site[i] = cs[e];
+      const int q = (int)d.d_nx((uint32_t)e);
+      bi[i] = q * Mx + (e - q * d.nx);
     }
   }
   c64 pv[NE][3];
@@ -361,16 +418,14 @@ __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *_
   double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < NE; ++i) {
-    const int e = threadIdx.x + i * kNT;
     if (site[i] >= 0) {
-      const int q = e / nx, x = e - q * nx;
       const c64 a = ai[comp ? comp[site[i]] : 0];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const size_t j = off + (size_t)3 * site[i] + c;
-        const cpx<T> fv = buf[(c * nrows + q) * Mx + x];
-        const c64 d = a * pv[i][c];
-        const c64 o = c64{d.x - double(fv.x), d.y - double(fv.y)};
+        const cpx<T> fv = buf[c * ne + bi[i]];
+        const c64 dd = a * pv[i][c];
+        const c64 o = c64{dd.x - double(fv.x), dd.y - double(fv.y)};
         out[j] = o;
         if (f.out_mode == 1) {
           const c64 g = cmulc(f.rh[j], o);
@@ -399,103 +454,149 @@ __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *_
 }
 
 // --------------------------------------------------------------- launchers --
+template <int V>
+using IC = std::integral_constant<int, V>;
+
 // Register arrays are sized by EPT = elements per thread (a compile-time
 // bound, one kernel instantiation per size).
-static inline int pick_ept(size_t elems) {
-  static const int opts[] = {4, 8, 12, 16, 20, 24, 32};
-  for (int e : opts)
-    if ((size_t)e * kNT >= elems) return e;
-  throw Error{DDA_ENOTSUP, "FFT tile too large for one block"};
+constexpr int pick_ept_c(size_t elems, bool xpass) {
+  const int opts[7] = {4, 8, 12, 16, 20, 24, 32};
+  for (int i = 0; i < (xpass ? 2 : 7); ++i)
+    if ((size_t)opts[i] * kNT >= elems) return opts[i];
+  return 0;
 }
 
-#define DDA_EPT_SWITCH(ept, BODY)                       \
-  switch (ept) {                                        \
-    case 4: { constexpr int E = 4; BODY; } break;       \
-    case 8: { constexpr int E = 8; BODY; } break;       \
-    case 12: { constexpr int E = 12; BODY; } break;     \
-    case 16: { constexpr int E = 16; BODY; } break;     \
-    case 20: { constexpr int E = 20; BODY; } break;     \
-    case 24: { constexpr int E = 24; BODY; } break;     \
-    default: { constexpr int E = 32; BODY; } break;     \
+template <bool XPASS, typename F>
+static inline void with_ept(size_t elems, F &&f) {
+  const int e = pick_ept_c(elems, XPASS);
+  if constexpr (XPASS) {
+    switch (e) {
+      case 4: f(IC<4>{}); break;
+      case 8: f(IC<8>{}); break;
+      default: throw Error{DDA_ENOTSUP, "FFT tile too large for one block"};
+    }
+  } else {
+    switch (e) {
+      case 4: f(IC<4>{}); break;
+      case 8: f(IC<8>{}); break;
+      case 12: f(IC<12>{}); break;
+      case 16: f(IC<16>{}); break;
+      case 20: f(IC<20>{}); break;
+      case 24: f(IC<24>{}); break;
+      case 32: f(IC<32>{}); break;
+      default: throw Error{DDA_ENOTSUP, "FFT tile too large for one block"};
+    }
   }
+}
 
-#define DDA_EPT_SWITCH_X(ept, BODY)                     \
-  switch (ept) {                                        \
-    case 4: { constexpr int E = 4; BODY; } break;       \
-    default: { constexpr int E = 8; BODY; } break;      \
+// Transform lengths with a compile-time plan; the others use the run-time one.
+template <typename F>
+static inline void with_len(int L, F &&f) {
+  switch (L) {
+    case 64: f(IC<64>{}); break;
+    case 96: f(IC<96>{}); break;
+    case 128: f(IC<128>{}); break;
+    case 192: f(IC<192>{}); break;
+    case 256: f(IC<256>{}); break;
+    default: f(IC<0>{}); break;
   }
+}
+
+// Calls f(IC<EPT>, IC<LC>) for a pass of `elems` elements per block along an
+// axis of length L (with LC > 0 the caller derives EPT from LC).
+template <bool XPASS, typename F>
+static inline void with_pass(int L, size_t elems, F &&f) {
+  with_len(L, [&](auto lc) {
+    constexpr int LC = decltype(lc)::value;
+    if constexpr (LC > 0) f(IC<0>{}, lc);
+    else with_ept<XPASS>(elems, [&](auto e) { f(e, lc); });
+  });
+}
 
 template <typename K>
 static inline void allow_lds(K kernel, size_t bytes) {
   if (bytes > 65536) DDA_HIP(hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
 }
 
-static inline int rows_per_block(int Mx) { return xpass_rows(Mx); }
-
 template <typename T>
 void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const hipEvent_t *ev, int only_pass,
                    int reps) {
   const bool f32 = sizeof(T) == 4;
+  constexpr int W = kW<T>;
   const int nxt = g.nxt(f32);
   const size_t ae = g.a_elems(f32), be = g.b_elems(f32);
+  DDA_REQUIRE(ae < (size_t(1) << 31) && be < (size_t(1) << 31), "grid too large for 32-bit tile offsets");
   cpx<T> *A = static_cast<cpx<T> *>(a.bufA);
   cpx<T> *B = static_cast<cpx<T> *>(a.bufB);
   const cpx<T> *twx = static_cast<const cpx<T> *>(a.twx);
   const cpx<T> *twy = static_cast<const cpx<T> *>(a.twy);
   const cpx<T> *twz = static_cast<const cpx<T> *>(a.twz);
   const int64_t n3 = 3 * g.n_sites;
-  const int nrows = rows_per_block(g.Mx);
+  const int nrows = xpass_rows(g.Mx);
   const int nrowblk = (g.ny * g.nz + nrows - 1) / nrows;
   const size_t cs = sizeof(cpx<T>);
-  constexpr int W = kW<T>;
+  PassDims d{};
+  d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
+  d.Mx = g.Mx; d.My = g.My;
+  d.nxt = nxt;
+  d.nrows = nrows;
+  d.Mxh = g.Mxh; d.Myh = g.Myh;
+  d.moct = (int64_t)g.oct_elems();
+  d.d_mx = make_fastdiv(g.Mx);
+  d.d_nx = make_fastdiv(g.nx);
+  d.d_ny = make_fastdiv(g.ny);
+  d.d_nxt = make_fastdiv(nxt);
+  d.d_nrows = make_fastdiv(nrows);
   const FuseArgs &f = a.fuse;
+  const size_t xlds = ((size_t)3 * nrows * g.Mx + g.Mx) * cs + (size_t)3 * nrows * sizeof(int);
   auto pass = [&](int k) {
     switch (k) {
-      case 0: {
-        const size_t elems = (size_t)3 * nrows * g.Mx;
-        const size_t lds = (elems + g.Mx) * cs;
-        DDA_EPT_SWITCH_X(pick_ept(elems), {
-          hipLaunchKernelGGL((k_xfwd<T, E>), dim3(nrowblk, a.nrhs), dim3(kNT), lds, s, a.in, n3, a.mask,
-                             a.cell_site, A, ae, twx, a.px, g.nx, g.ny, g.nz, nxt, nrows, f);
+      case 0:
+        with_pass<true>(g.Mx, (size_t)3 * nrows * g.Mx, [&](auto e, auto lc) {
+          constexpr int LC = decltype(lc)::value;
+          constexpr int E = LC > 0 ? pick_ept_c((size_t)3 * xpass_rows(LC) * LC, true) : decltype(e)::value;
+          hipLaunchKernelGGL((k_xfwd<T, E, LC>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s, a.in, n3, a.mask,
+                             a.cell_site, A, ae, twx, a.px, d, f);
         });
-      } break;
-      case 1: {
-        const size_t elems = (size_t)g.My * W;
-        const size_t lds = (elems + g.My) * cs;
-        DDA_EPT_SWITCH(pick_ept(elems), {
-          allow_lds(k_yfwd<T, E>, lds);
-          hipLaunchKernelGGL((k_yfwd<T, E>), dim3(3 * g.nz * nxt, a.nrhs), dim3(kNT), lds, s, a.mask, A, ae, B, be,
-                             twy, a.py, g.ny, g.nz, nxt);
+        break;
+      case 1:
+        with_pass<false>(g.My, (size_t)g.My * W, [&](auto e, auto lc) {
+          constexpr int LC = decltype(lc)::value;
+          constexpr int E = LC > 0 ? pick_ept_c((size_t)LC * W, false) : decltype(e)::value;
+          const size_t lds = ((size_t)g.My * W + g.My) * cs;
+          allow_lds(k_yfwd<T, E, LC>, lds);
+          hipLaunchKernelGGL((k_yfwd<T, E, LC>), dim3(3 * g.nz * nxt, a.nrhs), dim3(kNT), lds, s, a.mask, A, ae, B,
+                             be, twy, a.py, d);
         });
-      } break;
-      case 2: {
-        const size_t elems = (size_t)g.Mz * W;
-        const size_t lds = (elems + g.Mz) * cs;
-        DDA_EPT_SWITCH(pick_ept(elems), {
-          allow_lds(k_zpass<T, E>, lds);
-          hipLaunchKernelGGL((k_zpass<T, E>), dim3(g.My * nxt, a.nrhs), dim3(kNT), lds, s, a.mask, B, be,
-                             static_cast<const cpx<T> *>(a.ghat), twz, a.pz, g.Mx, g.My, g.nz, nxt, g.Mxh, g.Myh,
-                             g.oct_elems());
+        break;
+      case 2:
+        with_pass<false>(g.Mz, (size_t)g.Mz * W, [&](auto e, auto lc) {
+          constexpr int LC = decltype(lc)::value;
+          constexpr int E = LC > 0 ? pick_ept_c((size_t)LC * W, false) : decltype(e)::value;
+          const size_t lds = ((size_t)g.Mz * W + g.Mz) * cs;
+          allow_lds(k_zpass<T, E, LC>, lds);
+          hipLaunchKernelGGL((k_zpass<T, E, LC>), dim3(g.My * nxt, a.nrhs), dim3(kNT), lds, s, a.mask, B, be,
+                             static_cast<const cpx<T> *>(a.ghat), twz, a.pz, d);
         });
-      } break;
-      case 3: {
-        const size_t elems = (size_t)g.My * W;
-        const size_t lds = (elems + g.My) * cs;
-        DDA_EPT_SWITCH(pick_ept(elems), {
-          allow_lds(k_yinv<T, E>, lds);
-          hipLaunchKernelGGL((k_yinv<T, E>), dim3(3 * g.nz * nxt, a.nrhs), dim3(kNT), lds, s, a.mask, B, be, A, ae,
-                             twy, a.py, g.ny, g.nz, nxt);
+        break;
+      case 3:
+        with_pass<false>(g.My, (size_t)g.My * W, [&](auto e, auto lc) {
+          constexpr int LC = decltype(lc)::value;
+          constexpr int E = LC > 0 ? pick_ept_c((size_t)LC * W, false) : decltype(e)::value;
+          const size_t lds = ((size_t)g.My * W + g.My) * cs;
+          allow_lds(k_yinv<T, E, LC>, lds);
+          hipLaunchKernelGGL((k_yinv<T, E, LC>), dim3(3 * g.nz * nxt, a.nrhs), dim3(kNT), lds, s, a.mask, B, be, A,
+                             ae, twy, a.py, d);
         });
-      } break;
-      default: {
-        const size_t elems = (size_t)3 * nrows * g.Mx;
-        const size_t lds = (elems + g.Mx) * cs;
-        DDA_EPT_SWITCH_X(pick_ept(elems), {
-          hipLaunchKernelGGL((k_xinv<T, E>), dim3(nrowblk, a.nrhs), dim3(kNT), lds, s, a.in, a.out, n3, a.mask,
-                             a.ainv, a.ncomp, a.comp, a.cell_site, A, ae, twx, a.px, g.nx, g.ny, g.nz, nxt, nrows,
-                             f);
+        break;
+      default:
+        with_pass<true>(g.Mx, (size_t)3 * nrows * g.Mx, [&](auto e, auto lc) {
+          constexpr int LC = decltype(lc)::value;
+          constexpr int E = LC > 0 ? pick_ept_c((size_t)3 * xpass_rows(LC) * LC, true) : decltype(e)::value;
+          hipLaunchKernelGGL((k_xinv<T, E, LC>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s, a.in, a.out, n3,
+                             a.mask, a.ainv, a.ncomp, a.comp, a.cell_site, A, ae, twx, a.px, d, f);
         });
-      } break;
+        break;
     }
   };
   if (only_pass >= 0) {
