@@ -233,8 +233,17 @@ __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx
   cpx<T> *buf = reinterpret_cast<cpx<T> *>(dda_smem);
   cpx<T> *tw = buf + n;
   load_twiddles(tw, twz, Mz);
+  // XCD-aware order.  Workgroups are dispatched to the 8 XCDs round-robin
+  // (XCD = b mod 8), and each XCD has its own L2.  Logical index li runs
+  // through contiguous ranges per XCD, and consecutive li visit ky, My - ky
+  // and the x tiles t, nxt - 1 - t next to each other: the (up to) four
+  // columns that read the same octant Green values share one L2.
   const int b = blockIdx.x;
-  const int ky = b / d.nxt, xt = b - ky * d.nxt;
+  const int nb = d.My * d.nxt, per = nb >> 3;
+  const int li = b < (per << 3) ? (b & 7) * per + (b >> 3) : b;
+  const int iy = (int)d.d_nxt((uint32_t)li), ix = li - iy * d.nxt;
+  const int ky = (iy & 1) ? d.My - ((iy + 1) >> 1) : (iy >> 1);
+  const int xt = (ix & 1) ? d.nxt - 1 - (ix >> 1) : (ix >> 1);
   cpx<T> *tile = B + (size_t)r * b_elems + (((size_t)ky * d.nxt + xt) * 3) * d.nz * W;
   // two-slot ring: the rows of component c + 1 are in flight while c is transformed
   cpx<T> pre[2][NL];
