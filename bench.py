@@ -46,6 +46,21 @@ def algorithmic_bytes(box, grid, n_sites, fp32=True, nrhs=1):
     return total, zpass
 
 
+def measured_traffic(kernel_prefix):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated on a plain copy),
+    or None when the kernel sources changed since the counters were taken."""
+    from paper_1305_6497_amd import profile_matvec
+    path = os.path.join(ROOT, "profiles", f"{kernel_prefix}_{WORKLOAD}_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != profile_matvec.kernel_source_hash():
+        return None, "kernel sources changed since the counters were taken"
+    return rec["traffic_bytes"], os.path.relpath(path, ROOT)
+
+
 def cpu_baseline(sites, kd, m, rhs, gpu_fp64_iters, budget_s=20.0):
     """FP64 CPU oracle on a bounded sample of the same solve."""
     import numpy as np
@@ -287,6 +302,9 @@ def main():
     pass_bytes = dict(x_forward=48 * n + a_b, y_forward=a_b + b_b, z_pass=z_b, y_inverse=a_b + b_b,
                       x_inverse=a_b + 2 * 48 * n)
     achieved = pass_bytes[dom] / (prof[dom] * 1e-3) / 1e9
+    kprefix = dict(x_forward="k_xfwd", y_forward="k_yfwd", z_pass="k_zpass", y_inverse="k_yinv",
+                   x_inverse="k_xinv")[dom]
+    traffic, traffic_src = measured_traffic(kprefix)
     ms_per_step = 1e3 * total / args.steps
     extras = None if args.no_extras else extra_workloads(dda, inputs, torch, args.tol)
     cpu = None
@@ -326,7 +344,8 @@ def main():
         "matvec_algorithmic_bytes": tot_b,
         "matvec_effective_GBs": tot_b / (prof["total"] * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "traffic_source": traffic_src,
                      "algorithmic_bytes_per_launch": pass_bytes[dom]},
         "cpu_baseline": cpu,
         "q_rel_err_vs_oracle": (_rel_err(q, _reference(WORKLOAD)["results"][0]) if _reference(WORKLOAD) else None),
