@@ -33,6 +33,113 @@ __device__ __forceinline__ cpx<T> mul_i(cpx<T> z) {
   return {-z.y, z.x};
 }
 
+// exp(DIR * 2 pi i m / R) as compile-time constants.  cos and sin come from
+// their Taylor series on [0, pi/4] after reducing m / R by the symmetries of
+// the circle; the points on the axes and the diagonals are exact.
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double taylor_sin(double x) {
+  double t = x, s = x;
+  for (int k = 1; k < 12; ++k) {
+    t *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    s += t;
+  }
+  return s;
+}
+
+constexpr double taylor_cos(double x) {
+  double t = 1.0, s = 1.0;
+  for (int k = 1; k < 12; ++k) {
+    t *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    s += t;
+  }
+  return s;
+}
+
+struct Root {
+  double c, s;
+};
+
+// cos and sin of 2 pi m / R.  The angle is held as a = 8 m (units of
+// 2 pi / (8 R)) and folded into [0, R] (an angle in [0, pi/4]) with integer
+// arithmetic, so only the final series sees rounding.
+constexpr Root unit_root(int m, int R) {
+  m %= R;
+  if (m < 0) m += R;
+  long a = 8L * m;
+  double ss = 1.0, sc = 1.0;
+  if (a > 4L * R) { a = 8L * R - a; ss = -1.0; }       // theta -> 2 pi - theta
+  if (a > 2L * R) { a = 4L * R - a; sc = -1.0; }       // theta -> pi - theta
+  bool swap = false;
+  if (a > R) { a = 2L * R - a; swap = true; }          // theta -> pi/2 - theta
+  const double x = kPi * double(a) / (4.0 * R);
+  double c = taylor_cos(x), s = taylor_sin(x);
+  if (a == 0) { c = 1.0; s = 0.0; }
+  if (a == R) { c = 0.70710678118654752440; s = c; }
+  if (swap) { const double t = c; c = s; s = t; }
+  return {sc * c, ss * s};
+}
+
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dft_small(cpx<T> *a);
+
+// v * exp(DIR * 2 pi i M / R), with the trivial rotations done without multiplies
+template <int R, int M, int DIR, typename T>
+__device__ __forceinline__ cpx<T> rotate(cpx<T> v) {
+  constexpr int m = M % R;
+  if constexpr (m == 0) {
+    return v;
+  } else if constexpr (2 * m == R) {
+    return {-v.x, -v.y};
+  } else if constexpr (4 * m == R) {
+    return DIR < 0 ? cpx<T>{v.y, -v.x} : cpx<T>{-v.y, v.x};
+  } else if constexpr (4 * m == 3 * R) {
+    return DIR < 0 ? cpx<T>{-v.y, v.x} : cpx<T>{v.y, -v.x};
+  } else {
+    constexpr Root w = unit_root(m, R);
+    const T c = T(w.c), sn = T(DIR * w.s);
+    return {v.x * c - v.y * sn, v.x * sn + v.y * c};
+  }
+}
+
+// y[n1][k2] *= exp(DIR * 2 pi i n1 k2 / R) for n1 >= N1, k2 >= K2
+template <int R, int A, int B, int DIR, int N1, int K2, typename T>
+__device__ __forceinline__ void rotate_all(cpx<T> (&y)[A][B]) {
+  if constexpr (N1 < A) {
+    if constexpr (K2 < B) {
+      y[N1][K2] = rotate<R, N1 * K2, DIR>(y[N1][K2]);
+      rotate_all<R, A, B, DIR, N1, K2 + 1>(y);
+    } else {
+      rotate_all<R, A, B, DIR, N1 + 1, 1>(y);
+    }
+  }
+}
+
+// DFT of size R = A * B in registers (Cooley-Tukey): with n = n1 + A n2 and
+// k = B k1 + k2, X[B k1 + k2] = sum_n1 w_A^(n1 k1) w_R^(n1 k2) Y[n1][k2], where
+// Y[n1] is the size-B DFT of x[n1 + A n2] over n2.
+template <int A, int B, int DIR, typename T>
+__device__ __forceinline__ void dft_composite(cpx<T> *a) {
+  constexpr int R = A * B;
+  cpx<T> y[A][B];
+#pragma unroll
+  for (int n1 = 0; n1 < A; ++n1) {
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) y[n1][n2] = a[n1 + A * n2];
+    dft_small<B, DIR>(y[n1]);
+  }
+  rotate_all<R, A, B, DIR, 1, 1>(y);
+#pragma unroll
+  for (int k2 = 0; k2 < B; ++k2) {
+    cpx<T> z[A];
+#pragma unroll
+    for (int n1 = 0; n1 < A; ++n1) z[n1] = y[n1][k2];
+    dft_small<A, DIR>(z);
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) a[B * k1 + k2] = z[k1];
+  }
+}
+
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dft_small(cpx<T> *a) {
   if constexpr (R == 2) {
@@ -86,6 +193,20 @@ __device__ __forceinline__ void dft_small(cpx<T> *a) {
     a[6] = e[2] - o2;
     a[3] = e[3] + o3;
     a[7] = e[3] - o3;
+  } else if constexpr (R == 6) {
+    dft_composite<2, 3, DIR>(a);
+  } else if constexpr (R == 9) {
+    dft_composite<3, 3, DIR>(a);
+  } else if constexpr (R == 10) {
+    dft_composite<2, 5, DIR>(a);
+  } else if constexpr (R == 12) {
+    dft_composite<4, 3, DIR>(a);
+  } else if constexpr (R == 15) {
+    dft_composite<3, 5, DIR>(a);
+  } else if constexpr (R == 16) {
+    dft_composite<4, 4, DIR>(a);
+  } else {
+    static_assert(R == 2, "unsupported radix");
   }
 }
 
@@ -193,34 +314,84 @@ __device__ __forceinline__ void stage_rows(cpx<T> *buf, const cpx<T> *tw, int L,
   __syncthreads();
 }
 
-// The plan of a compile-time length: same radix order as make_axis_plan.
+// The plan of a compile-time length.  Besides the radices of the run-time plan
+// it may use the composite radices 6, 9, 10, 12, 15 and 16 (up to rmax): the
+// plan with the fewest stages (each stage is one LDS round trip and two
+// barriers) and, among those, the fewest flops, largest radix first (the
+// first stage needs no twiddles).
 struct StaticPlan {
   int n;
   int radix[kMaxStages];
   int ns[kMaxStages];
+  double cost;
 };
 
-constexpr StaticPlan static_plan(int L) {
-  StaticPlan p{};
-  const int order[5] = {8, 4, 2, 5, 3};
-  int n = L, ns = 1;
-  for (int o = 0; o < 5; ++o) {
-    while (n % order[o] == 0 && p.n < kMaxStages) {
-      p.radix[p.n] = order[o];
-      p.ns[p.n] = ns;
-      ++p.n;
-      ns *= order[o];
-      n /= order[o];
-    }
+// real flops per element of a radix-R DFT, and of its R - 1 twiddle products
+constexpr double radix_flops(int R) {
+  switch (R) {
+    case 2: return 2.0;
+    case 3: return 5.3;
+    case 4: return 4.0;
+    case 5: return 8.8;
+    case 6: return 9.3;
+    case 8: return 7.0;
+    case 9: return 13.3;
+    case 10: return 12.4;
+    case 12: return 12.3;
+    case 15: return 17.3;
+    default: return 10.9;     // 16
+  }
+}
+
+constexpr StaticPlan search_plan(int L, int rmax) {
+  StaticPlan best{};
+  best.cost = 1e30;
+  if (L == 1) {
+    best.cost = 0.0;
+    return best;
+  }
+  const int set[11] = {16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
+  for (int i = 0; i < 11; ++i) {
+    const int R = set[i];
+    if (R > rmax || L % R != 0) continue;
+    StaticPlan c = search_plan(L / R, rmax);
+    if (c.cost >= 1e29 || c.n + 1 > kMaxStages) continue;
+    c.radix[c.n++] = R;
+    c.cost += radix_flops(R) + 6.0 * (R - 1) / R;
+    if (best.cost >= 1e29 || c.n < best.n || (c.n == best.n && c.cost < best.cost)) best = c;
+  }
+  return best;
+}
+
+constexpr StaticPlan static_plan(int L, int rmax = 8) {
+  StaticPlan p = search_plan(L, rmax);
+  for (int i = 0; i < p.n; ++i)             // largest radix first
+    for (int j = i + 1; j < p.n; ++j)
+      if (p.radix[j] > p.radix[i]) {
+        const int t = p.radix[i];
+        p.radix[i] = p.radix[j];
+        p.radix[j] = t;
+      }
+  int ns = 1;
+  for (int i = 0; i < p.n; ++i) {
+    p.ns[i] = ns;
+    ns *= p.radix[i];
   }
   return p;
+}
+
+// Largest radix of a pen plan over 2^LOGP pencils: a radix-R stage keeps
+// L NPEN / R butterflies, and at least half the threads should get one.
+constexpr int pen_rmax(int L, int LOGP) {
+  const int r = 2 * (L << LOGP) / kNT;
+  return r < 8 ? 8 : (r > 16 ? 16 : r);
 }
 
 constexpr int cdiv_c(int a, int b) { return (a + b - 1) / b; }
 
 template <typename T, int DIR, int LOGP, int L, int S>
 __device__ __forceinline__ void fft_pen_c(cpx<T> *buf, const cpx<T> *tw) {
-  constexpr StaticPlan P = static_plan(L);
+  constexpr StaticPlan P = static_plan(L, pen_rmax(L, LOGP));
   if constexpr (S < P.n) {
     constexpr int R = P.radix[S], Ns = P.ns[S];
     constexpr int NB = cdiv_c((L / R) << LOGP, kNT);

@@ -209,49 +209,60 @@ __device__ __forceinline__ int fold(int k, int M, int &sgn) {
   return M - k;
 }
 
-// One block per (ky, x tile).  The three components are transformed one after
-// the other in an Mz x W LDS buffer (in-place stages); the nz data rows of the
-// next component are loaded into registers while the current one is
-// transformed.  Each thread owns
-// octant cells (oz, p), oz <= Mz/2, and with them the mirror frequency
-// Mz - oz of the same pencil: one read of the six Green values serves both,
-// with the z-odd components (xz, yz) negated for the mirror.  Forward spectra
-// of components 0 and 1 are parked in registers, component 2 stays in LDS.
-template <typename T, int EPT, int LC>
+// One block per (ky, x tile), or per half of an x tile (HALF = 1: the block
+// takes NP = W/2 of the tile's W pencils, which halves its registers for long
+// Mz; the two halves run next to each other and share the tile's 128-byte
+// lines in L2).  The three components are transformed one after the other in
+// an Mz x NP LDS buffer (in-place stages); the nz data rows of the next
+// component are loaded into registers while the current one is transformed.
+// Each thread owns octant cells (oz, p), oz <= Mz/2, and with them the mirror
+// frequency Mz - oz of the same pencil: one read of the six Green values
+// serves both, with the z-odd components (xz, yz) negated for the mirror.
+// Forward spectra of components 0 and 1 are parked in registers, component 2
+// stays in LDS.
+template <typename T, int EPT, int LC, int HALF>
 __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx<T> *__restrict__ B, size_t b_elems,
                                                 const cpx<T> *__restrict__ ghat, const cpx<T> *__restrict__ twz,
                                                 AxisPlan pz, PassDims d) {
   constexpr int W = kW<T>, LOGW = kLogW<T>;
-  constexpr int NQ = EPT / 2 + 1;        // octant cells per thread: (Mz/2 + 1) W <= NQ kNT
-  constexpr int NL = EPT / 2 + 1;        // data rows per thread: nz W <= (Mz + 1) W / 2 <= NL kNT
+  constexpr int LOGP = LOGW - HALF, NP = 1 << LOGP;
+  // octant cells per thread, (Mz/2 + 1) NP <= NQ kNT, and data rows per
+  // thread, nz NP <= (Mz + 1) NP / 2 <= NL kNT (exact when Mz = LC is known)
+  constexpr int NQ = LC > 0 ? cdiv_c((LC / 2 + 1) << LOGP, kNT) : EPT / 2 + 1;
+  constexpr int NL = LC > 0 ? cdiv_c(((LC + 1) / 2) << LOGP, kNT) : EPT / 2 + 1;
   const int r = blockIdx.y;
   if (mask && !mask[r]) return;
   const int Mz = LC > 0 ? LC : pz.L;
-  const int n = Mz << LOGW;
-  const int nq = ((Mz >> 1) + 1) << LOGW;
+  const int n = Mz << LOGP;
+  const int nq = ((Mz >> 1) + 1) << LOGP;
+  const int nzP = d.nz << LOGP;
   const int nzW = d.nz << LOGW;
   cpx<T> *buf = reinterpret_cast<cpx<T> *>(dda_smem);
   cpx<T> *tw = buf + n;
   load_twiddles(tw, twz, Mz);
   // XCD-aware order.  Workgroups are dispatched to the 8 XCDs round-robin
   // (XCD = b mod 8), and each XCD has its own L2.  Logical index li runs
-  // through contiguous ranges per XCD, and consecutive li visit ky, My - ky
-  // and the x tiles t, nxt - 1 - t next to each other: the (up to) four
-  // columns that read the same octant Green values share one L2.
+  // through contiguous ranges per XCD, and consecutive li visit the halves of
+  // a tile, ky and My - ky, and the x tiles t and nxt - 1 - t next to each
+  // other: the (up to) four columns that read the same octant Green values,
+  // and the two halves of a tile, share one L2.
   const int b = blockIdx.x;
-  const int nb = d.My * d.nxt, per = nb >> 3;
+  const int nb = (d.My * d.nxt) << HALF, per = nb >> 3;
   const int li = b < (per << 3) ? (b & 7) * per + (b >> 3) : b;
-  const int iy = (int)d.d_nxt((uint32_t)li), ix = li - iy * d.nxt;
+  const int h = li & HALF, lt = li >> HALF;
+  const int iy = (int)d.d_nxt((uint32_t)lt), ix = lt - iy * d.nxt;
   const int ky = (iy & 1) ? d.My - ((iy + 1) >> 1) : (iy >> 1);
   const int xt = (ix & 1) ? d.nxt - 1 - (ix >> 1) : (ix >> 1);
-  cpx<T> *tile = B + (size_t)r * b_elems + (((size_t)ky * d.nxt + xt) * 3) * d.nz * W;
+  cpx<T> *tile = B + (size_t)r * b_elems + (((size_t)ky * d.nxt + xt) * 3) * d.nz * W + h * NP;
+  // element e = m NP + p of the block is tile[m W + p] of its component
+  auto toff = [&](int e) { return HALF ? ((e >> LOGP) << LOGW) + (e & (NP - 1)) : e; };
   // two-slot ring: the rows of component c + 1 are in flight while c is transformed
   cpx<T> pre[2][NL];
   auto fetch = [&](int c, cpx<T>(&dst)[NL]) {
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
       const int e = threadIdx.x + i * kNT;
-      dst[i] = e < nzW ? tile[c * nzW + e] : cpx<T>{0, 0};
+      dst[i] = e < nzP ? tile[c * nzW + toff(e)] : cpx<T>{0, 0};
     }
   };
   fetch(0, pre[0]);
@@ -261,20 +272,20 @@ __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int e = threadIdx.x + i * kNT;
-      if (e < n) buf[e] = (i < NL && e < nzW) ? pre[c & 1][i < NL ? i : 0] : cpx<T>{0, 0};
+      if (e < n) buf[e] = (i < NL && e < nzP) ? pre[c & 1][i < NL ? i : 0] : cpx<T>{0, 0};
     }
     if (c < 2) fetch(c + 1, pre[(c + 1) & 1]);
     __syncthreads();
-    fft_pen<T, EPT, -1, LOGW, LC>(buf, tw, pz);
+    fft_pen<T, EPT, -1, LOGP, LC>(buf, tw, pz);
     if (c < 2) {
 #pragma unroll
       for (int i = 0; i < NQ; ++i) {
         const int q = threadIdx.x + i * kNT;
         if (q < nq) {
-          const int oz = q >> LOGW, p = q & (W - 1);
+          const int oz = q >> LOGP, p = q & (NP - 1);
           const bool mir = oz != 0 && 2 * oz != Mz;
           const cpx<T> va = buf[q];
-          const cpx<T> vb = mir ? buf[((Mz - oz) << LOGW) + p] : cpx<T>{0, 0};
+          const cpx<T> vb = mir ? buf[((Mz - oz) << LOGP) + p] : cpx<T>{0, 0};
           if (c == 0) { a0[i] = va; b0[i] = vb; }
           else { a1[i] = va; b1[i] = vb; }
         }
@@ -288,9 +299,9 @@ __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx
   for (int i = 0; i < NQ; ++i) {
     const int q = threadIdx.x + i * kNT;
     if (q < nq) {
-      const int oz = q >> LOGW, p = q & (W - 1), kx = (xt << LOGW) + p;
+      const int oz = q >> LOGP, p = q & (NP - 1), kx = (xt << LOGW) + h * NP + p;
       const bool mir = oz != 0 && 2 * oz != Mz;
-      const int zb = ((Mz - oz) << LOGW) + p;
+      const int zb = ((Mz - oz) << LOGP) + p;
       cpx<T> qa0 = {0, 0}, qa1 = {0, 0}, qa2 = {0, 0}, qb0 = {0, 0}, qb1 = {0, 0}, qb2 = {0, 0};
       if (kx < d.Mx) {
         int sx;
@@ -328,16 +339,16 @@ __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx
       for (int i = 0; i < NQ; ++i) {
         const int q = threadIdx.x + i * kNT;
         if (q < nq) {
-          const int oz = q >> LOGW, p = q & (W - 1);
+          const int oz = q >> LOGP, p = q & (NP - 1);
           buf[q] = c == 0 ? a0[i] : a1[i];
-          if (oz != 0 && 2 * oz != Mz) buf[((Mz - oz) << LOGW) + p] = c == 0 ? b0[i] : b1[i];
+          if (oz != 0 && 2 * oz != Mz) buf[((Mz - oz) << LOGP) + p] = c == 0 ? b0[i] : b1[i];
         }
       }
       __syncthreads();
     }
-    fft_pen<T, EPT, +1, LOGW, LC>(buf, tw, pz);
+    fft_pen<T, EPT, +1, LOGP, LC>(buf, tw, pz);
     cpx<T> *dst = tile + c * nzW;
-    for (int e = threadIdx.x; e < nzW; e += kNT) dst[e] = buf[e];
+    for (int e = threadIdx.x; e < nzP; e += kNT) dst[toff(e)] = buf[e];
     __syncthreads();
   }
 }
@@ -475,26 +486,20 @@ constexpr int pick_ept_c(size_t elems, bool xpass) {
   return 0;
 }
 
-template <bool XPASS, typename F>
+// f(IC<EPT>) for the smallest EPT in {4, 8, 12, 16, 20, 24, 32} with
+// EPT * kNT >= elems; only the sizes up to MAXE are instantiated.
+template <int MAXE, typename F>
 static inline void with_ept(size_t elems, F &&f) {
-  const int e = pick_ept_c(elems, XPASS);
-  if constexpr (XPASS) {
-    switch (e) {
-      case 4: f(IC<4>{}); break;
-      case 8: f(IC<8>{}); break;
-      default: throw Error{DDA_ENOTSUP, "FFT tile too large for one block"};
-    }
-  } else {
-    switch (e) {
-      case 4: f(IC<4>{}); break;
-      case 8: f(IC<8>{}); break;
-      case 12: f(IC<12>{}); break;
-      case 16: f(IC<16>{}); break;
-      case 20: f(IC<20>{}); break;
-      case 24: f(IC<24>{}); break;
-      case 32: f(IC<32>{}); break;
-      default: throw Error{DDA_ENOTSUP, "FFT tile too large for one block"};
-    }
+  const int e = pick_ept_c(elems, false);
+  if (e == 0 || e > MAXE) throw Error{DDA_ENOTSUP, "FFT tile too large for one block"};
+  switch (e) {
+    case 4: f(IC<4>{}); break;
+    case 8: if constexpr (MAXE >= 8) f(IC<8>{}); break;
+    case 12: if constexpr (MAXE >= 12) f(IC<12>{}); break;
+    case 16: if constexpr (MAXE >= 16) f(IC<16>{}); break;
+    case 20: if constexpr (MAXE >= 20) f(IC<20>{}); break;
+    case 24: if constexpr (MAXE >= 24) f(IC<24>{}); break;
+    default: if constexpr (MAXE >= 32) f(IC<32>{}); break;
   }
 }
 
@@ -502,23 +507,25 @@ static inline void with_ept(size_t elems, F &&f) {
 template <typename F>
 static inline void with_len(int L, F &&f) {
   switch (L) {
+    case 40: f(IC<40>{}); break;
     case 64: f(IC<64>{}); break;
     case 96: f(IC<96>{}); break;
     case 128: f(IC<128>{}); break;
     case 192: f(IC<192>{}); break;
     case 256: f(IC<256>{}); break;
+    case 270: f(IC<270>{}); break;
     default: f(IC<0>{}); break;
   }
 }
 
 // Calls f(IC<EPT>, IC<LC>) for a pass of `elems` elements per block along an
 // axis of length L (with LC > 0 the caller derives EPT from LC).
-template <bool XPASS, typename F>
+template <int MAXE, typename F>
 static inline void with_pass(int L, size_t elems, F &&f) {
   with_len(L, [&](auto lc) {
     constexpr int LC = decltype(lc)::value;
     if constexpr (LC > 0) f(IC<0>{}, lc);
-    else with_ept<XPASS>(elems, [&](auto e) { f(e, lc); });
+    else with_ept<MAXE>(elems, [&](auto e) { f(e, lc); });
   });
 }
 
@@ -561,7 +568,7 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
   auto pass = [&](int k) {
     switch (k) {
       case 0:
-        with_pass<true>(g.Mx, (size_t)3 * nrows * g.Mx, [&](auto e, auto lc) {
+        with_pass<8>(g.Mx, (size_t)3 * nrows * g.Mx, [&](auto e, auto lc) {
           constexpr int LC = decltype(lc)::value;
           constexpr int E = LC > 0 ? pick_ept_c((size_t)3 * xpass_rows(LC) * LC, true) : decltype(e)::value;
           hipLaunchKernelGGL((k_xfwd<T, E, LC>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s, a.in, n3, a.mask,
@@ -569,7 +576,7 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
         });
         break;
       case 1:
-        with_pass<false>(g.My, (size_t)g.My * W, [&](auto e, auto lc) {
+        with_pass<32>(g.My, (size_t)g.My * W, [&](auto e, auto lc) {
           constexpr int LC = decltype(lc)::value;
           constexpr int E = LC > 0 ? pick_ept_c((size_t)LC * W, false) : decltype(e)::value;
           const size_t lds = ((size_t)g.My * W + g.My) * cs;
@@ -578,18 +585,30 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
                              be, twy, a.py, d);
         });
         break;
-      case 2:
-        with_pass<false>(g.Mz, (size_t)g.Mz * W, [&](auto e, auto lc) {
+      case 2: {
+        // half tiles once a whole tile would exceed 2048 elements per block
+        const int half = g.Mz * W > 2048 ? 1 : 0;
+        auto launch = [&](auto e, auto lc, auto hf) {
+          constexpr int LC = decltype(lc)::value, H = decltype(hf)::value, E = decltype(e)::value;
+          const size_t lds = (((size_t)g.Mz * W >> H) + g.Mz) * cs;
+          allow_lds(k_zpass<T, E, LC, H>, lds);
+          hipLaunchKernelGGL((k_zpass<T, E, LC, H>), dim3((g.My * nxt) << H, a.nrhs), dim3(kNT), lds, s, a.mask, B,
+                             be, static_cast<const cpx<T> *>(a.ghat), twz, a.pz, d);
+        };
+        with_len(g.Mz, [&](auto lc) {
           constexpr int LC = decltype(lc)::value;
-          constexpr int E = LC > 0 ? pick_ept_c((size_t)LC * W, false) : decltype(e)::value;
-          const size_t lds = ((size_t)g.Mz * W + g.Mz) * cs;
-          allow_lds(k_zpass<T, E, LC>, lds);
-          hipLaunchKernelGGL((k_zpass<T, E, LC>), dim3(g.My * nxt, a.nrhs), dim3(kNT), lds, s, a.mask, B, be,
-                             static_cast<const cpx<T> *>(a.ghat), twz, a.pz, d);
+          if constexpr (LC > 0) {
+            constexpr int H = LC * W > 2048 ? 1 : 0;
+            launch(IC<pick_ept_c((size_t)(LC * W) >> H, false)>{}, lc, IC<H>{});
+          } else if (half) {
+            with_ept<16>((size_t)g.Mz * W / 2, [&](auto e) { launch(e, lc, IC<1>{}); });
+          } else {
+            with_ept<8>((size_t)g.Mz * W, [&](auto e) { launch(e, lc, IC<0>{}); });
+          }
         });
-        break;
+      } break;
       case 3:
-        with_pass<false>(g.My, (size_t)g.My * W, [&](auto e, auto lc) {
+        with_pass<32>(g.My, (size_t)g.My * W, [&](auto e, auto lc) {
           constexpr int LC = decltype(lc)::value;
           constexpr int E = LC > 0 ? pick_ept_c((size_t)LC * W, false) : decltype(e)::value;
           const size_t lds = ((size_t)g.My * W + g.My) * cs;
@@ -599,7 +618,7 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
         });
         break;
       default:
-        with_pass<true>(g.Mx, (size_t)3 * nrows * g.Mx, [&](auto e, auto lc) {
+        with_pass<8>(g.Mx, (size_t)3 * nrows * g.Mx, [&](auto e, auto lc) {
           constexpr int LC = decltype(lc)::value;
           constexpr int E = LC > 0 ? pick_ept_c((size_t)3 * xpass_rows(LC) * LC, true) : decltype(e)::value;
           hipLaunchKernelGGL((k_xinv<T, E, LC>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s, a.in, a.out, n3,

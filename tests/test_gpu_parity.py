@@ -87,6 +87,16 @@ SMALL_TARGETS = [
     ("RCTGLPRSM", (1, 1, 13)),         # a line: degenerate x and y extents
     ("RCTGLPRSM", (23, 2, 1)),
     ("ELLIPSOID", (21, 17, 14.5)),     # several FFT tiles in x, ragged
+    # long axes: the run-time plan with half-tile z blocks (Mz = 150, 288) and
+    # large y blocks (My = 288), and the compile-time plan of length 256 on
+    # each axis (x, y and half-tile z)
+    ("RCTGLPRSM", (4, 3, 75)),
+    ("RCTGLPRSM", (3, 2, 140)),
+    ("RCTGLPRSM", (3, 140, 2)),
+    ("RCTGLPRSM", (140, 2, 3)),
+    ("RCTGLPRSM", (2, 2, 128)),
+    ("RCTGLPRSM", (2, 128, 2)),
+    ("RCTGLPRSM", (128, 2, 2)),
 ]
 
 
