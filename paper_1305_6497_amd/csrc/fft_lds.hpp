@@ -229,12 +229,32 @@ __device__ __forceinline__ int mul24(int a, int b) { return __mul24(a, b); }
 // Pen layout, one stage.  Butterfly b = j * NPEN + p reads buf[b + k * nbf],
 // nbf = (L / R) * NPEN; with j = q * Ns + jm its outputs go to
 // buf[b + q * Ns (R - 1) NPEN + k * Ns NPEN], which is the Stockham position
-// ((j - jm) R + jm + k Ns) * NPEN + p.
+// ((j - jm) R + jm + k Ns) * NPEN + p.  pen_butterfly does the twiddles, the
+// DFT and hands each output and its position to `put`.
+template <typename T, int R, int DIR, int LOGP, typename DN, typename Put>
+__device__ __forceinline__ void pen_butterfly(cpx<T> (&v)[R], int b, const cpx<T> *tw, int Ns, int twstep, DN nsd,
+                                              Put &&put) {
+  const int j = b >> LOGP;
+  const int q = (int)nsd((uint32_t)j);
+  if (Ns > 1) {
+    const int st = mul24(j - mul24(q, Ns), twstep);
+    int ti = st;
+#pragma unroll
+    for (int k = 1; k < R; ++k) {
+      v[k] = twmul<DIR>(v[k], tw[ti]);
+      ti += st;
+    }
+  }
+  dft_small<R, DIR>(v);
+  const int o = b + (mul24(q, mul24(Ns, R - 1)) << LOGP);
+  const int ostr = Ns << LOGP;
+#pragma unroll
+  for (int k = 0; k < R; ++k) put(o + k * ostr, v[k]);
+}
+
 template <typename T, int R, int NB, int DIR, int LOGP, typename DN>
 __device__ __forceinline__ void stage_pen(cpx<T> *buf, const cpx<T> *tw, int lr, int Ns, int twstep, DN nsd) {
   const int nbf = lr << LOGP;
-  const int ostr = Ns << LOGP;
-  const int jump = mul24(Ns, R - 1) << LOGP;
   cpx<T> v[NB][R];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
@@ -248,23 +268,7 @@ __device__ __forceinline__ void stage_pen(cpx<T> *buf, const cpx<T> *tw, int lr,
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int b = threadIdx.x + i * kNT;
-    if (b < nbf) {
-      const int j = b >> LOGP;
-      const int q = (int)nsd((uint32_t)j);
-      if (Ns > 1) {
-        const int st = mul24(j - mul24(q, Ns), twstep);
-        int ti = st;
-#pragma unroll
-        for (int k = 1; k < R; ++k) {
-          v[i][k] = twmul<DIR>(v[i][k], tw[ti]);
-          ti += st;
-        }
-      }
-      dft_small<R, DIR>(v[i]);
-      cpx<T> *dst = buf + b + mul24(q, jump);
-#pragma unroll
-      for (int k = 0; k < R; ++k) dst[k * ostr] = v[i][k];
-    }
+    if (b < nbf) pen_butterfly<T, R, DIR, LOGP>(v[i], b, tw, Ns, twstep, nsd, [&](int o, cpx<T> x) { buf[o] = x; });
   }
   __syncthreads();
 }
@@ -389,14 +393,70 @@ constexpr int pen_rmax(int L, int LOGP) {
 
 constexpr int cdiv_c(int a, int b) { return (a + b - 1) / b; }
 
-template <typename T, int DIR, int LOGP, int L, int S>
+template <typename T, int DIR, int LOGP, int L, int S, int SEND = 64>
 __device__ __forceinline__ void fft_pen_c(cpx<T> *buf, const cpx<T> *tw) {
   constexpr StaticPlan P = static_plan(L, pen_rmax(L, LOGP));
-  if constexpr (S < P.n) {
+  if constexpr (S < P.n && S < SEND) {
     constexpr int R = P.radix[S], Ns = P.ns[S];
     constexpr int NB = cdiv_c((L / R) << LOGP, kNT);
     stage_pen<T, R, NB, DIR, LOGP>(buf, tw, L / R, Ns, L / (Ns * R), ConstDiv<Ns>{});
-    fft_pen_c<T, DIR, LOGP, L, S + 1>(buf, tw);
+    fft_pen_c<T, DIR, LOGP, L, S + 1, SEND>(buf, tw);
+  }
+}
+
+// First and last stage of a compile-time pen plan, for transforms whose input
+// comes from (or whose output goes to) global memory directly.
+template <int L, int LOGP>
+struct PenEnds {
+  static constexpr StaticPlan P = static_plan(L, pen_rmax(L, LOGP));
+  static constexpr int R0 = P.radix[0];                  // first stage
+  static constexpr int NBF0 = (L / R0) << LOGP;          // its butterflies
+  static constexpr int NB0 = cdiv_c(NBF0, kNT);          // ... per thread
+  static constexpr int RL = P.radix[P.n - 1];            // last stage
+  static constexpr int NBFL = (L / RL) << LOGP;
+  static constexpr int NBL = cdiv_c(NBFL, kNT);
+};
+
+// Pen transform whose first-stage inputs are already in registers:
+// v[i][k] = element b + k * NBF0 of the buffer for butterfly b = tid + i kNT.
+// buf must be free on entry (no thread still reading it); on exit the result
+// is in buf and a barrier has been passed.
+template <typename T, int DIR, int LOGP, int L>
+__device__ __forceinline__ void fft_pen_from_regs(cpx<T> *buf, const cpx<T> *tw,
+                                                  cpx<T> (&v)[PenEnds<L, LOGP>::NB0][PenEnds<L, LOGP>::R0]) {
+  using E = PenEnds<L, LOGP>;
+#pragma unroll
+  for (int i = 0; i < E::NB0; ++i) {
+    const int b = threadIdx.x + i * kNT;
+    if (b < E::NBF0)
+      pen_butterfly<T, E::R0, DIR, LOGP>(v[i], b, tw, 1, 0, ConstDiv<1>{}, [&](int o, cpx<T> x) { buf[o] = x; });
+  }
+  __syncthreads();
+  fft_pen_c<T, DIR, LOGP, L, 1>(buf, tw);
+}
+
+// Pen transform of buf whose last-stage outputs go to put(e, value), e the
+// element index in the pen layout, instead of back to LDS.  Data must be
+// visible to all threads on entry; no barrier follows the last stage, so the
+// caller synchronises before writing buf again.
+template <typename T, int DIR, int LOGP, int L, typename Put>
+__device__ __forceinline__ void fft_pen_to_store(cpx<T> *buf, const cpx<T> *tw, Put &&put) {
+  using E = PenEnds<L, LOGP>;
+  constexpr int S = E::P.n - 1, R = E::RL, Ns = E::P.ns[S];
+  fft_pen_c<T, DIR, LOGP, L, 0, S>(buf, tw);
+  cpx<T> v[E::NBL][R];
+#pragma unroll
+  for (int i = 0; i < E::NBL; ++i) {
+    const int b = threadIdx.x + i * kNT;
+    if (b < E::NBFL) {
+#pragma unroll
+      for (int k = 0; k < R; ++k) v[i][k] = buf[b + k * E::NBFL];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < E::NBL; ++i) {
+    const int b = threadIdx.x + i * kNT;
+    if (b < E::NBFL) pen_butterfly<T, R, DIR, LOGP>(v[i], b, tw, Ns, L / (Ns * R), ConstDiv<Ns>{}, put);
   }
 }
 

@@ -256,41 +256,72 @@ __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx
   cpx<T> *tile = B + (size_t)r * b_elems + (((size_t)ky * d.nxt + xt) * 3) * d.nz * W + h * NP;
   // element e = m NP + p of the block is tile[m W + p] of its component
   auto toff = [&](int e) { return HALF ? ((e >> LOGP) << LOGW) + (e & (NP - 1)) : e; };
-  // two-slot ring: the rows of component c + 1 are in flight while c is transformed
-  cpx<T> pre[2][NL];
-  auto fetch = [&](int c, cpx<T>(&dst)[NL]) {
-#pragma unroll
-    for (int i = 0; i < NL; ++i) {
-      const int e = threadIdx.x + i * kNT;
-      dst[i] = e < nzP ? tile[c * nzW + toff(e)] : cpx<T>{0, 0};
-    }
-  };
-  fetch(0, pre[0]);
   cpx<T> a0[NQ], b0[NQ], a1[NQ], b1[NQ];
+  // forward spectra of components 0 and 1 -> registers (after the transform)
+  auto park = [&](int c) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * kNT;
-      if (e < n) buf[e] = (i < NL && e < nzP) ? pre[c & 1][i < NL ? i : 0] : cpx<T>{0, 0};
+    for (int i = 0; i < NQ; ++i) {
+      const int q = threadIdx.x + i * kNT;
+      if (q < nq) {
+        const int oz = q >> LOGP, p = q & (NP - 1);
+        const bool mir = oz != 0 && 2 * oz != Mz;
+        const cpx<T> va = buf[q];
+        const cpx<T> vb = mir ? buf[((Mz - oz) << LOGP) + p] : cpx<T>{0, 0};
+        if (c == 0) { a0[i] = va; b0[i] = vb; }
+        else { a1[i] = va; b1[i] = vb; }
+      }
     }
-    if (c < 2) fetch(c + 1, pre[(c + 1) & 1]);
     __syncthreads();
-    fft_pen<T, EPT, -1, LOGP, LC>(buf, tw, pz);
-    if (c < 2) {
+  };
+  if constexpr (LC > 0) {
+    // Compile-time plan: the nz data rows are loaded straight into the
+    // registers of the first stage (rows >= (Mz + 1) / 2 >= nz are known
+    // zeros), in a two-slot ring so component c + 1 is in flight while c is
+    // transformed.
+    using PE = PenEnds<LC, LOGP>;
+    constexpr int MB = (LC + 1) / 2;
+    cpx<T> pre[2][PE::NB0][PE::R0];
+    auto fetch = [&](int c, cpx<T>(&dst)[PE::NB0][PE::R0]) {
 #pragma unroll
-      for (int i = 0; i < NQ; ++i) {
-        const int q = threadIdx.x + i * kNT;
-        if (q < nq) {
-          const int oz = q >> LOGP, p = q & (NP - 1);
-          const bool mir = oz != 0 && 2 * oz != Mz;
-          const cpx<T> va = buf[q];
-          const cpx<T> vb = mir ? buf[((Mz - oz) << LOGP) + p] : cpx<T>{0, 0};
-          if (c == 0) { a0[i] = va; b0[i] = vb; }
-          else { a1[i] = va; b1[i] = vb; }
+      for (int i = 0; i < PE::NB0; ++i) {
+        const int b = threadIdx.x + i * kNT;
+#pragma unroll
+        for (int k = 0; k < PE::R0; ++k) {
+          const int e = b + k * PE::NBF0;
+          const bool live = k * (LC / PE::R0) < MB && b < PE::NBF0 && (e >> LOGP) < d.nz;
+          dst[i][k] = live ? tile[c * nzW + toff(e)] : cpx<T>{0, 0};
         }
       }
+    };
+    fetch(0, pre[0]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (c < 2) fetch(c + 1, pre[(c + 1) & 1]);
+      fft_pen_from_regs<T, -1, LOGP, LC>(buf, tw, pre[c & 1]);
+      if (c < 2) park(c);
+    }
+  } else {
+    // two-slot ring: the rows of component c + 1 are in flight while c is transformed
+    cpx<T> pre[2][NL];
+    auto fetch = [&](int c, cpx<T>(&dst)[NL]) {
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        const int e = threadIdx.x + i * kNT;
+        dst[i] = e < nzP ? tile[c * nzW + toff(e)] : cpx<T>{0, 0};
+      }
+    };
+    fetch(0, pre[0]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = threadIdx.x + i * kNT;
+        if (e < n) buf[e] = (i < NL && e < nzP) ? pre[c & 1][i < NL ? i : 0] : cpx<T>{0, 0};
+      }
+      if (c < 2) fetch(c + 1, pre[(c + 1) & 1]);
       __syncthreads();
+      fft_pen<T, EPT, -1, LOGP, LC>(buf, tw, pz);
+      if (c < 2) park(c);
     }
   }
   int sy;
@@ -346,9 +377,16 @@ __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx
       }
       __syncthreads();
     }
-    fft_pen<T, EPT, +1, LOGP, LC>(buf, tw, pz);
     cpx<T> *dst = tile + c * nzW;
-    for (int e = threadIdx.x; e < nzP; e += kNT) dst[toff(e)] = buf[e];
+    if constexpr (LC > 0) {
+      // the last stage writes the nz kept rows straight to global memory
+      fft_pen_to_store<T, +1, LOGP, LC>(buf, tw, [&](int e, cpx<T> v) {
+        if ((e >> LOGP) < d.nz) dst[toff(e)] = v;
+      });
+    } else {
+      fft_pen<T, EPT, +1, LOGP, LC>(buf, tw, pz);
+      for (int e = threadIdx.x; e < nzP; e += kNT) dst[toff(e)] = buf[e];
+    }
     __syncthreads();
   }
 }
