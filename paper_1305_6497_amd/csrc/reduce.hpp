@@ -39,15 +39,30 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *out) {
 }
 
 // Sum the NV-value records [0, nblk) of RHS r in block order.  All threads of
-// the block take part; the result is valid in thread 0.
+// the block take part; the result is valid in thread 0.  Each thread adds the
+// records tid, tid + NT, tid + 2 NT, ... in that order; the loads of U of them
+// are issued before the first add, so the (cross-XCD) load latency is paid
+// once per U records rather than once per record.
 template <int NV, int NT>
 __device__ __forceinline__ void sum_records(const double *partial, int nblk, int r, double *out) {
+  constexpr int U = 8;
   double v[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = 0.0;
-  for (int j = threadIdx.x; j < nblk; j += NT)
+  const double *base = partial + (size_t)r * nblk * kPart;
+  for (int j0 = 0; j0 < nblk; j0 += U * NT) {
+    double t[U][NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += partial[((size_t)r * nblk + j) * kPart + k];
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + threadIdx.x + u * NT;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) t[u][k] = j < nblk ? base[(size_t)j * kPart + k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) v[k] += t[u][k];
+  }
   block_sum<NV, NT>(v, out);
 }
 
