@@ -22,6 +22,28 @@
   not pass, r is replaced by the true residual and the recurrence restarts
   from the current x.  A breakdown (rho' or omega ~ 0) also restarts.
   The guide starts from P = 0 (§12); so does this oracle.
+* ``bicgstab_l``: BiCGstab(l) of Sleijpen & Fokkema (1993), cited in §12 as
+  the basis of the PBCGS2 option (l = 2), the option the guide recommends.
+  The guide does not print it; the steps below are the published method in
+  its notation (hat vectors r_0..r_l and u_0..u_l, shadow residual rt):
+
+      rho0 = 1, alpha = 0, omega = 1, u_0 = 0, r_0 = E - A x
+      repeat (one cycle = l BiCG steps, 2 l products, then one MR step):
+          rho0 = -omega rho0
+          for j = 0 .. l-1:
+              rho1 = <rt, r_j>;  beta = alpha rho1 / rho0;  rho0 = rho1
+              u_i = r_i - beta u_i            (i = 0 .. j)
+              u_{j+1} = A u_j;  alpha = rho0 / <rt, u_{j+1}>
+              r_i = r_i - alpha u_{i+1}       (i = 0 .. j)
+              r_{j+1} = A r_j;  x = x + alpha u_0
+          gamma = argmin |r_0 - sum_{j=1..l} gamma_j r_j|   (least squares)
+          x = x + sum_j gamma_j r_{j-1};  r_0 = r_0 - sum_j gamma_j r_j
+          u_0 = u_0 - sum_j gamma_j u_j;  omega = gamma_l
+
+  (the MR step is written as the least-squares problem it solves; the
+  published algorithm does it by Gram-Schmidt on r_1..r_l).  Same stopping
+  rule and restarts as ``bicgstab``; ``iters`` counts BiCG steps (l per
+  cycle), so one iteration is two products as in ``bicgstab``.
 """
 
 import numpy as np
@@ -97,6 +119,87 @@ def bicgstab(matvec, b, tol=1e-10, maxiter=10000, x0=None):
             if rel <= tol:
                 return x.reshape(shape), dict(iters=it, matvecs=nmv, rel_resid=rel, converged=True)
             r = rtrue
+            restart = True
+    rel = np.linalg.norm(b - mv(x)) / nb
+    return x.reshape(shape), dict(iters=it, matvecs=nmv + 1, rel_resid=rel, converged=rel <= tol)
+
+
+def bicgstab_l(matvec, b, ell=2, tol=1e-10, maxiter=10000, x0=None):
+    """BiCGstab(ell); returns (x, info) like ``bicgstab`` (iters = BiCG steps)."""
+    b = np.asarray(b, dtype=complex)
+    shape = b.shape
+    b = b.ravel()
+    mv = lambda v: np.asarray(matvec(v.reshape(shape)), dtype=complex).ravel()
+    nb = np.linalg.norm(b)
+    x = np.zeros_like(b) if x0 is None else np.asarray(x0, dtype=complex).ravel().copy()
+    nmv = 0
+    if nb == 0.0:
+        return x.reshape(shape), dict(iters=0, matvecs=0, rel_resid=0.0, converged=True)
+    if x0 is None:
+        res = b.copy()
+    else:
+        res = b - mv(x)
+        nmv += 1
+    it = 0
+    restart = True
+    while it < maxiter:
+        if restart:
+            rt = res.copy()
+            r = [res.copy()] + [np.zeros_like(b) for _ in range(ell)]
+            u = [np.zeros_like(b) for _ in range(ell + 1)]
+            rho0, alpha, omega = 1.0 + 0j, 0.0 + 0j, 1.0 + 0j
+            restart = False
+        rho0 = -omega * rho0
+        broke = False
+        for j in range(ell):
+            rho1 = np.vdot(rt, r[j])
+            if abs(rho0) == 0.0 or abs(rho1) < 1e-30 * nb * nb:
+                broke = True
+                break
+            beta = alpha * rho1 / rho0
+            rho0 = rho1
+            for i in range(j + 1):
+                u[i] = r[i] - beta * u[i]
+            u[j + 1] = mv(u[j])
+            nmv += 1
+            gam = np.vdot(rt, u[j + 1])
+            if gam == 0:
+                broke = True
+                break
+            alpha = rho0 / gam
+            for i in range(j + 1):
+                r[i] = r[i] - alpha * u[i + 1]
+            r[j + 1] = mv(r[j])
+            nmv += 1
+            x = x + alpha * u[0]
+        if broke:
+            # rho or <rt, u> vanished: stop if x already solves the system,
+            # else restart from the true residual (the cycle still counts)
+            res = b - mv(x)
+            nmv += 1
+            it += ell
+            rel = np.linalg.norm(res) / nb
+            if rel <= tol:
+                return x.reshape(shape), dict(iters=it, matvecs=nmv, rel_resid=rel, converged=True)
+            restart = True
+            continue
+        g = np.linalg.lstsq(np.column_stack(r[1:]), r[0], rcond=None)[0]
+        for jj in range(1, ell + 1):
+            x = x + g[jj - 1] * r[jj - 1]
+            r[0] = r[0] - g[jj - 1] * r[jj]
+            u[0] = u[0] - g[jj - 1] * u[jj]
+        omega = g[ell - 1]
+        it += ell
+        if abs(omega) < 1e-30:
+            restart = True
+            res = r[0]
+        if np.linalg.norm(r[0]) / nb <= tol:
+            rtrue = b - mv(x)
+            nmv += 1
+            rel = np.linalg.norm(rtrue) / nb
+            if rel <= tol:
+                return x.reshape(shape), dict(iters=it, matvecs=nmv, rel_resid=rel, converged=True)
+            res = rtrue
             restart = True
     rel = np.linalg.norm(b - mv(x)) / nb
     return x.reshape(shape), dict(iters=it, matvecs=nmv + 1, rel_resid=rel, converged=rel <= tol)

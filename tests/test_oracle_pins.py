@@ -276,6 +276,69 @@ def test_bicgstab_zero_rhs_and_maxiter():
     assert not info["converged"] and info["iters"] == 1
 
 
+def test_bicgstab2_matches_dense_lu():
+    # BiCGstab(2) converges to the exact (LU) solution of the DDA system
+    s = targets.ellipsoid(10, 8, 7)
+    kd, m = 0.5, 1.7 + 0.05j
+    khat, e = np.array([1.0, 0, 0]), np.array([0, 1.0, 0])
+    ai = pol.alpha_inv_ldr(m, kd, khat, e)
+    E = incident.incident_field(s, kd, khat, e)
+    A = interaction.dense_matrix(s, kd, ai)
+    P_lu = solvers.lu_solve(A, E.ravel()).reshape(-1, 3)
+    P_it, info = solvers.bicgstab_l(interaction.FFTOperator(s, kd, ai).matvec, E, ell=2, tol=1e-13)
+    assert info["converged"] and info["iters"] % 2 == 0
+    assert np.abs(P_lu - P_it).max() < 1e-11 * np.abs(P_lu).max()
+
+
+def test_bicgstab_ell1_is_bicgstab():
+    # BiCGstab(1) and BiCGSTAB generate the same iterates in exact arithmetic:
+    # after the same number of steps (no convergence) x agrees to rounding.
+    # A dropped term, a wrong sign of beta or a transposed inner product in
+    # either recurrence breaks this.
+    s = targets.ellipsoid(7, 6, 5)
+    kd, m = 0.6, 1.5 + 0.1j
+    khat, e = np.array([0.0, 0.0, 1.0]), np.array([1.0, 0, 0])
+    ai = pol.alpha_inv_ldr(m, kd, khat, e)
+    E = incident.incident_field(s, kd, khat, e)
+    op = interaction.FFTOperator(s, kd, ai)
+    for n in (1, 2, 5):
+        x1, i1 = solvers.bicgstab(op.matvec, E, tol=1e-30, maxiter=n)
+        x2, i2 = solvers.bicgstab_l(op.matvec, E, ell=1, tol=1e-30, maxiter=n)
+        assert i1["iters"] == i2["iters"] == n
+        assert np.abs(x1 - x2).max() < 1e-10 * np.abs(x1).max(), n
+
+
+def test_bicgstab2_minimal_residual_step():
+    # Each cycle ends with a minimal-residual step over the Krylov directions
+    # it built: the residual after two steps of BiCGstab(2) is no larger than
+    # after two steps of BiCGSTAB, whose second step minimizes over one
+    # direction only (both start from the same first BiCG step).
+    s = targets.ellipsoid(8, 8, 6)
+    kd, m = 0.7, 1.8 + 0.05j
+    khat, e = np.array([1.0, 0, 0]), np.array([0, 0, 1.0])
+    ai = pol.alpha_inv_ldr(m, kd, khat, e)
+    E = incident.incident_field(s, kd, khat, e)
+    op = interaction.FFTOperator(s, kd, ai)
+    x2, _ = solvers.bicgstab_l(op.matvec, E, ell=2, tol=1e-30, maxiter=2)
+    x1, _ = solvers.bicgstab(op.matvec, E, tol=1e-30, maxiter=2)
+    r2 = np.linalg.norm(E - op.matvec(x2))
+    r1 = np.linalg.norm(E - op.matvec(x1))
+    assert r2 < np.linalg.norm(E) and r2 <= 1.05 * r1
+
+
+def test_bicgstab2_zero_rhs_and_scaled_identity():
+    s = targets.sphere(5)
+    op = interaction.FFTOperator(s, 0.3, pol.alpha_inv_cmrr(1.5, 0.3))
+    x, info = solvers.bicgstab_l(op.matvec, np.zeros((len(s), 3)), tol=1e-8)
+    assert info["converged"] and np.all(x == 0)
+    # A = c I: the first BiCG step already solves it
+    c = 2.0 - 0.5j
+    E = incident.incident_field(s, 0.3, [1, 0, 0], [0, 1, 0])
+    x, info = solvers.bicgstab_l(lambda v: c * v, E, tol=1e-12)
+    assert info["converged"] and info["iters"] == 2
+    assert np.abs(x - E / c).max() < 1e-14 * np.abs(E / c).max()
+
+
 # ---------------------------------------------------------- cross sections --
 
 def _solve_small(s, kd, m, khat, e, kind="LATTDR"):
