@@ -66,6 +66,10 @@ extern "C" {
 #define DDA_MIXED 1           /* complex FP32 FFT product; FP64 Krylov vectors,
                                  inner products, residual refinement and sums */
 
+/* Krylov solvers (§12, "Choice of Iterative Algorithm") */
+#define DDA_SOLVER_BICGSTAB 0   /* BiCGSTAB, van der Vorst 1992 (the guide's PBCGST) */
+#define DDA_SOLVER_BICGSTAB2 1  /* BiCGstab(2), Sleijpen & Fokkema 1993 (the guide's PBCGS2) */
+
 /* Built-in target shapes (§21, SHPAR conventions of the guide). */
 #define DDA_SHAPE_ELLIPSOID 1 /* shpar = diameters along x, y, z (a sphere: all equal) */
 #define DDA_SHAPE_RCTGLPRSM 2 /* shpar = x, y, z extents in dipoles */
@@ -106,11 +110,16 @@ typedef struct {
   int32_t use_graph;       /* 1: the check_every iterations between host checks run as one
                               captured HIP graph on a stream of the handle (ordered after and
                               before the caller's stream); 0: kernels are launched directly */
+  int32_t solver;          /* DDA_SOLVER_BICGSTAB (the PBCGST option of §12) or
+                              DDA_SOLVER_BICGSTAB2 (BiCGstab(2), the PBCGS2 option the guide
+                              recommends, §12); with BiCGstab(2) check_every counts cycles
+                              of two BiCG steps */
 } dda_solve_opts;
 
 typedef struct {
   int32_t status;          /* 0 converged, 1 max_iter, 2 breakdown without recovery */
-  int32_t iters;           /* BiCGSTAB iterations */
+  int32_t iters;           /* BiCGSTAB iterations, or BiCG steps of BiCGstab(2) (two per
+                              cycle); either way two products per iteration */
   int32_t matvecs;         /* FFT products in the iteration precision */
   int32_t outer;           /* true-residual evaluations (FP64 products) */
   double rel_resid;        /* final true relative residual |E - A P| / |E| (FP64) */

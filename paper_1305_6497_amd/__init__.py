@@ -26,6 +26,7 @@ SHAPES = {"ELLIPSOID": L.DDA_SHAPE_ELLIPSOID, "RCTGLPRSM": L.DDA_SHAPE_RCTGLPRSM
           "CYLINDER1": L.DDA_SHAPE_CYLINDER1, "HEX_PRISM": L.DDA_SHAPE_HEX_PRISM}
 ALPHA = {"LATTDR": L.DDA_ALPHA_LDR, "LDR": L.DDA_ALPHA_LDR, "CMRR": L.DDA_ALPHA_CMRR,
          "FLTRCD": L.DDA_ALPHA_FCD, "FCD": L.DDA_ALPHA_FCD}
+SOLVER = {"bicgstab": 0, "bicgstab2": 1}
 PRECISION = {"fp64": L.DDA_FP64, "mixed": L.DDA_MIXED}
 
 
@@ -147,12 +148,16 @@ class Target:
         return torch.empty((nrhs, self.n, 3), dtype=torch.complex128, device=f"cuda:{self.device}")
 
     def solve(self, rhs, tol=1e-5, max_iter=1000, precision="fp64", inner_tol=0.0, max_outer=20, check_every=8,
-              out=None, stream=None, use_graph=False):
-        """Solve A P = E for every (khat, e) in rhs.  Returns (P, stats)."""
+              out=None, stream=None, use_graph=False, solver="bicgstab"):
+        """Solve A P = E for every (khat, e) in rhs.  Returns (P, stats).
+
+        solver: "bicgstab" (the guide's PBCGST) or "bicgstab2" (BiCGstab(2),
+        the guide's PBCGS2)."""
         nrhs = len(rhs)
         P = self._vec(nrhs) if out is None else out
         opts = L.SolveOpts(tol=tol, max_iter=max_iter, precision=PRECISION[precision], inner_tol=inner_tol,
-                           max_outer=max_outer, check_every=check_every, use_graph=int(bool(use_graph)))
+                           max_outer=max_outer, check_every=check_every, use_graph=int(bool(use_graph)),
+                           solver=SOLVER[solver])
         st = (L.SolveStats * nrhs)()
         code = L.check(self._lib.dda_solve(self._h, _rhs_array(rhs), nrhs, ctypes.byref(opts),
                                            ctypes.c_void_p(P.data_ptr()), None, _stream_ptr(stream), st),

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "dda_internal.hpp"
+#include "reduce.hpp"
 
 using namespace dda;
 
@@ -51,7 +52,7 @@ struct dda_target {
   hipEvent_t upload_done = nullptr;
   // captured block of BiCGSTAB iterations (see run_iterations)
   hipGraphExec_t graph = nullptr;
-  int graph_nrhs = 0, graph_prec = -1, graph_k = 0;
+  int graph_nrhs = 0, graph_prec = -1, graph_k = 0, graph_solver = -1;
   uint64_t graph_gen = 0;
   uint64_t buffer_gen = 0;        // bumped whenever workspaces are reallocated
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -185,7 +186,7 @@ size_t krylov_bytes(const Geometry &g, int nrhs) {
   const int64_t n3 = 3 * g.n_sites;
   const size_t vec = (size_t)n3 * sizeof(c64) * nrhs;
   const int nblk = std::max(krylov_blocks(n3), std::max(xpass_blocks(g, true), xpass_blocks(g, false)));
-  return 8 * vec + (size_t)nrhs * nblk * 4 * sizeof(double) + (size_t)nrhs * kScal * sizeof(c64) +
+  return 9 * vec + (size_t)nrhs * nblk * kPart * sizeof(double) + (size_t)nrhs * kScal * sizeof(c64) +
          4 * (size_t)nrhs * sizeof(int) + (size_t)nrhs * (sizeof(RhsDev) + 2 * sizeof(double)) +
          (size_t)nrhs * 255 * sizeof(c64);
 }
@@ -220,7 +221,7 @@ void ensure_krylov(dda_target *t, int nrhs, hipStream_t s) {
   DDA_HIP(hipStreamSynchronize(s));
   if (t->upload_done) DDA_HIP(hipEventSynchronize(t->upload_done));
   KrylovState &k = t->k;
-  for (c64 *p : {k.x, k.r, k.rh, k.p, k.v, k.s, k.t, k.b}) t->release(p);
+  for (c64 *p : {k.x, k.r, k.rh, k.p, k.v, k.s, k.t, k.b, k.u2}) t->release(p);
   t->release(k.partial);
   t->release(k.scal);
   t->release(k.active);
@@ -243,7 +244,8 @@ void ensure_krylov(dda_target *t, int nrhs, hipStream_t s) {
   k.s = t->alloc<c64>(vec);
   k.t = t->alloc<c64>(vec);
   k.b = t->alloc<c64>(vec);
-  k.partial = t->alloc<double>((size_t)nrhs * k.nrec * 4 * sizeof(double));
+  k.u2 = t->alloc<c64>(vec);
+  k.partial = t->alloc<double>((size_t)nrhs * k.nrec * kPart * sizeof(double));
   k.scal = t->alloc<c64>((size_t)nrhs * kScal * sizeof(c64));
   k.active = t->alloc<int>(nrhs * sizeof(int));
   k.status = t->alloc<int>(nrhs * sizeof(int));
@@ -355,16 +357,75 @@ void iteration(dda_target *t, int precision, hipStream_t s) {
   k_scalar_rho(k, s);
 }
 
-// K BiCGSTAB iterations on stream s.  With use_graph the block is captured
+// One BiCGstab(2) cycle (two BiCG steps and the minimal-residual step, four
+// products) for every active RHS: 25 kernels.  Vectors: r = r_0, s = r_1,
+// t = r_2, p = u_0, v = u_1, u2 = u_2, rh = the shadow residual rt.
+//   product 1: u0 = r0 - beta u0 (fused), u1 = A u0, <rt, u1>; alpha
+//   product 2: r0 -= alpha u1, x += alpha u0 (fused), r1 = A r0, <rt, r1>; beta
+//   product 3: u1 = r1 - beta u1, u0 = r0 - beta u0 (fused), u2 = A u1, <rt, u2>; alpha
+//   product 4: r1 -= alpha u2, r0 -= alpha u1, x += alpha u0 (fused), r2 = A r1,
+//              Gram sums of r0, r1, r2; g1, g2 = omega
+//   update:    x += g1 r0 + g2 r1, r0 -= g1 r1 + g2 r2, u0 -= g1 u1 + g2 u2 with
+//              <rt, r0>, |r0|^2; next beta and the convergence status.
+void cycle2(dda_target *t, int precision, hipStream_t s) {
+  KrylovState &k = t->k;
+  const int nrec = xpass_blocks(t->g, precision == DDA_MIXED);
+  FuseArgs f;
+  f.rh = k.rh;
+  f.scal = k.scal;
+  f.active = k.active;
+  f.status = k.status;
+  f.partial = k.partial;
+  f.in_mode = 3;
+  auto ax = [&](int i, c64 *d, const c64 *a, const c64 *b, int slot, int neg) {
+    f.ax_d[i] = d;
+    f.ax_a[i] = a;
+    f.ax_b[i] = b;
+    f.ax_slot[i] = slot;
+    f.ax_neg[i] = neg;
+  };
+  f.out_mode = 1;
+  f.nax = 1;
+  ax(0, k.p, k.r, k.p, S_BETA, 1);
+  matvec(t, precision, k.p, k.v, k.nrhs, k.active, s, nullptr, -1, 1, &f);
+  k_scalar_alpha(k, s, nrec);
+  f.nax = 2;
+  ax(0, k.r, k.r, k.v, S_ALPHA, 1);
+  ax(1, k.x, k.x, k.p, S_ALPHA, 0);
+  matvec(t, precision, k.r, k.s, k.nrhs, k.active, s, nullptr, -1, 1, &f);
+  k2_scalar_rho1(k, s, nrec);
+  f.nax = 2;
+  ax(0, k.v, k.s, k.v, S_BETA, 1);
+  ax(1, k.p, k.r, k.p, S_BETA, 1);
+  matvec(t, precision, k.v, k.u2, k.nrhs, k.active, s, nullptr, -1, 1, &f);
+  k_scalar_alpha(k, s, nrec);
+  f.nax = 3;
+  ax(0, k.s, k.s, k.u2, S_ALPHA, 1);
+  ax(1, k.r, k.r, k.v, S_ALPHA, 1);
+  ax(2, k.x, k.x, k.p, S_ALPHA, 0);
+  f.out_mode = 3;
+  f.r = k.r;
+  matvec(t, precision, k.s, k.t, k.nrhs, k.active, s, nullptr, -1, 1, &f);
+  k2_scalar_mr(k, s, nrec);
+  k2_update_mr(k, s);
+  k_scalar_rho(k, s, 2, -1.0);
+}
+
+void step(dda_target *t, int precision, int solver, hipStream_t s) {
+  if (solver == DDA_SOLVER_BICGSTAB2) cycle2(t, precision, s);
+  else iteration(t, precision, s);
+}
+
+// K BiCGSTAB iterations (or K BiCGstab(2) cycles) on stream s.  With use_graph the block is captured
 // once into a HIP graph on the handle's own stream (capture needs a non-null
 // stream) and replayed; events order it after the work already queued on s
 // and make s wait for it.  Every kernel reads its scalars and flags from
 // device memory, so one captured block serves every replay; the graph is
 // captured again when the block shape or the buffers change.  The captured
 // kernels contain no memset nodes.
-void run_iterations(dda_target *t, int precision, int K, bool use_graph, hipStream_t s) {
+void run_iterations(dda_target *t, int precision, int solver, int K, bool use_graph, hipStream_t s) {
   if (!use_graph) {
-    for (int it = 0; it < K; ++it) iteration(t, precision, s);
+    for (int it = 0; it < K; ++it) step(t, precision, solver, s);
     return;
   }
   if (!t->ev_in) {
@@ -372,7 +433,7 @@ void run_iterations(dda_target *t, int precision, int K, bool use_graph, hipStre
     DDA_HIP(hipEventCreateWithFlags(&t->ev_out, hipEventDisableTiming));
   }
   if (!t->graph || t->graph_nrhs != t->k.nrhs || t->graph_prec != precision || t->graph_k != K ||
-      t->graph_gen != t->buffer_gen) {
+      t->graph_solver != solver || t->graph_gen != t->buffer_gen) {
     if (t->graph) {
       DDA_HIP(hipGraphExecDestroy(t->graph));
       t->graph = nullptr;
@@ -380,7 +441,7 @@ void run_iterations(dda_target *t, int precision, int K, bool use_graph, hipStre
     hipGraph_t g = nullptr;
     DDA_HIP(hipStreamBeginCapture(t->stream, hipStreamCaptureModeThreadLocal));
     try {
-      for (int it = 0; it < K; ++it) iteration(t, precision, t->stream);
+      for (int it = 0; it < K; ++it) step(t, precision, solver, t->stream);
     } catch (...) {
       (void)hipStreamEndCapture(t->stream, &g);
       if (g) (void)hipGraphDestroy(g);
@@ -392,6 +453,7 @@ void run_iterations(dda_target *t, int precision, int K, bool use_graph, hipStre
     DDA_HIP(e);
     t->graph_nrhs = t->k.nrhs;
     t->graph_prec = precision;
+    t->graph_solver = solver;
     t->graph_k = K;
     t->graph_gen = t->buffer_gen;
   }
@@ -637,6 +699,7 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     DDA_REQUIRE(opts->max_iter >= 1, "max_iter must be >= 1");
     DDA_REQUIRE(opts->precision == DDA_FP64 || opts->precision == DDA_MIXED, "unknown precision");
     DDA_REQUIRE(opts->inner_tol >= 0.0 && opts->inner_tol < 1.0, "inner_tol must be in [0, 1)");
+    DDA_REQUIRE(opts->solver == DDA_SOLVER_BICGSTAB || opts->solver == DDA_SOLVER_BICGSTAB2, "unknown solver");
     DDA_HIP(hipSetDevice(t->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int K = opts->check_every > 0 ? opts->check_every : 8;
@@ -700,7 +763,7 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
         }
       }
       if (!any_run) break;
-      run_iterations(t, opts->precision, K, opts->use_graph != 0, s);
+      run_iterations(t, opts->precision, opts->solver, K, opts->use_graph != 0, s);
     }
     DDA_HIP(hipMemcpyAsync(scal.data(), k.scal, scal.size() * sizeof(c64), hipMemcpyDeviceToHost, s));
     const size_t vec = (size_t)k.n3 * nrhs * sizeof(c64);

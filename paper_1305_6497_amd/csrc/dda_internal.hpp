@@ -142,14 +142,23 @@ struct FuseArgs {
   int in_mode = 0;     // 0: transform `in` as given
                        // 1: form p = r + beta (p - omega v), store it in w (= p), transform it
                        // 2: form s = r - alpha v, store it in w (= s), transform it
+                       // 3: nax element-wise updates d_i = a_i + c_i b_i, c_i = (-1)^neg_i scal[slot_i];
+                       //    d_0 is transformed (it must be `in`)
   int out_mode = 0;    // 0: nothing
                        // 1: per-block partial sums of <rh, out>
                        // 2: per-block partial sums of <out, in> and <out, out>
+                       // 3: per-block Gram sums of in = r1, out = r2 and r = r0:
+                       //    <r1,r1>, <r2,r2>, <r1,r2>, <r1,r0>, <r2,r0>
   const c64 *r = nullptr, *v = nullptr, *rh = nullptr;
   c64 *w = nullptr;
   c64 *scal = nullptr;
   int *active = nullptr, *status = nullptr;
-  double *partial = nullptr;      // [nrhs][x-pass blocks][4]
+  double *partial = nullptr;      // [nrhs][x-pass blocks][kPart]
+  int nax = 0;
+  c64 *ax_d[3] = {nullptr, nullptr, nullptr};
+  const c64 *ax_a[3] = {nullptr, nullptr, nullptr}, *ax_b[3] = {nullptr, nullptr, nullptr};
+  int ax_slot[3] = {0, 0, 0};
+  int ax_neg[3] = {0, 0, 0};
 };
 
 // Convolution + diagonal:  out_r = ainv_r[comp] * in_r - (G * in_r)   (r < nrhs)
@@ -200,9 +209,11 @@ void launch_fft_rows(const cpx<T> *in, cpx<T> *out, int64_t batch, const AxisPla
 struct KrylovState {
   int nrhs = 0;
   int64_t n3 = 0;                 // 3N complex entries per RHS
+  // BiCGSTAB: x, r, rh (shadow), p, v, s, t; b = E.  BiCGstab(2) uses
+  // x, r = r_0, rh = shadow, p = u_0, v = u_1, u2 = u_2, s = r_1, t = r_2.
   c64 *x = nullptr, *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *s = nullptr,
-      *t = nullptr, *b = nullptr;
-  double *partial = nullptr;      // [nrhs][nblk][4]
+      *t = nullptr, *b = nullptr, *u2 = nullptr;
+  double *partial = nullptr;      // [nrhs][nrec][kPart]
   c64 *scal = nullptr;            // [nrhs][kScal]
   int *active = nullptr;          // [nrhs]
   int *status = nullptr;          // [nrhs]
@@ -212,7 +223,11 @@ struct KrylovState {
 };
 
 // scalar slots per RHS
-enum : int { S_RHO = 0, S_ALPHA, S_OMEGA, S_BETA, S_RNORM2, S_BNORM2, S_THR2, S_ITERS, S_MAXIT, S_RH2, S_TRUE2, kScal };
+enum : int {
+  S_RHO = 0, S_ALPHA, S_OMEGA, S_BETA, S_RNORM2, S_BNORM2, S_THR2, S_ITERS, S_MAXIT, S_RH2, S_TRUE2,
+  S_G1,                           // BiCGstab(2): first minimal-residual coefficient (the second is omega)
+  kScal
+};
 
 // status values kept on the device
 enum : int { ST_RUN = 0, ST_CONV = 1, ST_BREAK = 2, ST_MAXIT = 3, ST_DONE = 4, ST_IDLE = 5 };
@@ -226,7 +241,12 @@ void k_update_s(const KrylovState &k, hipStream_t s);
 void k_dot_ts(const KrylovState &k, hipStream_t s);
 void k_scalar_omega(const KrylovState &k, hipStream_t s, int nrec);
 void k_update_xr(const KrylovState &k, hipStream_t s);
-void k_scalar_rho(const KrylovState &k, hipStream_t s);
+// step = 1, bsign = +1: BiCGSTAB; step = 2, bsign = -1: end of a BiCGstab(2) cycle
+void k_scalar_rho(const KrylovState &k, hipStream_t s, int step = 1, double bsign = 1.0);
+// BiCGstab(2): second BiCG step's beta, minimal-residual coefficients, closing update
+void k2_scalar_rho1(const KrylovState &k, hipStream_t s, int nrec);
+void k2_scalar_mr(const KrylovState &k, hipStream_t s, int nrec);
+void k2_update_mr(const KrylovState &k, hipStream_t s);
 
 // r_true = b - Ax (Ax given in `ax`) for RHS with check[r]; writes norms into partial/scal.
 void k_true_residual(const KrylovState &k, const c64 *ax, hipStream_t s);

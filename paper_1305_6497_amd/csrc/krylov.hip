@@ -6,6 +6,12 @@
 //     rho' = <rh, r>;  beta = (rho'/rho)(alpha/omega);  p = r + beta (p - omega v)
 //     v = A p;  alpha = rho' / <rh, v>;  s = r - alpha v
 //     t = A s;  omega = <t, s> / <t, t>;  x += alpha p + omega s;  r = s - omega t
+// BiCGstab(2) (Sleijpen & Fokkema 1993; the PBCGS2 option the guide
+// recommends, §12) runs on the same product kernels: the u/r updates of its
+// BiCG steps are fused into the x-forward pass (update lists), <rt, .> and
+// the Gram sums of its minimal-residual step into the x-inverse pass; the
+// kernels here do its scalar recurrences and the closing update
+//     x += g1 r0 + g2 r1;  r0 -= g1 r1 + g2 r2;  u0 -= g1 u1 + g2 u2.
 // Every RHS of a block carries its own scalars on the device, so a block of
 // iterations can be queued without host round trips: each kernel returns
 // early for an RHS whose `active` flag is cleared, and the scalar kernels
@@ -207,7 +213,11 @@ __global__ void kk_update_xr(const int *active, c64 *x, c64 *rr, const c64 *rh, 
   }
 }
 
-__global__ void kk_scalar_rho(const double *partial, int nblk, c64 *scal, int *active, int *status) {
+// End of a BiCGSTAB iteration (step = 1, bsign = +1) or of a BiCGstab(2)
+// cycle (step = 2, bsign = -1: rho0 is first replaced by -omega rho0, so
+// beta = alpha rho1 / (-omega rho0)).
+__global__ void kk_scalar_rho(const double *partial, int nblk, c64 *scal, int *active, int *status, int step,
+                              double bsign) {
   const int r = blockIdx.x;
   if (!active[r]) return;
   double s[3];
@@ -217,7 +227,7 @@ __global__ void kk_scalar_rho(const double *partial, int nblk, c64 *scal, int *a
     const c64 rho_new = {s[0], s[1]};
     const double rn2 = s[2];
     sc[S_RNORM2] = {rn2, 0.0};
-    sc[S_ITERS].x += 1.0;
+    sc[S_ITERS].x += double(step);
     const c64 omega = sc[S_OMEGA];
     if (!(rn2 == rn2)) {                                     // NaN
       active[r] = 0;
@@ -232,7 +242,7 @@ __global__ void kk_scalar_rho(const double *partial, int nblk, c64 *scal, int *a
       active[r] = 0;
       status[r] = ST_BREAK;
     } else {
-      sc[S_BETA] = cdiv(rho_new, sc[S_RHO]) * cdiv(sc[S_ALPHA], omega);
+      sc[S_BETA] = bsign * (cdiv(rho_new, sc[S_RHO]) * cdiv(sc[S_ALPHA], omega));
       sc[S_RHO] = rho_new;
     }
   }
@@ -295,6 +305,84 @@ __global__ void kk_restart_scalars(const int *restart, c64 *scal, int *active, i
   status[r] = ST_RUN;
 }
 
+// ------------------------------------------------------------- BiCGstab(2) --
+// Second BiCG step of a cycle: rho1 = <rt, r1> (records of the product that
+// made r1); beta = alpha rho1 / rho0; rho0 = rho1.
+__global__ void kk2_scalar_rho1(const double *partial, int nblk, c64 *scal, int *active, int *status) {
+  const int r = blockIdx.x;
+  if (!active[r]) return;
+  double s[2];
+  sum_partials<2>(partial, nblk, r, s);
+  if (threadIdx.x == 0) {
+    c64 *sc = scal + (size_t)r * kScal;
+    const c64 rho1 = {s[0], s[1]};
+    if (!(cabs2(rho1) > 1e-60 * sc[S_RH2].x * sc[S_RNORM2].x) || !(cabs2(sc[S_RHO]) > 0.0)) {
+      active[r] = 0;
+      status[r] = ST_BREAK;
+    } else {
+      sc[S_BETA] = sc[S_ALPHA] * cdiv(rho1, sc[S_RHO]);
+      sc[S_RHO] = rho1;
+    }
+  }
+}
+
+// Minimal-residual step: with the Gram sums <r1,r1>, <r2,r2>, <r1,r2>,
+// <r1,r0>, <r2,r0> (Hermitian products), solve the 2x2 normal equations of
+// min |r0 - g1 r1 - g2 r2|.  omega = g2.
+__global__ void kk2_scalar_mr(const double *partial, int nblk, c64 *scal, int *active, int *status) {
+  const int r = blockIdx.x;
+  if (!active[r]) return;
+  double s[8];
+  sum_partials<8>(partial, nblk, r, s);
+  if (threadIdx.x == 0) {
+    c64 *sc = scal + (size_t)r * kScal;
+    const double r11 = s[0], r22 = s[1];
+    const c64 r12 = {s[2], s[3]}, c1 = {s[4], s[5]}, c2 = {s[6], s[7]};
+    const double det = r11 * r22 - cabs2(r12);
+    if (!(det > 1e-14 * r11 * r22) || !(r11 > 0.0)) {
+      active[r] = 0;
+      status[r] = ST_BREAK;
+    } else {
+      const double id = 1.0 / det;
+      const c64 g1 = id * (r22 * c1 - r12 * c2);
+      const c64 g2 = id * (r11 * c2 - conj(r12) * c1);
+      sc[S_G1] = g1;
+      sc[S_OMEGA] = g2;
+    }
+  }
+}
+
+// x += g1 r0 + g2 r1;  r0 -= g1 r1 + g2 r2;  u0 -= g1 u1 + g2 u2;
+// partials <rt, r0>, |r0|^2 of the new r0.
+__global__ void kk2_update_mr(const int *active, c64 *x, c64 *r0, const c64 *r1, const c64 *r2, c64 *u0,
+                              const c64 *u1, const c64 *u2, const c64 *rt, const c64 *scal, int64_t n3,
+                              double *partial, int nblk) {
+  RHS_PREAMBLE
+  const c64 g1 = scal[(size_t)r * kScal + S_G1];
+  const c64 g2 = scal[(size_t)r * kScal + S_OMEGA];
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT) {
+    const size_t j = off + i;
+    const c64 a0 = r0[j], a1 = r1[j], a2 = r2[j];
+    x[j] = x[j] + g1 * a0 + g2 * a1;
+    const c64 rn = a0 - g1 * a1 - g2 * a2;
+    r0[j] = rn;
+    u0[j] = u0[j] - g1 * u1[j] - g2 * u2[j];
+    const c64 d = cmulc(rt[j], rn);
+    acc[0] += d.x;
+    acc[1] += d.y;
+    acc[2] += rn.x * rn.x + rn.y * rn.y;
+  }
+  double out[3];
+  block_sum<3>(acc, out);
+  if (threadIdx.x == 0) {
+    double *o = partial + ((size_t)r * nblk + blockIdx.x) * kPart;
+    o[0] = out[0];
+    o[1] = out[1];
+    o[2] = out[2];
+  }
+}
+
 // ------------------------------------------------------------- host wrappers --
 static dim3 vgrid(const KrylovState &k) { return dim3(k.nblk, k.nrhs); }
 
@@ -326,8 +414,19 @@ void k_update_xr(const KrylovState &k, hipStream_t s) {
   hipLaunchKernelGGL(kk_update_xr, vgrid(k), dim3(KNT), 0, s, k.active, k.x, k.r, k.rh, k.p, k.s, k.t, k.scal, k.n3,
                      k.partial, k.nblk);
 }
-void k_scalar_rho(const KrylovState &k, hipStream_t s) {
-  hipLaunchKernelGGL(kk_scalar_rho, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, k.nblk, k.scal, k.active, k.status);
+void k_scalar_rho(const KrylovState &k, hipStream_t s, int step, double bsign) {
+  hipLaunchKernelGGL(kk_scalar_rho, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, k.nblk, k.scal, k.active, k.status,
+                     step, bsign);
+}
+void k2_scalar_rho1(const KrylovState &k, hipStream_t s, int nrec) {
+  hipLaunchKernelGGL(kk2_scalar_rho1, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, nrec, k.scal, k.active, k.status);
+}
+void k2_scalar_mr(const KrylovState &k, hipStream_t s, int nrec) {
+  hipLaunchKernelGGL(kk2_scalar_mr, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, nrec, k.scal, k.active, k.status);
+}
+void k2_update_mr(const KrylovState &k, hipStream_t s) {
+  hipLaunchKernelGGL(kk2_update_mr, vgrid(k), dim3(KNT), 0, s, k.active, k.x, k.r, k.s, k.t, k.p, k.v, k.u2, k.rh,
+                     k.scal, k.n3, k.partial, k.nblk);
 }
 void k_true_residual(const KrylovState &k, const c64 *ax, hipStream_t s) {
   hipLaunchKernelGGL(kk_true_residual, vgrid(k), dim3(KNT), 0, s, k.check, k.b, ax, k.r, k.n3, k.partial, k.nblk);

@@ -132,6 +132,29 @@ __global__ __launch_bounds__(kNT) void k_xfwd(const c64 *__restrict__ in, int64_
     for (int i = 0; i < NE; ++i)
 #pragma unroll
       for (int c = 0; c < 3; ++c) v[i][c] = site[i] >= 0 ? in[off + (size_t)3 * site[i] + c] : c64{0, 0};
+  } else if (f.in_mode == 3) {
+    // update list d_i = a_i + c_i b_i; d_0 is transformed
+    const c64 *sc = f.scal + (size_t)r * kScal;
+    c64 cf[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const c64 g = a < f.nax ? sc[f.ax_slot[a]] : c64{0, 0};
+      cf[a] = f.ax_neg[a] ? c64{-g.x, -g.y} : g;
+    }
+#pragma unroll
+    for (int i = 0; i < NE; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        c64 val = {0, 0};
+        if (site[i] >= 0) {
+          const size_t j = off + (size_t)3 * site[i] + c;
+          val = f.ax_a[0][j] + cf[0] * f.ax_b[0][j];
+          f.ax_d[0][j] = val;
+          if (f.nax > 1) f.ax_d[1][j] = f.ax_a[1][j] + cf[1] * f.ax_b[1][j];
+          if (f.nax > 2) f.ax_d[2][j] = f.ax_a[2][j] + cf[2] * f.ax_b[2][j];
+        }
+        v[i][c] = val;
+      }
   } else {
     const c64 *sc = f.scal + (size_t)r * kScal;
     const c64 beta = sc[S_BETA], omega = sc[S_OMEGA], alpha = sc[S_ALPHA];
@@ -473,7 +496,7 @@ __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *_
   for (int i = 0; i < NE; ++i)
 #pragma unroll
     for (int c = 0; c < 3; ++c) pv[i][c] = site[i] >= 0 ? in[off + (size_t)3 * site[i] + c] : c64{0, 0};
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < NE; ++i) {
     if (site[i] >= 0) {
@@ -494,14 +517,35 @@ __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *_
           acc[0] += g.x;
           acc[1] += g.y;
           acc[2] += o.x * o.x + o.y * o.y;
+        } else if (f.out_mode == 3) {
+          // in = r1, out = r2, f.r = r0
+          const c64 r1 = pv[i][c], r0 = f.r[j];
+          const c64 g12 = cmulc(r1, o), g10 = cmulc(r1, r0), g20 = cmulc(o, r0);
+          acc[0] += r1.x * r1.x + r1.y * r1.y;
+          acc[1] += o.x * o.x + o.y * o.y;
+          acc[2] += g12.x;
+          acc[3] += g12.y;
+          acc[4] += g10.x;
+          acc[5] += g10.y;
+          acc[6] += g20.x;
+          acc[7] += g20.y;
         }
       }
     }
   }
-  if (f.out_mode != 0) {
+  if (f.out_mode == 3) {
     // one partial record per block; a one-block kernel adds them in block order
+    double tot[8];
+    block_sum<8, kNT>(acc, tot);
+    if (threadIdx.x == 0) {
+      double *o = f.partial + ((size_t)r * gridDim.x + blockIdx.x) * kPart;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) o[k] = tot[k];
+    }
+  } else if (f.out_mode != 0) {
+    double a3[3] = {acc[0], acc[1], acc[2]};
     double tot[3];
-    block_sum<3, kNT>(acc, tot);
+    block_sum<3, kNT>(a3, tot);
     if (threadIdx.x == 0) {
       double *o = f.partial + ((size_t)r * gridDim.x + blockIdx.x) * kPart;
       o[0] = tot[0];

@@ -12,7 +12,7 @@
 
 namespace dda {
 
-constexpr int kPart = 4;          // doubles per partial-sum record
+constexpr int kPart = 8;          // doubles per partial-sum record
 
 // Sum NV values over the block (wavefront shuffles, then across wavefronts).
 // The result is valid in thread 0.  Contains a barrier.

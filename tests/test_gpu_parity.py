@@ -147,9 +147,10 @@ def test_incident_field(dda):
 
 
 # ------------------------------------------------------------------ solves --
+@pytest.mark.parametrize("solver", ["bicgstab", "bicgstab2"])
 @pytest.mark.parametrize("m,alpha", [(1.33 + 0.01j, "LATTDR"), (1.7 + 0.3j, "LATTDR"), (2.5 + 0.5j, "CMRR"),
                                      (1.5 + 0.0j, "FLTRCD")])
-def test_solve_matches_dense_lu(dda, m, alpha):
+def test_solve_matches_dense_lu(dda, m, alpha, solver):
     shpar = (9.5, 8.0, 6.5)
     sites, box = dda.make_sites("ELLIPSOID", shpar)
     osites = targets.ellipsoid(*shpar)
@@ -157,7 +158,7 @@ def test_solve_matches_dense_lu(dda, m, alpha):
     b, th, ph = inputs.orientation_angles(1, seed=3)
     rhs = [dda.orient_rhs(b[0], th[0], ph[0], which=1), dda.orient_rhs(b[0], th[0], ph[0], which=2)]
     t = dda.Target(sites, box, m=m, kd=kd, alpha=alpha)
-    P, stats = t.solve(rhs, tol=1e-11, precision="fp64", max_iter=2000)
+    P, stats = t.solve(rhs, tol=1e-11, precision="fp64", max_iter=2000, solver=solver)
     q = t.cross_sections(rhs, P)
     Pg = P.cpu().numpy()
     t.close()
@@ -173,13 +174,14 @@ def test_solve_matches_dense_lu(dda, m, alpha):
             assert abs(q[r][key] - qo[key]) <= 1e-9 * qo["qext"], key
 
 
-def test_solve_mixed_reaches_fp64_tolerance(dda):
+@pytest.mark.parametrize("solver", ["bicgstab", "bicgstab2"])
+def test_solve_mixed_reaches_fp64_tolerance(dda, solver):
     sites, box = dda.make_sites("RCTGLPRSM", (16, 12, 10))
     osites = targets.rctglprsm(16, 12, 10)
     kd, m = 0.35, 1.5 + 0.1j
     rhs = [dda.orient_rhs(0, 0, 0, which=1)]
     t = dda.Target(sites, box, m=m, kd=kd)
-    P, st = t.solve(rhs, tol=1e-8, precision="mixed")
+    P, st = t.solve(rhs, tol=1e-8, precision="mixed", solver=solver)
     Pg = P.cpu().numpy()[0]
     t.close()
     assert st[0]["status"] == 0
@@ -189,17 +191,18 @@ def test_solve_mixed_reaches_fp64_tolerance(dda):
     assert res <= 1e-8
 
 
-def test_batched_block_equals_single_solves_bitwise(dda):
+@pytest.mark.parametrize("solver", ["bicgstab", "bicgstab2"])
+def test_batched_block_equals_single_solves_bitwise(dda, solver):
     sites, box = dda.make_sites("ELLIPSOID", (14, 10, 8))
     kd, m = 0.4, 1.7 + 0.05j
     b, th, ph = inputs.orientation_angles(3, seed=4)
     rhs = [dda.orient_rhs(b[i], th[i], ph[i], which=1 + (i % 2)) for i in range(3)]
     t = dda.Target(sites, box, m=m, kd=kd)
     for prec in ("fp64", "mixed"):
-        Pb, sb = t.solve(rhs, tol=1e-7, precision=prec)
+        Pb, sb = t.solve(rhs, tol=1e-7, precision=prec, solver=solver)
         Pb = Pb.cpu().numpy()
         for i in range(3):
-            Ps, ss = t.solve([rhs[i]], tol=1e-7, precision=prec)
+            Ps, ss = t.solve([rhs[i]], tol=1e-7, precision=prec, solver=solver)
             assert np.array_equal(Ps.cpu().numpy()[0], Pb[i]), (prec, i)
             assert ss[0]["iters"] == sb[i]["iters"]
     t.close()
@@ -221,6 +224,8 @@ def test_not_converged_and_zero_rhs(dda):
     rhs = [dda.orient_rhs(0, 0, 0)]
     P, st = t.solve(rhs, tol=1e-12, max_iter=1, max_outer=1)
     assert st[0]["status"] == 1 and st[0]["iters"] == 1
+    P, st = t.solve(rhs, tol=1e-12, max_iter=2, max_outer=1, solver="bicgstab2")
+    assert st[0]["status"] == 1 and st[0]["iters"] == 2 and st[0]["matvecs"] == 4
     with pytest.raises(dda.DDAError):
         t.solve([(np.array([1.0, 0, 0]), np.array([1.0, 0, 0]))])      # khat . e != 0
     with pytest.raises(dda.DDAError):
@@ -291,7 +296,8 @@ def test_sphere_d20_fp64_solve_against_oracle(dda):
             assert abs(q[r][key] - qo[key]) <= 1e-5 * abs(qo[key]), (key, q[r][key], qo[key])
 
 
-def test_graph_replay_matches_eager_bitwise(dda):
+@pytest.mark.parametrize("solver", ["bicgstab", "bicgstab2"])
+def test_graph_replay_matches_eager_bitwise(dda, solver):
     # The iteration block is captured once and replayed several times per
     # solve (host checks between replays); each solve also replays the graph
     # captured by the previous one.  Every result must equal the eager path.
@@ -300,9 +306,9 @@ def test_graph_replay_matches_eager_bitwise(dda):
     b, th, ph = inputs.orientation_angles(2, seed=8)
     rhs = [dda.orient_rhs(b[i], th[i], ph[i], which=1 + i) for i in range(2)]
     for prec in ("fp64", "mixed"):
-        ref, sr = t.solve(rhs, tol=1e-9, precision=prec, use_graph=False, check_every=3)
+        ref, sr = t.solve(rhs, tol=1e-9, precision=prec, use_graph=False, check_every=3, solver=solver)
         for rep in range(3):
-            got, sg = t.solve(rhs, tol=1e-9, precision=prec, use_graph=True, check_every=3)
+            got, sg = t.solve(rhs, tol=1e-9, precision=prec, use_graph=True, check_every=3, solver=solver)
             assert torch.equal(got, ref), (prec, rep)
             assert [s["iters"] for s in sg] == [s["iters"] for s in sr]
         assert all(s["iters"] > 6 for s in sr)          # several replays per solve
@@ -316,9 +322,10 @@ def test_graph_replay_matches_eager_bitwise(dda):
 # 1e-9, the efficiencies differ from the stored ones by O(1e-9) times the
 # conditioning of Q in P; block_64 solved to 1e-5 already agrees to 4e-6, so
 # 1e-7 of Q_ext leaves a margin of two orders of magnitude.
+@pytest.mark.parametrize("solver", ["bicgstab", "bicgstab2"])
 @pytest.mark.parametrize("name", ["au_block_16x32x32", "block_64", "ellipsoid_96x64x48"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_full_size_efficiencies_against_oracle(dda, name, prec):
+def test_full_size_efficiencies_against_oracle(dda, name, prec, solver):
     import json
     import os
     with open(os.path.join(os.path.dirname(__file__), "golden", f"reference_{name}.json")) as f:
@@ -330,10 +337,33 @@ def test_full_size_efficiencies_against_oracle(dda, name, prec):
     assert abs(kd - ref["kd"]) <= 1e-15 * kd
     rhs = [(np.array(r["khat"]), np.array(r["e_re"]) + 1j * np.array(r["e_im"])) for r in ref["results"]]
     t = dda.Target(sites, box, m=w["m"], kd=kd)
-    P, st = t.solve(rhs, tol=1e-9, precision=prec, max_iter=5000)
+    P, st = t.solve(rhs, tol=1e-9, precision=prec, max_iter=5000, solver=solver)
     q = t.cross_sections(rhs, P)
     t.close()
     for i, r in enumerate(ref["results"]):
         assert st[i]["status"] == 0 and st[i]["rel_resid"] <= 1e-9, (i, st[i])
         for key in ("qext", "qabs", "qsca"):
             assert abs(q[i][key] - r[key]) <= 1e-7 * abs(r["qext"]), (name, prec, i, key, q[i][key], r[key])
+
+
+def test_bicgstab2_follows_the_oracle_recurrence(dda):
+    # Same algorithm, same FP64 arithmetic up to rounding order (and the
+    # normal equations of the 2x2 minimal-residual step instead of a QR): the
+    # GPU needs the same number of BiCG steps as the oracle's BiCGstab(2), up
+    # to one cycle, and reaches the same solution.
+    shpar = (13, 11, 9)
+    sites, box = dda.make_sites("ELLIPSOID", shpar)
+    osites = targets.ellipsoid(*shpar)
+    kd, m = 0.55, 1.6 + 0.02j
+    rhs = [dda.orient_rhs(0.4, 0.9, 1.3, which=1)]
+    t = dda.Target(sites, box, m=m, kd=kd)
+    P, st = t.solve(rhs, tol=1e-8, precision="fp64", solver="bicgstab2", check_every=1)
+    Pg = P.cpu().numpy()[0]
+    t.close()
+    ai = _oracle_ainv(m, kd, *rhs[0])
+    E = incident.incident_field(osites, kd, *rhs[0])
+    op = interaction.FFTOperator(osites, kd, ai)
+    Po, info = solvers.bicgstab_l(op.matvec, E, ell=2, tol=1e-8)
+    assert st[0]["status"] == 0 and info["converged"]
+    assert abs(st[0]["iters"] - info["iters"]) <= 2, (st[0]["iters"], info["iters"])
+    assert _rel(Pg, Po) < 1e-6
