@@ -207,6 +207,14 @@ def extra_workloads(dda, inputs, torch, tol):
                 iters=[x["iters"] for x in st], rel_resid=[x["rel_resid"] for x in st], q=q, mie=mie)
     d133["q_rel_err_vs_mie"] = [_rel_err(v, mie) for v in q] if mie else None
     d133["config"] = {"n_sites": len(sites), "fft_grid": list(t.info()["grid"]), "precision": "mixed"}
+    # the same solve with BiCGstab(2), the guide's recommended PBCGS2
+    s0 = time.perf_counter()
+    P, st2 = t.solve(rhs, tol=tol, precision="mixed", out=P, solver="bicgstab2")
+    q2 = t.cross_sections(rhs, P)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter() - s0
+    d133["bicgstab2"] = dict(solves_per_s=len(rhs) / t2, iters=[x["iters"] for x in st2],
+                             q_rel_err_vs_mie=[_rel_err(v, mie) for v in q2] if mie else None)
     out["sphere_d133"] = d133
     t.close()
 
@@ -257,8 +265,8 @@ def main():
     info = t.info()
     P = torch.empty((1, n, 3), dtype=torch.complex128, device="cuda")
 
-    def step(precision):
-        Pp, st = t.solve(rhs, tol=args.tol, precision=precision, out=P)
+    def step(precision, solver="bicgstab"):
+        Pp, st = t.solve(rhs, tol=args.tol, precision=precision, out=P, solver=solver)
         q = t.cross_sections(rhs, Pp)
         return st[0], q[0]
 
@@ -289,6 +297,15 @@ def main():
         st64, q64 = step("fp64")
     torch.cuda.synchronize()
     fp64_s = (time.perf_counter() - f0) / nf
+
+    # BiCGstab(2) (the guide's PBCGS2), mixed, same workload
+    step("mixed", "bicgstab2")
+    torch.cuda.synchronize()
+    f0 = time.perf_counter()
+    for _ in range(nf):
+        stb2, qb2 = step("mixed", "bicgstab2")
+    torch.cuda.synchronize()
+    b2_s = (time.perf_counter() - f0) / nf
 
     # event timing of the five FFT passes (mixed product)
     Pr = torch.tensor(inputs.random_polarization(n, 1, seed=1), device="cuda")
@@ -337,6 +354,7 @@ def main():
         "q": q,
         "rel_resid": st["rel_resid"],
         "iters": st["iters"],
+        "bicgstab2_solver": {"solves_per_s": 1.0 / b2_s, "iters": stb2["iters"], "q": qb2, "precision": "mixed"},
         "fp64_solver": {"solves_per_s": 1.0 / fp64_s, "iters": st64["iters"], "q": q64,
                         "speedup_mixed_over_fp64": (args.steps / total) * fp64_s},
         "matvec_event_ms": {"mixed": prof, "fp64": prof64},
