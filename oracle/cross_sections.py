@@ -18,6 +18,19 @@ integral dOmega (I - n n) e^{i k n.R} = 4 pi K(kR),
 (spherical Bessel functions j_n).  ``c_sca_quadrature`` evaluates the same
 far-field integral by brute-force angular quadrature, as an independent check
 of ``c_sca_exact``.
+
+``far_field`` does the same quadrature about the incident direction khat and
+also returns the angular averages of §3.1, weighted by the scattered
+intensity |F_perp(n)|^2 with cos theta = n . khat:
+
+    g = <cos theta>,   <cos^2 theta>.
+
+The guide chooses its scattering directions by the parameter ETASCA (number
+of directions proportional to [(3 + x)/ETASCA]^2) without printing the rule.
+Reading: Gauss-Legendre in cos theta with n_theta = ceil((3 + x)/ETASCA) + 1
+nodes and a uniform phi grid of 2 n_theta points, which integrates the
+band-limited far-field intensity (degree about 2x in each angle) exactly for
+ETASCA <= 1.
 """
 
 import math
@@ -79,6 +92,38 @@ def c_sca_quadrature(sites, kd, P, n_theta=96, n_phi=192):
     integrand = np.sum(np.abs(F) ** 2, axis=-1)
     total = np.sum(w[:, None] * integrand) * (2.0 * math.pi / n_phi)
     return kd ** 4 * float(total)
+
+
+def far_field_directions(x, etasca=0.5):
+    """(n_theta, n_phi) of the reading of ETASCA in the module docstring."""
+    nt = int(math.ceil((3.0 + x) / etasca)) + 1
+    return nt, 2 * nt
+
+
+def far_field(sites, kd, P, khat, n_theta, n_phi):
+    """dict(c_sca, g, cos2) by quadrature about khat (see module docstring)."""
+    sites = np.asarray(sites, dtype=float)
+    P = np.asarray(P, dtype=complex)
+    khat = np.asarray(khat, dtype=float)
+    khat = khat / np.linalg.norm(khat)
+    # an orthonormal frame (e1, e2, khat)
+    t = np.array([1.0, 0.0, 0.0]) if abs(khat[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    e1 = t - khat * np.dot(t, khat)
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(khat, e1)
+    mu, w = np.polynomial.legendre.leggauss(n_theta)
+    phi = 2.0 * math.pi * np.arange(n_phi) / n_phi
+    st = np.sqrt(1.0 - mu * mu)
+    n = (mu[:, None, None] * khat + (st[:, None] * np.cos(phi))[..., None] * e1
+         + (st[:, None] * np.sin(phi))[..., None] * e2)                    # [T, F, 3]
+    phase = np.exp(-1j * kd * np.einsum("tfc,jc->tfj", n, sites))
+    F = np.einsum("tfj,ja->tfa", phase, P)
+    F = F - n * np.sum(n * F, axis=-1, keepdims=True)
+    inten = np.sum(np.abs(F) ** 2, axis=-1) * w[:, None] * (2.0 * math.pi / n_phi)
+    tot = float(np.sum(inten))
+    g = float(np.sum(inten * mu[:, None])) / tot
+    cos2 = float(np.sum(inten * (mu * mu)[:, None])) / tot
+    return dict(c_sca=kd ** 4 * tot, g=g, cos2=cos2)
 
 
 def efficiencies(n_sites, kd, E_inc, alpha_inv_sites, P, sites=None, exact_sca=False):

@@ -13,7 +13,11 @@ D_{n-1} = n/z - 1/(D_n + n/z)),
     Q_ext = (2/x^2) sum (2n+1) Re(a_n + b_n)
     Q_sca = (2/x^2) sum (2n+1) (|a_n|^2 + |b_n|^2),   Q_abs = Q_ext - Q_sca
 
-summed to n_max = x + 4 x^(1/3) + 2 (Wiscombe 1980).
+summed to n_max = x + 4 x^(1/3) + 2 (Wiscombe 1980).  The asymmetry parameter
+g = <cos theta> (the guide's <cos theta>, §3.1 output) is the textbook sum
+
+    g Q_sca = (4/x^2) sum [ n(n+2)/(n+1) Re(a_n a*_{n+1} + b_n b*_{n+1})
+                            + (2n+1)/(n(n+1)) Re(a_n b*_n) ].
 """
 
 import math
@@ -22,8 +26,8 @@ import numpy as np
 import scipy.special as ssp
 
 
-def mie_q(m, x):
-    """Return dict(qext, qsca, qabs) for relative index m and size parameter x."""
+def mie_coefficients(m, x):
+    """Arrays a[n], b[n] for n = 0..n_max (index 0 unused, zero)."""
     m = complex(m)
     nmax = int(round(x + 4.0 * x ** (1.0 / 3.0) + 2.0))
     mx = m * x
@@ -34,15 +38,26 @@ def mie_q(m, x):
     n = np.arange(0, nmax + 1)
     psi = x * ssp.spherical_jn(n, x)
     xi = x * (ssp.spherical_jn(n, x) + 1j * ssp.spherical_yn(n, x))
-    qe = 0.0
-    qs = 0.0
+    a = np.zeros(nmax + 1, dtype=complex)
+    b = np.zeros(nmax + 1, dtype=complex)
     for k in range(1, nmax + 1):
         da = D[k] / m + k / x
         db = m * D[k] + k / x
-        an = (da * psi[k] - psi[k - 1]) / (da * xi[k] - xi[k - 1])
-        bn = (db * psi[k] - psi[k - 1]) / (db * xi[k] - xi[k - 1])
-        qe += (2 * k + 1) * (an + bn).real
-        qs += (2 * k + 1) * (abs(an) ** 2 + abs(bn) ** 2)
-    qe *= 2.0 / (x * x)
-    qs *= 2.0 / (x * x)
-    return dict(qext=qe, qsca=qs, qabs=qe - qs)
+        a[k] = (da * psi[k] - psi[k - 1]) / (da * xi[k] - xi[k - 1])
+        b[k] = (db * psi[k] - psi[k - 1]) / (db * xi[k] - xi[k - 1])
+    return a, b
+
+
+def mie_q(m, x):
+    """Return dict(qext, qsca, qabs, g) for relative index m and size parameter x."""
+    a, b = mie_coefficients(m, x)
+    nmax = len(a) - 1
+    k = np.arange(1, nmax + 1)
+    qe = 2.0 / (x * x) * float(np.sum((2 * k + 1) * (a[1:] + b[1:]).real))
+    qs = 2.0 / (x * x) * float(np.sum((2 * k + 1) * (np.abs(a[1:]) ** 2 + np.abs(b[1:]) ** 2)))
+    a1 = np.append(a, 0.0)
+    b1 = np.append(b, 0.0)
+    gq = float(np.sum(k * (k + 2) / (k + 1) * (a1[k] * np.conj(a1[k + 1]) + b1[k] * np.conj(b1[k + 1])).real))
+    gq += float(np.sum((2 * k + 1) / (k * (k + 1)) * (a[k] * np.conj(b[k])).real))
+    g = 4.0 / (x * x) * gq / qs if qs > 0 else 0.0
+    return dict(qext=qe, qsca=qs, qabs=qe - qs, g=g)

@@ -358,6 +358,73 @@ def test_c_sca_exact_matches_angular_quadrature():
     assert abs(a - b) < 1e-10 * abs(a)
 
 
+def test_far_field_single_dipole_closed_form():
+    # One dipole p = x (k along z): |F_perp|^2 = 1 - (n.x)^2, so
+    # C_sca = (8 pi / 3) k^4, <cos theta> = 0 and <cos^2 theta> = 2/5 exactly.
+    kd = 0.7
+    ff = cs.far_field(np.zeros((1, 3)), kd, np.array([[1.0 + 0j, 0, 0]]), [0, 0, 1.0], 6, 12)
+    assert abs(ff["c_sca"] - 8 * math.pi / 3 * kd ** 4) < 1e-14
+    assert abs(ff["g"]) < 1e-15 and abs(ff["cos2"] - 0.4) < 1e-14
+
+
+def test_far_field_matches_exact_csca_about_any_axis():
+    s = targets.ellipsoid(5, 4, 3)
+    kd = 0.8
+    rng = np.random.default_rng(6)
+    P = rng.standard_normal((len(s), 3)) + 1j * rng.standard_normal((len(s), 3))
+    a = cs.c_sca_exact(s, kd, P)
+    for khat in ([0, 0, 1.0], [0.6, -0.48, 0.64], [1.0, 0, 0]):
+        ff = cs.far_field(s, kd, P, khat, 48, 96)
+        assert abs(ff["c_sca"] - a) < 1e-10 * a
+    # reversing the axis reverses <cos theta> and keeps <cos^2 theta>
+    f1 = cs.far_field(s, kd, P, [0.6, -0.48, 0.64], 48, 96)
+    f2 = cs.far_field(s, kd, P, [-0.6, 0.48, -0.64], 48, 96)
+    assert abs(f1["g"] + f2["g"]) < 1e-12 and abs(f1["cos2"] - f2["cos2"]) < 1e-12
+
+
+def test_mie_g_equals_phase_function_integral():
+    # g from the coefficient sum equals <cos theta> integrated from the
+    # amplitude functions S1, S2 built from the same a_n, b_n (and Q_sca from
+    # its series equals the integral of |S1|^2 + |S2|^2).
+    for m, x in ((1.33 + 0.01j, 1.0), (1.5 + 0.1j, 7.0), (1.33 + 0.001j, 12.0)):
+        a, b = mie.mie_coefficients(m, x)
+        nmax = len(a) - 1
+        mu, w = np.polynomial.legendre.leggauss(4 * nmax + 20)
+        pi_prev, pi_cur = np.zeros_like(mu), np.ones_like(mu)
+        S1 = np.zeros_like(mu, dtype=complex)
+        S2 = np.zeros_like(mu, dtype=complex)
+        for n in range(1, nmax + 1):
+            if n > 1:
+                pi_prev, pi_cur = pi_cur, ((2 * n - 1) * mu * pi_cur - n * pi_prev) / (n - 1)
+            tau = n * mu * pi_cur - (n + 1) * pi_prev
+            c = (2 * n + 1) / (n * (n + 1))
+            S1 += c * (a[n] * pi_cur + b[n] * tau)
+            S2 += c * (a[n] * tau + b[n] * pi_cur)
+        i = np.abs(S1) ** 2 + np.abs(S2) ** 2
+        q = mie.mie_q(m, x)
+        assert abs(np.sum(w * i) / x ** 2 - q["qsca"]) < 1e-10 * q["qsca"]
+        assert abs(np.sum(w * mu * i) / np.sum(w * i) - q["g"]) < 1e-10
+
+
+def test_far_field_of_dda_sphere_against_mie():
+    # D = 20 pseudosphere (N = 4224), x = 3: the DDA <cos theta> is within
+    # 0.5% of Mie, and the quadrature C_sca equals C_ext - C_abs (the dipole
+    # array's optical theorem) for the solved P.
+    s = targets.ellipsoid(20, 20, 20)
+    m, x = 1.33 + 0.01j, 3.0
+    kd = targets.kd_from_x(x, len(s))
+    khat, e = np.array([1.0, 0, 0]), np.array([0, 1.0, 0])
+    ai = pol.alpha_inv_ldr(m, kd, khat, e)
+    E = incident.incident_field(s, kd, khat, e)
+    P, info = solvers.bicgstab(interaction.FFTOperator(s, kd, ai).matvec, E, tol=1e-11)
+    nt, nf = cs.far_field_directions(x)
+    ff = cs.far_field(s, kd, P, khat, nt, nf)
+    q = cs.efficiencies(len(s), kd, E, ai, P)
+    geo = math.pi * q["aeff"] ** 2
+    assert abs(ff["c_sca"] / geo - q["qsca"]) < 1e-9 * q["qsca"]
+    assert abs(ff["g"] - mie.mie_q(m, x)["g"]) < 5e-3 * mie.mie_q(m, x)["g"]
+
+
 def test_optical_theorem():
     s = targets.ellipsoid(9, 7, 5)
     for m, kind in ((1.7 + 0.3j, "LATTDR"), (2.2 + 0.5j, "CMRR"), (1.3 + 0.1j, "FLTRCD")):
