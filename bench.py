@@ -207,6 +207,15 @@ def extra_workloads(dda, inputs, torch, tol):
                 iters=[x["iters"] for x in st], rel_resid=[x["rel_resid"] for x in st], q=q, mie=mie)
     d133["q_rel_err_vs_mie"] = [_rel_err(v, mie) for v in q] if mie else None
     d133["config"] = {"n_sites": len(sites), "fft_grid": list(t.info()["grid"]), "precision": "mixed"}
+    # far field: Q_sca by quadrature (optical theorem check) and <cos theta> against Mie
+    s0 = time.perf_counter()
+    far = t.far_field(rhs, P, etasca=0.5)
+    torch.cuda.synchronize()
+    d133["far_field"] = dict(seconds=time.perf_counter() - s0, n_theta=far[0]["n_theta"], n_phi=far[0]["n_phi"],
+                             qsca=[f["qsca"] for f in far], g=[f["g"] for f in far], cos2=[f["cos2"] for f in far],
+                             mie_g=mie.get("g") if mie else None,
+                             qsca_rel_diff_vs_qext_minus_qabs=[abs(f["qsca"] - v["qsca"]) / v["qext"]
+                                                               for f, v in zip(far, q)])
     # the same solve with BiCGstab(2), the guide's recommended PBCGS2
     s0 = time.perf_counter()
     P, st2 = t.solve(rhs, tol=tol, precision="mixed", out=P, solver="bicgstab2")

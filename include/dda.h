@@ -130,6 +130,15 @@ typedef struct {
   double aeff;             /* effective radius in lattice units (§2) */
 } dda_q;
 
+/* Far-field averages of one solved RHS (§3.1 outputs). */
+typedef struct {
+  double qsca;             /* Q_sca = C_sca / (pi a_eff^2), C_sca = k^4 * integral |F_perp|^2 dOmega
+                              by quadrature (an independent check of Q_ext - Q_abs) */
+  double g;                /* <cos theta>, theta the scattering angle from khat */
+  double cos2;             /* <cos^2 theta> */
+  int32_t n_theta, n_phi;  /* quadrature: Gauss-Legendre nodes in cos theta, uniform phi */
+} dda_far;
+
 typedef struct {
   int32_t box[3];          /* nx, ny, nz */
   int32_t grid[3];         /* padded FFT extents Mx, My, Mz (2/3/5-smooth, >= 2n-1) */
@@ -201,6 +210,18 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
  * p_host (host).  out: host [nrhs].  Synchronous. */
 int dda_cross_sections(dda_target *t, const dda_rhs *rhs, int32_t nrhs,
                        const void *p_dev, const dda_c64 *p_host, void *stream, dda_q *out);
+
+/* Q_sca, <cos theta> and <cos^2 theta> of solved polarizations P (device
+ * [nrhs][N][3]) from the far field F(n) = sum_j P_j exp(-i k n.r_j), weighted
+ * by |F_perp|^2 (§3.1).  Directions: Gauss-Legendre in cos theta about khat
+ * with n_theta = ceil((3 + x)/etasca) + 1 nodes and 2 n_theta uniform phi,
+ * x = k a_eff (the guide's ETASCA resolution parameter, §9: the number of
+ * directions grows as [(3 + x)/ETASCA]^2; 0.5 is its recommended value).
+ * out: host [nrhs].  Synchronous; allocates and frees a scratch buffer.
+ * Errors: DDA_EINVAL (etasca <= 0 or so small that n_theta > 2048,
+ * |khat| != 1); DDA_ENOMEM; DDA_EDEVICE. */
+int dda_far_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const void *p_dev, double etasca,
+                  void *stream, dda_far *out);
 
 /* The product AP = A P for nrhs vectors (device [nrhs][N][3] in and out, may
  * not alias), in DDA_FP64 or DDA_MIXED (FP32 FFT convolution, FP64 diagonal

@@ -173,6 +173,14 @@ class Target:
                                              _stream_ptr(stream), q))
         return [dict(qext=v.qext, qabs=v.qabs, qsca=v.qsca, aeff=v.aeff) for v in q]
 
+    def far_field(self, rhs, P, etasca=0.5, stream=None):
+        """Q_sca by far-field quadrature, <cos theta>, <cos^2 theta> per RHS."""
+        nrhs = len(rhs)
+        out = (L.Far * nrhs)()
+        L.check(self._lib.dda_far_field(self._h, _rhs_array(rhs), nrhs, ctypes.c_void_p(P.data_ptr()),
+                                        float(etasca), _stream_ptr(stream), out))
+        return [dict(qsca=v.qsca, g=v.g, cos2=v.cos2, n_theta=v.n_theta, n_phi=v.n_phi) for v in out]
+
     def apply(self, rhs, P, precision="fp64", stream=None):
         out = self._vec(len(rhs))
         L.check(self._lib.dda_apply(self._h, _rhs_array(rhs), len(rhs), PRECISION[precision],

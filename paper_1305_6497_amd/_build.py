@@ -20,6 +20,7 @@ SOURCES = {
     "matvec_f64.hip": [],
     "fft_generic.hip": [],
     "krylov.hip": [],
+    "farfield.hip": [],
     "api.hip": [],
     "host.cpp": ["-ffp-contract=off"],
 }

@@ -58,6 +58,11 @@ class SolveStats(ctypes.Structure):
                 ("outer", ctypes.c_int32), ("rel_resid", ctypes.c_double)]
 
 
+class Far(ctypes.Structure):
+    _fields_ = [("qsca", ctypes.c_double), ("g", ctypes.c_double), ("cos2", ctypes.c_double),
+                ("n_theta", ctypes.c_int32), ("n_phi", ctypes.c_int32)]
+
+
 class Q(ctypes.Structure):
     _fields_ = [("qext", ctypes.c_double), ("qabs", ctypes.c_double), ("qsca", ctypes.c_double),
                 ("aeff", ctypes.c_double)]
@@ -85,6 +90,8 @@ SIGNATURES = [
                                  ctypes.POINTER(C64), _VP, ctypes.POINTER(SolveStats)]),
     ("dda_cross_sections", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), ctypes.c_int32, _VP, ctypes.POINTER(C64), _VP,
                                           ctypes.POINTER(Q)]),
+    ("dda_far_field", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), ctypes.c_int32, _VP, ctypes.c_double, _VP,
+                                     ctypes.POINTER(Far)]),
     ("dda_apply", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP]),
     ("dda_incident_field", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), ctypes.c_int32, _VP, _VP]),
     ("dda_free_target", None, [_VP]),

@@ -785,6 +785,79 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
   });
 }
 
+int dda_far_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const void *p_dev, double etasca, void *stream,
+                  dda_far *out) {
+  return guarded([&]() -> int {
+    DDA_REQUIRE(t && rhs && p_dev && out, "NULL argument");
+    DDA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    DDA_REQUIRE(std::isfinite(etasca) && etasca > 0.0, "etasca must be > 0");
+    DDA_HIP(hipSetDevice(t->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double x = t->kd * t->aeff;
+    const double ntd = std::ceil((3.0 + x) / etasca) + 1.0;
+    DDA_REQUIRE(ntd <= 2048.0, "etasca too small: more than 2048 polar angles");
+    const int nt = (int)ntd, nf = 2 * nt, ndir = nt * nf;
+    std::vector<double> gx, gw;
+    gauss_legendre(nt, gx, gw);
+    std::vector<double> mu((size_t)ndir), w((size_t)ndir), dirs((size_t)ndir * 3);
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < nt; ++i)
+      for (int j = 0; j < nf; ++j) {
+        mu[(size_t)i * nf + j] = gx[i];
+        w[(size_t)i * nf + j] = gw[i] * 2.0 * pi / nf;
+      }
+    const size_t scratch = far_field_scratch_bytes(t->g, ndir);
+    const size_t bytes = (size_t)ndir * 5 * sizeof(double) + scratch + 3 * sizeof(double);
+    double *buf = t->alloc<double>(bytes);
+    double *d_dirs = buf, *d_mu = buf + (size_t)ndir * 3, *d_w = d_mu + ndir, *d_scr = d_w + ndir;
+    double *d_sums = d_scr + scratch / sizeof(double);
+    std::vector<double> sums(3);
+    try {
+      DDA_HIP(hipMemcpyAsync(d_mu, mu.data(), (size_t)ndir * sizeof(double), hipMemcpyHostToDevice, s));
+      DDA_HIP(hipMemcpyAsync(d_w, w.data(), (size_t)ndir * sizeof(double), hipMemcpyHostToDevice, s));
+      for (int r = 0; r < nrhs; ++r) {
+        const double *kh = rhs[r].khat;
+        const double kn = std::sqrt(kh[0] * kh[0] + kh[1] * kh[1] + kh[2] * kh[2]);
+        DDA_REQUIRE(std::fabs(kn - 1.0) <= 1e-12, "|khat| must be 1");
+        // frame (e1, e2, khat): e1 from x (or y when khat is near x)
+        const double k[3] = {kh[0] / kn, kh[1] / kn, kh[2] / kn};
+        double tt[3] = {1.0, 0.0, 0.0};
+        if (std::fabs(k[0]) >= 0.9) tt[0] = 0.0, tt[1] = 1.0;
+        const double tk = tt[0] * k[0] + tt[1] * k[1] + tt[2] * k[2];
+        double e1[3] = {tt[0] - tk * k[0], tt[1] - tk * k[1], tt[2] - tk * k[2]};
+        const double e1n = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+        for (double &v : e1) v /= e1n;
+        const double e2[3] = {k[1] * e1[2] - k[2] * e1[1], k[2] * e1[0] - k[0] * e1[2], k[0] * e1[1] - k[1] * e1[0]};
+        for (int i = 0; i < nt; ++i) {
+          const double st = std::sqrt(std::max(0.0, 1.0 - gx[i] * gx[i]));
+          for (int j = 0; j < nf; ++j) {
+            const double ph = 2.0 * pi * j / nf, cp = std::cos(ph), sp = std::sin(ph);
+            double *n = &dirs[((size_t)i * nf + j) * 3];
+            for (int a = 0; a < 3; ++a) n[a] = gx[i] * k[a] + st * (cp * e1[a] + sp * e2[a]);
+          }
+        }
+        DDA_HIP(hipMemcpyAsync(d_dirs, dirs.data(), dirs.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        const c64 *P = static_cast<const c64 *>(p_dev) + (size_t)r * 3 * t->g.n_sites;
+        launch_far_field(t->g, t->d_cell_site, P, t->kd, d_dirs, d_mu, d_w, ndir, d_scr, d_sums, s);
+        DDA_HIP(hipMemcpyAsync(sums.data(), d_sums, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+        DDA_HIP(hipStreamSynchronize(s));
+        const double k4 = t->kd * t->kd * t->kd * t->kd;
+        out[r].qsca = k4 * sums[0] / (pi * t->aeff * t->aeff);
+        out[r].g = sums[0] > 0.0 ? sums[1] / sums[0] : 0.0;
+        out[r].cos2 = sums[0] > 0.0 ? sums[2] / sums[0] : 0.0;
+        out[r].n_theta = nt;
+        out[r].n_phi = nf;
+      }
+    } catch (...) {
+      (void)hipStreamSynchronize(s);
+      t->release(buf);
+      throw;
+    }
+    t->release(buf);
+    return DDA_OK;
+  });
+}
+
 int dda_cross_sections(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const void *p_dev, const dda_c64 *p_host,
                        void *stream, dda_q *out) {
   return guarded([&]() -> int {

@@ -261,6 +261,14 @@ void launch_cross_sums(const Geometry &g, const int32_t *ijk, const RhsDev *rhs,
                        const c64 *P, const c64 *ainv, int ncomp, const uint8_t *comp, double *partial,
                        double *sums, hipStream_t s);
 void copy_vec(c64 *dst, const c64 *src, int64_t n, hipStream_t s);
+
+// Gauss-Legendre nodes and weights on [-1, 1] (host, Newton iteration).
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w);
+// Far-field quadrature sums over ndir directions (one RHS): sums[0..2] =
+// sum w |F_perp|^2, sum w mu |F_perp|^2, sum w mu^2 |F_perp|^2.
+size_t far_field_scratch_bytes(const Geometry &g, int ndir);
+void launch_far_field(const Geometry &g, const int *cell_site, const c64 *P, double kd, const double *dirs,
+                      const double *mu, const double *w, int ndir, double *scratch, double *sums, hipStream_t s);
 void zero_vec(c64 *dst, int64_t n, hipStream_t s);
 
 // --------------------------------------------------------------- host side --

@@ -239,6 +239,49 @@ int next_smooth(int n) {
 
 // Radix plan of a transform: radix 8 while it divides, then 4, 2, 5, 3
 // (the radices fft_lds.hpp implements).
+// Nodes: roots of P_n by Newton's method from cos(pi (i + 3/4) / (n + 1/2)),
+// with P_n and P_n' from the three-term recurrence; weights
+// 2 / ((1 - x^2) P_n'(x)^2).
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+  DDA_REQUIRE(n >= 1, "need at least one node");
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(pi * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      // p1 = P_n(z), p0 = P_{n-1}(z)
+      dp = n == 1 ? 1.0 : n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    if (n == 1) dp = 1.0;
+    {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n == 1 ? 1.0 : n * (z * p1 - p0) / (z * z - 1.0);
+    }
+    const double wi = 2.0 / ((1.0 - z * z) * dp * dp);
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = wi;
+    w[n - 1 - i] = wi;
+  }
+  if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
 FastDiv make_fastdiv(uint32_t d) {
   DDA_REQUIRE(d >= 1, "division by zero");
   FastDiv f;

@@ -367,3 +367,50 @@ def test_bicgstab2_follows_the_oracle_recurrence(dda):
     assert st[0]["status"] == 0 and info["converged"]
     assert abs(st[0]["iters"] - info["iters"]) <= 2, (st[0]["iters"], info["iters"])
     assert _rel(Pg, Po) < 1e-6
+
+
+# ------------------------------------------------------------- far field --
+@pytest.mark.parametrize("shape,shpar,khat", [
+    ("ELLIPSOID", (9.5, 8.0, 6.5), (1.0, 0.0, 0.0)),
+    ("RCTGLPRSM", (7, 5, 3), (0.6, -0.48, 0.64)),
+    ("HEX_PRISM", (6, 9, 2), (0.0, 0.0, 1.0)),
+    ("RCTGLPRSM", (1, 1, 1), (0.0, 1.0, 0.0)),
+])
+def test_far_field_matches_oracle_quadrature(dda, shape, shpar, khat):
+    # same directions (the ETASCA rule), random P: the GPU row recurrence and
+    # the oracle's direct phase sums agree to rounding
+    sites, box = dda.make_sites(shape, shpar)
+    osites = targets.make(shape, shpar)
+    kd = 0.7
+    khat = np.array(khat) / np.linalg.norm(khat)
+    e = np.cross(khat, [0.3, 0.5, 0.7])
+    e /= np.linalg.norm(e)
+    t = dda.Target(sites, box, m=1.5 + 0.1j, kd=kd)
+    P = inputs.random_polarization(len(sites), 2, seed=12)
+    rhs = [(khat, e), (khat, e)]
+    far = t.far_field(rhs, torch.tensor(P, device="cuda"), etasca=0.5)
+    aeff = t.info()["aeff"]
+    t.close()
+    nt, nf = cross_sections.far_field_directions(kd * aeff, 0.5)
+    for r in range(2):
+        ref = cross_sections.far_field(osites, kd, P[r], khat, nt, nf)
+        assert (far[r]["n_theta"], far[r]["n_phi"]) == (nt, nf)
+        assert abs(far[r]["qsca"] * math.pi * aeff ** 2 - ref["c_sca"]) <= 1e-11 * ref["c_sca"]
+        assert abs(far[r]["g"] - ref["g"]) <= 1e-11 and abs(far[r]["cos2"] - ref["cos2"]) <= 1e-11
+
+
+@pytest.mark.parametrize("name", ["au_block_16x32x32", "block_64"])
+def test_far_field_optical_theorem_full_size(dda, name):
+    # for a converged solution the far-field Q_sca equals Q_ext - Q_abs
+    w = inputs.WORKLOADS[name]
+    sites, box = dda.make_sites(w["shape"], w["shpar"])
+    kd = dda.kd_from_x(w["x"], len(sites))
+    t = dda.Target(sites, box, m=w["m"], kd=kd)
+    rhs = [dda.orient_rhs(0, 0, 0, which=1)]
+    P, st = t.solve(rhs, tol=1e-9, precision="fp64", max_iter=3000)
+    q = t.cross_sections(rhs, P)
+    far = t.far_field(rhs, P, etasca=0.5)
+    t.close()
+    assert st[0]["status"] == 0
+    assert abs(far[0]["qsca"] - q[0]["qsca"]) <= 1e-7 * q[0]["qext"], (far[0], q[0])
+    assert -1.0 < far[0]["g"] < 1.0 and 0.0 < far[0]["cos2"] < 1.0
