@@ -23,6 +23,7 @@ SOURCES = {
     "farfield.hip": [],
     "api.hip": [],
     "host.cpp": ["-ffp-contract=off"],
+    "devmem.cpp": [],
 }
 
 

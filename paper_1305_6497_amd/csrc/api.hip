@@ -57,37 +57,73 @@ struct dda_target {
   uint64_t buffer_gen = 0;        // bumped whenever workspaces are reallocated
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   uint64_t bytes = 0;
-  std::vector<std::pair<void *, size_t>> allocs;
+  struct Block {
+    void *p;
+    size_t bytes, granted;
+  };
+  std::vector<Block> allocs;
+  // one event per stream this handle has queued work on, recorded after each
+  // call, so its blocks go back to the device cache only once that work is done
+  std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
 
   template <typename P>
   P *alloc(size_t bytes_) {
-    void *p = nullptr;
-    DDA_HIP(hipMalloc(&p, std::max<size_t>(bytes_, 16)));
-    allocs.push_back({p, bytes_});
+    size_t granted = 0;
+    void *p = dev_alloc(device, bytes_, &granted);
+    allocs.push_back({p, bytes_, granted});
     bytes += bytes_;
     return static_cast<P *>(p);
+  }
+  void note_use(hipStream_t s) {
+    for (auto &u : uses)
+      if (u.first == s) {
+        (void)hipEventRecord(u.second, s);
+        return;
+      }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipStreamSynchronize(s);      // cannot track: wait now instead
+      return;
+    }
+    (void)hipEventRecord(e, s);
+    uses.push_back({s, e});
+  }
+  // wait for every piece of work this handle has queued
+  void quiesce() {
+    for (auto &u : uses) (void)hipEventSynchronize(u.second);
+    if (upload_done) (void)hipEventSynchronize(upload_done);
+    if (stream) (void)hipStreamSynchronize(stream);
   }
   void release(void *p) {
     if (!p) return;
     for (size_t i = 0; i < allocs.size(); ++i)
-      if (allocs[i].first == p) {
-        bytes -= allocs[i].second;
-        (void)hipFree(p);
+      if (allocs[i].p == p) {
+        quiesce();
+        bytes -= allocs[i].bytes;
+        dev_release(device, p, allocs[i].granted);
         allocs.erase(allocs.begin() + i);
         return;
       }
   }
   ~dda_target() {
     (void)hipSetDevice(device);
-    if (upload_done) (void)hipEventSynchronize(upload_done);
-    if (stream) (void)hipStreamSynchronize(stream);
+    quiesce();
     if (graph) (void)hipGraphExecDestroy(graph);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
-    for (auto &a : allocs) (void)hipFree(a.first);
+    for (auto &a : allocs) dev_release(device, a.p, a.granted);
+    for (auto &u : uses) (void)hipEventDestroy(u.second);
     if (upload_done) (void)hipEventDestroy(upload_done);
     if (stream) (void)hipStreamDestroy(stream);
   }
+};
+
+// Records, when the call returns, that the handle queued work on stream s.
+struct StreamUse {
+  dda_target *t;
+  hipStream_t s;
+  ~StreamUse() { t->note_use(s); }
 };
 
 namespace {
@@ -172,8 +208,10 @@ void make_twiddles(dda_target *t, Twiddles &tw, int L) {
   tw.L = L;
   tw.d64 = t->alloc<c64>(sizeof(c64) * L);
   tw.d32 = t->alloc<c32>(sizeof(c32) * L);
-  DDA_HIP(hipMemcpy(tw.d64, h64.data(), sizeof(c64) * L, hipMemcpyHostToDevice));
-  DDA_HIP(hipMemcpy(tw.d32, h32.data(), sizeof(c32) * L, hipMemcpyHostToDevice));
+  // on the handle's own (non-blocking) stream: no ordering against other streams
+  DDA_HIP(hipMemcpyAsync(tw.d64, h64.data(), sizeof(c64) * L, hipMemcpyHostToDevice, t->stream));
+  DDA_HIP(hipMemcpyAsync(tw.d32, h32.data(), sizeof(c32) * L, hipMemcpyHostToDevice, t->stream));
+  DDA_HIP(hipStreamSynchronize(t->stream));
 }
 
 size_t workspace_bytes(const Geometry &g, int nrhs) {
@@ -564,13 +602,15 @@ int dda_setup_target(const dda_target_desc *desc, dda_target **out) {
     make_twiddles(t.get(), t->ty, t->g.My);
     make_twiddles(t.get(), t->tz, t->g.Mz);
     t->d_ijk = t->alloc<int32_t>((size_t)n * 3 * sizeof(int32_t));
-    DDA_HIP(hipMemcpy(t->d_ijk, desc->ijk, (size_t)n * 3 * sizeof(int32_t), hipMemcpyHostToDevice));
+    DDA_HIP(hipMemcpyAsync(t->d_ijk, desc->ijk, (size_t)n * 3 * sizeof(int32_t), hipMemcpyHostToDevice,
+                           t->stream));
     if (desc->comp && t->ncomp > 1) {
       t->d_comp = t->alloc<uint8_t>((size_t)n);
-      DDA_HIP(hipMemcpy(t->d_comp, desc->comp, (size_t)n, hipMemcpyHostToDevice));
+      DDA_HIP(hipMemcpyAsync(t->d_comp, desc->comp, (size_t)n, hipMemcpyHostToDevice, t->stream));
     }
     t->d_cell_site = t->alloc<int>(cell.size() * sizeof(int));
-    DDA_HIP(hipMemcpy(t->d_cell_site, cell.data(), cell.size() * sizeof(int), hipMemcpyHostToDevice));
+    DDA_HIP(hipMemcpyAsync(t->d_cell_site, cell.data(), cell.size() * sizeof(int), hipMemcpyHostToDevice,
+                           t->stream));
     const Geometry &g = t->g;
     const size_t M = (size_t)g.Mx * g.My * g.Mz;
     t->d_ghat64 = t->alloc<c64>(6 * g.oct_elems() * sizeof(c64));
@@ -615,6 +655,7 @@ int dda_incident_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, void *e_
     DDA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
     DDA_HIP(hipSetDevice(t->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamUse use_{t, s};
     std::vector<RhsDev> rd;
     std::vector<c64> ai;
     prepare_rhs(t, rhs, nrhs, rd, ai);
@@ -634,6 +675,7 @@ int dda_apply(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t precision
     DDA_REQUIRE(precision == DDA_FP64 || precision == DDA_MIXED, "unknown precision");
     DDA_HIP(hipSetDevice(t->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamUse use_{t, s};
     std::vector<RhsDev> rd;
     std::vector<c64> ai;
     prepare_rhs(t, rhs, nrhs, rd, ai);
@@ -654,6 +696,7 @@ int dda_profile_matvec(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t 
     DDA_REQUIRE(precision == DDA_FP64 || precision == DDA_MIXED, "unknown precision");
     DDA_HIP(hipSetDevice(t->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamUse use_{t, s};
     std::vector<RhsDev> rd;
     std::vector<c64> ai;
     prepare_rhs(t, rhs, nrhs, rd, ai);
@@ -702,6 +745,7 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     DDA_REQUIRE(opts->solver == DDA_SOLVER_BICGSTAB || opts->solver == DDA_SOLVER_BICGSTAB2, "unknown solver");
     DDA_HIP(hipSetDevice(t->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamUse use_{t, s};
     const int K = opts->check_every > 0 ? opts->check_every : 8;
     const int max_outer = opts->max_outer > 0 ? opts->max_outer : 20;
     std::vector<RhsDev> rd;
@@ -793,6 +837,7 @@ int dda_far_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const void *p
     DDA_REQUIRE(std::isfinite(etasca) && etasca > 0.0, "etasca must be > 0");
     DDA_HIP(hipSetDevice(t->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamUse use_{t, s};
     const double x = t->kd * t->aeff;
     const double ntd = std::ceil((3.0 + x) / etasca) + 1.0;
     DDA_REQUIRE(ntd <= 2048.0, "etasca too small: more than 2048 polar angles");
@@ -866,6 +911,7 @@ int dda_cross_sections(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const vo
     DDA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
     DDA_HIP(hipSetDevice(t->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamUse use_{t, s};
     std::vector<RhsDev> rd;
     std::vector<c64> ai;
     prepare_rhs(t, rhs, nrhs, rd, ai);
@@ -909,6 +955,7 @@ int dda_fft_pencils(int32_t n, int64_t batch, int32_t sign, int32_t precision, d
     const AxisPlan p = make_axis_plan(n);
     dda_target tmp;         // owns the temporary twiddle tables
     tmp.device = device;
+    StreamUse use_{&tmp, s};  // destroyed first: tmp then waits for the transform before releasing
     make_twiddles(&tmp, tmp.tx, n);
     if (precision == DDA_FP64)
       launch_fft_rows<double>(static_cast<const c64 *>(in_dev), static_cast<c64 *>(out_dev), batch, p, tmp.tx.d64,

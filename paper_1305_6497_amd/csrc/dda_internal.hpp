@@ -262,6 +262,12 @@ void launch_cross_sums(const Geometry &g, const int32_t *ijk, const RhsDev *rhs,
                        double *sums, hipStream_t s);
 void copy_vec(c64 *dst, const c64 *src, int64_t n, hipStream_t s);
 
+// Device blocks from the library's per-device cache (see devmem.cpp): the
+// granted size (>= bytes) must be passed back on release, and a block may be
+// released only when no queued work uses it any more.
+void *dev_alloc(int device, size_t bytes, size_t *granted);
+void dev_release(int device, void *p, size_t granted);
+
 // Gauss-Legendre nodes and weights on [-1, 1] (host, Newton iteration).
 void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w);
 // Far-field quadrature sums over ndir directions (one RHS): sums[0..2] =
