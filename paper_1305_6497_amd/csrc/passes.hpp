@@ -585,19 +585,26 @@ static inline void with_ept(size_t elems, F &&f) {
   }
 }
 
-// Transform lengths with a compile-time plan; the others use the run-time one.
+// Transform lengths with a compile-time plan: every 2/3/5-smooth length from
+// 27 to 192 (the padded extents of targets up to 96 dipoles across) and the
+// 256 and 270 of larger workloads; the others use the run-time plan.
+template <int... Ls>
+struct LenList {};
+using StaticLens = LenList<27, 30, 32, 36, 40, 45, 48, 50, 54, 60, 64, 72, 75, 80, 81, 90, 96, 100, 108, 120, 125, 128,
+                           135, 144, 150, 160, 162, 180, 192, 256, 270>;
+
+template <typename F>
+static inline void with_len_in(int, F &&f, LenList<>) {
+  f(IC<0>{});
+}
+template <typename F, int L0, int... Ls>
+static inline void with_len_in(int L, F &&f, LenList<L0, Ls...>) {
+  if (L == L0) f(IC<L0>{});
+  else with_len_in(L, f, LenList<Ls...>{});
+}
 template <typename F>
 static inline void with_len(int L, F &&f) {
-  switch (L) {
-    case 40: f(IC<40>{}); break;
-    case 64: f(IC<64>{}); break;
-    case 96: f(IC<96>{}); break;
-    case 128: f(IC<128>{}); break;
-    case 192: f(IC<192>{}); break;
-    case 256: f(IC<256>{}); break;
-    case 270: f(IC<270>{}); break;
-    default: f(IC<0>{}); break;
-  }
+  with_len_in(L, f, StaticLens{});
 }
 
 // Calls f(IC<EPT>, IC<LC>) for a pass of `elems` elements per block along an
@@ -668,8 +675,10 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
         });
         break;
       case 2: {
-        // half tiles once a whole tile would exceed 2048 elements per block
-        const int half = g.Mz * W > 2048 ? 1 : 0;
+        // half tiles for long columns (FP32: Mz > 128, FP64: Mz > 128): it halves
+        // the registers a thread needs for the parked spectra
+        constexpr int kHalfAbove = sizeof(T) == 4 ? 2048 : 1024;
+        const int half = g.Mz * W > kHalfAbove ? 1 : 0;
         auto launch = [&](auto e, auto lc, auto hf) {
           constexpr int LC = decltype(lc)::value, H = decltype(hf)::value, E = decltype(e)::value;
           const size_t lds = (((size_t)g.Mz * W >> H) + g.Mz) * cs;
@@ -680,7 +689,7 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
         with_len(g.Mz, [&](auto lc) {
           constexpr int LC = decltype(lc)::value;
           if constexpr (LC > 0) {
-            constexpr int H = LC * W > 2048 ? 1 : 0;
+            constexpr int H = LC * W > kHalfAbove ? 1 : 0;
             launch(IC<pick_ept_c((size_t)(LC * W) >> H, false)>{}, lc, IC<H>{});
           } else if (half) {
             with_ept<16>((size_t)g.Mz * W / 2, [&](auto e) { launch(e, lc, IC<1>{}); });
