@@ -224,7 +224,7 @@ size_t krylov_bytes(const Geometry &g, int nrhs) {
   const int64_t n3 = 3 * g.n_sites;
   const size_t vec = (size_t)n3 * sizeof(c64) * nrhs;
   const int nblk = std::max(krylov_blocks(n3), std::max(xpass_blocks(g, true), xpass_blocks(g, false)));
-  return 9 * vec + (size_t)nrhs * nblk * kPart * sizeof(double) + (size_t)nrhs * kScal * sizeof(c64) +
+  return 9 * vec + 2 * (size_t)nrhs * nblk * kPart * sizeof(double) + (size_t)nrhs * kScal * sizeof(c64) +
          4 * (size_t)nrhs * sizeof(int) + (size_t)nrhs * (sizeof(RhsDev) + 2 * sizeof(double)) +
          (size_t)nrhs * 255 * sizeof(c64);
 }
@@ -261,6 +261,7 @@ void ensure_krylov(dda_target *t, int nrhs, hipStream_t s) {
   KrylovState &k = t->k;
   for (c64 *p : {k.x, k.r, k.rh, k.p, k.v, k.s, k.t, k.b, k.u2}) t->release(p);
   t->release(k.partial);
+  t->release(k.partial2);
   t->release(k.scal);
   t->release(k.active);
   t->release(k.status);
@@ -284,6 +285,7 @@ void ensure_krylov(dda_target *t, int nrhs, hipStream_t s) {
   k.b = t->alloc<c64>(vec);
   k.u2 = t->alloc<c64>(vec);
   k.partial = t->alloc<double>((size_t)nrhs * k.nrec * kPart * sizeof(double));
+  k.partial2 = t->alloc<double>((size_t)nrhs * k.nblk * kPart * sizeof(double));
   k.scal = t->alloc<c64>((size_t)nrhs * kScal * sizeof(c64));
   k.active = t->alloc<int>(nrhs * sizeof(int));
   k.status = t->alloc<int>(nrhs * sizeof(int));
@@ -363,12 +365,14 @@ void matvec(dda_target *t, int precision, const c64 *in, c64 *out, int nrhs, con
   }
 }
 
-// One BiCGSTAB iteration for every active RHS of the block: 14 kernels.
+// One BiCGSTAB iteration for every active RHS of the block: 12 kernels.
 //   product 1: x-forward forms p = r + beta (p - omega v); x-inverse writes
-//              v = A p and partial sums of <rh, v>; alpha = rho / <rh, v>
-//   product 2: x-forward forms s = r - alpha v; x-inverse writes t = A s and
-//              partial sums of <t, s>, <t, t>; omega = <t, s> / <t, t>
-//   update:    x += alpha p + omega s, r = s - omega t with <rh, r>, |r|^2;
+//              v = A p and partial sums of <rh, v>
+//   product 2: x-forward computes alpha = rho / <rh, v> (every block, from
+//              the records) and forms s = r - alpha v; x-inverse writes
+//              t = A s and partial sums of <t, s>, <t, t>
+//   update:    omega = <t, s> / <t, t> (every block, from the records),
+//              x += alpha p + omega s, r = s - omega t with <rh, r>, |r|^2;
 //              rho, beta and the convergence status.
 void iteration(dda_target *t, int precision, hipStream_t s) {
   KrylovState &k = t->k;
@@ -385,13 +389,13 @@ void iteration(dda_target *t, int precision, hipStream_t s) {
   f.out_mode = 1;
   f.w = k.p;
   matvec(t, precision, k.p, k.v, k.nrhs, k.active, s, nullptr, -1, 1, &f);
-  k_scalar_alpha(k, s, nrec);
   f.in_mode = 2;
+  f.fold_alpha = 1;
+  f.nrec = nrec;
   f.out_mode = 2;
   f.w = k.s;
   matvec(t, precision, k.s, k.t, k.nrhs, k.active, s, nullptr, -1, 1, &f);
-  k_scalar_omega(k, s, nrec);
-  k_update_xr(k, s);
+  k_update_xr(k, s, nrec);
   k_scalar_rho(k, s);
 }
 

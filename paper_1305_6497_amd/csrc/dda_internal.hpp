@@ -153,7 +153,12 @@ struct FuseArgs {
   c64 *w = nullptr;
   c64 *scal = nullptr;
   int *active = nullptr, *status = nullptr;
-  double *partial = nullptr;      // [nrhs][x-pass blocks][kPart]
+  double *partial = nullptr;      // records [nrhs][kPart][x-pass blocks] (see reduce.hpp)
+  // in_mode 2 with fold_alpha: every block computes alpha = rho / <rh, v> from
+  // the nrec records in `partial` of the product that made v (no separate
+  // scalar kernel); block 0 stores it
+  int fold_alpha = 0;
+  int nrec = 0;
   int nax = 0;
   c64 *ax_d[3] = {nullptr, nullptr, nullptr};
   const c64 *ax_a[3] = {nullptr, nullptr, nullptr}, *ax_b[3] = {nullptr, nullptr, nullptr};
@@ -213,7 +218,8 @@ struct KrylovState {
   // x, r = r_0, rh = shadow, p = u_0, v = u_1, u2 = u_2, s = r_1, t = r_2.
   c64 *x = nullptr, *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *s = nullptr,
       *t = nullptr, *b = nullptr, *u2 = nullptr;
-  double *partial = nullptr;      // [nrhs][nrec][kPart]
+  double *partial = nullptr;      // records [nrhs][kPart][nrec] of the products and of most Krylov kernels
+  double *partial2 = nullptr;     // records of kk_update_xr (written while `partial` is read)
   c64 *scal = nullptr;            // [nrhs][kScal]
   int *active = nullptr;          // [nrhs]
   int *status = nullptr;          // [nrhs]
@@ -234,13 +240,11 @@ enum : int { ST_RUN = 0, ST_CONV = 1, ST_BREAK = 2, ST_MAXIT = 3, ST_DONE = 4, S
 
 int krylov_blocks(int64_t n3);
 void k_init_state(const KrylovState &k, double tol, int max_iter, hipStream_t s);
-void k_update_p(const KrylovState &k, hipStream_t s);
-void k_dot_rv(const KrylovState &k, hipStream_t s);
 void k_scalar_alpha(const KrylovState &k, hipStream_t s, int nrec);
-void k_update_s(const KrylovState &k, hipStream_t s);
-void k_dot_ts(const KrylovState &k, hipStream_t s);
-void k_scalar_omega(const KrylovState &k, hipStream_t s, int nrec);
-void k_update_xr(const KrylovState &k, hipStream_t s);
+// x += alpha p + omega s, r = s - omega t; omega is computed by every block
+// from the nrec records (<t, s>, <t, t>) in k.partial; records of <rh, r>,
+// |r|^2 go to k.partial2 (read by k_scalar_rho)
+void k_update_xr(const KrylovState &k, hipStream_t s, int nrec);
 // step = 1, bsign = +1: BiCGSTAB; step = 2, bsign = -1: end of a BiCGstab(2) cycle
 void k_scalar_rho(const KrylovState &k, hipStream_t s, int step = 1, double bsign = 1.0);
 // BiCGstab(2): second BiCG step's beta, minimal-residual coefficients, closing update
@@ -260,7 +264,6 @@ void launch_incident(const Geometry &g, const int32_t *ijk, const RhsDev *rhs, i
 void launch_cross_sums(const Geometry &g, const int32_t *ijk, const RhsDev *rhs, int nrhs, double kd,
                        const c64 *P, const c64 *ainv, int ncomp, const uint8_t *comp, double *partial,
                        double *sums, hipStream_t s);
-void copy_vec(c64 *dst, const c64 *src, int64_t n, hipStream_t s);
 
 // Device blocks from the library's per-device cache (see devmem.cpp): the
 // granted size (>= bytes) must be passed back on release, and a block may be
@@ -275,7 +278,6 @@ void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w);
 size_t far_field_scratch_bytes(const Geometry &g, int ndir);
 void launch_far_field(const Geometry &g, const int *cell_site, const c64 *P, double kd, const double *dirs,
                       const double *mu, const double *w, int ndir, double *scratch, double *sums, hipStream_t s);
-void zero_vec(c64 *dst, int64_t n, hipStream_t s);
 
 // --------------------------------------------------------------- host side --
 std::vector<int32_t> make_sites(int shape, const double shpar[3], int32_t box[3]);

@@ -99,12 +99,7 @@ __global__ __launch_bounds__(kFT) void kf_intensity(const double *__restrict__ f
   }
   double out[3];
   block_sum<3, kFT>(acc, out);
-  if (threadIdx.x == 0) {
-    double *o = rec + (size_t)blockIdx.x * kPart;
-    o[0] = out[0];
-    o[1] = out[1];
-    o[2] = out[2];
-  }
+  if (threadIdx.x == 0) write_record<3>(rec, 0, gridDim.x, blockIdx.x, out);
 }
 
 __global__ __launch_bounds__(kFT) void kf_final(const double *__restrict__ rec, int nblk, double *__restrict__ sums) {

@@ -69,7 +69,7 @@ __global__ void kk_init(c64 *x, c64 *rr, c64 *rh, c64 *p, c64 *v, const c64 *b, 
   }
   double out[1];
   block_sum<1>(acc, out);
-  if (threadIdx.x == 0) partial[((size_t)r * nblk + blockIdx.x) * kPart] = out[0];
+  if (threadIdx.x == 0) write_record<1>(partial, r, nblk, blockIdx.x, out);
 }
 
 __global__ void kk_init_scalars(const double *partial, int nblk, c64 *scal, int *active, int *status, double tol2,
@@ -96,36 +96,6 @@ __global__ void kk_init_scalars(const double *partial, int nblk, c64 *scal, int 
   }
 }
 
-// p = r + beta (p - omega v)
-__global__ void kk_update_p(const int *active, const c64 *rr, c64 *p, const c64 *v, const c64 *scal, int64_t n3,
-                            int nblk) {
-  RHS_PREAMBLE
-  const c64 beta = scal[(size_t)r * kScal + S_BETA];
-  const c64 omega = scal[(size_t)r * kScal + S_OMEGA];
-  for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT) {
-    const c64 pv = p[off + i], vv = v[off + i];
-    p[off + i] = rr[off + i] + beta * (pv - omega * vv);
-  }
-}
-
-// partial <rh, v>
-__global__ void kk_dot_rv(const int *active, const c64 *rh, const c64 *v, int64_t n3, double *partial, int nblk) {
-  RHS_PREAMBLE
-  double acc[2] = {0.0, 0.0};
-  for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT) {
-    const c64 d = cmulc(rh[off + i], v[off + i]);
-    acc[0] += d.x;
-    acc[1] += d.y;
-  }
-  double out[2];
-  block_sum<2>(acc, out);
-  if (threadIdx.x == 0) {
-    double *o = partial + ((size_t)r * nblk + blockIdx.x) * kPart;
-    o[0] = out[0];
-    o[1] = out[1];
-  }
-}
-
 
 __global__ void kk_scalar_alpha(const double *partial, int nblk, c64 *scal, int *active, int *status) {
   const int r = blockIdx.x;
@@ -145,53 +115,26 @@ __global__ void kk_scalar_alpha(const double *partial, int nblk, c64 *scal, int 
   }
 }
 
-// s = r - alpha v
-__global__ void kk_update_s(const int *active, const c64 *rr, const c64 *v, c64 *s, const c64 *scal, int64_t n3,
-                            int nblk) {
-  RHS_PREAMBLE
-  const c64 alpha = scal[(size_t)r * kScal + S_ALPHA];
-  for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT)
-    s[off + i] = rr[off + i] - alpha * v[off + i];
-}
-
-// partial <t, s>, <t, t>
-__global__ void kk_dot_ts(const int *active, const c64 *t, const c64 *s, int64_t n3, double *partial, int nblk) {
-  RHS_PREAMBLE
-  double acc[3] = {0.0, 0.0, 0.0};
-  for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT) {
-    const c64 tv = t[off + i];
-    const c64 d = cmulc(tv, s[off + i]);
-    acc[0] += d.x;
-    acc[1] += d.y;
-    acc[2] += tv.x * tv.x + tv.y * tv.y;
-  }
-  double out[3];
-  block_sum<3>(acc, out);
-  if (threadIdx.x == 0) {
-    double *o = partial + ((size_t)r * nblk + blockIdx.x) * kPart;
-    o[0] = out[0];
-    o[1] = out[1];
-    o[2] = out[2];
-  }
-}
-
-__global__ void kk_scalar_omega(const double *partial, int nblk, c64 *scal, const int *active) {
-  const int r = blockIdx.x;
-  if (!active[r]) return;
-  double s[3];
-  sum_partials<3>(partial, nblk, r, s);
-  if (threadIdx.x == 0) {
-    c64 *sc = scal + (size_t)r * kScal;
-    sc[S_OMEGA] = s[2] > 0.0 ? c64{s[0] / s[2], s[1] / s[2]} : c64{0.0, 0.0};
-  }
-}
-
-// x += alpha p + omega s;  r = s - omega t;  partial <rh, r>, |r|^2
+// x += alpha p + omega s;  r = s - omega t;  partial <rh, r>, |r|^2.
+// omega = <t, s> / <t, t> is computed by every block from the records of the
+// product that made t (same sum and order in every block); block 0 stores it.
 __global__ void kk_update_xr(const int *active, c64 *x, c64 *rr, const c64 *rh, const c64 *p, const c64 *s,
-                             const c64 *t, const c64 *scal, int64_t n3, double *partial, int nblk) {
+                             const c64 *t, c64 *scal, int64_t n3, const double *rec_in, int nrec_in,
+                             double *partial, int nblk) {
   RHS_PREAMBLE
+  __shared__ c64 s_omega;
+  {
+    double q[3];
+    sum_partials<3>(rec_in, nrec_in, r, q);
+    if (threadIdx.x == 0) {
+      const c64 om = q[2] > 0.0 ? c64{q[0] / q[2], q[1] / q[2]} : c64{0.0, 0.0};
+      s_omega = om;
+      if (blockIdx.x == 0) scal[(size_t)r * kScal + S_OMEGA] = om;
+    }
+    __syncthreads();
+  }
   const c64 alpha = scal[(size_t)r * kScal + S_ALPHA];
-  const c64 omega = scal[(size_t)r * kScal + S_OMEGA];
+  const c64 omega = s_omega;
   double acc[3] = {0.0, 0.0, 0.0};
   for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT) {
     const c64 sv = s[off + i];
@@ -205,17 +148,9 @@ __global__ void kk_update_xr(const int *active, c64 *x, c64 *rr, const c64 *rh, 
   }
   double out[3];
   block_sum<3>(acc, out);
-  if (threadIdx.x == 0) {
-    double *o = partial + ((size_t)r * nblk + blockIdx.x) * kPart;
-    o[0] = out[0];
-    o[1] = out[1];
-    o[2] = out[2];
-  }
+  if (threadIdx.x == 0) write_record<3>(partial, r, nblk, blockIdx.x, out);
 }
 
-// End of a BiCGSTAB iteration (step = 1, bsign = +1) or of a BiCGstab(2)
-// cycle (step = 2, bsign = -1: rho0 is first replaced by -omega rho0, so
-// beta = alpha rho1 / (-omega rho0)).
 __global__ void kk_scalar_rho(const double *partial, int nblk, c64 *scal, int *active, int *status, int step,
                               double bsign) {
   const int r = blockIdx.x;
@@ -262,7 +197,7 @@ __global__ void kk_true_residual(const int *check, const c64 *b, const c64 *ax, 
   }
   double out[1];
   block_sum<1>(acc, out);
-  if (threadIdx.x == 0) partial[((size_t)r * nblk + blockIdx.x) * kPart] = out[0];
+  if (threadIdx.x == 0) write_record<1>(partial, r, nblk, blockIdx.x, out);
 }
 
 __global__ void kk_scalar_true(const double *partial, int nblk, c64 *scal, const int *check) {
@@ -375,12 +310,7 @@ __global__ void kk2_update_mr(const int *active, c64 *x, c64 *r0, const c64 *r1,
   }
   double out[3];
   block_sum<3>(acc, out);
-  if (threadIdx.x == 0) {
-    double *o = partial + ((size_t)r * nblk + blockIdx.x) * kPart;
-    o[0] = out[0];
-    o[1] = out[1];
-    o[2] = out[2];
-  }
+  if (threadIdx.x == 0) write_record<3>(partial, r, nblk, blockIdx.x, out);
 }
 
 // ------------------------------------------------------------- host wrappers --
@@ -392,31 +322,17 @@ void k_init_state(const KrylovState &k, double tol, int max_iter, hipStream_t s)
                      tol * tol, max_iter);
   DDA_HIP(hipGetLastError());
 }
-void k_update_p(const KrylovState &k, hipStream_t s) {
-  hipLaunchKernelGGL(kk_update_p, vgrid(k), dim3(KNT), 0, s, k.active, k.r, k.p, k.v, k.scal, k.n3, k.nblk);
-}
-void k_dot_rv(const KrylovState &k, hipStream_t s) {
-  hipLaunchKernelGGL(kk_dot_rv, vgrid(k), dim3(KNT), 0, s, k.active, k.rh, k.v, k.n3, k.partial, k.nblk);
-}
 void k_scalar_alpha(const KrylovState &k, hipStream_t s, int nrec) {
   hipLaunchKernelGGL(kk_scalar_alpha, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, nrec, k.scal, k.active, k.status);
 }
-void k_update_s(const KrylovState &k, hipStream_t s) {
-  hipLaunchKernelGGL(kk_update_s, vgrid(k), dim3(KNT), 0, s, k.active, k.r, k.v, k.s, k.scal, k.n3, k.nblk);
-}
-void k_dot_ts(const KrylovState &k, hipStream_t s) {
-  hipLaunchKernelGGL(kk_dot_ts, vgrid(k), dim3(KNT), 0, s, k.active, k.t, k.s, k.n3, k.partial, k.nblk);
-}
-void k_scalar_omega(const KrylovState &k, hipStream_t s, int nrec) {
-  hipLaunchKernelGGL(kk_scalar_omega, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, nrec, k.scal, k.active);
-}
-void k_update_xr(const KrylovState &k, hipStream_t s) {
+void k_update_xr(const KrylovState &k, hipStream_t s, int nrec) {
   hipLaunchKernelGGL(kk_update_xr, vgrid(k), dim3(KNT), 0, s, k.active, k.x, k.r, k.rh, k.p, k.s, k.t, k.scal, k.n3,
-                     k.partial, k.nblk);
+                     k.partial, nrec, k.partial2, k.nblk);
 }
 void k_scalar_rho(const KrylovState &k, hipStream_t s, int step, double bsign) {
-  hipLaunchKernelGGL(kk_scalar_rho, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, k.nblk, k.scal, k.active, k.status,
-                     step, bsign);
+  // BiCGSTAB: records of kk_update_xr (partial2); BiCGstab(2): of kk2_update_mr (partial)
+  hipLaunchKernelGGL(kk_scalar_rho, dim3(k.nrhs), dim3(KNT), 0, s, step == 1 ? k.partial2 : k.partial, k.nblk,
+                     k.scal, k.active, k.status, step, bsign);
 }
 void k2_scalar_rho1(const KrylovState &k, hipStream_t s, int nrec) {
   hipLaunchKernelGGL(kk2_scalar_rho1, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, nrec, k.scal, k.active, k.status);
@@ -492,11 +408,7 @@ __global__ void kk_cross(const int32_t *ijk, int64_t n, const RhsDev *rhs, doubl
   }
   double out[2];
   block_sum<2>(acc, out);
-  if (threadIdx.x == 0) {
-    double *o = partial + ((size_t)r * nblk + blockIdx.x) * kPart;
-    o[0] = out[0];
-    o[1] = out[1];
-  }
+  if (threadIdx.x == 0) write_record<2>(partial, r, nblk, blockIdx.x, out);
 }
 
 __global__ void kk_cross_final(const double *partial, int nblk, double *sums) {
@@ -516,26 +428,6 @@ void launch_cross_sums(const Geometry &g, const int32_t *ijk, const RhsDev *rhs,
   hipLaunchKernelGGL(kk_cross, dim3(nblk, nrhs), dim3(KNT), 0, s, ijk, g.n_sites, rhs, kd, P, ainv, ncomp, comp,
                      partial, nblk);
   hipLaunchKernelGGL(kk_cross_final, dim3(nrhs), dim3(KNT), 0, s, partial, nblk, sums);
-  DDA_HIP(hipGetLastError());
-}
-
-// ------------------------------------------------------------ misc vectors --
-__global__ void kk_copy(c64 *dst, const c64 *src, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = src[i];
-}
-__global__ void kk_zero(c64 *dst, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = {0.0, 0.0};
-}
-void copy_vec(c64 *dst, const c64 *src, int64_t n, hipStream_t s) {
-  const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(kk_copy, dim3(nb), dim3(256), 0, s, dst, src, n);
-  DDA_HIP(hipGetLastError());
-}
-void zero_vec(c64 *dst, int64_t n, hipStream_t s) {
-  const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(kk_zero, dim3(nb), dim3(256), 0, s, dst, n);
   DDA_HIP(hipGetLastError());
 }
 

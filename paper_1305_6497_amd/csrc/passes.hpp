@@ -90,6 +90,35 @@ __device__ __forceinline__ void x_row_offsets(int *rowoff, const PassDims &d, in
   }
 }
 
+// BiCGSTAB alpha = rho / <rh, v> from the records of the product that made v.
+// Every block computes the same sum in the same order, so all agree; block 0
+// stores alpha, or flags the breakdown.  Returns false on breakdown.
+__device__ __forceinline__ bool block_alpha(const FuseArgs &f, int r, c64 &alpha) {
+  __shared__ c64 s_alpha;
+  __shared__ int s_ok;
+  double s[2];
+  sum_records<2, kNT>(f.partial, f.nrec, r, s);
+  if (threadIdx.x == 0) {
+    c64 *sc = f.scal + (size_t)r * kScal;
+    const c64 den = {s[0], s[1]};
+    const bool ok = cabs2(den) > 1e-60 * sc[S_RH2].x * sc[S_RNORM2].x && cabs2(den) > 0.0;
+    const c64 a = ok ? cdiv(sc[S_RHO], den) : c64{0, 0};
+    s_alpha = a;
+    s_ok = ok ? 1 : 0;
+    if (blockIdx.x == 0) {
+      if (ok) {
+        sc[S_ALPHA] = a;
+      } else {
+        f.active[r] = 0;
+        f.status[r] = ST_BREAK;
+      }
+    }
+  }
+  __syncthreads();
+  alpha = s_alpha;
+  return s_ok != 0;
+}
+
 // --------------------------------------------------------------- x-forward --
 // f.in_mode (see FuseArgs): 0 transforms `in`; 1 and 2 first form the BiCGSTAB
 // vector p or s from r, v (and the old p) and store it, so the vector update
@@ -157,7 +186,9 @@ __global__ __launch_bounds__(kNT) void k_xfwd(const c64 *__restrict__ in, int64_
       }
   } else {
     const c64 *sc = f.scal + (size_t)r * kScal;
-    const c64 beta = sc[S_BETA], omega = sc[S_OMEGA], alpha = sc[S_ALPHA];
+    const c64 beta = sc[S_BETA], omega = sc[S_OMEGA];
+    c64 alpha = sc[S_ALPHA];
+    if (f.in_mode == 2 && f.fold_alpha && !block_alpha(f, r, alpha)) return;   // uniform per block
 #pragma unroll
     for (int i = 0; i < NE; ++i)
 #pragma unroll
@@ -537,21 +568,12 @@ __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *_
     // one partial record per block; a one-block kernel adds them in block order
     double tot[8];
     block_sum<8, kNT>(acc, tot);
-    if (threadIdx.x == 0) {
-      double *o = f.partial + ((size_t)r * gridDim.x + blockIdx.x) * kPart;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) o[k] = tot[k];
-    }
+    if (threadIdx.x == 0) write_record<8>(f.partial, r, gridDim.x, blockIdx.x, tot);
   } else if (f.out_mode != 0) {
     double a3[3] = {acc[0], acc[1], acc[2]};
     double tot[3];
     block_sum<3, kNT>(a3, tot);
-    if (threadIdx.x == 0) {
-      double *o = f.partial + ((size_t)r * gridDim.x + blockIdx.x) * kPart;
-      o[0] = tot[0];
-      o[1] = tot[1];
-      o[2] = tot[2];
-    }
+    if (threadIdx.x == 0) write_record<3>(f.partial, r, gridDim.x, blockIdx.x, tot);
   }
 }
 

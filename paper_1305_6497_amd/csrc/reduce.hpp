@@ -38,6 +38,16 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *out) {
   __syncthreads();
 }
 
+// Partial-sum records: value k of block b (of nblk) for RHS r is stored at
+// partial[(r * kPart + k) * nblk + b], so one kind of value is contiguous
+// across blocks.
+template <int NV>
+__device__ __forceinline__ void write_record(double *partial, int r, int nblk, int b, const double (&v)[NV]) {
+  static_assert(NV <= kPart, "record too long");
+#pragma unroll
+  for (int k = 0; k < NV; ++k) partial[((size_t)r * kPart + k) * nblk + b] = v[k];
+}
+
 // Sum the NV-value records [0, nblk) of RHS r in block order.  All threads of
 // the block take part; the result is valid in thread 0.  Each thread adds the
 // records tid, tid + NT, tid + 2 NT, ... in that order; the loads of U of them
@@ -49,14 +59,14 @@ __device__ __forceinline__ void sum_records(const double *partial, int nblk, int
   double v[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = 0.0;
-  const double *base = partial + (size_t)r * nblk * kPart;
+  const double *base = partial + (size_t)r * kPart * nblk;
   for (int j0 = 0; j0 < nblk; j0 += U * NT) {
     double t[U][NV];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int j = j0 + threadIdx.x + u * NT;
 #pragma unroll
-      for (int k = 0; k < NV; ++k) t[u][k] = j < nblk ? base[(size_t)j * kPart + k] : 0.0;
+      for (int k = 0; k < NV; ++k) t[u][k] = j < nblk ? base[(size_t)k * nblk + j] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
