@@ -33,6 +33,7 @@ struct dda_target {
   int32_t *d_ijk = nullptr;
   uint8_t *d_comp = nullptr;
   int *d_cell_site = nullptr;
+  int4 *d_rowtab = nullptr;       // see MatvecArgs::rowtab
   c64 *d_ghat64 = nullptr;
   c32 *d_ghat32 = nullptr;
   // workspace, grown on demand
@@ -345,6 +346,7 @@ void matvec(dda_target *t, int precision, const c64 *in, c64 *out, int nrhs, con
   a.ncomp = t->ncomp;
   a.comp = t->d_comp;
   a.cell_site = t->d_cell_site;
+  a.rowtab = t->d_rowtab;
   a.bufA = t->d_bufA;
   a.bufB = t->d_bufB;
   a.px = t->px;
@@ -615,6 +617,29 @@ int dda_setup_target(const dda_target_desc *desc, dda_target **out) {
     t->d_cell_site = t->alloc<int>(cell.size() * sizeof(int));
     DDA_HIP(hipMemcpyAsync(t->d_cell_site, cell.data(), cell.size() * sizeof(int), hipMemcpyHostToDevice,
                            t->stream));
+    // rows as runs: {first site, first x, count}, the sites numbered row after
+    // row; any other numbering disables the table.  An empty row takes the
+    // first site of the next occupied one, so the first sites never decrease.
+    std::vector<int4> rows((size_t)ny * nz);
+    bool runs = true;
+    int next = 0;
+    for (size_t row = 0; row < rows.size() && runs; ++row) {
+      const int *c = &cell[row * nx];
+      int x0 = 0;
+      while (x0 < nx && c[x0] < 0) ++x0;
+      int len = 0;
+      while (x0 + len < nx && c[x0 + len] == next + len) ++len;
+      for (int x = x0 + len; x < nx; ++x)
+        if (c[x] >= 0) runs = false;
+      if (x0 < nx && len == 0) runs = false;
+      rows[row] = int4{next, x0 < nx ? x0 : 0, len, 0};
+      next += len;
+    }
+    if (runs) {
+      t->d_rowtab = t->alloc<int4>(rows.size() * sizeof(int4));
+      DDA_HIP(hipMemcpyAsync(t->d_rowtab, rows.data(), rows.size() * sizeof(int4), hipMemcpyHostToDevice,
+                             t->stream));
+    }
     const Geometry &g = t->g;
     const size_t M = (size_t)g.Mx * g.My * g.Mz;
     t->d_ghat64 = t->alloc<c64>(6 * g.oct_elems() * sizeof(c64));

@@ -177,6 +177,10 @@ struct MatvecArgs {
   int ncomp;
   const uint8_t *comp;            // device [N] or nullptr
   const int *cell_site;           // device [nz][ny][nx], -1 = empty
+  // device [nz * ny] of {first site, first x, count} when every row's sites are
+  // one run of consecutive x with consecutive site indices (count 0: empty
+  // row), else nullptr; the x passes then move P as contiguous runs
+  const int4 *rowtab;
   void *bufA, *bufB;              // workspaces (sized for nrhs in FP64)
   const void *ghat;               // octant Green transform [6][Mzh][Myh][Mxh] (scaled by 1/M)
   const void *twx, *twy, *twz;    // twiddles of the T precision

@@ -24,6 +24,7 @@
 #pragma once
 
 #include <algorithm>
+#include <climits>
 #include <type_traits>
 
 #include "dda_internal.hpp"
@@ -90,6 +91,118 @@ __device__ __forceinline__ void x_row_offsets(int *rowoff, const PassDims &d, in
   }
 }
 
+// Rows of an x-pass block when the sites are numbered row after row
+// (MatvecArgs::rowtab): the block's sites are then one contiguous range of P,
+// read and written as one run of 3 * count complex values.
+template <int NR>
+struct RowRuns {
+  // Per-row values are combined with arithmetic masks, not selected by row
+  // index: a select between array elements becomes an indexed load, which
+  // would put the arrays in scratch memory.
+  int first, count;               // first site of the block, number of sites
+  int s0[NR];                     // block-relative first site (INT_MAX past the block)
+  int step[NR];                   // change of (LDS position - site) from row q-1 to q
+  int lo[NR], len[NR];            // first x and count of row q
+  __device__ __forceinline__ RowRuns(const int4 *__restrict__ tab, int row0, int nrow, int L) {
+    const int *t = reinterpret_cast<const int *>(tab + row0);
+    first = t[0];
+    count = 0;
+    int prev = 0;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      int s = INT_MAX, x0 = 0, n = 0;
+      if (q < nrow) {
+        s = t[4 * q] - first;
+        x0 = t[4 * q + 1];
+        n = t[4 * q + 2];
+      }
+      const int base = q < nrow ? q * L + x0 - s : prev;   // LDS position of site s: base + s
+      s0[q] = s;
+      step[q] = base - prev;
+      prev = base;
+      lo[q] = x0;
+      len[q] = n;
+      count += n;
+    }
+  }
+  // LDS position q * L + x of the block-relative site s (the first sites never
+  // decrease, so the steps of rows q with s0[q] <= s add up to row q's offset)
+  __device__ __forceinline__ int pos(int s) const {
+    int b = step[0];
+#pragma unroll
+    for (int q = 1; q < NR; ++q) b += int(s0[q] <= s) * step[q];
+    return b + s;
+  }
+  // whether position x of row q holds a site
+  __device__ __forceinline__ bool holds(int q, int x) const {
+    int l = 0, n = 0;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const int m = int(q == k);
+      l += m * lo[k];
+      n += m * len[k];
+    }
+    return unsigned(x - l) < unsigned(n);
+  }
+};
+
+// Element-wise work on a run of n values, element e = threadIdx.x + i kNT:
+// every load is issued before the first store.
+template <int EPT>
+__device__ __forceinline__ void runs_load(c64 (&v)[EPT], int n, const c64 *src) {
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kNT;
+    if (e < n) v[i] = src[e];
+  }
+}
+
+// v = d = a + c b
+template <int EPT>
+__device__ __forceinline__ void runs_axpy(c64 (&v)[EPT], int n, const c64 *a, const c64 *b, c64 *d, c64 c) {
+  c64 bv[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kNT;
+    if (e < n) {
+      v[i] = a[e];
+      bv[i] = b[e];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kNT;
+    if (e < n) {
+      v[i] = v[i] + c * bv[i];
+      d[e] = v[i];
+    }
+  }
+}
+
+// v = p = r + beta (p - omega w)
+template <int EPT>
+__device__ __forceinline__ void runs_p(c64 (&v)[EPT], int n, const c64 *r, c64 *p, const c64 *w, c64 beta,
+                                       c64 omega) {
+  c64 pv[EPT], wv[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kNT;
+    if (e < n) {
+      v[i] = r[e];
+      pv[i] = p[e];
+      wv[i] = w[e];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kNT;
+    if (e < n) {
+      v[i] = v[i] + beta * (pv[i] - omega * wv[i]);
+      p[e] = v[i];
+    }
+  }
+}
+
 // BiCGSTAB alpha = rho / <rh, v> from the records of the product that made v.
 // Every block computes the same sum in the same order, so all agree; block 0
 // stores alpha, or flags the breakdown.  Returns false on breakdown.
@@ -125,7 +238,8 @@ __device__ __forceinline__ bool block_alpha(const FuseArgs &f, int r, c64 &alpha
 // costs no pass of its own.  LC > 0: Mx = LC, known at compile time.
 template <typename T, int EPT, int LC>
 __global__ __launch_bounds__(kNT) void k_xfwd(const c64 *__restrict__ in, int64_t n3, const int *__restrict__ mask,
-                                               const int *__restrict__ cell_site, cpx<T> *__restrict__ A,
+                                               const int *__restrict__ cell_site, const int4 *__restrict__ rowtab,
+                                               cpx<T> *__restrict__ A,
                                                size_t a_elems, const cpx<T> *__restrict__ twx, AxisPlan px,
                                                PassDims d, FuseArgs f) {
   constexpr int W = kW<T>, LOGW = kLogW<T>;
@@ -144,71 +258,118 @@ __global__ __launch_bounds__(kNT) void k_xfwd(const c64 *__restrict__ in, int64_
   const int nrow = min(nrows, d.ny * d.nz - row0);
   x_row_offsets<T, LC>(rowoff, d, nrows, row0, nrow);
   const size_t off = (size_t)r * n3;
-  int site[NE];
-#pragma unroll
-  for (int i = 0; i < NE; ++i) {
-    const int e = threadIdx.x + i * kNT;
-    site[i] = -1;
-    if (e < ne) {
-      const int q = LC > 0 ? e / LC : (int)d.d_mx((uint32_t)e);
-      const int x = e - q * Mx;
-      if (q < nrow && x < d.nx) site[i] = cell_site[(size_t)(row0 + q) * d.nx + x];
-    }
-  }
-  c64 v[NE][3];
-  if (f.in_mode == 0) {
-#pragma unroll
-    for (int i = 0; i < NE; ++i)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) v[i][c] = site[i] >= 0 ? in[off + (size_t)3 * site[i] + c] : c64{0, 0};
-  } else if (f.in_mode == 3) {
-    // update list d_i = a_i + c_i b_i; d_0 is transformed
+  c64 beta = {0, 0}, omega = {0, 0}, alpha = {0, 0}, cf[3] = {{0, 0}, {0, 0}, {0, 0}};
+  if (f.in_mode == 1 || f.in_mode == 2) {
     const c64 *sc = f.scal + (size_t)r * kScal;
-    c64 cf[3];
+    beta = sc[S_BETA];
+    omega = sc[S_OMEGA];
+    alpha = sc[S_ALPHA];
+    if (f.in_mode == 2 && f.fold_alpha && !block_alpha(f, r, alpha)) return;   // uniform per block
+  } else if (f.in_mode == 3) {
+    const c64 *sc = f.scal + (size_t)r * kScal;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const c64 g = a < f.nax ? sc[f.ax_slot[a]] : c64{0, 0};
       cf[a] = f.ax_neg[a] ? c64{-g.x, -g.y} : g;
     }
-#pragma unroll
-    for (int i = 0; i < NE; ++i)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        c64 val = {0, 0};
-        if (site[i] >= 0) {
-          const size_t j = off + (size_t)3 * site[i] + c;
-          val = f.ax_a[0][j] + cf[0] * f.ax_b[0][j];
-          f.ax_d[0][j] = val;
-          if (f.nax > 1) f.ax_d[1][j] = f.ax_a[1][j] + cf[1] * f.ax_b[1][j];
-          if (f.nax > 2) f.ax_d[2][j] = f.ax_a[2][j] + cf[2] * f.ax_b[2][j];
-        }
-        v[i][c] = val;
-      }
-  } else {
-    const c64 *sc = f.scal + (size_t)r * kScal;
-    const c64 beta = sc[S_BETA], omega = sc[S_OMEGA];
-    c64 alpha = sc[S_ALPHA];
-    if (f.in_mode == 2 && f.fold_alpha && !block_alpha(f, r, alpha)) return;   // uniform per block
-#pragma unroll
-    for (int i = 0; i < NE; ++i)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        c64 val = {0, 0};
-        if (site[i] >= 0) {
-          const size_t j = off + (size_t)3 * site[i] + c;
-          if (f.in_mode == 1) val = f.r[j] + beta * (f.w[j] - omega * f.v[j]);
-          else val = f.r[j] - alpha * f.v[j];
-          f.w[j] = val;
-        }
-        v[i][c] = val;
-      }
   }
+  bool staged = false;
+  if constexpr (LC > 0) {
+    // the block's sites as one run of P; with Mx >= 2 nx - 1 a block holds at
+    // most NR (Mx + 1) / 2 sites, which sizes the registers of this path
+    constexpr int NR = xpass_rows(LC > 0 ? LC : 1);
+    constexpr int ER = (3 * NR * ((LC + 1) / 2) + kNT - 1) / kNT;
+    if (rowtab && d.nx <= (LC + 1) / 2) {
+      const RowRuns<NR> rr(rowtab, row0, nrow, LC);
+      const int n = 3 * rr.count;
+      const size_t j0 = off + (size_t)3 * rr.first;
+      c64 v[ER];
+      if (f.in_mode == 0) {
+        runs_load(v, n, in + j0);
+      } else if (f.in_mode == 1) {
+        runs_p(v, n, f.r + j0, f.w + j0, f.v + j0, beta, omega);
+      } else if (f.in_mode == 2) {
+        runs_axpy(v, n, f.r + j0, f.v + j0, f.w + j0, c64{-alpha.x, -alpha.y});
+      } else {
+        runs_axpy(v, n, f.ax_a[0] + j0, f.ax_b[0] + j0, f.ax_d[0] + j0, cf[0]);
+        c64 u[ER];
+        if (f.nax > 1) runs_axpy(u, n, f.ax_a[1] + j0, f.ax_b[1] + j0, f.ax_d[1] + j0, cf[1]);
+        if (f.nax > 2) runs_axpy(u, n, f.ax_a[2] + j0, f.ax_b[2] + j0, f.ax_d[2] + j0, cf[2]);
+      }
 #pragma unroll
-  for (int i = 0; i < NE; ++i) {
-    const int e = threadIdx.x + i * kNT;
-    if (e < ne) {
+      for (int i = 0; i < ER; ++i) {
+        const int e = threadIdx.x + i * kNT;
+        if (e < n) {
+          const int st = e / 3;
+          buf[(e - 3 * st) * ne + rr.pos(st)] = to_t<T>(v[i]);
+        }
+      }
+      for (int e = threadIdx.x; e < ne; e += kNT) {
+        const int q = e / LC;
+        if (!rr.holds(q, e - q * LC)) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) buf[c * ne + e] = to_t<T>(v[i][c]);
+          for (int c = 0; c < 3; ++c) buf[c * ne + e] = cpx<T>{0, 0};
+        }
+      }
+      staged = true;
+    }
+  }
+  if (!staged) {
+    int site[NE];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = threadIdx.x + i * kNT;
+      site[i] = -1;
+      if (e < ne) {
+        const int q = LC > 0 ? e / LC : (int)d.d_mx((uint32_t)e);
+        const int x = e - q * Mx;
+        if (q < nrow && x < d.nx) site[i] = cell_site[(size_t)(row0 + q) * d.nx + x];
+      }
+    }
+    c64 v[NE][3];
+    if (f.in_mode == 0) {
+#pragma unroll
+      for (int i = 0; i < NE; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[i][c] = site[i] >= 0 ? in[off + (size_t)3 * site[i] + c] : c64{0, 0};
+    } else if (f.in_mode == 3) {
+      // update list d_i = a_i + c_i b_i; d_0 is transformed
+#pragma unroll
+      for (int i = 0; i < NE; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          c64 val = {0, 0};
+          if (site[i] >= 0) {
+            const size_t j = off + (size_t)3 * site[i] + c;
+            val = f.ax_a[0][j] + cf[0] * f.ax_b[0][j];
+            f.ax_d[0][j] = val;
+            if (f.nax > 1) f.ax_d[1][j] = f.ax_a[1][j] + cf[1] * f.ax_b[1][j];
+            if (f.nax > 2) f.ax_d[2][j] = f.ax_a[2][j] + cf[2] * f.ax_b[2][j];
+          }
+          v[i][c] = val;
+        }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NE; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          c64 val = {0, 0};
+          if (site[i] >= 0) {
+            const size_t j = off + (size_t)3 * site[i] + c;
+            if (f.in_mode == 1) val = f.r[j] + beta * (f.w[j] - omega * f.v[j]);
+            else val = f.r[j] - alpha * f.v[j];
+            f.w[j] = val;
+          }
+          v[i][c] = val;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = threadIdx.x + i * kNT;
+      if (e < ne) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) buf[c * ne + e] = to_t<T>(v[i][c]);
+      }
     }
   }
   __syncthreads();
@@ -478,9 +639,9 @@ template <typename T, int EPT, int LC>
 __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *__restrict__ out, int64_t n3,
                                                const int *__restrict__ mask, const c64 *__restrict__ ainv,
                                                int ncomp, const uint8_t *__restrict__ comp,
-                                               const int *__restrict__ cell_site, const cpx<T> *__restrict__ A,
-                                               size_t a_elems, const cpx<T> *__restrict__ twx, AxisPlan px,
-                                               PassDims d, FuseArgs f) {
+                                               const int *__restrict__ cell_site, const int4 *__restrict__ rowtab,
+                                               const cpx<T> *__restrict__ A, size_t a_elems,
+                                               const cpx<T> *__restrict__ twx, AxisPlan px, PassDims d, FuseArgs f) {
   constexpr int W = kW<T>, LOGW = kLogW<T>;
   constexpr int NE = (EPT + 2) / 3;
   const int r = blockIdx.y;
@@ -508,58 +669,92 @@ __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *_
   fft_rows<T, EPT, +1, LC>(buf, tw, px, 3 * nrows);
   const size_t off = (size_t)r * n3;
   const c64 *ai = ainv + (size_t)r * ncomp;
-  const int nsite = nrow * d.nx;
-  const int *cs = cell_site + (size_t)row0 * d.nx;
-  int site[NE], bi[NE];
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  // out = ainv P - (G P) at one element; x is rh (out_mode 1) or r0 (out_mode 3)
+  auto finish = [&](size_t j, c64 a, c64 pv, cpx<T> fv, c64 x) {
+    const c64 dd = a * pv;
+    const c64 o = c64{dd.x - double(fv.x), dd.y - double(fv.y)};
+    out[j] = o;
+    if (f.out_mode == 1) {
+      const c64 g = cmulc(x, o);
+      acc[0] += g.x;
+      acc[1] += g.y;
+    } else if (f.out_mode == 2) {
+      const c64 g = cmulc(o, pv);
+      acc[0] += g.x;
+      acc[1] += g.y;
+      acc[2] += o.x * o.x + o.y * o.y;
+    } else if (f.out_mode == 3) {
+      // in = r1, out = r2, f.r = r0
+      const c64 g12 = cmulc(pv, o), g10 = cmulc(pv, x), g20 = cmulc(o, x);
+      acc[0] += pv.x * pv.x + pv.y * pv.y;
+      acc[1] += o.x * o.x + o.y * o.y;
+      acc[2] += g12.x;
+      acc[3] += g12.y;
+      acc[4] += g10.x;
+      acc[5] += g10.y;
+      acc[6] += g20.x;
+      acc[7] += g20.y;
+    }
+  };
+  const c64 *xsrc = f.out_mode == 1 ? f.rh : f.out_mode == 3 ? f.r : nullptr;
+  bool done = false;
+  if constexpr (LC > 0) {
+    constexpr int NR = xpass_rows(LC > 0 ? LC : 1);
+    constexpr int ER = (3 * NR * ((LC + 1) / 2) + kNT - 1) / kNT;
+    if (rowtab && d.nx <= (LC + 1) / 2) {
+      const RowRuns<NR> rr(rowtab, row0, nrow, LC);
+      const int n = 3 * rr.count;
+      const size_t j0 = off + (size_t)3 * rr.first;
+      c64 pv[ER], xv[ER], av[ER];
 #pragma unroll
-  for (int i = 0; i < NE; ++i) {
-    const int e = threadIdx.x + i * kNT;
-    site[i] = -1;
-    bi[i] = 0;
-    if (e < nsite) {
-      site[i] = cs[e];
-      const int q = (int)d.d_nx((uint32_t)e);
-      bi[i] = q * Mx + (e - q * d.nx);
+      for (int i = 0; i < ER; ++i) {
+        const int e = threadIdx.x + i * kNT;
+        if (e < n) {
+          pv[i] = in[j0 + e];
+          xv[i] = xsrc ? xsrc[j0 + e] : c64{0, 0};
+          av[i] = ai[comp ? comp[rr.first + e / 3] : 0];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < ER; ++i) {
+        const int e = threadIdx.x + i * kNT;
+        if (e < n) {
+          const int st = e / 3;
+          finish(j0 + e, av[i], pv[i], buf[(e - 3 * st) * ne + rr.pos(st)], xv[i]);
+        }
+      }
+      done = true;
     }
   }
-  c64 pv[NE][3];
+  if (!done) {
+    const int nsite = nrow * d.nx;
+    const int *cs = cell_site + (size_t)row0 * d.nx;
+    int site[NE], bi[NE];
 #pragma unroll
-  for (int i = 0; i < NE; ++i)
+    for (int i = 0; i < NE; ++i) {
+      const int e = threadIdx.x + i * kNT;
+      site[i] = -1;
+      bi[i] = 0;
+      if (e < nsite) {
+        site[i] = cs[e];
+        const int q = (int)d.d_nx((uint32_t)e);
+        bi[i] = q * Mx + (e - q * d.nx);
+      }
+    }
+    c64 pv[NE][3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) pv[i][c] = site[i] >= 0 ? in[off + (size_t)3 * site[i] + c] : c64{0, 0};
-  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < NE; ++i)
 #pragma unroll
-  for (int i = 0; i < NE; ++i) {
-    if (site[i] >= 0) {
-      const c64 a = ai[comp ? comp[site[i]] : 0];
+      for (int c = 0; c < 3; ++c) pv[i][c] = site[i] >= 0 ? in[off + (size_t)3 * site[i] + c] : c64{0, 0};
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const size_t j = off + (size_t)3 * site[i] + c;
-        const cpx<T> fv = buf[c * ne + bi[i]];
-        const c64 dd = a * pv[i][c];
-        const c64 o = c64{dd.x - double(fv.x), dd.y - double(fv.y)};
-        out[j] = o;
-        if (f.out_mode == 1) {
-          const c64 g = cmulc(f.rh[j], o);
-          acc[0] += g.x;
-          acc[1] += g.y;
-        } else if (f.out_mode == 2) {
-          const c64 g = cmulc(o, pv[i][c]);
-          acc[0] += g.x;
-          acc[1] += g.y;
-          acc[2] += o.x * o.x + o.y * o.y;
-        } else if (f.out_mode == 3) {
-          // in = r1, out = r2, f.r = r0
-          const c64 r1 = pv[i][c], r0 = f.r[j];
-          const c64 g12 = cmulc(r1, o), g10 = cmulc(r1, r0), g20 = cmulc(o, r0);
-          acc[0] += r1.x * r1.x + r1.y * r1.y;
-          acc[1] += o.x * o.x + o.y * o.y;
-          acc[2] += g12.x;
-          acc[3] += g12.y;
-          acc[4] += g10.x;
-          acc[5] += g10.y;
-          acc[6] += g20.x;
-          acc[7] += g20.y;
+    for (int i = 0; i < NE; ++i) {
+      if (site[i] >= 0) {
+        const c64 a = ai[comp ? comp[site[i]] : 0];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const size_t j = off + (size_t)3 * site[i] + c;
+          finish(j, a, pv[i][c], buf[c * ne + bi[i]], xsrc ? xsrc[j] : c64{0, 0});
         }
       }
     }
@@ -683,7 +878,7 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
           constexpr int LC = decltype(lc)::value;
           constexpr int E = LC > 0 ? pick_ept_c((size_t)3 * xpass_rows(LC) * LC, true) : decltype(e)::value;
           hipLaunchKernelGGL((k_xfwd<T, E, LC>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s, a.in, n3, a.mask,
-                             a.cell_site, A, ae, twx, a.px, d, f);
+                             a.cell_site, a.rowtab, A, ae, twx, a.px, d, f);
         });
         break;
       case 1:
@@ -735,7 +930,7 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
           constexpr int LC = decltype(lc)::value;
           constexpr int E = LC > 0 ? pick_ept_c((size_t)3 * xpass_rows(LC) * LC, true) : decltype(e)::value;
           hipLaunchKernelGGL((k_xinv<T, E, LC>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s, a.in, a.out, n3,
-                             a.mask, a.ainv, a.ncomp, a.comp, a.cell_site, A, ae, twx, a.px, d, f);
+                             a.mask, a.ainv, a.ncomp, a.comp, a.cell_site, a.rowtab, A, ae, twx, a.px, d, f);
         });
         break;
     }

@@ -97,6 +97,10 @@ SMALL_TARGETS = [
     ("RCTGLPRSM", (2, 2, 128)),
     ("RCTGLPRSM", (2, 128, 2)),
     ("RCTGLPRSM", (128, 2, 2)),
+    # the largest supported extent: 256 dipoles -> a padded axis of 512
+    ("RCTGLPRSM", (2, 2, 256)),
+    ("RCTGLPRSM", (2, 256, 2)),
+    ("RCTGLPRSM", (256, 2, 2)),
 ]
 
 
@@ -116,6 +120,54 @@ def test_matvec_fp64_and_mixed_against_direct_sum(dda, shape, shpar):
     t.close()
     assert _rel(a64, ref) < 1e-12
     assert _rel(a32, ref) < 5e-6
+
+
+# Sites numbered row after row (the order make_sites returns) take the x
+# passes' contiguous-run path; any other numbering takes the per-cell path.
+# Both must give the same products and the same solves.
+@pytest.mark.parametrize("shape,shpar", [("ELLIPSOID", (11, 6, 5)), ("HEX_PRISM", (6, 9, 2)),
+                                         ("ELLIPSOID", (21, 17, 14.5)), ("RCTGLPRSM", (3, 140, 2))])
+def test_matvec_independent_of_site_numbering(dda, shape, shpar):
+    sites, box = dda.make_sites(shape, shpar)
+    osites = targets.make(shape, shpar)
+    perm = np.random.default_rng(17).permutation(len(sites))
+    kd, m = 0.45, 1.6 + 0.05j
+    rhs = [dda.orient_rhs(0.3, 1.1, 2.0, which=1)]
+    P = inputs.random_polarization(len(sites), 1, seed=6)
+    ref = interaction.direct_matvec(osites, kd, _oracle_ainv(m, kd, *rhs[0]), P[0])
+    for order in (np.arange(len(sites)), perm):
+        t = dda.Target(np.ascontiguousarray(sites[order]), box, m=m, kd=kd)
+        Pt = torch.tensor(P[:, order], dtype=torch.complex128, device="cuda")
+        a64 = t.apply(rhs, Pt, "fp64").cpu().numpy()[0]
+        a32 = t.apply(rhs, Pt, "mixed").cpu().numpy()[0]
+        t.close()
+        assert _rel(a64, ref[order]) < 1e-12
+        assert _rel(a32, ref[order]) < 5e-6
+
+
+@pytest.mark.parametrize("solver", ["bicgstab", "bicgstab2"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_independent_of_site_numbering(dda, solver, precision):
+    sites, box = dda.make_sites("ELLIPSOID", (13, 10, 8.5))
+    perm = np.random.default_rng(23).permutation(len(sites))
+    kd, m = 0.4, 1.7 + 0.1j
+    rhs = [dda.orient_rhs(0.2, 0.7, 1.3, which=1), dda.orient_rhs(0.2, 0.7, 1.3, which=2)]
+    out = []
+    for order in (np.arange(len(sites)), perm):
+        t = dda.Target(np.ascontiguousarray(sites[order]), box, m=m, kd=kd)
+        P, st = t.solve(rhs, tol=1e-9, precision=precision, solver=solver)
+        q = t.cross_sections(rhs, P)
+        Pg = P.cpu().numpy()
+        t.close()
+        assert all(s["status"] == 0 for s in st)
+        inv = np.empty_like(order)
+        inv[order] = np.arange(len(order))
+        out.append((Pg[:, inv], q))
+    # two solves to residual 1e-9: P agrees to the conditioning times that
+    assert _rel(out[0][0], out[1][0]) < 1e-6
+    for r in range(2):
+        for key in ("qext", "qabs", "qsca"):
+            assert abs(out[0][1][r][key] - out[1][1][r][key]) <= 1e-8 * out[0][1][r]["qext"], key
 
 
 def test_matvec_multi_composition(dda):

@@ -121,6 +121,11 @@ def test_invalid_inputs_are_rejected_before_device_work(dda):
     with pytest.raises(dda.DDAError) as ei:
         dda.footprint_bytes((300, 10, 10), 100)
     assert ei.value.code == L.DDA_ENOTSUP
+    # 256 dipoles pad to 512, the largest transform; 257 would need 513 -> 540
+    assert dda.footprint_bytes((256, 2, 2), 100) > 0
+    with pytest.raises(dda.DDAError) as ei:
+        dda.footprint_bytes((2, 257, 2), 100)
+    assert ei.value.code == L.DDA_ENOTSUP
 
 
 def test_setup_rejects_bad_sites_without_device(dda):
