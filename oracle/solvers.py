@@ -44,6 +44,37 @@
   published algorithm does it by Gram-Schmidt on r_1..r_l).  Same stopping
   rule and restarts as ``bicgstab``; ``iters`` counts BiCG steps (l per
   cycle), so one iteration is two products as in ``bicgstab``.
+* ``cocg``: conjugate orthogonal conjugate gradients (van der Vorst &
+  Melissen 1990), CG with the bilinear form a^T b in place of the inner
+  product; it applies because A is complex symmetric (A^T = A: the Green
+  tensor is symmetric in its indices and in the two sites, and the diagonal
+  is alpha^-1 I).  One product per iteration:
+
+      r = E - A x,  p = r,  rho = r^T r
+      repeat:
+          q = A p;  alpha = rho / p^T q;  x = x + alpha p;  r = r - alpha q
+          rho' = r^T r;  beta = rho'/rho;  rho = rho';  p = r + beta p
+
+  Same stopping rule and restarts as ``bicgstab`` (breakdown: p^T q or
+  rho' ~ 0).  Not among the guide's options; it is the method its QMRCCG
+  option smooths (next item).
+* ``qmr_cs``: the quasi-minimal-residual method for complex symmetric
+  systems (Freund 1992), the QMRCCG option of §12 (the guide cites its
+  authors' code without printing it).  Complex-symmetric Lanczos with
+  Lanczos vectors of unit 2-norm, v_1 = E / |E|, rho_1 = |E|:
+
+      delta_n = v_n^T v_n;  alpha_n = v_n^T A v_n / delta_n
+      beta_n = rho_n delta_n / delta_{n-1}            (n > 1; 0 for n = 1)
+      w = A v_n - alpha_n v_n - beta_n v_{n-1};  rho_{n+1} = |w|;  v_{n+1} = w / rho_{n+1}
+
+  so A V_n = V_{n+1} T_n with T_n tridiagonal (diagonal alpha_n, subdiagonal
+  rho_{n+1}, superdiagonal beta_{n+1}), and x_n = V_n z_n with z_n the
+  least-squares solution of T_n z = rho_1 e_1, updated by Givens rotations
+  (c real, s complex) and three-term search directions
+      d_n = (v_n - zeta_n d_{n-1} - eps_n d_{n-2}) / gamma_n,   x_n = x_{n-1} + tau_n d_n.
+  The quasi-residual |phi_{n+1}| bounds the true residual by
+  sqrt(n+1) |phi_{n+1}|; when |phi_{n+1}| <= tol |E| the true residual is
+  computed and, if it does not pass, the method restarts from the current x.
 """
 
 import numpy as np
@@ -201,5 +232,156 @@ def bicgstab_l(matvec, b, ell=2, tol=1e-10, maxiter=10000, x0=None):
                 return x.reshape(shape), dict(iters=it, matvecs=nmv, rel_resid=rel, converged=True)
             res = rtrue
             restart = True
+    rel = np.linalg.norm(b - mv(x)) / nb
+    return x.reshape(shape), dict(iters=it, matvecs=nmv + 1, rel_resid=rel, converged=rel <= tol)
+
+
+def cocg(matvec, b, tol=1e-10, maxiter=10000, x0=None, trace=None):
+    """COCG; returns (x, info) like ``bicgstab`` (one product per iteration).
+
+    ``trace``: optional list; the iterate x and the residual r after every
+    iteration are appended (for tests).
+    """
+    b = np.asarray(b, dtype=complex)
+    shape = b.shape
+    b = b.ravel()
+    mv = lambda v: np.asarray(matvec(v.reshape(shape)), dtype=complex).ravel()
+    nb = np.linalg.norm(b)
+    x = np.zeros_like(b) if x0 is None else np.asarray(x0, dtype=complex).ravel().copy()
+    nmv = 0
+    if nb == 0.0:
+        return x.reshape(shape), dict(iters=0, matvecs=0, rel_resid=0.0, converged=True)
+    if x0 is None:
+        r = b.copy()
+    else:
+        r = b - mv(x)
+        nmv += 1
+    it = 0
+    restart = True
+    while it < maxiter:
+        if restart:
+            p = r.copy()
+            rho = r @ r
+            restart = False
+        q = mv(p)
+        nmv += 1
+        pq = p @ q
+        if abs(pq) <= 1e-30 * nb * np.linalg.norm(p) or abs(rho) <= 1e-30 * nb * nb:
+            r = b - mv(x)
+            nmv += 1
+            restart = True
+            it += 1
+            continue
+        alpha = rho / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        it += 1
+        if trace is not None:
+            trace.append((x.copy(), r.copy()))
+        if np.linalg.norm(r) / nb <= tol:
+            rtrue = b - mv(x)
+            nmv += 1
+            rel = np.linalg.norm(rtrue) / nb
+            if rel <= tol:
+                return x.reshape(shape), dict(iters=it, matvecs=nmv, rel_resid=rel, converged=True)
+            r = rtrue
+            restart = True
+            continue
+        rho_new = r @ r
+        beta = rho_new / rho
+        rho = rho_new
+        p = r + beta * p
+    rel = np.linalg.norm(b - mv(x)) / nb
+    return x.reshape(shape), dict(iters=it, matvecs=nmv + 1, rel_resid=rel, converged=rel <= tol)
+
+
+def _givens(a, b):
+    """(c, s, g) with c real >= 0, |c|^2 + |s|^2 = 1 and
+    [[c, s], [-conj(s), c]] (a, b) = (g, 0)."""
+    if b == 0:
+        return 1.0, 0.0 + 0j, a
+    if a == 0:
+        return 0.0, 1.0 + 0j, b
+    h = np.hypot(abs(a), abs(b))
+    ph = a / abs(a)
+    return abs(a) / h, ph * np.conj(b) / h, ph * h
+
+
+def qmr_cs(matvec, b, tol=1e-10, maxiter=10000, x0=None, trace=None):
+    """QMR for complex symmetric A; returns (x, info) like ``bicgstab``.
+
+    ``trace``: optional list; (x_n, |phi_{n+1}|) is appended after every
+    iteration of the first Lanczos run (for tests).
+    """
+    b = np.asarray(b, dtype=complex)
+    shape = b.shape
+    b = b.ravel()
+    mv = lambda v: np.asarray(matvec(v.reshape(shape)), dtype=complex).ravel()
+    nb = np.linalg.norm(b)
+    x = np.zeros_like(b) if x0 is None else np.asarray(x0, dtype=complex).ravel().copy()
+    nmv = 0
+    if nb == 0.0:
+        return x.reshape(shape), dict(iters=0, matvecs=0, rel_resid=0.0, converged=True)
+    if x0 is None:
+        r = b.copy()
+    else:
+        r = b - mv(x)
+        nmv += 1
+    it = 0
+    first = True
+    while it < maxiter:
+        # one Lanczos run from the residual r of the current x
+        rho = np.linalg.norm(r)
+        v = r / rho
+        v_old = np.zeros_like(b)
+        d1 = np.zeros_like(b)
+        d2 = np.zeros_like(b)
+        c1 = c2 = 1.0
+        s1 = s2 = 0.0 + 0j
+        phi = rho + 0j
+        delta_old = 1.0 + 0j
+        n = 0
+        while it < maxiter:
+            n += 1
+            delta = v @ v
+            if abs(delta) <= 1e-30:
+                # Lanczos breakdown: restart from the current x
+                it += 1
+                r = b - mv(x)
+                nmv += 1
+                break
+            w = mv(v)
+            nmv += 1
+            alpha = (v @ w) / delta
+            beta = rho * delta / delta_old if n > 1 else 0.0
+            w = w - alpha * v - beta * v_old
+            rho_next = np.linalg.norm(w)
+            # column n of T_n: beta_n (row n-1), alpha_n (row n), rho_{n+1} (row n+1)
+            eps = s2 * beta
+            bp = c2 * beta
+            zeta = c1 * bp + s1 * alpha
+            gp = -np.conj(s1) * bp + c1 * alpha
+            c, sn, gamma = _givens(gp, rho_next)
+            tau = c * phi
+            phi = -np.conj(sn) * phi
+            d = (v - zeta * d1 - eps * d2) / gamma
+            x = x + tau * d
+            it += 1
+            d2, d1 = d1, d
+            c2, s2, c1, s1 = c1, s1, c, sn
+            if first and trace is not None:
+                trace.append((x.copy(), abs(phi)))
+            if abs(phi) <= tol * nb or rho_next == 0.0:
+                r = b - mv(x)
+                nmv += 1
+                rel = np.linalg.norm(r) / nb
+                if rel <= tol:
+                    return x.reshape(shape), dict(iters=it, matvecs=nmv, rel_resid=rel, converged=True)
+                break                        # restart from the true residual
+            v_old = v
+            v = w / rho_next
+            delta_old = delta
+            rho = rho_next
+        first = False
     rel = np.linalg.norm(b - mv(x)) / nb
     return x.reshape(shape), dict(iters=it, matvecs=nmv + 1, rel_resid=rel, converged=rel <= tol)

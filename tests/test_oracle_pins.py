@@ -339,6 +339,120 @@ def test_bicgstab2_zero_rhs_and_scaled_identity():
     assert np.abs(x - E / c).max() < 1e-14 * np.abs(E / c).max()
 
 
+def test_dda_matrix_is_complex_symmetric():
+    # COCG and QMR-CS need A^T = A (not A^H = A): the Green tensor is
+    # symmetric in its indices and in the pair of sites
+    s = targets.ellipsoid(5, 4, 3)
+    kd, m = 0.6, 1.7 + 0.3j
+    ai = pol.alpha_inv_ldr(m, kd, np.array([1.0, 0, 0]), np.array([0, 1.0, 0]))
+    A = interaction.dense_matrix(s, kd, ai)
+    assert np.abs(A - A.T).max() < 1e-14 * np.abs(A).max()
+    assert np.abs(A - A.conj().T).max() > 1e-3 * np.abs(A).max()
+
+
+def test_cocg_is_cg_for_real_spd():
+    # On a real symmetric positive definite system the bilinear form is the
+    # inner product: COCG's iterates are textbook CG's (SciPy's cg, x0 = 0)
+    sp_linalg = pytest.importorskip("scipy.sparse.linalg")
+    rng = np.random.default_rng(3)
+    n = 30
+    Q = rng.standard_normal((n, n))
+    A = Q @ Q.T + n * np.eye(n)
+    b = rng.standard_normal(n)
+    ref = []
+    sp_linalg.cg(A, b, rtol=1e-30, atol=0.0, maxiter=8, callback=lambda xk: ref.append(xk.copy()))
+    tr = []
+    solvers.cocg(lambda v: A @ v, b.astype(complex), tol=1e-30, maxiter=8, trace=tr)
+    assert len(ref) == len(tr) == 8
+    for xr, (xc, _) in zip(ref, tr):
+        assert np.abs(xc - xr).max() < 1e-12 * np.abs(xr).max()
+        assert np.abs(xc.imag).max() == 0.0
+
+
+def test_cocg_residuals_are_conjugate_orthogonal():
+    # r_i^T r_j = 0 for i != j (bilinear, not Hermitian) on a complex symmetric A
+    rng = np.random.default_rng(4)
+    n = 40
+    B = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    A = (B + B.T) / 2 + 8 * np.eye(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    tr = []
+    solvers.cocg(lambda v: A @ v, b, tol=1e-30, maxiter=6, trace=tr)
+    res = [b] + [r for _, r in tr]
+    for i in range(len(res)):
+        for j in range(i):
+            bil = abs(res[i] @ res[j]) / (np.linalg.norm(res[i]) * np.linalg.norm(res[j]))
+            assert bil < 1e-10, (i, j)
+    # while the Hermitian products are not zero
+    assert abs(np.vdot(res[1], res[0])) > 1e-3 * np.linalg.norm(res[1]) * np.linalg.norm(res[0])
+
+
+def test_qmr_cs_is_qmr_smoothing_of_cocg():
+    # Two independent formulations of the same iterates: QMR-CS from the
+    # complex-symmetric Lanczos process with Givens rotations, and the
+    # quasi-minimal-residual smoothing of COCG (Zhou & Walker 1994):
+    #     theta = |r_k| / tau;  c^2 = 1 / (1 + theta^2);  tau = tau theta c
+    #     y_k = y_{k-1} + c^2 (x_k - y_{k-1})
+    # agree iterate by iterate, and tau_k is QMR's quasi-residual |phi_{k+1}|.
+    rng = np.random.default_rng(5)
+    n = 16
+    B = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    A = (B + B.T) / 2 + 4 * np.eye(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    tc, tq = [], []
+    solvers.cocg(lambda v: A @ v, b, tol=1e-30, maxiter=10, trace=tc)
+    solvers.qmr_cs(lambda v: A @ v, b, tol=1e-30, maxiter=10, trace=tq)
+    tau = np.linalg.norm(b)
+    y = np.zeros(n, complex)
+    prev = tau
+    for (xk, rk), (xq, phi) in zip(tc, tq):
+        th = np.linalg.norm(rk) / tau
+        c2 = 1.0 / (1.0 + th * th)
+        tau = tau * th * np.sqrt(c2)
+        y = y + c2 * (xk - y)
+        assert np.abs(y - xq).max() < 1e-12 * np.abs(xq).max()
+        assert abs(tau - phi) < 1e-12 * prev
+        assert phi <= prev * (1 + 1e-14)          # quasi-residual never grows
+        prev = phi
+
+
+@pytest.mark.parametrize("name", ["cocg", "qmr_cs"])
+def test_complex_symmetric_solvers_match_dense_lu(name):
+    s = targets.ellipsoid(10, 8, 7)
+    kd, m = 0.5, 1.7 + 0.05j
+    khat, e = np.array([1.0, 0, 0]), np.array([0, 1.0, 0])
+    ai = pol.alpha_inv_ldr(m, kd, khat, e)
+    E = incident.incident_field(s, kd, khat, e)
+    A = interaction.dense_matrix(s, kd, ai)
+    P_lu = solvers.lu_solve(A, E.ravel()).reshape(-1, 3)
+    P_it, info = getattr(solvers, name)(interaction.FFTOperator(s, kd, ai).matvec, E, tol=1e-13)
+    assert info["converged"]
+    assert np.abs(P_lu - P_it).max() < 1e-11 * np.abs(P_lu).max()
+    # finite termination on a small dense system: at most n steps
+    rng = np.random.default_rng(6)
+    n = 12
+    B = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    A2 = (B + B.T) / 2 + 6 * np.eye(n)
+    b2 = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x2, info2 = getattr(solvers, name)(lambda v: A2 @ v, b2, tol=1e-12)
+    assert info2["converged"] and info2["iters"] <= n
+    assert np.abs(x2 - np.linalg.solve(A2, b2)).max() < 1e-11
+
+
+@pytest.mark.parametrize("name", ["cocg", "qmr_cs"])
+def test_complex_symmetric_solvers_zero_rhs_and_scaled_identity(name):
+    f = getattr(solvers, name)
+    s = targets.sphere(5)
+    op = interaction.FFTOperator(s, 0.3, pol.alpha_inv_cmrr(1.5, 0.3))
+    x, info = f(op.matvec, np.zeros((len(s), 3)), tol=1e-8)
+    assert info["converged"] and np.all(x == 0)
+    c = 2.0 - 0.5j
+    E = incident.incident_field(s, 0.3, [1, 0, 0], [0, 1, 0])
+    x, info = f(lambda v: c * v, E, tol=1e-12)
+    assert info["converged"] and info["iters"] == 1
+    assert np.abs(x - E / c).max() < 1e-14 * np.abs(E / c).max()
+
+
 # ---------------------------------------------------------- cross sections --
 
 def _solve_small(s, kd, m, khat, e, kind="LATTDR"):
