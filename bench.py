@@ -316,6 +316,19 @@ def main():
     torch.cuda.synchronize()
     b2_s = (time.perf_counter() - f0) / nf
 
+    # COCG and QMR (the guide's QMRCCG, as the smoothing of COCG), mixed, same workload
+    cs = {}
+    for solver in ("cocg", "qmr"):
+        step("mixed", solver)
+        torch.cuda.synchronize()
+        f0 = time.perf_counter()
+        for _ in range(nf):
+            stc, qc = step("mixed", solver)
+        torch.cuda.synchronize()
+        assert stc["status"] == 0 and stc["rel_resid"] <= args.tol, (solver, stc)
+        cs[solver] = {"solves_per_s": nf / (time.perf_counter() - f0), "iters": stc["iters"],
+                      "matvecs": stc["matvecs"], "q": qc, "precision": "mixed"}
+
     # event timing of the five FFT passes (mixed product)
     Pr = torch.tensor(inputs.random_polarization(n, 1, seed=1), device="cuda")
     prof = t.profile_matvec(rhs, Pr, precision="mixed", reps=50)
@@ -364,6 +377,8 @@ def main():
         "rel_resid": st["rel_resid"],
         "iters": st["iters"],
         "bicgstab2_solver": {"solves_per_s": 1.0 / b2_s, "iters": stb2["iters"], "q": qb2, "precision": "mixed"},
+        "cocg_solver": cs["cocg"],
+        "qmr_solver": cs["qmr"],
         "fp64_solver": {"solves_per_s": 1.0 / fp64_s, "iters": st64["iters"], "q": q64,
                         "speedup_mixed_over_fp64": (args.steps / total) * fp64_s},
         "matvec_event_ms": {"mixed": prof, "fp64": prof64},

@@ -69,6 +69,12 @@ extern "C" {
 /* Krylov solvers (§12, "Choice of Iterative Algorithm") */
 #define DDA_SOLVER_BICGSTAB 0   /* BiCGSTAB, van der Vorst 1992 (the guide's PBCGST) */
 #define DDA_SOLVER_BICGSTAB2 1  /* BiCGstab(2), Sleijpen & Fokkema 1993 (the guide's PBCGS2) */
+#define DDA_SOLVER_COCG 2       /* conjugate orthogonal CG, van der Vorst & Melissen 1990: CG with
+                                   the bilinear form x^T y, valid because A is complex symmetric;
+                                   one product per iteration (not among the guide's options) */
+#define DDA_SOLVER_QMR 3        /* QMR for complex symmetric A, Freund 1992 (the guide's QMRCCG),
+                                   computed as the quasi-minimal-residual smoothing of COCG
+                                   (the same iterates); one product per iteration */
 
 /* Built-in target shapes (§21, SHPAR conventions of the guide). */
 #define DDA_SHAPE_ELLIPSOID 1 /* shpar = diameters along x, y, z (a sphere: all equal) */
@@ -110,16 +116,16 @@ typedef struct {
   int32_t use_graph;       /* 1: the check_every iterations between host checks run as one
                               captured HIP graph on a stream of the handle (ordered after and
                               before the caller's stream); 0: kernels are launched directly */
-  int32_t solver;          /* DDA_SOLVER_BICGSTAB (the PBCGST option of §12) or
+  int32_t solver;          /* DDA_SOLVER_BICGSTAB (the PBCGST option of §12),
                               DDA_SOLVER_BICGSTAB2 (BiCGstab(2), the PBCGS2 option the guide
-                              recommends, §12); with BiCGstab(2) check_every counts cycles
-                              of two BiCG steps */
+                              recommends, §12; check_every then counts cycles of two BiCG
+                              steps), DDA_SOLVER_COCG or DDA_SOLVER_QMR (the QMRCCG option) */
 } dda_solve_opts;
 
 typedef struct {
   int32_t status;          /* 0 converged, 1 max_iter, 2 breakdown without recovery */
-  int32_t iters;           /* BiCGSTAB iterations, or BiCG steps of BiCGstab(2) (two per
-                              cycle); either way two products per iteration */
+  int32_t iters;           /* BiCGSTAB iterations or BiCG steps of BiCGstab(2) (two per
+                              cycle), two products each; COCG / QMR iterations, one each */
   int32_t matvecs;         /* FFT products in the iteration precision */
   int32_t outer;           /* true-residual evaluations (FP64 products) */
   double rel_resid;        /* final true relative residual |E - A P| / |E| (FP64) */

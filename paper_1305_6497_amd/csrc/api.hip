@@ -455,8 +455,35 @@ void cycle2(dda_target *t, int precision, hipStream_t s) {
   k_scalar_rho(k, s, 2, -1.0);
 }
 
+// One COCG / QMR iteration (one product) for every active RHS: 7 kernels.
+//   p = r + beta p (fused into the x-forward pass), q = A p -> v with p^T q
+//   (x-inverse records); alpha, x and r (QMR: the smoothing first); next
+//   beta, QMR's weight and the convergence status.
+void cocg_iteration(dda_target *t, int precision, bool qmr, hipStream_t s) {
+  KrylovState &k = t->k;
+  const int nrec = xpass_blocks(t->g, precision == DDA_MIXED);
+  FuseArgs f;
+  f.scal = k.scal;
+  f.active = k.active;
+  f.status = k.status;
+  f.partial = k.partial;
+  f.in_mode = 3;
+  f.nax = 1;
+  f.ax_d[0] = k.p;
+  f.ax_a[0] = k.r;
+  f.ax_b[0] = k.p;
+  f.ax_slot[0] = S_BETA;
+  f.ax_neg[0] = 0;
+  f.out_mode = 4;
+  matvec(t, precision, k.p, k.v, k.nrhs, k.active, s, nullptr, -1, 1, &f);
+  k_cocg_update(k, s, nrec, qmr);
+  k_cocg_scalar(k, s, qmr);
+}
+
 void step(dda_target *t, int precision, int solver, hipStream_t s) {
   if (solver == DDA_SOLVER_BICGSTAB2) cycle2(t, precision, s);
+  else if (solver == DDA_SOLVER_COCG || solver == DDA_SOLVER_QMR)
+    cocg_iteration(t, precision, solver == DDA_SOLVER_QMR, s);
   else iteration(t, precision, s);
 }
 
@@ -771,7 +798,7 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     DDA_REQUIRE(opts->max_iter >= 1, "max_iter must be >= 1");
     DDA_REQUIRE(opts->precision == DDA_FP64 || opts->precision == DDA_MIXED, "unknown precision");
     DDA_REQUIRE(opts->inner_tol >= 0.0 && opts->inner_tol < 1.0, "inner_tol must be in [0, 1)");
-    DDA_REQUIRE(opts->solver == DDA_SOLVER_BICGSTAB || opts->solver == DDA_SOLVER_BICGSTAB2, "unknown solver");
+    DDA_REQUIRE(opts->solver >= DDA_SOLVER_BICGSTAB && opts->solver <= DDA_SOLVER_QMR, "unknown solver");
     DDA_HIP(hipSetDevice(t->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     StreamUse use_{t, s};
@@ -785,7 +812,7 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     KrylovState &k = t->k;
     upload_rhs(t, rd, ai, s);
     launch_incident(t->g, t->d_ijk, t->d_rhs, nrhs, t->kd, k.b, s);
-    k_init_state(k, opts->tol, opts->max_iter, s);
+    k_init_state(k, opts->tol, opts->max_iter, opts->solver, s);
 
     std::vector<int> status(nrhs), check(nrhs), restart(nrhs), outer(nrhs, 0), final_status(nrhs, -1);
     std::vector<c64> scal((size_t)nrhs * kScal);
@@ -831,7 +858,7 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
         }
         if (any_restart) {
           DDA_HIP(hipMemcpyAsync(t->d_restart, restart.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
-          k_restart(k, t->d_restart, tol, inner, s);
+          k_restart(k, t->d_restart, tol, inner, opts->solver, s);
           any_run = true;
         }
       }
@@ -849,7 +876,8 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
       if (stats) {
         stats[r].status = final_status[r];
         stats[r].iters = (int)scal[(size_t)r * kScal + S_ITERS].x;
-        stats[r].matvecs = 2 * stats[r].iters;
+        stats[r].matvecs = (opts->solver == DDA_SOLVER_COCG || opts->solver == DDA_SOLVER_QMR ? 1 : 2) *
+                           stats[r].iters;
         stats[r].outer = outer[r];
         stats[r].rel_resid = rel[r];
       }

@@ -149,6 +149,7 @@ struct FuseArgs {
                        // 2: per-block partial sums of <out, in> and <out, out>
                        // 3: per-block Gram sums of in = r1, out = r2 and r = r0:
                        //    <r1,r1>, <r2,r2>, <r1,r2>, <r1,r0>, <r2,r0>
+                       // 4: per-block partial sums of the bilinear in^T out (COCG / QMR)
   const c64 *r = nullptr, *v = nullptr, *rh = nullptr;
   c64 *w = nullptr;
   c64 *scal = nullptr;
@@ -236,6 +237,9 @@ struct KrylovState {
 enum : int {
   S_RHO = 0, S_ALPHA, S_OMEGA, S_BETA, S_RNORM2, S_BNORM2, S_THR2, S_ITERS, S_MAXIT, S_RH2, S_TRUE2,
   S_G1,                           // BiCGstab(2): first minimal-residual coefficient (the second is omega)
+  S_TRUEB,                        // bilinear r^T r of the last true residual (COCG / QMR restarts)
+  S_TAU, S_ETA,                   // QMR smoothing: quasi-residual tau and the weight of the next step
+  S_FLAG,                         // COCG / QMR: nonzero when p^T q broke down in the last update
   kScal
 };
 
@@ -243,7 +247,9 @@ enum : int {
 enum : int { ST_RUN = 0, ST_CONV = 1, ST_BREAK = 2, ST_MAXIT = 3, ST_DONE = 4, ST_IDLE = 5 };
 
 int krylov_blocks(int64_t n3);
-void k_init_state(const KrylovState &k, double tol, int max_iter, hipStream_t s);
+// solver: DDA_SOLVER_*; COCG / QMR start from the bilinear rho = b^T b, QMR
+// also sets its raw COCG iterate (k.s) to 0 and its smoothed residual (k.t) to b
+void k_init_state(const KrylovState &k, double tol, int max_iter, int solver, hipStream_t s);
 void k_scalar_alpha(const KrylovState &k, hipStream_t s, int nrec);
 // x += alpha p + omega s, r = s - omega t; omega is computed by every block
 // from the nrec records (<t, s>, <t, t>) in k.partial; records of <rh, r>,
@@ -255,12 +261,21 @@ void k_scalar_rho(const KrylovState &k, hipStream_t s, int step = 1, double bsig
 void k2_scalar_rho1(const KrylovState &k, hipStream_t s, int nrec);
 void k2_scalar_mr(const KrylovState &k, hipStream_t s, int nrec);
 void k2_update_mr(const KrylovState &k, hipStream_t s);
+// COCG / QMR: alpha = rho / p^T q from the nrec records in k.partial (every
+// block), x += alpha p, r -= alpha q; QMR first applies the smoothing of the
+// previous step to x (the smoothed iterate) and k.t (the smoothed residual)
+// with the raw COCG iterate in k.s.  Records of r^T r, |r|^2, |t|^2 go to
+// k.partial2; k_cocg_scalar turns them into beta, QMR's weights and the status.
+void k_cocg_update(const KrylovState &k, hipStream_t s, int nrec, bool qmr);
+void k_cocg_scalar(const KrylovState &k, hipStream_t s, bool qmr);
 
 // r_true = b - Ax (Ax given in `ax`) for RHS with check[r]; writes norms into partial/scal.
 void k_true_residual(const KrylovState &k, const c64 *ax, hipStream_t s);
 // Restart RHS with restart[r] from the current x: r holds the true residual;
-// rh = r, p = v = 0, fresh scalars, inner threshold max(tol |b|, inner_tol |r|).
-void k_restart(const KrylovState &k, const int *restart, double tol, double inner_tol, hipStream_t s);
+// rh = r, p = v = 0, fresh scalars, inner threshold max(tol |b|, inner_tol |r|);
+// QMR: raw iterate k.s = x, smoothed residual k.t = r.
+void k_restart(const KrylovState &k, const int *restart, double tol, double inner_tol, int solver,
+               hipStream_t s);
 
 void launch_incident(const Geometry &g, const int32_t *ijk, const RhsDev *rhs, int nrhs, double kd,
                      c64 *e, hipStream_t s);

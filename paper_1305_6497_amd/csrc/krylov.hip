@@ -12,6 +12,17 @@
 // the Gram sums of its minimal-residual step into the x-inverse pass; the
 // kernels here do its scalar recurrences and the closing update
 //     x += g1 r0 + g2 r1;  r0 -= g1 r1 + g2 r2;  u0 -= g1 u1 + g2 u2.
+// COCG (van der Vorst & Melissen 1990) and QMR for complex symmetric systems
+// (Freund 1992; the QMRCCG option of §12) use the bilinear form a^T b, valid
+// because A^T = A:
+//     q = A p;  alpha = rho / p^T q;  x += alpha p;  r -= alpha q
+//     rho' = r^T r;  beta = rho'/rho;  p = r + beta p
+// p is formed in the x-forward pass (update list) and p^T q summed in the
+// x-inverse pass.  QMR's iterates are the quasi-minimal-residual smoothing of
+// COCG's (Zhou & Walker 1994):
+//     theta = |r| / tau;  eta = 1 / (1 + theta^2);  tau = tau theta sqrt(eta)
+//     y += eta (x - y);   s += eta (r - s)
+// with y the QMR iterate and s its residual, whose norm decides convergence.
 // Every RHS of a block carries its own scalars on the device, so a block of
 // iterations can be queued without host round trips: each kernel returns
 // early for an RHS whose `active` flag is cleared, and the scalar kernels
@@ -53,11 +64,12 @@ __device__ __forceinline__ void sum_partials(const double *partial, int nblk, in
   const size_t off = (size_t)r * n3;
 
 // ------------------------------------------------------------- init/restart --
-__global__ void kk_init(c64 *x, c64 *rr, c64 *rh, c64 *p, c64 *v, const c64 *b, int64_t n3, double *partial,
-                        int nblk) {
+// xs, ss: QMR's raw iterate (set to 0) and smoothed residual (set to b), or null
+__global__ void kk_init(c64 *x, c64 *rr, c64 *rh, c64 *p, c64 *v, c64 *xs, c64 *ss, const c64 *b, int64_t n3,
+                        double *partial, int nblk) {
   const int r = blockIdx.y;
   const size_t off = (size_t)r * n3;
-  double acc[1] = {0.0};
+  double acc[3] = {0.0, 0.0, 0.0};
   for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT) {
     const c64 bv = b[off + i];
     x[off + i] = {0, 0};
@@ -65,22 +77,32 @@ __global__ void kk_init(c64 *x, c64 *rr, c64 *rh, c64 *p, c64 *v, const c64 *b, 
     rh[off + i] = bv;
     p[off + i] = {0, 0};
     v[off + i] = {0, 0};
+    if (xs) {
+      xs[off + i] = {0, 0};
+      ss[off + i] = bv;
+    }
     acc[0] += bv.x * bv.x + bv.y * bv.y;
+    acc[1] += bv.x * bv.x - bv.y * bv.y;           // b^T b
+    acc[2] += 2.0 * bv.x * bv.y;
   }
-  double out[1];
-  block_sum<1>(acc, out);
-  if (threadIdx.x == 0) write_record<1>(partial, r, nblk, blockIdx.x, out);
+  double out[3];
+  block_sum<3>(acc, out);
+  if (threadIdx.x == 0) write_record<3>(partial, r, nblk, blockIdx.x, out);
 }
 
+// bilinear: rho = b^T b (COCG / QMR), else |b|^2 (rh = b)
 __global__ void kk_init_scalars(const double *partial, int nblk, c64 *scal, int *active, int *status, double tol2,
-                                int max_iter) {
+                                int max_iter, int bilinear) {
   const int r = blockIdx.x;
-  double s[1];
-  sum_partials<1>(partial, nblk, r, s);
+  double s[3];
+  sum_partials<3>(partial, nblk, r, s);
   if (threadIdx.x == 0) {
     c64 *sc = scal + (size_t)r * kScal;
     const double b2 = s[0];
-    sc[S_RHO] = {b2, 0.0};
+    sc[S_RHO] = bilinear ? c64{s[1], s[2]} : c64{b2, 0.0};
+    sc[S_TAU] = {sqrt(b2), 0.0};
+    sc[S_ETA] = {0.0, 0.0};
+    sc[S_FLAG] = {0.0, 0.0};
     sc[S_ALPHA] = {1.0, 0.0};
     sc[S_OMEGA] = {1.0, 0.0};
     sc[S_BETA] = {0.0, 0.0};
@@ -189,45 +211,61 @@ __global__ void kk_true_residual(const int *check, const c64 *b, const c64 *ax, 
   const int r = blockIdx.y;
   if (!check[r]) return;
   const size_t off = (size_t)r * n3;
-  double acc[1] = {0.0};
+  double acc[3] = {0.0, 0.0, 0.0};
   for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT) {
     const c64 rv = b[off + i] - ax[off + i];
     rr[off + i] = rv;
     acc[0] += rv.x * rv.x + rv.y * rv.y;
+    acc[1] += rv.x * rv.x - rv.y * rv.y;           // r^T r
+    acc[2] += 2.0 * rv.x * rv.y;
   }
-  double out[1];
-  block_sum<1>(acc, out);
-  if (threadIdx.x == 0) write_record<1>(partial, r, nblk, blockIdx.x, out);
+  double out[3];
+  block_sum<3>(acc, out);
+  if (threadIdx.x == 0) write_record<3>(partial, r, nblk, blockIdx.x, out);
 }
 
 __global__ void kk_scalar_true(const double *partial, int nblk, c64 *scal, const int *check) {
   const int r = blockIdx.x;
   if (!check[r]) return;
-  double s[1];
-  sum_partials<1>(partial, nblk, r, s);
-  if (threadIdx.x == 0) scal[(size_t)r * kScal + S_TRUE2] = {s[0], 0.0};
+  double s[3];
+  sum_partials<3>(partial, nblk, r, s);
+  if (threadIdx.x == 0) {
+    scal[(size_t)r * kScal + S_TRUE2] = {s[0], 0.0};
+    scal[(size_t)r * kScal + S_TRUEB] = {s[1], s[2]};
+  }
 }
 
 // Restart from the current x for RHS with restart[r]: r already holds the true
 // residual; rh = r, p = v = 0 and fresh scalars.
-__global__ void kk_restart(const int *restart, const c64 *rr, c64 *rh, c64 *p, c64 *v, int64_t n3, int nblk) {
+// xs, ss (QMR, else null): the raw COCG iterate restarts at x, the smoothed
+// residual at r
+__global__ void kk_restart(const int *restart, const c64 *rr, c64 *rh, c64 *p, c64 *v, const c64 *x, c64 *xs,
+                           c64 *ss, int64_t n3, int nblk) {
   const int r = blockIdx.y;
   if (!restart[r]) return;
   const size_t off = (size_t)r * n3;
   for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT) {
-    rh[off + i] = rr[off + i];
+    const c64 rv = rr[off + i];
+    rh[off + i] = rv;
     p[off + i] = {0, 0};
     v[off + i] = {0, 0};
+    if (xs) {
+      xs[off + i] = x[off + i];
+      ss[off + i] = rv;
+    }
   }
 }
 
 __global__ void kk_restart_scalars(const int *restart, c64 *scal, int *active, int *status, int nrhs, double tol2,
-                                   double inner2) {
+                                   double inner2, int bilinear) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrhs || !restart[r]) return;
   c64 *sc = scal + (size_t)r * kScal;
   const double t2 = sc[S_TRUE2].x;
-  sc[S_RHO] = {t2, 0.0};
+  sc[S_RHO] = bilinear ? sc[S_TRUEB] : c64{t2, 0.0};
+  sc[S_TAU] = {sqrt(t2), 0.0};
+  sc[S_ETA] = {0.0, 0.0};
+  sc[S_FLAG] = {0.0, 0.0};
   sc[S_ALPHA] = {1.0, 0.0};
   sc[S_OMEGA] = {1.0, 0.0};
   sc[S_BETA] = {0.0, 0.0};
@@ -313,14 +351,124 @@ __global__ void kk2_update_mr(const int *active, c64 *x, c64 *r0, const c64 *r1,
   if (threadIdx.x == 0) write_record<3>(partial, r, nblk, blockIdx.x, out);
 }
 
+// ------------------------------------------------------------- COCG / QMR --
+// alpha = rho / p^T q: every block sums the records of the product q = A p in
+// the same order, so all agree; a breakdown (p^T q ~ 0) leaves x and r as
+// they are and is flagged in S_FLAG for kk_cocg_scalar (no block clears
+// `active` here, so every block does the same work).
+// QMR (xs, ss non-null): x holds the smoothed iterate y, xs the COCG iterate
+// and ss the smoothed residual; the smoothing of the previous step comes first:
+//     y += eta (xs - y);  ss += eta (r - ss);  then xs += alpha p;  r -= alpha q.
+// Records: r^T r, |r|^2 and |ss|^2 (the smoothed residual just formed).
+__global__ void kk_cocg_update(const int *active, c64 *x, c64 *rr, const c64 *p, const c64 *q, c64 *xs, c64 *ss,
+                               c64 *scal, int64_t n3, const double *rec_in, int nrec_in, double *partial,
+                               int nblk) {
+  RHS_PREAMBLE
+  __shared__ c64 s_alpha;
+  {
+    double d[2];
+    sum_partials<2>(rec_in, nrec_in, r, d);
+    if (threadIdx.x == 0) {
+      c64 *sc = scal + (size_t)r * kScal;
+      const c64 den = {d[0], d[1]}, rho = sc[S_RHO];
+      const bool ok = cabs2(den) > 1e-60 * cabs2(rho) && cabs2(den) > 0.0 && cabs2(den) < 1e300;
+      const c64 a = ok ? cdiv(rho, den) : c64{0.0, 0.0};
+      s_alpha = a;
+      if (blockIdx.x == 0) {
+        sc[S_ALPHA] = a;
+        sc[S_FLAG] = {ok ? 0.0 : 1.0, 0.0};
+      }
+    }
+    __syncthreads();
+  }
+  const c64 alpha = s_alpha;
+  const c64 eta = xs ? scal[(size_t)r * kScal + S_ETA] : c64{0.0, 0.0};
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT) {
+    const size_t j = off + i;
+    const c64 pv = p[j], qv = q[j];
+    c64 rv = rr[j];
+    if (xs) {
+      const c64 xv = xs[j], yv = x[j], sv = ss[j];
+      x[j] = yv + eta * (xv - yv);
+      const c64 sn = sv + eta * (rv - sv);
+      ss[j] = sn;
+      acc[3] += sn.x * sn.x + sn.y * sn.y;
+      xs[j] = xv + alpha * pv;
+    } else {
+      x[j] = x[j] + alpha * pv;
+    }
+    rv = rv - alpha * qv;
+    rr[j] = rv;
+    acc[0] += rv.x * rv.x - rv.y * rv.y;             // r^T r
+    acc[1] += 2.0 * rv.x * rv.y;
+    acc[2] += rv.x * rv.x + rv.y * rv.y;
+  }
+  double out[4];
+  block_sum<4>(acc, out);
+  if (threadIdx.x == 0) write_record<4>(partial, r, nblk, blockIdx.x, out);
+}
+
+// rho' = r^T r, beta = rho'/rho; convergence on |r| (COCG) or on the smoothed
+// residual |s| (QMR); QMR's tau and eta for the next smoothing step.
+__global__ void kk_cocg_scalar(const double *partial, int nblk, c64 *scal, int *active, int *status, int qmr) {
+  const int r = blockIdx.x;
+  if (!active[r]) return;
+  double s[4];
+  sum_partials<4>(partial, nblk, r, s);
+  if (threadIdx.x == 0) {
+    c64 *sc = scal + (size_t)r * kScal;
+    const c64 rho_new = {s[0], s[1]};
+    const double rn2 = s[2];
+    const double crit = qmr ? s[3] : rn2;
+    sc[S_RNORM2] = {rn2, 0.0};
+    sc[S_ITERS].x += 1.0;
+    if (!(rn2 == rn2) || !(crit == crit) || sc[S_FLAG].x != 0.0) {
+      active[r] = 0;
+      status[r] = ST_BREAK;
+    } else if (crit <= sc[S_THR2].x) {
+      active[r] = 0;
+      status[r] = ST_CONV;
+    } else if (sc[S_ITERS].x >= sc[S_MAXIT].x) {
+      active[r] = 0;
+      status[r] = ST_MAXIT;
+    } else if (!(cabs2(rho_new) > 1e-60 * rn2 * rn2) || !(cabs2(sc[S_RHO]) > 0.0)) {
+      active[r] = 0;
+      status[r] = ST_BREAK;
+    } else {
+      sc[S_BETA] = cdiv(rho_new, sc[S_RHO]);
+      sc[S_RHO] = rho_new;
+      if (qmr) {
+        const double tau = sc[S_TAU].x;
+        const double th = sqrt(rn2) / tau;
+        const double eta = 1.0 / (1.0 + th * th);
+        sc[S_TAU] = {tau * th * sqrt(eta), 0.0};
+        sc[S_ETA] = {eta, 0.0};
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------- host wrappers --
 static dim3 vgrid(const KrylovState &k) { return dim3(k.nblk, k.nrhs); }
 
-void k_init_state(const KrylovState &k, double tol, int max_iter, hipStream_t s) {
-  hipLaunchKernelGGL(kk_init, vgrid(k), dim3(KNT), 0, s, k.x, k.r, k.rh, k.p, k.v, k.b, k.n3, k.partial, k.nblk);
+static bool bilinear_solver(int solver) { return solver == DDA_SOLVER_COCG || solver == DDA_SOLVER_QMR; }
+
+void k_init_state(const KrylovState &k, double tol, int max_iter, int solver, hipStream_t s) {
+  const bool qmr = solver == DDA_SOLVER_QMR;
+  hipLaunchKernelGGL(kk_init, vgrid(k), dim3(KNT), 0, s, k.x, k.r, k.rh, k.p, k.v, qmr ? k.s : nullptr,
+                     qmr ? k.t : nullptr, k.b, k.n3, k.partial, k.nblk);
   hipLaunchKernelGGL(kk_init_scalars, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, k.nblk, k.scal, k.active, k.status,
-                     tol * tol, max_iter);
+                     tol * tol, max_iter, bilinear_solver(solver) ? 1 : 0);
   DDA_HIP(hipGetLastError());
+}
+void k_cocg_update(const KrylovState &k, hipStream_t s, int nrec, bool qmr) {
+  hipLaunchKernelGGL(kk_cocg_update, vgrid(k), dim3(KNT), 0, s, k.active, k.x, k.r, k.p, k.v, qmr ? k.s : nullptr,
+                     qmr ? k.t : nullptr, k.scal, k.n3, k.partial, nrec, k.partial2, k.nblk);
+}
+void k_cocg_scalar(const KrylovState &k, hipStream_t s, bool qmr) {
+  hipLaunchKernelGGL(kk_cocg_scalar, dim3(k.nrhs), dim3(KNT), 0, s, k.partial2, k.nblk, k.scal, k.active, k.status,
+                     qmr ? 1 : 0);
 }
 void k_scalar_alpha(const KrylovState &k, hipStream_t s, int nrec) {
   hipLaunchKernelGGL(kk_scalar_alpha, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, nrec, k.scal, k.active, k.status);
@@ -349,10 +497,13 @@ void k_true_residual(const KrylovState &k, const c64 *ax, hipStream_t s) {
   hipLaunchKernelGGL(kk_scalar_true, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, k.nblk, k.scal, k.check);
   DDA_HIP(hipGetLastError());
 }
-void k_restart(const KrylovState &k, const int *restart, double tol, double inner_tol, hipStream_t s) {
-  hipLaunchKernelGGL(kk_restart, vgrid(k), dim3(KNT), 0, s, restart, k.r, k.rh, k.p, k.v, k.n3, k.nblk);
+void k_restart(const KrylovState &k, const int *restart, double tol, double inner_tol, int solver,
+               hipStream_t s) {
+  const bool qmr = solver == DDA_SOLVER_QMR;
+  hipLaunchKernelGGL(kk_restart, vgrid(k), dim3(KNT), 0, s, restart, k.r, k.rh, k.p, k.v, k.x, qmr ? k.s : nullptr,
+                     qmr ? k.t : nullptr, k.n3, k.nblk);
   hipLaunchKernelGGL(kk_restart_scalars, dim3((k.nrhs + 63) / 64), dim3(64), 0, s, restart, k.scal, k.active,
-                     k.status, k.nrhs, tol * tol, inner_tol * inner_tol);
+                     k.status, k.nrhs, tol * tol, inner_tol * inner_tol, bilinear_solver(solver) ? 1 : 0);
   DDA_HIP(hipGetLastError());
 }
 

@@ -684,6 +684,10 @@ __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *_
       acc[0] += g.x;
       acc[1] += g.y;
       acc[2] += o.x * o.x + o.y * o.y;
+    } else if (f.out_mode == 4) {
+      const c64 g = pv * o;                          // bilinear in^T out
+      acc[0] += g.x;
+      acc[1] += g.y;
     } else if (f.out_mode == 3) {
       // in = r1, out = r2, f.r = r0
       const c64 g12 = cmulc(pv, o), g10 = cmulc(pv, x), g20 = cmulc(o, x);

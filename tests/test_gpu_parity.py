@@ -34,6 +34,9 @@ def dda():
     return m
 
 
+SOLVERS = ["bicgstab", "bicgstab2", "cocg", "qmr"]
+
+
 def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
@@ -145,7 +148,7 @@ def test_matvec_independent_of_site_numbering(dda, shape, shpar):
         assert _rel(a32, ref[order]) < 5e-6
 
 
-@pytest.mark.parametrize("solver", ["bicgstab", "bicgstab2"])
+@pytest.mark.parametrize("solver", SOLVERS)
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_solve_independent_of_site_numbering(dda, solver, precision):
     sites, box = dda.make_sites("ELLIPSOID", (13, 10, 8.5))
@@ -199,7 +202,7 @@ def test_incident_field(dda):
 
 
 # ------------------------------------------------------------------ solves --
-@pytest.mark.parametrize("solver", ["bicgstab", "bicgstab2"])
+@pytest.mark.parametrize("solver", SOLVERS)
 @pytest.mark.parametrize("m,alpha", [(1.33 + 0.01j, "LATTDR"), (1.7 + 0.3j, "LATTDR"), (2.5 + 0.5j, "CMRR"),
                                      (1.5 + 0.0j, "FLTRCD")])
 def test_solve_matches_dense_lu(dda, m, alpha, solver):
@@ -226,7 +229,7 @@ def test_solve_matches_dense_lu(dda, m, alpha, solver):
             assert abs(q[r][key] - qo[key]) <= 1e-9 * qo["qext"], key
 
 
-@pytest.mark.parametrize("solver", ["bicgstab", "bicgstab2"])
+@pytest.mark.parametrize("solver", SOLVERS)
 def test_solve_mixed_reaches_fp64_tolerance(dda, solver):
     sites, box = dda.make_sites("RCTGLPRSM", (16, 12, 10))
     osites = targets.rctglprsm(16, 12, 10)
@@ -243,7 +246,7 @@ def test_solve_mixed_reaches_fp64_tolerance(dda, solver):
     assert res <= 1e-8
 
 
-@pytest.mark.parametrize("solver", ["bicgstab", "bicgstab2"])
+@pytest.mark.parametrize("solver", SOLVERS)
 def test_batched_block_equals_single_solves_bitwise(dda, solver):
     sites, box = dda.make_sites("ELLIPSOID", (14, 10, 8))
     kd, m = 0.4, 1.7 + 0.05j
@@ -278,6 +281,9 @@ def test_not_converged_and_zero_rhs(dda):
     assert st[0]["status"] == 1 and st[0]["iters"] == 1
     P, st = t.solve(rhs, tol=1e-12, max_iter=2, max_outer=1, solver="bicgstab2")
     assert st[0]["status"] == 1 and st[0]["iters"] == 2 and st[0]["matvecs"] == 4
+    for solver in ("cocg", "qmr"):
+        P, st = t.solve(rhs, tol=1e-12, max_iter=3, max_outer=1, solver=solver)
+        assert st[0]["status"] == 1 and st[0]["iters"] == 3 and st[0]["matvecs"] == 3
     with pytest.raises(dda.DDAError):
         t.solve([(np.array([1.0, 0, 0]), np.array([1.0, 0, 0]))])      # khat . e != 0
     with pytest.raises(dda.DDAError):
@@ -348,7 +354,7 @@ def test_sphere_d20_fp64_solve_against_oracle(dda):
             assert abs(q[r][key] - qo[key]) <= 1e-5 * abs(qo[key]), (key, q[r][key], qo[key])
 
 
-@pytest.mark.parametrize("solver", ["bicgstab", "bicgstab2"])
+@pytest.mark.parametrize("solver", SOLVERS)
 def test_graph_replay_matches_eager_bitwise(dda, solver):
     # The iteration block is captured once and replayed several times per
     # solve (host checks between replays); each solve also replays the graph
@@ -374,7 +380,7 @@ def test_graph_replay_matches_eager_bitwise(dda, solver):
 # 1e-9, the efficiencies differ from the stored ones by O(1e-9) times the
 # conditioning of Q in P; block_64 solved to 1e-5 already agrees to 4e-6, so
 # 1e-7 of Q_ext leaves a margin of two orders of magnitude.
-@pytest.mark.parametrize("solver", ["bicgstab", "bicgstab2"])
+@pytest.mark.parametrize("solver", SOLVERS)
 @pytest.mark.parametrize("name", ["au_block_16x32x32", "block_64", "ellipsoid_96x64x48"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_full_size_efficiencies_against_oracle(dda, name, prec, solver):
@@ -418,6 +424,35 @@ def test_bicgstab2_follows_the_oracle_recurrence(dda):
     Po, info = solvers.bicgstab_l(op.matvec, E, ell=2, tol=1e-8)
     assert st[0]["status"] == 0 and info["converged"]
     assert abs(st[0]["iters"] - info["iters"]) <= 2, (st[0]["iters"], info["iters"])
+    assert _rel(Pg, Po) < 1e-6
+
+
+@pytest.mark.parametrize("solver", ["cocg", "qmr"])
+def test_complex_symmetric_solvers_follow_the_oracle(dda, solver):
+    # COCG and QMR in FP64 take the oracle's iterates up to rounding order.
+    # COCG's residual oscillates, so rounding can move the first iteration
+    # below the threshold: the GPU must stop no earlier than the oracle's
+    # residual (COCG) or quasi-residual (QMR) first comes within 2x of the
+    # threshold and no later than two iterations after the oracle stops.
+    shpar = (13, 11, 9)
+    sites, box = dda.make_sites("ELLIPSOID", shpar)
+    osites = targets.ellipsoid(*shpar)
+    kd, m = 0.55, 1.6 + 0.02j
+    rhs = [dda.orient_rhs(0.4, 0.9, 1.3, which=2)]
+    t = dda.Target(sites, box, m=m, kd=kd)
+    P, st = t.solve(rhs, tol=1e-8, precision="fp64", solver=solver, check_every=1)
+    Pg = P.cpu().numpy()[0]
+    t.close()
+    ai = _oracle_ainv(m, kd, *rhs[0])
+    E = incident.incident_field(osites, kd, *rhs[0])
+    op = interaction.FFTOperator(osites, kd, ai)
+    trace = []
+    Po, info = getattr(solvers, "cocg" if solver == "cocg" else "qmr_cs")(op.matvec, E, tol=1e-8, trace=trace)
+    assert st[0]["status"] == 0 and info["converged"]
+    nb = np.linalg.norm(E)
+    res = [np.linalg.norm(r) / nb if solver == "cocg" else r / nb for _, r in trace]
+    k_lo = 1 + next(k for k, v in enumerate(res) if v <= 2e-8)
+    assert k_lo <= st[0]["iters"] <= info["iters"] + 2, (k_lo, st[0]["iters"], info["iters"])
     assert _rel(Pg, Po) < 1e-6
 
 
