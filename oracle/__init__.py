@@ -18,11 +18,13 @@ Contents, each following the passage of the DDSCAT 7.3 user guide
                         incident field at the dipoles (§12, eq. AP=E).
 * ``interaction``    -- the 3N x 3N matrix A of eq. (AP=E): dense build,
                         direct-sum product, FFT-convolution product (§13).
-* ``solvers``        -- dense LU and BiCGSTAB (§12).
+* ``solvers``        -- dense LU, BiCGSTAB, BiCGstab(l), COCG and QMR (§12).
 * ``cross_sections`` -- C_ext, C_abs, exact C_sca and the efficiencies
                         Q = C / (pi a_eff^2) (§3.1).
 * ``mie``            -- Mie-theory efficiencies of a homogeneous sphere, the
                         kd -> 0 limit the DDA must approach (§2).
+* ``near_field``     -- E at lattice points in and near the target and along
+                        a line (§29, §30).
 
 Everything is complex128 / float64.  Formulas the guide cites but does not
 print (the dipole field tensor, the LDR coefficients, the cross-section sums,
@@ -30,4 +32,4 @@ BiCGSTAB) are written out from the cited physics; every such reading is named
 in the docstring where it is used.
 """
 
-from . import targets, polarizability, incident, interaction, solvers, cross_sections, mie  # noqa: F401
+from . import targets, polarizability, incident, interaction, solvers, cross_sections, mie, near_field  # noqa: F401
