@@ -229,6 +229,26 @@ int dda_cross_sections(dda_target *t, const dda_rhs *rhs, int32_t nrhs,
 int dda_far_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const void *p_dev, double etasca,
                   void *stream, dda_far *out);
 
+/* Near field (§29; the post-processor of §30 reads it).  For polarizations
+ * p_dev (device [nrhs][N][3], solved for the same rhs) the field at every
+ * lattice point q of the target's box extended by margin[a] >= 0 points on
+ * both sides of axis a:
+ *     E(q) = E_inc(q) + sum over sites l with r_l != q of G(r_q - r_l) P_l,
+ * the dipole at q itself excluded, so at an occupied site E is the field that
+ * polarizes that dipole (E = P / alpha for an exact solution).  With
+ * macroscopic != 0 the field at occupied sites is multiplied by 3 / (eps + 2),
+ * eps = m^2 of the site's composition (eq. macro_vs_micro of §29); the line
+ * the guide prints in §30 is the field without that factor.
+ * e_dev: device [nrhs][Z][Y][X][3] complex128, X = nx + 2 margin[0] (likewise
+ * Y, Z); output point (i, j, k) is site coordinate (i - margin[0],
+ * j - margin[1], k - margin[2]), and E_inc has the phase origin of the sites.
+ * The sum is the FFT product of the extended box, in FP64, on a grid set up
+ * for the call (freed before returning).  Queued on the stream; the call
+ * returns after its own setup.  Errors: DDA_EINVAL (NULL, negative margin,
+ * invalid rhs); DDA_ENOTSUP (an extended extent above 256); DDA_ENOMEM. */
+int dda_near_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const void *p_dev,
+                   const int32_t margin[3], int32_t macroscopic, void *e_dev, void *stream);
+
 /* The product AP = A P for nrhs vectors (device [nrhs][N][3] in and out, may
  * not alias), in DDA_FP64 or DDA_MIXED (FP32 FFT convolution, FP64 diagonal
  * and output).  The polarizabilities are those of the given RHS.  Queued on

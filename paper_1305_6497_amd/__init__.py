@@ -181,6 +181,20 @@ class Target:
                                         float(etasca), _stream_ptr(stream), out))
         return [dict(qsca=v.qsca, g=v.g, cos2=v.cos2, n_theta=v.n_theta, n_phi=v.n_phi) for v in out]
 
+    def near_field(self, rhs, P, margin=(0, 0, 0), macroscopic=False, stream=None):
+        """E at every lattice point of the box extended by ``margin`` points on
+        both sides of each axis: complex128 [nrhs, Z, Y, X, 3] on the device,
+        point (i, j, k) at site coordinate (i, j, k) - margin."""
+        import torch
+        mg = [int(v) for v in margin]
+        box = self.info()["box"]
+        X, Y, Z = (box[a] + 2 * mg[a] for a in range(3))
+        out = torch.empty((len(rhs), Z, Y, X, 3), dtype=torch.complex128, device=f"cuda:{self.device}")
+        L.check(self._lib.dda_near_field(self._h, _rhs_array(rhs), len(rhs), ctypes.c_void_p(P.data_ptr()),
+                                         (ctypes.c_int32 * 3)(*mg), int(bool(macroscopic)),
+                                         ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
     def apply(self, rhs, P, precision="fp64", stream=None):
         out = self._vec(len(rhs))
         L.check(self._lib.dda_apply(self._h, _rhs_array(rhs), len(rhs), PRECISION[precision],

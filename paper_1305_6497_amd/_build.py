@@ -21,6 +21,7 @@ SOURCES = {
     "fft_generic.hip": [],
     "krylov.hip": [],
     "farfield.hip": [],
+    "nearfield.hip": [],
     "api.hip": [],
     "host.cpp": ["-ffp-contract=off"],
     "devmem.cpp": [],

@@ -92,6 +92,8 @@ SIGNATURES = [
                                           ctypes.POINTER(Q)]),
     ("dda_far_field", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), ctypes.c_int32, _VP, ctypes.c_double, _VP,
                                      ctypes.POINTER(Far)]),
+    ("dda_near_field", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), ctypes.c_int32, _VP, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.c_int32, _VP, _VP]),
     ("dda_apply", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP]),
     ("dda_incident_field", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), ctypes.c_int32, _VP, _VP]),
     ("dda_free_target", None, [_VP]),

@@ -886,6 +886,95 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
   });
 }
 
+int dda_near_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const void *p_dev, const int32_t margin[3],
+                   int32_t macroscopic, void *e_dev, void *stream) {
+  return guarded([&]() -> int {
+    DDA_REQUIRE(t && rhs && p_dev && margin && e_dev, "NULL argument");
+    DDA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    DDA_REQUIRE(margin[0] >= 0 && margin[1] >= 0 && margin[2] >= 0, "margins must be >= 0");
+    const int mg[3] = {margin[0], margin[1], margin[2]};
+    const int64_t Xl = t->g.nx + 2 * (int64_t)mg[0], Yl = t->g.ny + 2 * (int64_t)mg[1], Zl = t->g.nz + 2 * (int64_t)mg[2];
+    if (Xl > 256 || Yl > 256 || Zl > 256)
+      throw Error{DDA_ENOTSUP, "extended box extent exceeds 256 (padded FFT extent 512)"};
+    const int X = (int)Xl, Y = (int)Yl, Z = (int)Zl;
+    const int64_t ne = Xl * Yl * Zl, n = t->g.n_sites;
+    DDA_HIP(hipSetDevice(t->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamUse use_{t, s};
+    // a target occupying the whole extended box, numbered row after row
+    std::vector<int32_t> ijk((size_t)ne * 3);
+    for (int z = 0, j = 0; z < Z; ++z)
+      for (int y = 0; y < Y; ++y)
+        for (int x = 0; x < X; ++x, ++j) {
+          ijk[3 * (size_t)j] = x;
+          ijk[3 * (size_t)j + 1] = y;
+          ijk[3 * (size_t)j + 2] = z;
+        }
+    const dda_c64 any_m = {1.5, 0.0};           // unused: the diagonal is set to zero below
+    dda_target_desc d{};
+    d.nx = X;
+    d.ny = Y;
+    d.nz = Z;
+    d.n_sites = ne;
+    d.ijk = ijk.data();
+    d.comp = nullptr;
+    d.n_comp = 1;
+    d.m = &any_m;
+    d.kd = t->kd;
+    d.alpha_kind = DDA_ALPHA_LDR;
+    d.device = t->device;
+    dda_target *ext = nullptr;
+    const int rc = dda_setup_target(&d, &ext);
+    if (rc < 0) throw Error{rc, std::string("near field: ") + dda_last_error()};
+    std::unique_ptr<dda_target, void (*)(dda_target *)> hold(ext, dda_free_target);
+    {
+      StreamUse use_ext{ext, s};
+      std::vector<RhsDev> rd;
+      std::vector<c64> ai;
+      prepare_rhs(ext, rhs, nrhs, rd, ai);
+      std::fill(ai.begin(), ai.end(), c64{0.0, 0.0});     // zero diagonal: A P_ext = -G * P_ext
+      ensure_krylov(ext, nrhs, s);
+      ensure_workspace(ext, nrhs, s);
+      upload_rhs(ext, rd, ai, s);
+      // site i -> extended point; composition at each extended point (-1: vacuum)
+      std::vector<int32_t> sites((size_t)n * 3);
+      DDA_HIP(hipMemcpy(sites.data(), t->d_ijk, sites.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+      std::vector<uint8_t> comp;
+      if (t->d_comp) {
+        comp.resize((size_t)n);
+        DDA_HIP(hipMemcpy(comp.data(), t->d_comp, comp.size(), hipMemcpyDeviceToHost));
+      }
+      std::vector<int> map((size_t)n), cellc((size_t)ne, -1);
+      for (int64_t i = 0; i < n; ++i) {
+        const int64_t j = ((int64_t)(sites[3 * i + 2] + mg[2]) * Y + (sites[3 * i + 1] + mg[1])) * X +
+                          (sites[3 * i] + mg[0]);
+        map[i] = (int)j;
+        cellc[j] = comp.empty() ? 0 : comp[i];
+      }
+      std::vector<c64> fac((size_t)t->ncomp);
+      for (int c = 0; c < t->ncomp; ++c) {
+        const c64 m = t->m[c];
+        const c64 eps2 = {m.x * m.x - m.y * m.y + 2.0, 2.0 * m.x * m.y};
+        const double den = eps2.x * eps2.x + eps2.y * eps2.y;
+        fac[c] = {3.0 * eps2.x / den, -3.0 * eps2.y / den};
+      }
+      int *d_map = ext->alloc<int>(map.size() * sizeof(int));
+      int *d_cellc = ext->alloc<int>(cellc.size() * sizeof(int));
+      c64 *d_fac = ext->alloc<c64>(fac.size() * sizeof(c64));
+      DDA_HIP(hipMemcpy(d_map, map.data(), map.size() * sizeof(int), hipMemcpyHostToDevice));
+      DDA_HIP(hipMemcpy(d_cellc, cellc.data(), cellc.size() * sizeof(int), hipMemcpyHostToDevice));
+      DDA_HIP(hipMemcpy(d_fac, fac.data(), fac.size() * sizeof(c64), hipMemcpyHostToDevice));
+      KrylovState &k = ext->k;
+      DDA_HIP(hipMemsetAsync(k.x, 0, (size_t)nrhs * ne * 3 * sizeof(c64), s));
+      launch_near_field_embed(static_cast<const c64 *>(p_dev), n, d_map, k.x, ne, nrhs, s);
+      matvec(ext, DDA_FP64, k.x, k.v, nrhs, nullptr, s);
+      launch_near_field_combine(k.v, ne, X, Y, mg, ext->d_rhs, nrhs, t->kd, d_cellc, macroscopic ? d_fac : nullptr,
+                                static_cast<c64 *>(e_dev), s);
+    }
+    return DDA_OK;
+  });
+}
+
 int dda_far_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const void *p_dev, double etasca, void *stream,
                   dda_far *out) {
   return guarded([&]() -> int {

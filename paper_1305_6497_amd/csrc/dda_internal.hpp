@@ -298,6 +298,14 @@ size_t far_field_scratch_bytes(const Geometry &g, int ndir);
 void launch_far_field(const Geometry &g, const int *cell_site, const c64 *P, double kd, const double *dirs,
                       const double *mu, const double *w, int ndir, double *scratch, double *sums, hipStream_t s);
 
+// Near field: embed P [nrhs][n][3] into the extended box (P_ext[r][map[i]] =
+// P[r][i]; P_ext zeroed by the caller), and E = E_inc - AP_ext on the box
+// (fac[c] = 3 / (eps_c + 2) at points with cellc >= 0, or fac = nullptr).
+void launch_near_field_embed(const c64 *P, int64_t n, const int *map, c64 *Pext, int64_t ne, int nrhs,
+                             hipStream_t s);
+void launch_near_field_combine(const c64 *AP, int64_t ne, int X, int Y, const int margin[3], const RhsDev *rhs,
+                               int nrhs, double kd, const int *cellc, const c64 *fac, c64 *E, hipStream_t s);
+
 // --------------------------------------------------------------- host side --
 std::vector<int32_t> make_sites(int shape, const double shpar[3], int32_t box[3]);
 void orient_rhs(double beta, double theta, double phi, const c64 e01[3], int which, RhsDev &out);

@@ -501,3 +501,86 @@ def test_far_field_optical_theorem_full_size(dda, name):
     assert st[0]["status"] == 0
     assert abs(far[0]["qsca"] - q[0]["qsca"]) <= 1e-7 * q[0]["qext"], (far[0], q[0])
     assert -1.0 < far[0]["g"] < 1.0 and 0.0 < far[0]["cos2"] < 1.0
+
+
+# ------------------------------------------------------------- near field --
+@pytest.mark.parametrize("shape,shpar,margin,ncomp", [
+    ("ELLIPSOID", (6, 5, 4), (3, 2, 4), 1),
+    ("RCTGLPRSM", (1, 1, 1), (2, 2, 2), 1),
+    ("HEX_PRISM", (6, 9, 2), (0, 0, 0), 1),
+    ("ELLIPSOID", (9, 7, 5.5), (1, 3, 2), 3),
+])
+def test_near_field_matches_oracle_direct_sum(dda, shape, shpar, margin, ncomp):
+    from oracle import near_field
+    sites, box = dda.make_sites(shape, shpar)
+    osites = targets.make(shape, shpar)
+    n = len(sites)
+    kd = 0.42
+    ms = [1.6 + 0.1j, 2.2 + 0.6j, 1.2 + 0.0j][:ncomp]
+    comp = (np.arange(n) % ncomp).astype(np.uint8) if ncomp > 1 else None
+    t = dda.Target(sites, box, m=ms if ncomp > 1 else ms[0], kd=kd, comp=comp)
+    rhs = [dda.orient_rhs(0.3, 1.1, 2.0, which=1), dda.orient_rhs(0.7, 0.4, 5.0, which=2)]
+    P = inputs.random_polarization(n, 2, seed=12)
+    Pt = torch.tensor(P, dtype=torch.complex128, device="cuda")
+    E = t.near_field(rhs, Pt, margin=margin).cpu().numpy()
+    Em = t.near_field(rhs, Pt, margin=margin, macroscopic=True).cpu().numpy()
+    t.close()
+    X, Y, Z = (box[a] + 2 * margin[a] for a in range(3))
+    assert E.shape == (2, Z, Y, X, 3)
+    zz, yy, xx = np.meshgrid(np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    pts = np.stack([xx.ravel() - margin[0], yy.ravel() - margin[1], zz.ravel() - margin[2]], axis=1)
+    eps = (np.array(ms) ** 2)[comp if comp is not None else np.zeros(n, dtype=int)]
+    for r in range(2):
+        ref = near_field.lattice_field(osites, kd, P[r], pts, *rhs[r])
+        assert _rel(E[r].reshape(-1, 3), ref) < 1e-11
+        refm = near_field.macroscopic(ref, pts, osites, eps)
+        assert _rel(Em[r].reshape(-1, 3), refm) < 1e-11
+
+
+def test_near_field_au_sphere_matches_printed_line(dda):
+    # The guide's Au sphere (§30): solved on the GPU in FP64 to 1e-5, the
+    # near field on the printed 96^3 extended volume, interpolated
+    # trilinearly along the printed line, matches the printed E_y as the
+    # oracle does (5e-3; 2.5e-3 more than one spacing outside the sphere).
+    import json
+    import os
+    from oracle import near_field
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "au_sphere_nearfield_line.json")))
+    sites, box = dda.make_sites("ELLIPSOID", (48.49, 48.49, 48.49))
+    assert len(sites) == fx["n_sites"] and tuple(box) == (48, 48, 48)
+    kd, m, d = fx["kd"], complex(*fx["m"]), fx["d_um"]
+    rhs = [(np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0]))]
+    t = dda.Target(sites, box, m=m, kd=kd)
+    P, st = t.solve(rhs, tol=1e-5, precision="fp64")
+    assert st[0]["status"] == 0
+    E = t.near_field(rhs, P, margin=(24, 24, 24)).cpu().numpy()[0]       # [Z][Y][X][3]
+    t.close()
+    assert E.shape == (96, 96, 96, 3)
+    c = (np.array(box) - 1) / 2.0                                          # centre in site coordinates
+    E = E * np.exp(-1j * kd * c[0])                                        # phase origin at the centre
+    rows = np.array(fx["rows"])
+    pos = np.stack([c[0] + rows[:, 0] / d, np.full(len(rows), c[1]), np.full(len(rows), c[2])], axis=1) + 24
+    lattice = lambda q: E[q[:, 2], q[:, 1], q[:, 0]]
+    Ef = near_field.field_on_line(lattice, pos)
+    err = np.abs(Ef[:, 1] - (rows[:, 5] + 1j * rows[:, 6]))
+    assert err.max() < 5e-3, err.max()
+    assert err[np.abs(rows[:, 0]) > 0.42].max() < 2.5e-3
+    assert np.abs(Ef[:, [0, 2]]).max() < 1e-5
+
+
+def test_near_field_errors(dda):
+    sites, box = dda.make_sites("ELLIPSOID", (6, 5, 4))
+    t = dda.Target(sites, box, m=1.5, kd=0.4)
+    rhs = [dda.orient_rhs(0, 0, 0)]
+    P = torch.zeros((1, len(sites), 3), dtype=torch.complex128, device="cuda")
+    with pytest.raises(dda.DDAError):
+        t.near_field(rhs, P, margin=(-1, 0, 0))
+    with pytest.raises(dda.DDAError):
+        t.near_field(rhs, P, margin=(126, 0, 0))          # 6 + 252 > 256
+    E = t.near_field(rhs, P, margin=(1, 1, 1)).cpu().numpy()[0]
+    t.close()
+    # P = 0: the incident wave alone (k along x, E along y)
+    assert E.shape == (6, 7, 8, 3)
+    assert np.abs(E[..., [0, 2]]).max() < 1e-15 and np.allclose(np.abs(E[..., 1]), 1.0, rtol=0, atol=1e-14)
+    x = np.arange(8) - 1
+    assert np.allclose(E[0, 0, :, 1], np.exp(1j * 0.4 * x), rtol=0, atol=1e-14)
