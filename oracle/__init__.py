@@ -25,6 +25,8 @@ Contents, each following the passage of the DDSCAT 7.3 user guide
                         kd -> 0 limit the DDA must approach (§2).
 * ``near_field``     -- E at lattice points in and near the target and along
                         a line (§29, §30).
+* ``scattering``     -- amplitude matrix f_ml, S_1..S_4 and the Mueller
+                        matrix S_ij in Lab-Frame directions (§26).
 
 Everything is complex128 / float64.  Formulas the guide cites but does not
 print (the dipole field tensor, the LDR coefficients, the cross-section sums,
@@ -32,4 +34,4 @@ BiCGSTAB) are written out from the cited physics; every such reading is named
 in the docstring where it is used.
 """
 
-from . import targets, polarizability, incident, interaction, solvers, cross_sections, mie, near_field  # noqa: F401
+from . import targets, polarizability, incident, interaction, solvers, cross_sections, mie, near_field, scattering  # noqa: F401

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from oracle import cross_sections as cs
-from oracle import incident, interaction, mie, near_field, solvers, targets
+from oracle import incident, interaction, mie, near_field, scattering, solvers, targets
 from oracle import polarizability as pol
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -514,6 +514,95 @@ def test_near_field_at_sites_is_the_dipole_equation():
     q = np.array([[2, -1, 3]])
     want = interaction.green_tensor(q.astype(float), kd)[0] @ p1[0] + incident.incident_field(q, kd, khat, e)[0]
     assert np.allclose(near_field.lattice_field(one, kd, p1, q, khat, e)[0], want, rtol=0, atol=1e-15)
+
+
+# ------------------------------------------------------- scattering matrix --
+
+def test_scattering_matrix_of_one_dipole_is_rayleigh():
+    # one dipole P^(l) = alpha e_0l at the origin: S_1 = -i k^3 alpha,
+    # S_2 = -i k^3 alpha cos(theta), S_3 = S_4 = 0 (Bohren & Huffman's small
+    # particle), so S_11 = k^6 |alpha|^2 (1 + cos^2) / 2 and
+    # S_12 = k^6 |alpha|^2 (cos^2 - 1) / 2 in every scattering plane
+    kd, alpha = 0.7, 0.31 - 0.12j
+    lab = np.eye(3)
+    th = np.radians([0.0, 30.0, 90.0, 135.0, 180.0, 60.0])
+    ph = np.radians([0.0, 0.0, 45.0, 90.0, 200.0, 300.0])
+    one = np.zeros((1, 3))
+    f = scattering.f_matrix(one, kd, [alpha * np.array([0, 1.0, 0])], [alpha * np.array([0, 0, 1.0])], th, ph, lab)
+    S1, S2, S3, S4 = scattering.amplitude_matrix(f, ph, [0, 1, 0], [0, 0, 1], lab)
+    k3a = kd ** 3 * alpha
+    assert np.allclose(S1, -1j * k3a, atol=1e-15) and np.allclose(S2, -1j * k3a * np.cos(th), atol=1e-15)
+    assert np.abs(S3).max() < 1e-15 and np.abs(S4).max() < 1e-15
+    M = scattering.mueller(S1, S2, S3, S4)
+    c2 = np.cos(th) ** 2
+    assert np.allclose(M[:, 0, 0], abs(k3a) ** 2 * (1 + c2) / 2, rtol=1e-13)
+    assert np.allclose(M[:, 0, 1], abs(k3a) ** 2 * (c2 - 1) / 2, rtol=1e-13, atol=1e-18)
+    assert np.allclose(M[:, 0, 1], M[:, 1, 0]) and np.allclose(M[:, 3, 3], M[:, 2, 2])
+
+
+def test_scattering_matrix_optical_theorem_and_total_scattering():
+    # C_ext = (4 pi / k^2) Re S(0) for each polarization (the forward
+    # amplitude: S_2(0) for e01 = y_LF, S_1(0) for e02 = z_LF), and the
+    # integral of S_11 over directions is k^2 times the mean C_sca of the two
+    # polarizations
+    s = targets.ellipsoid(6, 5, 4)
+    kd, m = 0.6, 1.5 + 0.2j
+    lab = np.eye(3)
+    Ps, cext, csca = [], [], []
+    for e in (np.array([0, 1.0, 0]), np.array([0, 0, 1.0])):
+        ai = pol.alpha_inv_ldr(m, kd, lab[0], e)
+        E = incident.incident_field(s, kd, lab[0], e)
+        P = solvers.lu_solve(interaction.dense_matrix(s, kd, ai), E.ravel()).reshape(-1, 3)
+        Ps.append(P)
+        cext.append(cs.c_ext(kd, E, P))
+        csca.append(cs.c_sca_exact(s, kd, P))
+    f = scattering.f_matrix(s, kd, Ps[0], Ps[1], [0.0], [0.0], lab)
+    S1, S2, S3, S4 = scattering.amplitude_matrix(f, np.array([0.0]), [0, 1, 0], [0, 0, 1], lab)
+    assert abs(4 * math.pi / kd ** 2 * S2[0].real - cext[0]) < 1e-12 * cext[0]
+    assert abs(4 * math.pi / kd ** 2 * S1[0].real - cext[1]) < 1e-12 * cext[1]
+    nt, nf = 48, 96
+    x, w = np.polynomial.legendre.leggauss(nt)
+    th = np.repeat(np.arccos(x), nf)
+    ph = np.tile(2 * math.pi * np.arange(nf) / nf, nt)
+    f = scattering.f_matrix(s, kd, Ps[0], Ps[1], th, ph, lab)
+    M = scattering.mueller(*scattering.amplitude_matrix(f, ph, [0, 1, 0], [0, 0, 1], lab))
+    integral = np.sum(np.repeat(w, nf) * (2 * math.pi / nf) * M[:, 0, 0]) / kd ** 2
+    assert abs(integral - 0.5 * (csca[0] + csca[1])) < 1e-10 * csca[0]
+
+
+def test_mueller_matrix_matches_printed_au_block():
+    # The .avg appendix prints S_11, S_12, S_21, S_22, S_31, S_41 and P in the
+    # phi = 0 and 90 deg planes for the 16 x 32 x 32 Au block (GKDLDR, not
+    # printed; LDR here), and g, <cos^2>.  LDR moves the deep minimum near
+    # 55 deg most: S_11 within 6% everywhere and 2% outside 40-75 deg,
+    # P within 0.05, S_12 within 10% of S_11, g and <cos^2> within 1%.  A
+    # wrong sign of S_12, a swapped plane, a power of k or the factor 1/2 all
+    # miss by far more.
+    fx = json.load(open(os.path.join(GOLDEN, "au_block_mueller.json")))
+    s = targets.rctglprsm(*fx["box"])
+    kd, m = fx["kd"], complex(*fx["m"])
+    lab = np.eye(3)
+    Ps = []
+    for e in (np.array([0, 1.0, 0]), np.array([0, 0, 1.0])):
+        ai = pol.alpha_inv_ldr(m, kd, lab[0], e)
+        E = incident.incident_field(s, kd, lab[0], e)
+        P, info = solvers.bicgstab(interaction.FFTOperator(s, kd, ai).matvec, E, tol=1e-7)
+        assert info["converged"]
+        Ps.append(P)
+    rows = np.array(fx["rows"])
+    th, ph = np.radians(rows[:, 0]), np.radians(rows[:, 1])
+    f = scattering.f_matrix(s, kd, Ps[0], Ps[1], th, ph, lab)
+    M = scattering.mueller(*scattering.amplitude_matrix(f, ph, [0, 1, 0], [0, 0, 1], lab))
+    rel = np.abs(M[:, 0, 0] / rows[:, 3] - 1)
+    off_min = (rows[:, 0] < 40) | (rows[:, 0] > 75)
+    assert rel.max() < 0.06 and rel[off_min].max() < 0.02
+    assert np.abs(scattering.polarization(M) - rows[:, 2]).max() < 0.05
+    assert np.all(np.abs(M[:, 0, 1] - rows[:, 4]) < 0.1 * rows[:, 3])
+    assert np.allclose(M[:, 1, 0], M[:, 0, 1]) and np.allclose(M[:, 1, 1], M[:, 0, 0], rtol=1e-12)
+    ff = [cs.far_field(s, kd, P, lab[0], 40, 80) for P in Ps]
+    g = 0.5 * (ff[0]["g"] + ff[1]["g"])
+    c2 = 0.5 * (ff[0]["cos2"] + ff[1]["cos2"])
+    assert abs(g / fx["g"] - 1) < 0.01 and abs(c2 / fx["cos2"] - 1) < 0.01
 
 
 # ---------------------------------------------------------- cross sections --
