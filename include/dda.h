@@ -169,6 +169,21 @@ int dda_make_sites(int32_t shape, const double shpar[3], int64_t *n_sites,
 double dda_aeff(int64_t n_sites);
 double dda_kd_from_x(double x, int64_t n_sites);
 
+/* Target orientations for orientational averaging (§20): nbeta x ntheta x
+ * nphi orientations with weights summing to 1, written as index
+ * (it * nphi + ip) * nbeta + ib of the host arrays beta, theta, phi, weight
+ * (radians; caller-allocated, nbeta * ntheta * nphi each).  beta and phi are
+ * uniformly spaced over [min, max) (min + j (max - min) / n), theta uniformly
+ * in cos(theta) between cos(theta_min) and cos(theta_max): for odd ntheta the
+ * end points are included with Simpson weights (1, 4, 2, ..., 4, 1) /
+ * (3 (ntheta - 1)), for even ntheta the midpoints of ntheta equal intervals
+ * with equal weights; n = 1 takes the minimum.  The orientation average of
+ * a quantity is sum weight_i Q_i.  Errors: DDA_EINVAL for a count < 1, NULL
+ * outputs or non-finite angles. */
+int dda_orientation_grid(double beta_min, double beta_max, int32_t nbeta, double theta_min, double theta_max,
+                         int32_t ntheta, double phi_min, double phi_max, int32_t nphi, double *beta,
+                         double *theta, double *phi, double *weight);
+
 /* Incident direction and polarization in the Target Frame for target
  * orientation (beta, theta, phi) (radians, §19) and Lab-Frame polarization
  * e01 (normalised; x component must be 0).  which = 1 gives e01, which = 2 the
@@ -228,6 +243,30 @@ int dda_cross_sections(dda_target *t, const dda_rhs *rhs, int32_t nrhs,
  * |khat| != 1); DDA_ENOMEM; DDA_EDEVICE. */
 int dda_far_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const void *p_dev, double etasca,
                   void *stream, dda_far *out);
+
+/* Scattering amplitude and Mueller matrices of one incidence (§26). */
+typedef struct {
+  dda_c64 f[2][2];         /* f_ml: m = 0 scattered polarization along theta_hat_s, 1 along
+                              phi_hat_s; l = incident polarization e01, e02 (eq. f_ml_def) */
+  dda_c64 s[4];            /* S_1, S_2, S_3, S_4 (eq. S_ampl_def) */
+  double mueller[4][4];    /* S_ij = mueller[i-1][j-1] (Bohren & Huffman relations of §26) */
+} dda_scat;
+
+/* Amplitude and Mueller matrices (§26) in ndir scattering directions for the
+ * two solved incident polarizations rhs[0] = e01 and rhs[1] = e02 of one
+ * incident direction (p_dev: device [2][N][3], solved for those rhs).
+ * lab (host [3][3]): the Lab Frame axes x_LF, y_LF, z_LF in the target frame,
+ * with x_LF the common khat of both rhs.  theta_phi (host [ndir][2], radians):
+ * the scattering direction n = cos(theta) x_LF + sin(theta) (cos(phi) y_LF +
+ * sin(phi) z_LF); theta_hat and phi_hat are the derivatives of n.
+ * f_ml = kd^3 e_m . sum_j P^(l)_j exp(-i kd n . r_j) (phase origin at the
+ * origin of the site coordinates, as for the incident field), S_1..S_4 from
+ * f_ml by the four relations of §26 with a = e01* . y_LF, b = e01* . z_LF,
+ * c = e02* . y_LF, d = e02* . z_LF.  Synchronous.  Errors: DDA_EINVAL (NULL,
+ * ndir < 1, a lab frame that is not orthonormal or whose x_LF is not khat of
+ * both rhs); DDA_ENOMEM. */
+int dda_scattering_matrix(dda_target *t, const dda_rhs rhs[2], const void *p_dev, const double lab[9],
+                          int32_t ndir, const double *theta_phi, void *stream, dda_scat *out);
 
 /* Near field (§29; the post-processor of §30 reads it).  For polarizations
  * p_dev (device [nrhs][N][3], solved for the same rhs) the field at every

@@ -27,6 +27,7 @@ Contents, each following the passage of the DDSCAT 7.3 user guide
                         a line (§29, §30).
 * ``scattering``     -- amplitude matrix f_ml, S_1..S_4 and the Mueller
                         matrix S_ij in Lab-Frame directions (§26).
+* ``orientation``    -- orientation sampling and weights for averages (§20).
 
 Everything is complex128 / float64.  Formulas the guide cites but does not
 print (the dipole field tensor, the LDR coefficients, the cross-section sums,
@@ -34,4 +35,4 @@ BiCGSTAB) are written out from the cited physics; every such reading is named
 in the docstring where it is used.
 """
 
-from . import targets, polarizability, incident, interaction, solvers, cross_sections, mie, near_field, scattering  # noqa: F401
+from . import targets, polarizability, incident, interaction, solvers, cross_sections, mie, near_field, scattering, orientation  # noqa: F401

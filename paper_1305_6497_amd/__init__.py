@@ -65,6 +65,19 @@ def orient_rhs(beta, theta, phi, e01=(0.0, 1.0, 0.0), which=1):
     return khat, ev
 
 
+def orientation_grid(beta=(0.0, 0.0, 1), theta=(0.0, 0.0, 1), phi=(0.0, 0.0, 1)):
+    """Orientations (beta, theta, phi) in radians and weights of §20, each a
+    (min, max, count) range; returns four float64 arrays of length
+    nbeta * ntheta * nphi (beta fastest)."""
+    n = int(beta[2]) * int(theta[2]) * int(phi[2])
+    out = [np.empty(max(n, 1)) for _ in range(4)]
+    ptr = [o.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for o in out]
+    L.check(L.lib().dda_orientation_grid(float(beta[0]), float(beta[1]), int(beta[2]), float(theta[0]),
+                                         float(theta[1]), int(theta[2]), float(phi[0]), float(phi[1]),
+                                         int(phi[2]), *ptr))
+    return tuple(o[:n] for o in out)
+
+
 def _rhs_array(rhs):
     arr = (L.Rhs * len(rhs))()
     for i, (khat, e) in enumerate(rhs):
@@ -180,6 +193,24 @@ class Target:
         L.check(self._lib.dda_far_field(self._h, _rhs_array(rhs), nrhs, ctypes.c_void_p(P.data_ptr()),
                                         float(etasca), _stream_ptr(stream), out))
         return [dict(qsca=v.qsca, g=v.g, cos2=v.cos2, n_theta=v.n_theta, n_phi=v.n_phi) for v in out]
+
+    def scattering_matrix(self, rhs, P, lab, theta_phi, stream=None):
+        """Amplitude and Mueller matrices for the two polarizations rhs[0], rhs[1]
+        of one incidence: (f [ndir, 2, 2], S [ndir, 4], mueller [ndir, 4, 4])
+        as NumPy arrays; lab = (x_LF, y_LF, z_LF) in the target frame,
+        theta_phi [ndir, 2] in radians."""
+        import numpy as np
+        tp = np.ascontiguousarray(theta_phi, dtype=np.float64).reshape(-1, 2)
+        lb = np.ascontiguousarray(lab, dtype=np.float64).reshape(9)
+        out = (L.Scat * len(tp))()
+        L.check(self._lib.dda_scattering_matrix(
+            self._h, _rhs_array(rhs), ctypes.c_void_p(P.data_ptr()),
+            lb.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(tp),
+            tp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream_ptr(stream), out))
+        f = np.array([[[complex(o.f[m][l].re, o.f[m][l].im) for l in range(2)] for m in range(2)] for o in out])
+        S = np.array([[complex(o.s[j].re, o.s[j].im) for j in range(4)] for o in out])
+        M = np.array([[list(o.mueller[i]) for i in range(4)] for o in out])
+        return f, S, M
 
     def near_field(self, rhs, P, margin=(0, 0, 0), macroscopic=False, stream=None):
         """E at every lattice point of the box extended by ``margin`` points on

@@ -63,6 +63,10 @@ class Far(ctypes.Structure):
                 ("n_theta", ctypes.c_int32), ("n_phi", ctypes.c_int32)]
 
 
+class Scat(ctypes.Structure):
+    _fields_ = [("f", C64 * 2 * 2), ("s", C64 * 4), ("mueller", ctypes.c_double * 4 * 4)]
+
+
 class Q(ctypes.Structure):
     _fields_ = [("qext", ctypes.c_double), ("qabs", ctypes.c_double), ("qsca", ctypes.c_double),
                 ("aeff", ctypes.c_double)]
@@ -80,6 +84,9 @@ SIGNATURES = [
                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.c_int64]),
     ("dda_aeff", ctypes.c_double, [ctypes.c_int64]),
     ("dda_kd_from_x", ctypes.c_double, [ctypes.c_double, ctypes.c_int64]),
+    ("dda_orientation_grid", ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_int32] + [ctypes.POINTER(ctypes.c_double)] * 4),
     ("dda_orient_rhs", ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.POINTER(C64),
                                       ctypes.c_int32, ctypes.POINTER(Rhs)]),
     ("dda_setup_target", ctypes.c_int, [ctypes.POINTER(TargetDesc), ctypes.POINTER(_VP)]),
@@ -92,6 +99,9 @@ SIGNATURES = [
                                           ctypes.POINTER(Q)]),
     ("dda_far_field", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), ctypes.c_int32, _VP, ctypes.c_double, _VP,
                                      ctypes.POINTER(Far)]),
+    ("dda_scattering_matrix", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), _VP, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _VP,
+                                             ctypes.POINTER(Scat)]),
     ("dda_near_field", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), ctypes.c_int32, _VP, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.c_int32, _VP, _VP]),
     ("dda_apply", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP]),

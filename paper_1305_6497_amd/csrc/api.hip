@@ -565,6 +565,31 @@ int dda_make_sites(int32_t shape, const double shpar[3], int64_t *n_sites, int32
   });
 }
 
+int dda_orientation_grid(double beta_min, double beta_max, int32_t nbeta, double theta_min, double theta_max,
+                         int32_t ntheta, double phi_min, double phi_max, int32_t nphi, double *beta,
+                         double *theta, double *phi, double *weight) {
+  return guarded([&]() -> int {
+    DDA_REQUIRE(beta && theta && phi && weight, "NULL argument");
+    DDA_REQUIRE(nbeta >= 1 && ntheta >= 1 && nphi >= 1, "orientation counts must be >= 1");
+    for (double v : {beta_min, beta_max, theta_min, theta_max, phi_min, phi_max})
+      DDA_REQUIRE(std::isfinite(v), "angles must be finite");
+    std::vector<double> b, wb, t, wt, p, wp;
+    periodic_rule(beta_min, beta_max, nbeta, b, wb);
+    cos_theta_rule(theta_min, theta_max, ntheta, t, wt);
+    periodic_rule(phi_min, phi_max, nphi, p, wp);
+    for (int it = 0; it < ntheta; ++it)
+      for (int ip = 0; ip < nphi; ++ip)
+        for (int ib = 0; ib < nbeta; ++ib) {
+          const size_t i = ((size_t)it * nphi + ip) * nbeta + ib;
+          beta[i] = b[ib];
+          theta[i] = t[it];
+          phi[i] = p[ip];
+          weight[i] = wt[it] * wp[ip] * wb[ib];
+        }
+    return DDA_OK;
+  });
+}
+
 int dda_orient_rhs(double beta, double theta, double phi, const dda_c64 e01_lf[3], int32_t which, dda_rhs *out) {
   return guarded([&]() -> int {
     DDA_REQUIRE(e01_lf && out, "NULL argument");
@@ -883,6 +908,116 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
       }
     }
     return all_ok ? DDA_OK : DDA_NOT_CONVERGED;
+  });
+}
+
+int dda_scattering_matrix(dda_target *t, const dda_rhs rhs[2], const void *p_dev, const double lab[9],
+                          int32_t ndir, const double *theta_phi, void *stream, dda_scat *out) {
+  return guarded([&]() -> int {
+    DDA_REQUIRE(t && rhs && p_dev && lab && theta_phi && out, "NULL argument");
+    DDA_REQUIRE(ndir >= 1, "ndir must be >= 1");
+    std::vector<RhsDev> rd;
+    std::vector<c64> ai;
+    prepare_rhs(t, rhs, 2, rd, ai);
+    const double *X = lab, *Y = lab + 3, *Z = lab + 6;
+    auto dot = [](const double *u, const double *v) { return u[0] * v[0] + u[1] * v[1] + u[2] * v[2]; };
+    DDA_REQUIRE(std::fabs(dot(X, X) - 1) < 1e-9 && std::fabs(dot(Y, Y) - 1) < 1e-9 && std::fabs(dot(Z, Z) - 1) < 1e-9 &&
+                    std::fabs(dot(X, Y)) < 1e-9 && std::fabs(dot(X, Z)) < 1e-9 && std::fabs(dot(Y, Z)) < 1e-9,
+                "lab frame must be orthonormal");
+    for (int r = 0; r < 2; ++r)
+      DDA_REQUIRE(std::fabs(dot(X, rd[r].khat) - 1.0) < 1e-9, "x_LF must be khat of both rhs");
+    DDA_HIP(hipSetDevice(t->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamUse use_{t, s};
+    // directions and the scattered basis (theta_hat, phi_hat) in the target frame
+    std::vector<double> dirs((size_t)ndir * 3), eth((size_t)ndir * 3), eph((size_t)ndir * 3);
+    for (int d = 0; d < ndir; ++d) {
+      const double th = theta_phi[2 * d], ph = theta_phi[2 * d + 1];
+      DDA_REQUIRE(std::isfinite(th) && std::isfinite(ph), "directions must be finite");
+      const double ct = std::cos(th), st = std::sin(th), cp = std::cos(ph), sp = std::sin(ph);
+      for (int a = 0; a < 3; ++a) {
+        dirs[3 * d + a] = ct * X[a] + st * (cp * Y[a] + sp * Z[a]);
+        eth[3 * d + a] = -st * X[a] + ct * (cp * Y[a] + sp * Z[a]);
+        eph[3 * d + a] = -sp * Y[a] + cp * Z[a];
+      }
+    }
+    const size_t scratch = far_field_scratch_bytes(t->g, ndir);
+    const size_t bytes = (size_t)ndir * 3 * sizeof(double) + scratch + (size_t)2 * ndir * 6 * sizeof(double);
+    double *buf = t->alloc<double>(bytes);
+    double *d_dirs = buf, *d_scr = buf + (size_t)ndir * 3, *d_F = d_scr + scratch / sizeof(double);
+    std::vector<double> F((size_t)2 * ndir * 6);
+    try {
+      DDA_HIP(hipMemcpyAsync(d_dirs, dirs.data(), dirs.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      for (int l = 0; l < 2; ++l) {
+        const c64 *P = static_cast<const c64 *>(p_dev) + (size_t)l * 3 * t->g.n_sites;
+        launch_far_amplitudes(t->g, t->d_cell_site, P, t->kd, d_dirs, ndir, d_scr, d_F + (size_t)l * ndir * 6, s);
+      }
+      DDA_HIP(hipMemcpyAsync(F.data(), d_F, F.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      DDA_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      (void)hipStreamSynchronize(s);
+      t->release(buf);
+      throw;
+    }
+    t->release(buf);
+    // f_ml, S_1..S_4 and the Mueller matrix (host arithmetic, §26)
+    using cd = std::complex<double>;
+    cd ab[2][2];                                 // [l][0] = e0l* . y_LF, [l][1] = e0l* . z_LF
+    for (int l = 0; l < 2; ++l) {
+      cd py = 0.0, pz = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        const cd ec = std::conj(cd(rd[l].e[a].x, rd[l].e[a].y));
+        py += ec * Y[a];
+        pz += ec * Z[a];
+      }
+      ab[l][0] = py;
+      ab[l][1] = pz;
+    }
+    const cd a = ab[0][0], b = ab[0][1], c = ab[1][0], d4 = ab[1][1], I(0.0, 1.0);
+    const double k3 = t->kd * t->kd * t->kd;
+    for (int d = 0; d < ndir; ++d) {
+      cd f[2][2];
+      for (int l = 0; l < 2; ++l) {
+        const double *q = &F[((size_t)l * ndir + d) * 6];
+        cd ft = 0.0, fp = 0.0;
+        for (int a3 = 0; a3 < 3; ++a3) {
+          const cd Fa(q[2 * a3], q[2 * a3 + 1]);
+          ft += eth[3 * d + a3] * Fa;
+          fp += eph[3 * d + a3] * Fa;
+        }
+        f[0][l] = k3 * ft;
+        f[1][l] = k3 * fp;
+      }
+      const double cp = std::cos(theta_phi[2 * d + 1]), sp = std::sin(theta_phi[2 * d + 1]);
+      const cd S1 = -I * (f[1][0] * (b * cp - a * sp) + f[1][1] * (d4 * cp - c * sp));
+      const cd S2 = -I * (f[0][0] * (a * cp + b * sp) + f[0][1] * (c * cp + d4 * sp));
+      const cd S3 = I * (f[0][0] * (b * cp - a * sp) + f[0][1] * (d4 * cp - c * sp));
+      const cd S4 = I * (f[1][0] * (a * cp + b * sp) + f[1][1] * (c * cp + d4 * sp));
+      dda_scat &o = out[d];
+      for (int m = 0; m < 2; ++m)
+        for (int l = 0; l < 2; ++l) o.f[m][l] = dda_c64{f[m][l].real(), f[m][l].imag()};
+      const cd Sv[4] = {S1, S2, S3, S4};
+      for (int j = 0; j < 4; ++j) o.s[j] = dda_c64{Sv[j].real(), Sv[j].imag()};
+      const double a1 = std::norm(S1), a2 = std::norm(S2), a3 = std::norm(S3), a4 = std::norm(S4);
+      double(*M)[4] = o.mueller;
+      M[0][0] = (a1 + a2 + a3 + a4) / 2;
+      M[0][1] = (a2 - a1 + a4 - a3) / 2;
+      M[0][2] = std::real(S2 * std::conj(S3) + S1 * std::conj(S4));
+      M[0][3] = std::imag(S2 * std::conj(S3) - S1 * std::conj(S4));
+      M[1][0] = (a2 - a1 + a3 - a4) / 2;
+      M[1][1] = (a1 + a2 - a3 - a4) / 2;
+      M[1][2] = std::real(S2 * std::conj(S3) - S1 * std::conj(S4));
+      M[1][3] = std::imag(S2 * std::conj(S3) + S1 * std::conj(S4));
+      M[2][0] = std::real(S2 * std::conj(S4) + S1 * std::conj(S3));
+      M[2][1] = std::real(S2 * std::conj(S4) - S1 * std::conj(S3));
+      M[2][2] = std::real(S1 * std::conj(S2) + S3 * std::conj(S4));
+      M[2][3] = std::imag(S2 * std::conj(S1) + S4 * std::conj(S3));
+      M[3][0] = std::imag(S4 * std::conj(S2) + S1 * std::conj(S3));
+      M[3][1] = std::imag(S4 * std::conj(S2) - S1 * std::conj(S3));
+      M[3][2] = std::imag(S1 * std::conj(S2) - S3 * std::conj(S4));
+      M[3][3] = std::real(S1 * std::conj(S2) - S3 * std::conj(S4));
+    }
+    return DDA_OK;
   });
 }
 

@@ -298,6 +298,11 @@ size_t far_field_scratch_bytes(const Geometry &g, int ndir);
 void launch_far_field(const Geometry &g, const int *cell_site, const c64 *P, double kd, const double *dirs,
                       const double *mu, const double *w, int ndir, double *scratch, double *sums, hipStream_t s);
 
+// Phase sums F(n_d) = sum_j P_j exp(-i kd n_d . r_j) for ndir directions (one
+// RHS): F host-visible device [ndir][3] complex; scratch as for the far field.
+void launch_far_amplitudes(const Geometry &g, const int *cell_site, const c64 *P, double kd, const double *dirs,
+                           int ndir, double *scratch, double *F, hipStream_t s);
+
 // Near field: embed P [nrhs][n][3] into the extended box (P_ext[r][map[i]] =
 // P[r][i]; P_ext zeroed by the caller), and E = E_inc - AP_ext on the box
 // (fac[c] = 3 / (eps_c + 2) at points with cellc >= 0, or fac = nullptr).
@@ -309,6 +314,11 @@ void launch_near_field_combine(const c64 *AP, int64_t ne, int X, int Y, const in
 // --------------------------------------------------------------- host side --
 std::vector<int32_t> make_sites(int shape, const double shpar[3], int32_t box[3]);
 void orient_rhs(double beta, double theta, double phi, const c64 e01[3], int which, RhsDev &out);
+// Orientation sampling of §20: n points min + j (max - min) / n with weights
+// 1/n (beta, phi); theta uniform in cos(theta), Simpson weights for odd n
+// (end points included), midpoints with equal weights for even n.
+void periodic_rule(double lo, double hi, int n, std::vector<double> &x, std::vector<double> &w);
+void cos_theta_rule(double lo, double hi, int n, std::vector<double> &theta, std::vector<double> &w);
 c64 alpha_inverse(int kind, c64 m, double kd, const double khat[3], const c64 e[3]);
 
 }  // namespace dda

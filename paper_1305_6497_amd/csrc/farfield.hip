@@ -112,6 +112,22 @@ __global__ __launch_bounds__(kFT) void kf_final(const double *__restrict__ rec, 
   }
 }
 
+// F[d] = sum over chunks of the partial sums (chunk order): the phase sums
+// F(n_d) = sum_j P_j exp(-i k n_d . r_j), 3 complex values per direction
+__global__ __launch_bounds__(kFT) void kf_collect(const double *__restrict__ fpart, int nchunk, int ndir,
+                                                  double *__restrict__ F) {
+  const int d = blockIdx.x * kFT + threadIdx.x;
+  if (d >= ndir) return;
+  double f[6] = {0, 0, 0, 0, 0, 0};
+  for (int c = 0; c < nchunk; ++c) {
+    const double *q = fpart + ((size_t)c * ndir + d) * 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) f[k] += q[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) F[(size_t)d * 6 + k] = f[k];
+}
+
 size_t far_field_scratch_bytes(const Geometry &g, int ndir) {
   const int dblk = (ndir + kFT - 1) / kFT;
   const int nrows = g.ny * g.nz;
@@ -132,6 +148,19 @@ void launch_far_field(const Geometry &g, const int *cell_site, const c64 *P, dou
                      ndir, fpart);
   hipLaunchKernelGGL(kf_intensity, dim3(dblk), dim3(kFT), 0, s, fpart, nchunk, dirs, mu, w, ndir, rec);
   hipLaunchKernelGGL(kf_final, dim3(1), dim3(kFT), 0, s, rec, dblk, sums);
+  DDA_HIP(hipGetLastError());
+}
+
+void launch_far_amplitudes(const Geometry &g, const int *cell_site, const c64 *P, double kd, const double *dirs,
+                           int ndir, double *scratch, double *F, hipStream_t s) {
+  const int dblk = (ndir + kFT - 1) / kFT;
+  const int nrows = g.ny * g.nz;
+  int nchunk = std::min(nrows, std::max(1, (2048 + dblk - 1) / dblk));
+  const int rpc = (nrows + nchunk - 1) / nchunk;
+  nchunk = (nrows + rpc - 1) / rpc;
+  hipLaunchKernelGGL(kf_partial, dim3(dblk, nchunk), dim3(kFT), 0, s, cell_site, g.nx, g.ny, nrows, rpc, P, kd, dirs,
+                     ndir, scratch);
+  hipLaunchKernelGGL(kf_collect, dim3(dblk), dim3(kFT), 0, s, scratch, nchunk, ndir, F);
   DDA_HIP(hipGetLastError());
 }
 

@@ -167,6 +167,35 @@ std::vector<int32_t> make_sites(int shape, const double shpar[3], int32_t box[3]
 // ------------------------------------------------------------ orientation --
 // §19: x_LF, y_LF, z_LF in the basis of the target axes (a1, a2, a3), which
 // are x_TF, y_TF, z_TF for the built-in targets used here.
+void periodic_rule(double lo, double hi, int n, std::vector<double> &x, std::vector<double> &w) {
+  x.resize(n);
+  w.assign(n, 1.0 / n);
+  for (int j = 0; j < n; ++j) x[j] = lo + j * (hi - lo) / n;
+}
+
+void cos_theta_rule(double lo, double hi, int n, std::vector<double> &theta, std::vector<double> &w) {
+  theta.resize(n);
+  w.resize(n);
+  const double c0 = std::cos(lo), c1 = std::cos(hi);
+  if (n == 1) {
+    theta[0] = lo;
+    w[0] = 1.0;
+  } else if (n % 2 == 1) {
+    for (int j = 0; j < n; ++j) {
+      const double u = c0 + (c1 - c0) * j / (n - 1);
+      theta[j] = std::acos(std::min(1.0, std::max(-1.0, u)));
+      const double simpson = (j == 0 || j == n - 1) ? 1.0 : (j % 2 == 1 ? 4.0 : 2.0);
+      w[j] = simpson / (3.0 * (n - 1));
+    }
+  } else {
+    for (int j = 0; j < n; ++j) {
+      const double u = c0 + (c1 - c0) * (j + 0.5) / n;
+      theta[j] = std::acos(std::min(1.0, std::max(-1.0, u)));
+      w[j] = 1.0 / n;
+    }
+  }
+}
+
 void orient_rhs(double beta, double theta, double phi, const c64 e01[3], int which, RhsDev &out) {
   DDA_REQUIRE(which == 1 || which == 2, "which must be 1 or 2");
   const std::complex<double> ey(e01[1].x, e01[1].y), ez(e01[2].x, e01[2].y);

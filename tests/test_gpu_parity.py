@@ -584,3 +584,118 @@ def test_near_field_errors(dda):
     assert np.abs(E[..., [0, 2]]).max() < 1e-15 and np.allclose(np.abs(E[..., 1]), 1.0, rtol=0, atol=1e-14)
     x = np.arange(8) - 1
     assert np.allclose(E[0, 0, :, 1], np.exp(1j * 0.4 * x), rtol=0, atol=1e-14)
+
+
+# ------------------------------------------------------- scattering matrix --
+@pytest.mark.parametrize("shape,shpar,angles", [
+    ("ELLIPSOID", (9.5, 8.0, 6.5), (0.0, 0.0, 0.0)),
+    ("RCTGLPRSM", (7, 5, 3), (0.4, 1.1, 2.0)),
+    ("HEX_PRISM", (6, 9, 2), (2.5, 2.2, 0.7)),
+    ("RCTGLPRSM", (1, 1, 1), (0.3, 0.9, 4.0)),
+])
+def test_scattering_matrix_matches_oracle(dda, shape, shpar, angles):
+    from oracle import scattering
+    sites, box = dda.make_sites(shape, shpar)
+    osites = targets.make(shape, shpar)
+    kd = 0.55
+    rhs = [dda.orient_rhs(*angles, which=1), dda.orient_rhs(*angles, which=2)]
+    khat = np.asarray(rhs[0][0], dtype=float)
+    # a Lab Frame with x_LF = khat: y_LF along Re(e01) (linear e01), z_LF = x_LF x y_LF
+    y = np.real(np.asarray(rhs[0][1], dtype=complex))
+    y = y / np.linalg.norm(y)
+    lab = np.stack([khat, y, np.cross(khat, y)])
+    t = dda.Target(sites, box, m=1.5 + 0.05j, kd=kd)
+    P = inputs.random_polarization(len(sites), 2, seed=21)
+    rng = np.random.default_rng(22)
+    tp = np.stack([rng.uniform(0, np.pi, 37), rng.uniform(0, 2 * np.pi, 37)], axis=1)
+    tp[0] = (0.0, 0.0)
+    tp[1] = (np.pi, 1.0)
+    f, S, M = t.scattering_matrix(rhs, torch.tensor(P, device="cuda"), lab, tp)
+    t.close()
+    fo = scattering.f_matrix(osites, kd, P[0], P[1], tp[:, 0], tp[:, 1], lab)
+    So = np.stack(scattering.amplitude_matrix(fo, tp[:, 1], rhs[0][1], rhs[1][1], lab), axis=1)
+    Mo = scattering.mueller(*So.T)
+    assert _rel(f, fo) < 1e-12
+    assert _rel(S, So) < 1e-12
+    assert _rel(M, Mo) < 1e-12
+
+
+def test_scattering_matrix_au_block_matches_printed(dda):
+    # GPU solve (FP64) of the printed Au block and its Mueller matrix in the
+    # printed directions: the oracle pin's tolerances (LDR against the printed
+    # GKDLDR run), and the optical theorem against the GPU cross sections.
+    import json
+    import os
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "au_block_mueller.json")))
+    sites, box = dda.make_sites("RCTGLPRSM", fx["box"])
+    kd, m = fx["kd"], complex(*fx["m"])
+    lab = np.eye(3)
+    rhs = [(lab[0], np.array([0, 1.0, 0])), (lab[0], np.array([0, 0, 1.0]))]
+    t = dda.Target(sites, box, m=m, kd=kd)
+    P, st = t.solve(rhs, tol=1e-7, precision="fp64")
+    assert all(x["status"] == 0 for x in st)
+    rows = np.array(fx["rows"])
+    tp = np.radians(rows[:, :2])
+    f, S, M = t.scattering_matrix(rhs, P, lab, np.vstack([tp, [[0.0, 0.0]]]))
+    q = t.cross_sections(rhs, P)
+    t.close()
+    S0 = S[-1]
+    aeff = q[0]["aeff"]
+    assert abs(4 * np.pi / kd ** 2 * S0[1].real / (np.pi * aeff ** 2) - q[0]["qext"]) < 1e-10 * q[0]["qext"]
+    assert abs(4 * np.pi / kd ** 2 * S0[0].real / (np.pi * aeff ** 2) - q[1]["qext"]) < 1e-10 * q[1]["qext"]
+    M = M[:-1]
+    rel = np.abs(M[:, 0, 0] / rows[:, 3] - 1)
+    off_min = (rows[:, 0] < 40) | (rows[:, 0] > 75)
+    assert rel.max() < 0.06 and rel[off_min].max() < 0.02
+    pol_ = np.sqrt(M[:, 1, 0] ** 2 + M[:, 2, 0] ** 2) / M[:, 0, 0]
+    assert np.abs(pol_ - rows[:, 2]).max() < 0.05
+    assert np.all(np.abs(M[:, 0, 1] - rows[:, 4]) < 0.1 * rows[:, 3])
+
+
+def test_scattering_matrix_errors(dda):
+    sites, box = dda.make_sites("ELLIPSOID", (6, 5, 4))
+    t = dda.Target(sites, box, m=1.5, kd=0.4)
+    rhs = [dda.orient_rhs(0, 0, 0, which=1), dda.orient_rhs(0, 0, 0, which=2)]
+    P = torch.zeros((2, len(sites), 3), dtype=torch.complex128, device="cuda")
+    with pytest.raises(dda.DDAError):
+        t.scattering_matrix(rhs, P, np.eye(3)[[1, 0, 2]], [[0.1, 0.2]])      # x_LF is not khat
+    with pytest.raises(dda.DDAError):
+        t.scattering_matrix(rhs, P, 2 * np.eye(3), [[0.1, 0.2]])             # not orthonormal
+    f, S, M = t.scattering_matrix(rhs, P, np.eye(3), [[0.1, 0.2]])
+    t.close()
+    assert np.all(f == 0) and np.all(S == 0) and np.all(M == 0)
+
+
+# ---------------------------------------------------- orientation averaging --
+def test_orientation_averaged_efficiencies_match_oracle(dda):
+    # §20: every orientation of the grid and both polarizations solved as one
+    # block of right-hand sides; the weighted average of Q against the
+    # oracle's dense solves of the same orientations
+    from oracle import orientation
+    two_pi = 2 * np.pi
+    rng = ((0.0, two_pi, 2), (0.0, np.pi, 3), (0.0, two_pi, 3))
+    b, th, ph, w = dda.orientation_grid(*rng)
+    shpar = (7, 5, 4)
+    sites, box = dda.make_sites("ELLIPSOID", shpar)
+    osites = targets.ellipsoid(*shpar)
+    kd, m = 0.5, 1.7 + 0.1j
+    rhs = [dda.orient_rhs(b[i], th[i], ph[i], which=k) for i in range(len(w)) for k in (1, 2)]
+    t = dda.Target(sites, box, m=m, kd=kd)
+    P, st = t.solve(rhs, tol=1e-11, precision="fp64", max_iter=3000)
+    q = t.cross_sections(rhs, P)
+    t.close()
+    assert all(x["status"] == 0 for x in st)
+    qg = np.array([[q[2 * i + k][key] for key in ("qext", "qabs", "qsca")] for i in range(len(w)) for k in (0, 1)])
+    avg = orientation.average(0.5 * (qg[0::2] + qg[1::2]), w)
+    ref = []
+    for i in range(len(w)):
+        for k in (1, 2):
+            khat, e = rhs[2 * i + k - 1]
+            ai = _oracle_ainv(m, kd, khat, e)
+            E = incident.incident_field(osites, kd, khat, e)
+            Po = solvers.lu_solve(interaction.dense_matrix(osites, kd, ai), E.ravel()).reshape(-1, 3)
+            qo = cross_sections.efficiencies(len(osites), kd, E, ai, Po)
+            ref.append([qo["qext"], qo["qabs"], qo["qsca"]])
+    ref = np.array(ref)
+    ravg = orientation.average(0.5 * (ref[0::2] + ref[1::2]), w)
+    assert np.abs(avg - ravg).max() < 1e-9 * ravg[0]

@@ -10,7 +10,7 @@ import re
 import numpy as np
 import pytest
 
-from oracle import incident, targets
+from oracle import incident, orientation, targets
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -81,6 +81,18 @@ def test_orientation_matches_oracle(dda):
             ko, eo = incident.incident_in_tf(b[i], t[i], p[i], e1 if which == 1 else e2)
             assert np.allclose(k, ko, atol=1e-14) and np.allclose(e, eo, atol=1e-14)
             assert abs(np.dot(k, e)) < 1e-13
+
+
+@pytest.mark.parametrize("rng", [((0.0, 6.283185307179586, 4), (0.0, 3.141592653589793, 7), (0.0, 6.283185307179586, 3)),
+                                 ((0.2, 1.5, 3), (0.1, 1.2, 6), (0.0, 1.0, 1)),
+                                 ((0.0, 0.0, 1), (0.0, 0.0, 1), (0.0, 0.0, 1))])
+def test_orientation_grid_matches_oracle(dda, rng):
+    got = dda.orientation_grid(*rng)
+    ref = orientation.grid(*rng)
+    for g, r in zip(got, ref):
+        assert g.shape == r.shape and np.abs(g - r).max() <= 1e-15 * max(1.0, np.abs(r).max())
+    with pytest.raises(dda.DDAError):
+        dda.orientation_grid((0.0, 1.0, 0))
 
 
 def test_next_smooth(dda):

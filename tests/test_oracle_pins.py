@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from oracle import cross_sections as cs
-from oracle import incident, interaction, mie, near_field, scattering, solvers, targets
+from oracle import incident, interaction, mie, near_field, orientation, scattering, solvers, targets
 from oracle import polarizability as pol
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -603,6 +603,55 @@ def test_mueller_matrix_matches_printed_au_block():
     g = 0.5 * (ff[0]["g"] + ff[1]["g"])
     c2 = 0.5 * (ff[0]["cos2"] + ff[1]["cos2"])
     assert abs(g / fx["g"] - 1) < 0.01 and abs(c2 / fx["cos2"] - 1) < 0.01
+
+
+# ------------------------------------------------------ orientation average --
+
+@pytest.mark.parametrize("nb,nt,npf", [(1, 1, 1), (3, 5, 4), (4, 6, 3), (2, 9, 5)])
+def test_orientation_weights_and_exactness(nb, nt, npf):
+    two_pi = 2 * math.pi
+    b, t, p, w = orientation.grid((0.0, two_pi, nb), (0.0, math.pi, nt), (0.0, two_pi, npf))
+    assert len(w) == nb * nt * npf and abs(w.sum() - 1.0) < 1e-14
+    if nt == 1:
+        return
+    c = np.cos(t)
+    # uniform in cos(Theta) on [-1, 1]: <cos> = 0; Simpson (odd) is exact to
+    # cubic order, <cos^2> = 1/3, <cos^3> = 0
+    assert abs(np.sum(w * c)) < 1e-14
+    if nt % 2 == 1:
+        assert abs(np.sum(w * c ** 2) - 1 / 3) < 1e-14 and abs(np.sum(w * c ** 3)) < 1e-14
+    # the periodic rules average cos(m x) to 0 for 0 < m < n
+    for m in range(1, nb):
+        assert abs(np.sum(w * np.cos(m * b))) < 1e-14
+    for m in range(1, npf):
+        assert abs(np.sum(w * np.cos(m * p))) < 1e-14
+
+
+def test_orientation_average_of_random_orientations():
+    # with the §19 orientation algebra, a grid exact to the needed degree
+    # reproduces the SO(3) averages <(khat . u)^2> = 1/3 for any fixed unit u
+    # and <|e . u|^2> = 1/3 for the incident polarization
+    two_pi = 2 * math.pi
+    b, t, p, w = orientation.grid((0.0, two_pi, 3), (0.0, math.pi, 5), (0.0, two_pi, 3))
+    u = np.array([0.3, -0.5, 0.8]) / np.linalg.norm([0.3, -0.5, 0.8])
+    kk, ee = [], []
+    for bi, ti, pi in zip(b, t, p):
+        khat, e = incident.incident_in_tf(bi, ti, pi, [0, 1, 0])
+        kk.append(float(np.dot(khat, u)) ** 2)
+        ee.append(abs(np.dot(e, u)) ** 2)
+    assert abs(orientation.average(kk, w) - 1 / 3) < 1e-13
+    assert abs(orientation.average(ee, w) - 1 / 3) < 1e-13
+    # a sphere's extinction does not depend on orientation
+    s = targets.sphere(4)
+    kd, m = 0.5, 1.4 + 0.05j
+    q = []
+    for bi, ti, pi in list(zip(b, t, p))[::7]:
+        khat, e = incident.incident_in_tf(bi, ti, pi, [0, 1, 0])
+        ai = pol.alpha_inv_cmrr(m, kd)
+        E = incident.incident_field(s, kd, khat, e)
+        P = solvers.lu_solve(interaction.dense_matrix(s, kd, ai), E.ravel()).reshape(-1, 3)
+        q.append(cs.c_ext(kd, E, P))
+    assert np.ptp(q) < 0.02 * np.mean(q)
 
 
 # ---------------------------------------------------------- cross sections --
