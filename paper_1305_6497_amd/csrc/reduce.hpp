@@ -52,10 +52,11 @@ __device__ __forceinline__ void write_record(double *partial, int r, int nblk, i
 // the block take part; the result is valid in thread 0.  Each thread adds the
 // records tid, tid + NT, tid + 2 NT, ... in that order; the loads of U of them
 // are issued before the first add, so the (cross-XCD) load latency is paid
-// once per U records rather than once per record.
+// once per U records rather than once per record (U does not change the
+// order of the additions).
 template <int NV, int NT>
 __device__ __forceinline__ void sum_records(const double *partial, int nblk, int r, double *out) {
-  constexpr int U = 8;
+  constexpr int U = NV <= 2 ? 8 : NV <= 4 ? 4 : 2;      // U * NV loads in flight, without spilling
   double v[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = 0.0;
