@@ -112,7 +112,10 @@ typedef struct {
   double inner_tol;        /* MIXED: inner recursive-residual target relative to the
                               current true residual; 0 => tol (one refinement pass) */
   int32_t max_outer;       /* cap on true-residual checks / refinement passes per RHS */
-  int32_t check_every;     /* iterations between host convergence checks (>= 1; 0 => 8) */
+  int32_t check_every;     /* iterations between host convergence checks (>= 1); 0 => the
+                              first check after 8, then (eager launches) where the decay of the
+                              recursive residuals since the last check predicts that the slowest
+                              RHS converges (4..64); with use_graph, 0 => 8 */
   int32_t use_graph;       /* 1: the check_every iterations between host checks run as one
                               captured HIP graph on a stream of the handle (ordered after and
                               before the caller's stream); 0: kernels are launched directly */

@@ -160,7 +160,7 @@ class Target:
         import torch
         return torch.empty((nrhs, self.n, 3), dtype=torch.complex128, device=f"cuda:{self.device}")
 
-    def solve(self, rhs, tol=1e-5, max_iter=1000, precision="fp64", inner_tol=0.0, max_outer=20, check_every=8,
+    def solve(self, rhs, tol=1e-5, max_iter=1000, precision="fp64", inner_tol=0.0, max_outer=20, check_every=0,
               out=None, stream=None, use_graph=False, solver="bicgstab"):
         """Solve A P = E for every (khat, e) in rhs.  Returns (P, stats).
 

@@ -827,7 +827,12 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     DDA_HIP(hipSetDevice(t->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     StreamUse use_{t, s};
-    const int K = opts->check_every > 0 ? opts->check_every : 8;
+    // iterations between host checks: fixed, or (check_every = 0, eager
+    // launches) predicted from the recursive residual's decay since the last
+    // check, so that the next check falls where the slowest RHS should have
+    // converged (each check costs a host round trip with the GPU idle)
+    int K = opts->check_every > 0 ? opts->check_every : 8;
+    const bool adaptive = opts->check_every <= 0 && opts->use_graph == 0;
     const int max_outer = opts->max_outer > 0 ? opts->max_outer : 20;
     std::vector<RhsDev> rd;
     std::vector<c64> ai;
@@ -841,13 +846,31 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
 
     std::vector<int> status(nrhs), check(nrhs), restart(nrhs), outer(nrhs, 0), final_status(nrhs, -1);
     std::vector<c64> scal((size_t)nrhs * kScal);
-    std::vector<double> rel(nrhs, 0.0);
+    std::vector<double> rel(nrhs, 0.0), r2_prev(nrhs, -1.0);
+    int k_prev = 0;                                  // iterations since the residuals in r2_prev
     const double tol = opts->tol;
     const double inner = opts->precision == DDA_MIXED ? opts->inner_tol : 0.0;
     // P = 0 start: an RHS with E = 0 is already solved.
     while (true) {
       DDA_HIP(hipMemcpyAsync(status.data(), k.status, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
+      if (adaptive)
+        DDA_HIP(hipMemcpyAsync(scal.data(), k.scal, scal.size() * sizeof(c64), hipMemcpyDeviceToHost, s));
       DDA_HIP(hipStreamSynchronize(s));
+      if (adaptive) {
+        int kmax = 0;
+        for (int r = 0; r < nrhs; ++r) {
+          if (final_status[r] >= 0 || status[r] != ST_RUN) continue;
+          const double r2 = scal[(size_t)r * kScal + S_RNORM2].x, thr = scal[(size_t)r * kScal + S_THR2].x;
+          int kr = 8;
+          if (k_prev > 0 && r2_prev[r] > 0.0 && r2 < r2_prev[r] && r2 > thr && thr > 0.0) {
+            const double need = k_prev * std::log(thr / r2) / std::log(r2 / r2_prev[r]);
+            kr = need < 63.0 ? (int)std::ceil(need) + 1 : 64;
+          }
+          kmax = std::max(kmax, kr);
+          r2_prev[r] = r2;
+        }
+        K = std::min(64, std::max(4, kmax > 0 ? kmax : 8));
+      }
       bool any_run = false, any_check = false;
       for (int r = 0; r < nrhs; ++r) {
         check[r] = 0;
@@ -885,10 +908,17 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
           DDA_HIP(hipMemcpyAsync(t->d_restart, restart.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
           k_restart(k, t->d_restart, tol, inner, opts->solver, s);
           any_run = true;
+          if (adaptive) {
+            // a restarted RHS starts a new residual history
+            for (int r = 0; r < nrhs; ++r)
+              if (restart[r]) r2_prev[r] = scal[(size_t)r * kScal + S_TRUE2].x;
+            K = std::max(K, 8);
+          }
         }
       }
       if (!any_run) break;
       run_iterations(t, opts->precision, opts->solver, K, opts->use_graph != 0, s);
+      k_prev = K;
     }
     DDA_HIP(hipMemcpyAsync(scal.data(), k.scal, scal.size() * sizeof(c64), hipMemcpyDeviceToHost, s));
     const size_t vec = (size_t)k.n3 * nrhs * sizeof(c64);
