@@ -51,6 +51,12 @@ struct dda_target {
   std::vector<RhsDev> h_rhs;
   std::vector<c64> h_ainv;
   hipEvent_t upload_done = nullptr;
+  // pinned host copies of the per-RHS status and scalars read at every host
+  // check of a solve (a pinned copy returns sooner than a pageable one)
+  int *h_status = nullptr;
+  c64 *h_scal = nullptr;
+  size_t h_status_granted = 0, h_scal_granted = 0;
+  int h_nrhs = 0;
   // captured block of BiCGSTAB iterations (see run_iterations)
   hipGraphExec_t graph = nullptr;
   int graph_nrhs = 0, graph_prec = -1, graph_k = 0, graph_solver = -1;
@@ -116,6 +122,8 @@ struct dda_target {
     for (auto &a : allocs) dev_release(device, a.p, a.granted);
     for (auto &u : uses) (void)hipEventDestroy(u.second);
     if (upload_done) (void)hipEventDestroy(upload_done);
+    pinned_release(h_status, h_status_granted);
+    pinned_release(h_scal, h_scal_granted);
     if (stream) (void)hipStreamDestroy(stream);
   }
 };
@@ -844,6 +852,17 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     launch_incident(t->g, t->d_ijk, t->d_rhs, nrhs, t->kd, k.b, s);
     k_init_state(k, opts->tol, opts->max_iter, opts->solver, s);
 
+    if (t->h_nrhs < nrhs) {
+      DDA_HIP(hipStreamSynchronize(s));               // no copy into the old blocks is pending
+      pinned_release(t->h_status, t->h_status_granted);
+      pinned_release(t->h_scal, t->h_scal_granted);
+      t->h_status = nullptr;
+      t->h_scal = nullptr;
+      t->h_nrhs = 0;
+      t->h_status = static_cast<int *>(pinned_alloc(3 * nrhs * sizeof(int), &t->h_status_granted));
+      t->h_scal = static_cast<c64 *>(pinned_alloc((size_t)nrhs * kScal * sizeof(c64), &t->h_scal_granted));
+      t->h_nrhs = nrhs;
+    }
     std::vector<int> status(nrhs), check(nrhs), restart(nrhs), outer(nrhs, 0), final_status(nrhs, -1);
     std::vector<c64> scal((size_t)nrhs * kScal);
     std::vector<double> rel(nrhs, 0.0), r2_prev(nrhs, -1.0);
@@ -852,10 +871,12 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     const double inner = opts->precision == DDA_MIXED ? opts->inner_tol : 0.0;
     // P = 0 start: an RHS with E = 0 is already solved.
     while (true) {
-      DDA_HIP(hipMemcpyAsync(status.data(), k.status, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
+      DDA_HIP(hipMemcpyAsync(t->h_status, k.status, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
       if (adaptive)
-        DDA_HIP(hipMemcpyAsync(scal.data(), k.scal, scal.size() * sizeof(c64), hipMemcpyDeviceToHost, s));
+        DDA_HIP(hipMemcpyAsync(t->h_scal, k.scal, scal.size() * sizeof(c64), hipMemcpyDeviceToHost, s));
       DDA_HIP(hipStreamSynchronize(s));
+      std::copy(t->h_status, t->h_status + nrhs, status.begin());
+      if (adaptive) std::copy(t->h_scal, t->h_scal + scal.size(), scal.begin());
       if (adaptive) {
         int kmax = 0;
         for (int r = 0; r < nrhs; ++r) {
@@ -883,11 +904,14 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
       }
       if (any_check) {
         // FP64 true residual r = E - A x for the stopped RHS
-        DDA_HIP(hipMemcpyAsync(k.check, check.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+        int *h_check = t->h_status + nrhs;           // pinned; not rewritten before the sync below
+        std::copy(check.begin(), check.end(), h_check);
+        DDA_HIP(hipMemcpyAsync(k.check, h_check, nrhs * sizeof(int), hipMemcpyHostToDevice, s));
         matvec(t, DDA_FP64, k.x, k.t, nrhs, k.check, s);
         k_true_residual(k, k.t, s);
-        DDA_HIP(hipMemcpyAsync(scal.data(), k.scal, scal.size() * sizeof(c64), hipMemcpyDeviceToHost, s));
+        DDA_HIP(hipMemcpyAsync(t->h_scal, k.scal, scal.size() * sizeof(c64), hipMemcpyDeviceToHost, s));
         DDA_HIP(hipStreamSynchronize(s));
+        std::copy(t->h_scal, t->h_scal + scal.size(), scal.begin());
         bool any_restart = false;
         for (int r = 0; r < nrhs; ++r) {
           restart[r] = 0;
@@ -905,7 +929,9 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
           }
         }
         if (any_restart) {
-          DDA_HIP(hipMemcpyAsync(t->d_restart, restart.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+          int *h_restart = t->h_status + 2 * nrhs;   // pinned; read by the copy before the next sync
+          std::copy(restart.begin(), restart.end(), h_restart);
+          DDA_HIP(hipMemcpyAsync(t->d_restart, h_restart, nrhs * sizeof(int), hipMemcpyHostToDevice, s));
           k_restart(k, t->d_restart, tol, inner, opts->solver, s);
           any_run = true;
           if (adaptive) {
@@ -920,11 +946,12 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
       run_iterations(t, opts->precision, opts->solver, K, opts->use_graph != 0, s);
       k_prev = K;
     }
-    DDA_HIP(hipMemcpyAsync(scal.data(), k.scal, scal.size() * sizeof(c64), hipMemcpyDeviceToHost, s));
+    DDA_HIP(hipMemcpyAsync(t->h_scal, k.scal, scal.size() * sizeof(c64), hipMemcpyDeviceToHost, s));
     const size_t vec = (size_t)k.n3 * nrhs * sizeof(c64);
     if (p_dev) DDA_HIP(hipMemcpyAsync(p_dev, k.x, vec, hipMemcpyDeviceToDevice, s));
     if (p_host) DDA_HIP(hipMemcpyAsync(p_host, k.x, vec, hipMemcpyDeviceToHost, s));
     DDA_HIP(hipStreamSynchronize(s));
+    std::copy(t->h_scal, t->h_scal + scal.size(), scal.begin());
     bool all_ok = true;
     for (int r = 0; r < nrhs; ++r) {
       if (final_status[r] != 0) all_ok = false;

@@ -289,6 +289,9 @@ void launch_cross_sums(const Geometry &g, const int32_t *ijk, const RhsDev *rhs,
 // released only when no queued work uses it any more.
 void *dev_alloc(int device, size_t bytes, size_t *granted);
 void dev_release(int device, void *p, size_t granted);
+// pinned host blocks from a process-wide pool (reused, never freed)
+void *pinned_alloc(size_t bytes, size_t *granted);
+void pinned_release(void *p, size_t granted);
 
 // Gauss-Legendre nodes and weights on [-1, 1] (host, Newton iteration).
 void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w);

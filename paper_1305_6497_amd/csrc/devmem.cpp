@@ -7,7 +7,8 @@
 // (best fit within 25%).  Callers return a block only after the work that used
 // it has finished.  The cache holds at most a quarter of the device memory;
 // blocks beyond that, and the whole cache when hipMalloc runs out of memory,
-// are released with hipFree.
+// are released with hipFree.  Small pinned host blocks (the status reads of
+// the solve loop) come from a pool of their own.
 #include <map>
 #include <mutex>
 #include <vector>
@@ -102,6 +103,50 @@ void dev_release(int device, void *p, size_t granted) {
   }
   c.free_blocks[device].emplace(granted, p);
   c.cached[device] += granted;
+}
+
+// Pinned host blocks for the small status reads of the solve loop.  They are
+// kept for reuse, never freed: hipHostFree can wait for the device, which
+// would stall a closing handle behind other requests' kernels.
+namespace {
+struct PinnedPool {
+  std::mutex mu;
+  std::multimap<size_t, void *> free_blocks;
+};
+PinnedPool &pinned_pool() {
+  static PinnedPool *p = new PinnedPool;
+  return *p;
+}
+}  // namespace
+
+void *pinned_alloc(size_t bytes, size_t *granted) {
+  const size_t want = round_size(bytes < 16 ? 16 : bytes);
+  PinnedPool &pool = pinned_pool();
+  {
+    std::lock_guard<std::mutex> lk(pool.mu);
+    auto it = pool.free_blocks.lower_bound(want);
+    if (it != pool.free_blocks.end() && it->first <= 2 * want) {
+      void *p = it->second;
+      *granted = it->first;
+      pool.free_blocks.erase(it);
+      return p;
+    }
+  }
+  void *p = nullptr;
+  const hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error{e == hipErrorOutOfMemory ? DDA_ENOMEM : DDA_EDEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e)};
+  }
+  *granted = want;
+  return p;
+}
+
+void pinned_release(void *p, size_t granted) {
+  if (!p) return;
+  PinnedPool &pool = pinned_pool();
+  std::lock_guard<std::mutex> lk(pool.mu);
+  pool.free_blocks.emplace(granted, p);
 }
 
 }  // namespace dda
