@@ -865,33 +865,46 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     }
     std::vector<int> status(nrhs), check(nrhs), restart(nrhs), outer(nrhs, 0), final_status(nrhs, -1);
     std::vector<c64> scal((size_t)nrhs * kScal);
-    std::vector<double> rel(nrhs, 0.0), r2_prev(nrhs, -1.0);
-    int k_prev = 0;                                  // iterations since the residuals in r2_prev
+    std::vector<double> rel(nrhs, 0.0);
+    // per RHS: residual^2 and iteration count of the last reference point
+    // (the start, |b|^2 at 0 iterations; a restart, its true residual^2)
+    std::vector<double> ref_r2(nrhs, -1.0), ref_it(nrhs, 0.0);
+    const double steps_per_k = opts->solver == DDA_SOLVER_BICGSTAB2 ? 2.0 : 1.0;
     const double tol = opts->tol;
     const double inner = opts->precision == DDA_MIXED ? opts->inner_tol : 0.0;
-    // P = 0 start: an RHS with E = 0 is already solved.
+    // P = 0 start: an RHS with E = 0 is already solved (its status says so
+    // after the first block; the first block is queued without a read)
+    bool first = true;
     while (true) {
-      DDA_HIP(hipMemcpyAsync(t->h_status, k.status, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
-      if (adaptive)
-        DDA_HIP(hipMemcpyAsync(t->h_scal, k.scal, scal.size() * sizeof(c64), hipMemcpyDeviceToHost, s));
-      DDA_HIP(hipStreamSynchronize(s));
-      std::copy(t->h_status, t->h_status + nrhs, status.begin());
-      if (adaptive) std::copy(t->h_scal, t->h_scal + scal.size(), scal.begin());
-      if (adaptive) {
+      if (first) {
+        std::fill(status.begin(), status.end(), (int)ST_RUN);
+      } else {
+        DDA_HIP(hipMemcpyAsync(t->h_status, k.status, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
+        if (adaptive)
+          DDA_HIP(hipMemcpyAsync(t->h_scal, k.scal, scal.size() * sizeof(c64), hipMemcpyDeviceToHost, s));
+        DDA_HIP(hipStreamSynchronize(s));
+        std::copy(t->h_status, t->h_status + nrhs, status.begin());
+        if (adaptive) std::copy(t->h_scal, t->h_scal + scal.size(), scal.begin());
+      }
+      if (adaptive && !first) {
         int kmax = 0;
         for (int r = 0; r < nrhs; ++r) {
           if (final_status[r] >= 0 || status[r] != ST_RUN) continue;
-          const double r2 = scal[(size_t)r * kScal + S_RNORM2].x, thr = scal[(size_t)r * kScal + S_THR2].x;
+          const c64 *sc = &scal[(size_t)r * kScal];
+          const double r2 = sc[S_RNORM2].x, thr = sc[S_THR2].x, it = sc[S_ITERS].x;
+          if (ref_r2[r] < 0.0) ref_r2[r] = sc[S_BNORM2].x;
           int kr = 8;
-          if (k_prev > 0 && r2_prev[r] > 0.0 && r2 < r2_prev[r] && r2 > thr && thr > 0.0) {
-            const double need = k_prev * std::log(thr / r2) / std::log(r2 / r2_prev[r]);
+          if (it > ref_it[r] && ref_r2[r] > 0.0 && r2 < ref_r2[r] && r2 > thr && thr > 0.0) {
+            const double need = (it - ref_it[r]) * std::log(thr / r2) / std::log(r2 / ref_r2[r]) / steps_per_k;
             kr = need < 63.0 ? (int)std::ceil(need) + 1 : 64;
           }
           kmax = std::max(kmax, kr);
-          r2_prev[r] = r2;
+          ref_r2[r] = r2;
+          ref_it[r] = it;
         }
         K = std::min(64, std::max(4, kmax > 0 ? kmax : 8));
       }
+      first = false;
       bool any_run = false, any_check = false;
       for (int r = 0; r < nrhs; ++r) {
         check[r] = 0;
@@ -937,14 +950,16 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
           if (adaptive) {
             // a restarted RHS starts a new residual history
             for (int r = 0; r < nrhs; ++r)
-              if (restart[r]) r2_prev[r] = scal[(size_t)r * kScal + S_TRUE2].x;
+              if (restart[r]) {
+                ref_r2[r] = scal[(size_t)r * kScal + S_TRUE2].x;
+                ref_it[r] = scal[(size_t)r * kScal + S_ITERS].x;
+              }
             K = std::max(K, 8);
           }
         }
       }
       if (!any_run) break;
       run_iterations(t, opts->precision, opts->solver, K, opts->use_graph != 0, s);
-      k_prev = K;
     }
     DDA_HIP(hipMemcpyAsync(t->h_scal, k.scal, scal.size() * sizeof(c64), hipMemcpyDeviceToHost, s));
     const size_t vec = (size_t)k.n3 * nrhs * sizeof(c64);
