@@ -164,8 +164,11 @@ class Target:
               out=None, stream=None, use_graph=False, solver="bicgstab"):
         """Solve A P = E for every (khat, e) in rhs.  Returns (P, stats).
 
-        solver: "bicgstab" (the guide's PBCGST) or "bicgstab2" (BiCGstab(2),
-        the guide's PBCGS2)."""
+        solver: "bicgstab" (the guide's PBCGST), "bicgstab2" (BiCGstab(2), the
+        guide's PBCGS2), "cocg" or "qmr" (QMR smoothing of COCG, the guide's
+        QMRCCG).  check_every: iterations between host convergence checks; 0
+        picks them from the residual decay after a first block of 8, -n does
+        the same after a first block of n."""
         nrhs = len(rhs)
         P = self._vec(nrhs) if out is None else out
         opts = L.SolveOpts(tol=tol, max_iter=max_iter, precision=PRECISION[precision], inner_tol=inner_tol,

@@ -835,11 +835,12 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     DDA_HIP(hipSetDevice(t->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     StreamUse use_{t, s};
-    // iterations between host checks: fixed, or (check_every = 0, eager
-    // launches) predicted from the recursive residual's decay since the last
-    // check, so that the next check falls where the slowest RHS should have
-    // converged (each check costs a host round trip with the GPU idle)
-    int K = opts->check_every > 0 ? opts->check_every : 8;
+    // iterations between host checks: fixed, or (check_every <= 0, eager
+    // launches) a first block of 8 (or -check_every) iterations, then blocks
+    // predicted from the recursive residual's decay since the last check, so
+    // that the next check falls where the slowest RHS should have converged
+    // (each check costs a host round trip with the GPU idle)
+    int K = opts->check_every > 0 ? opts->check_every : opts->check_every < 0 ? std::min(-opts->check_every, 64) : 8;
     const bool adaptive = opts->check_every <= 0 && opts->use_graph == 0;
     const int max_outer = opts->max_outer > 0 ? opts->max_outer : 20;
     std::vector<RhsDev> rd;

@@ -705,12 +705,13 @@ def test_orientation_averaged_efficiencies_match_oracle(dda):
 def test_check_interval_does_not_change_results(dda, solver):
     # Host checks only read the status: the iterates, the stopping iteration
     # and the refinement restarts are the same for a fixed interval of 1 or 8
-    # iterations and for the adaptive interval (check_every = 0)
+    # iterations and for the adaptive interval (check_every = 0, first check
+    # after 8; check_every = -3, first check after 3)
     sites, box = dda.make_sites("ELLIPSOID", (12, 9, 7))
     rhs = [dda.orient_rhs(0.3, 0.8, 1.1, which=1), dda.orient_rhs(0.3, 0.8, 1.1, which=2)]
     t = dda.Target(sites, box, m=1.8 + 0.05j, kd=0.5)
     out = []
-    for ce in (0, 1, 8):
+    for ce in (0, 1, 8, -3):
         P, st = t.solve(rhs, tol=1e-8, precision="mixed", check_every=ce, solver=solver)
         out.append((P.cpu().numpy(), [(x["iters"], x["outer"], x["status"]) for x in st]))
     t.close()
