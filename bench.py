@@ -224,6 +224,15 @@ def extra_workloads(dda, inputs, torch, tol):
     t2 = time.perf_counter() - s0
     d133["bicgstab2"] = dict(solves_per_s=len(rhs) / t2, iters=[x["iters"] for x in st2],
                              q_rel_err_vs_mie=[_rel_err(v, mie) for v in q2] if mie else None)
+    # and with COCG (one product per iteration, bilinear form of the complex-symmetric A)
+    s0 = time.perf_counter()
+    P, st3 = t.solve(rhs, tol=tol, precision="mixed", out=P, solver="cocg")
+    q3 = t.cross_sections(rhs, P)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter() - s0
+    d133["cocg"] = dict(solves_per_s=len(rhs) / t3, iters=[x["iters"] for x in st3],
+                        rel_resid=[x["rel_resid"] for x in st3],
+                        q_rel_err_vs_mie=[_rel_err(v, mie) for v in q3] if mie else None)
     out["sphere_d133"] = d133
     t.close()
 

@@ -124,6 +124,11 @@ typedef struct {
                               DDA_SOLVER_BICGSTAB2 (BiCGstab(2), the PBCGS2 option the guide
                               recommends, §12; check_every then counts cycles of two BiCG
                               steps), DDA_SOLVER_COCG or DDA_SOLVER_QMR (the QMRCCG option) */
+  int32_t fold_records;    /* tuning only, results are bit-identical: a product with at most this
+                              many per-block partial records per RHS lets each block of the
+                              kernel that needs its step length (BiCGSTAB alpha and omega, COCG
+                              and QMR alpha) sum the records itself; above, one block computes
+                              it first.  0 => 1024; < 0 => never */
 } dda_solve_opts;
 
 typedef struct {

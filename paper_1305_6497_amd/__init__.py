@@ -161,19 +161,20 @@ class Target:
         return torch.empty((nrhs, self.n, 3), dtype=torch.complex128, device=f"cuda:{self.device}")
 
     def solve(self, rhs, tol=1e-5, max_iter=1000, precision="fp64", inner_tol=0.0, max_outer=20, check_every=0,
-              out=None, stream=None, use_graph=False, solver="bicgstab"):
+              out=None, stream=None, use_graph=False, solver="bicgstab", fold_records=0):
         """Solve A P = E for every (khat, e) in rhs.  Returns (P, stats).
 
         solver: "bicgstab" (the guide's PBCGST), "bicgstab2" (BiCGstab(2), the
         guide's PBCGS2), "cocg" or "qmr" (QMR smoothing of COCG, the guide's
         QMRCCG).  check_every: iterations between host convergence checks; 0
         picks them from the residual decay after a first block of 8, -n does
-        the same after a first block of n."""
+        the same after a first block of n.  fold_records: tuning only (results
+        are bit-identical), see dda_solve_opts."""
         nrhs = len(rhs)
         P = self._vec(nrhs) if out is None else out
         opts = L.SolveOpts(tol=tol, max_iter=max_iter, precision=PRECISION[precision], inner_tol=inner_tol,
                            max_outer=max_outer, check_every=check_every, use_graph=int(bool(use_graph)),
-                           solver=SOLVER[solver])
+                           solver=SOLVER[solver], fold_records=fold_records)
         st = (L.SolveStats * nrhs)()
         code = L.check(self._lib.dda_solve(self._h, _rhs_array(rhs), nrhs, ctypes.byref(opts),
                                            ctypes.c_void_p(P.data_ptr()), None, _stream_ptr(stream), st),

@@ -20,6 +20,10 @@ static thread_local std::string g_last_error;
 void set_error(const std::string &msg) { g_last_error = msg; }
 }  // namespace dda
 
+// Default of dda_solve_opts.fold_records: folding costs every consuming block
+// a read of all records, O(blocks x records), which is cheap up to about this.
+constexpr int kFoldRecords = 1024;
+
 struct dda_target {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -59,7 +63,11 @@ struct dda_target {
   int h_nrhs = 0;
   // captured block of BiCGSTAB iterations (see run_iterations)
   hipGraphExec_t graph = nullptr;
-  int graph_nrhs = 0, graph_prec = -1, graph_k = 0, graph_solver = -1;
+  int graph_nrhs = 0, graph_prec = -1, graph_k = 0, graph_solver = -1, graph_fold = -1;
+  // products with at most this many partial records per RHS hand their
+  // scalar (alpha, omega) to the consuming kernel, which computes it in every
+  // block; larger ones get a one-block kernel first (set by each solve)
+  int fold_records = kFoldRecords;
   uint64_t graph_gen = 0;
   uint64_t buffer_gen = 0;        // bumped whenever workspaces are reallocated
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -375,18 +383,20 @@ void matvec(dda_target *t, int precision, const c64 *in, c64 *out, int nrhs, con
   }
 }
 
-// One BiCGSTAB iteration for every active RHS of the block: 12 kernels.
+// One BiCGSTAB iteration for every active RHS of the block: 12 kernels
+// (14 when the products have more than fold_records records).
 //   product 1: x-forward forms p = r + beta (p - omega v); x-inverse writes
 //              v = A p and partial sums of <rh, v>
 //   product 2: x-forward computes alpha = rho / <rh, v> (every block, from
-//              the records) and forms s = r - alpha v; x-inverse writes
-//              t = A s and partial sums of <t, s>, <t, t>
-//   update:    omega = <t, s> / <t, t> (every block, from the records),
+//              the records, or one block before it) and forms s = r - alpha v;
+//              x-inverse writes t = A s and partial sums of <t, s>, <t, t>
+//   update:    omega = <t, s> / <t, t> (likewise),
 //              x += alpha p + omega s, r = s - omega t with <rh, r>, |r|^2;
 //              rho, beta and the convergence status.
 void iteration(dda_target *t, int precision, hipStream_t s) {
   KrylovState &k = t->k;
   const int nrec = xpass_blocks(t->g, precision == DDA_MIXED);
+  const bool fold = nrec <= t->fold_records;
   FuseArgs f;
   f.r = k.r;
   f.v = k.v;
@@ -400,12 +410,16 @@ void iteration(dda_target *t, int precision, hipStream_t s) {
   f.w = k.p;
   matvec(t, precision, k.p, k.v, k.nrhs, k.active, s, nullptr, -1, 1, &f);
   f.in_mode = 2;
-  f.fold_alpha = 1;
-  f.nrec = nrec;
+  if (fold) {
+    f.fold_alpha = 1;
+    f.nrec = nrec;
+  } else {
+    k_scalar_alpha(k, s, nrec);
+  }
   f.out_mode = 2;
   f.w = k.s;
   matvec(t, precision, k.s, k.t, k.nrhs, k.active, s, nullptr, -1, 1, &f);
-  k_update_xr(k, s, nrec);
+  k_update_xr(k, s, nrec, fold);
   k_scalar_rho(k, s);
 }
 
@@ -484,7 +498,7 @@ void cocg_iteration(dda_target *t, int precision, bool qmr, hipStream_t s) {
   f.ax_neg[0] = 0;
   f.out_mode = 4;
   matvec(t, precision, k.p, k.v, k.nrhs, k.active, s, nullptr, -1, 1, &f);
-  k_cocg_update(k, s, nrec, qmr);
+  k_cocg_update(k, s, nrec, nrec <= t->fold_records, qmr);
   k_cocg_scalar(k, s, qmr);
 }
 
@@ -512,7 +526,7 @@ void run_iterations(dda_target *t, int precision, int solver, int K, bool use_gr
     DDA_HIP(hipEventCreateWithFlags(&t->ev_out, hipEventDisableTiming));
   }
   if (!t->graph || t->graph_nrhs != t->k.nrhs || t->graph_prec != precision || t->graph_k != K ||
-      t->graph_solver != solver || t->graph_gen != t->buffer_gen) {
+      t->graph_solver != solver || t->graph_fold != t->fold_records || t->graph_gen != t->buffer_gen) {
     if (t->graph) {
       DDA_HIP(hipGraphExecDestroy(t->graph));
       t->graph = nullptr;
@@ -533,6 +547,7 @@ void run_iterations(dda_target *t, int precision, int solver, int K, bool use_gr
     t->graph_nrhs = t->k.nrhs;
     t->graph_prec = precision;
     t->graph_solver = solver;
+    t->graph_fold = t->fold_records;
     t->graph_k = K;
     t->graph_gen = t->buffer_gen;
   }
@@ -840,6 +855,7 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     // predicted from the recursive residual's decay since the last check, so
     // that the next check falls where the slowest RHS should have converged
     // (each check costs a host round trip with the GPU idle)
+    t->fold_records = opts->fold_records > 0 ? opts->fold_records : opts->fold_records < 0 ? 0 : kFoldRecords;
     int K = opts->check_every > 0 ? opts->check_every : opts->check_every < 0 ? std::min(-opts->check_every, 64) : 8;
     const bool adaptive = opts->check_every <= 0 && opts->use_graph == 0;
     const int max_outer = opts->max_outer > 0 ? opts->max_outer : 20;

@@ -192,7 +192,9 @@ struct MatvecArgs {
 // The x passes keep 3 * rows * Mx <= kXBudget elements per block (EPT <= 8):
 // more, lighter blocks keep more loads in flight than few heavy ones.
 constexpr int kXBudget = 1536;
-constexpr int xpass_rows(int Mx) { return 3 * Mx >= kXBudget ? 1 : kXBudget / (3 * Mx); }
+constexpr int xpass_rows(int Mx) {
+  return 3 * Mx >= kXBudget ? 1 : kXBudget / (3 * Mx) >= 2 ? kXBudget / (3 * Mx) : 6 * Mx <= 2048 ? 2 : 1;
+}
 
 // Blocks of the x passes (= partial records an out_mode reduction writes).
 int xpass_blocks(const Geometry &g, bool fp32);
@@ -254,7 +256,9 @@ void k_scalar_alpha(const KrylovState &k, hipStream_t s, int nrec);
 // x += alpha p + omega s, r = s - omega t; omega is computed by every block
 // from the nrec records (<t, s>, <t, t>) in k.partial; records of <rh, r>,
 // |r|^2 go to k.partial2 (read by k_scalar_rho)
-void k_update_xr(const KrylovState &k, hipStream_t s, int nrec);
+// fold: the consuming kernel computes omega (alpha) from the nrec records in
+// every block; otherwise a one-block kernel computes it first.
+void k_update_xr(const KrylovState &k, hipStream_t s, int nrec, bool fold);
 // step = 1, bsign = +1: BiCGSTAB; step = 2, bsign = -1: end of a BiCGstab(2) cycle
 void k_scalar_rho(const KrylovState &k, hipStream_t s, int step = 1, double bsign = 1.0);
 // BiCGstab(2): second BiCG step's beta, minimal-residual coefficients, closing update
@@ -266,7 +270,7 @@ void k2_update_mr(const KrylovState &k, hipStream_t s);
 // previous step to x (the smoothed iterate) and k.t (the smoothed residual)
 // with the raw COCG iterate in k.s.  Records of r^T r, |r|^2, |t|^2 go to
 // k.partial2; k_cocg_scalar turns them into beta, QMR's weights and the status.
-void k_cocg_update(const KrylovState &k, hipStream_t s, int nrec, bool qmr);
+void k_cocg_update(const KrylovState &k, hipStream_t s, int nrec, bool fold, bool qmr);
 void k_cocg_scalar(const KrylovState &k, hipStream_t s, bool qmr);
 
 // r_true = b - Ax (Ax given in `ax`) for RHS with check[r]; writes norms into partial/scal.

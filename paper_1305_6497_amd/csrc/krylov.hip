@@ -137,22 +137,42 @@ __global__ void kk_scalar_alpha(const double *partial, int nblk, c64 *scal, int 
   }
 }
 
+// omega = <t, s> / <t, t> from the records of the product that made t.
+__device__ __forceinline__ c64 omega_from(const double (&q)[3]) {
+  return q[2] > 0.0 ? c64{q[0] / q[2], q[1] / q[2]} : c64{0.0, 0.0};
+}
+
+// One block per RHS: omega into S_OMEGA, for kk_update_xr without records.
+__global__ void kk_scalar_omega(const double *partial, int nblk, c64 *scal, const int *active) {
+  const int r = blockIdx.x;
+  if (!active[r]) return;
+  double q[3];
+  sum_partials<3>(partial, nblk, r, q);
+  if (threadIdx.x == 0) scal[(size_t)r * kScal + S_OMEGA] = omega_from(q);
+}
+
 // x += alpha p + omega s;  r = s - omega t;  partial <rh, r>, |r|^2.
-// omega = <t, s> / <t, t> is computed by every block from the records of the
-// product that made t (same sum and order in every block); block 0 stores it.
+// With rec_in, omega is computed by every block from the records of the
+// product that made t (same sum and order in every block, and as
+// kk_scalar_omega computes it); block 0 stores it.  Without, it is read from
+// S_OMEGA.  Every block reading all records costs O(blocks x records), so
+// the host folds only products with few records.
 __global__ void kk_update_xr(const int *active, c64 *x, c64 *rr, const c64 *rh, const c64 *p, const c64 *s,
                              const c64 *t, c64 *scal, int64_t n3, const double *rec_in, int nrec_in,
                              double *partial, int nblk) {
   RHS_PREAMBLE
   __shared__ c64 s_omega;
-  {
+  if (rec_in) {
     double q[3];
     sum_partials<3>(rec_in, nrec_in, r, q);
     if (threadIdx.x == 0) {
-      const c64 om = q[2] > 0.0 ? c64{q[0] / q[2], q[1] / q[2]} : c64{0.0, 0.0};
+      const c64 om = omega_from(q);
       s_omega = om;
       if (blockIdx.x == 0) scal[(size_t)r * kScal + S_OMEGA] = om;
     }
+    __syncthreads();
+  } else {
+    if (threadIdx.x == 0) s_omega = scal[(size_t)r * kScal + S_OMEGA];
     __syncthreads();
   }
   const c64 alpha = scal[(size_t)r * kScal + S_ALPHA];
@@ -352,10 +372,35 @@ __global__ void kk2_update_mr(const int *active, c64 *x, c64 *r0, const c64 *r1,
 }
 
 // ------------------------------------------------------------- COCG / QMR --
-// alpha = rho / p^T q: every block sums the records of the product q = A p in
-// the same order, so all agree; a breakdown (p^T q ~ 0) leaves x and r as
-// they are and is flagged in S_FLAG for kk_cocg_scalar (no block clears
-// `active` here, so every block does the same work).
+// alpha = rho / p^T q and the breakdown flag (p^T q ~ 0).
+__device__ __forceinline__ bool cocg_alpha(const double (&d)[2], const c64 *sc, c64 &a) {
+  const c64 den = {d[0], d[1]}, rho = sc[S_RHO];
+  const bool ok = cabs2(den) > 1e-60 * cabs2(rho) && cabs2(den) > 0.0 && cabs2(den) < 1e300;
+  a = ok ? cdiv(rho, den) : c64{0.0, 0.0};
+  return ok;
+}
+
+// One block per RHS: alpha into S_ALPHA and the flag into S_FLAG, for
+// kk_cocg_update without records.
+__global__ void kk_cocg_alpha(const double *partial, int nblk, c64 *scal, const int *active) {
+  const int r = blockIdx.x;
+  if (!active[r]) return;
+  double d[2];
+  sum_partials<2>(partial, nblk, r, d);
+  if (threadIdx.x == 0) {
+    c64 *sc = scal + (size_t)r * kScal;
+    c64 a;
+    const bool ok = cocg_alpha(d, sc, a);
+    sc[S_ALPHA] = a;
+    sc[S_FLAG] = {ok ? 0.0 : 1.0, 0.0};
+  }
+}
+
+// alpha = rho / p^T q: with rec_in every block sums the records of the
+// product q = A p in the same order (as kk_cocg_alpha does), so all agree;
+// without, alpha is read from S_ALPHA.  A breakdown leaves x and r as they
+// are and is flagged in S_FLAG for kk_cocg_scalar (no block clears `active`
+// here, so every block does the same work).
 // QMR (xs, ss non-null): x holds the smoothed iterate y, xs the COCG iterate
 // and ss the smoothed residual; the smoothing of the previous step comes first:
 //     y += eta (xs - y);  ss += eta (r - ss);  then xs += alpha p;  r -= alpha q.
@@ -365,20 +410,22 @@ __global__ void kk_cocg_update(const int *active, c64 *x, c64 *rr, const c64 *p,
                                int nblk) {
   RHS_PREAMBLE
   __shared__ c64 s_alpha;
-  {
+  if (rec_in) {
     double d[2];
     sum_partials<2>(rec_in, nrec_in, r, d);
     if (threadIdx.x == 0) {
       c64 *sc = scal + (size_t)r * kScal;
-      const c64 den = {d[0], d[1]}, rho = sc[S_RHO];
-      const bool ok = cabs2(den) > 1e-60 * cabs2(rho) && cabs2(den) > 0.0 && cabs2(den) < 1e300;
-      const c64 a = ok ? cdiv(rho, den) : c64{0.0, 0.0};
+      c64 a;
+      const bool ok = cocg_alpha(d, sc, a);
       s_alpha = a;
       if (blockIdx.x == 0) {
         sc[S_ALPHA] = a;
         sc[S_FLAG] = {ok ? 0.0 : 1.0, 0.0};
       }
     }
+    __syncthreads();
+  } else {
+    if (threadIdx.x == 0) s_alpha = scal[(size_t)r * kScal + S_ALPHA];
     __syncthreads();
   }
   const c64 alpha = s_alpha;
@@ -462,9 +509,11 @@ void k_init_state(const KrylovState &k, double tol, int max_iter, int solver, hi
                      tol * tol, max_iter, bilinear_solver(solver) ? 1 : 0);
   DDA_HIP(hipGetLastError());
 }
-void k_cocg_update(const KrylovState &k, hipStream_t s, int nrec, bool qmr) {
+void k_cocg_update(const KrylovState &k, hipStream_t s, int nrec, bool fold, bool qmr) {
+  if (!fold)
+    hipLaunchKernelGGL(kk_cocg_alpha, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, nrec, k.scal, k.active);
   hipLaunchKernelGGL(kk_cocg_update, vgrid(k), dim3(KNT), 0, s, k.active, k.x, k.r, k.p, k.v, qmr ? k.s : nullptr,
-                     qmr ? k.t : nullptr, k.scal, k.n3, k.partial, nrec, k.partial2, k.nblk);
+                     qmr ? k.t : nullptr, k.scal, k.n3, fold ? k.partial : nullptr, nrec, k.partial2, k.nblk);
 }
 void k_cocg_scalar(const KrylovState &k, hipStream_t s, bool qmr) {
   hipLaunchKernelGGL(kk_cocg_scalar, dim3(k.nrhs), dim3(KNT), 0, s, k.partial2, k.nblk, k.scal, k.active, k.status,
@@ -473,9 +522,11 @@ void k_cocg_scalar(const KrylovState &k, hipStream_t s, bool qmr) {
 void k_scalar_alpha(const KrylovState &k, hipStream_t s, int nrec) {
   hipLaunchKernelGGL(kk_scalar_alpha, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, nrec, k.scal, k.active, k.status);
 }
-void k_update_xr(const KrylovState &k, hipStream_t s, int nrec) {
+void k_update_xr(const KrylovState &k, hipStream_t s, int nrec, bool fold) {
+  if (!fold)
+    hipLaunchKernelGGL(kk_scalar_omega, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, nrec, k.scal, k.active);
   hipLaunchKernelGGL(kk_update_xr, vgrid(k), dim3(KNT), 0, s, k.active, k.x, k.r, k.rh, k.p, k.s, k.t, k.scal, k.n3,
-                     k.partial, nrec, k.partial2, k.nblk);
+                     fold ? k.partial : nullptr, nrec, k.partial2, k.nblk);
 }
 void k_scalar_rho(const KrylovState &k, hipStream_t s, int step, double bsign) {
   // BiCGSTAB: records of kk_update_xr (partial2); BiCGstab(2): of kk2_update_mr (partial)

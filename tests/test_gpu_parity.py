@@ -702,6 +702,23 @@ def test_orientation_averaged_efficiencies_match_oracle(dda):
 
 
 @pytest.mark.parametrize("solver", SOLVERS)
+def test_where_step_lengths_are_summed_does_not_change_results(dda, solver):
+    # alpha and omega come from the same records summed in the same order
+    # whether every block of the kernel that uses them sums the records
+    # (default for few records) or one block does it first (fold_records < 0)
+    sites, box = dda.make_sites("ELLIPSOID", (12, 9, 7))
+    rhs = [dda.orient_rhs(0.3, 0.8, 1.1, which=1), dda.orient_rhs(0.3, 0.8, 1.1, which=2)]
+    t = dda.Target(sites, box, m=1.8 + 0.05j, kd=0.5)
+    out = []
+    for fr in (0, -1):
+        P, st = t.solve(rhs, tol=1e-8, precision="mixed", fold_records=fr, solver=solver)
+        out.append((P.cpu().numpy(), [(x["iters"], x["outer"], x["status"]) for x in st]))
+    t.close()
+    assert out[1][1] == out[0][1]
+    assert np.array_equal(out[1][0], out[0][0])
+
+
+@pytest.mark.parametrize("solver", SOLVERS)
 def test_check_interval_does_not_change_results(dda, solver):
     # Host checks only read the status: the iterates, the stopping iteration
     # and the refinement restarts are the same for a fixed interval of 1 or 8
