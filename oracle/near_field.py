@@ -1,5 +1,8 @@
-"""Near fields: E at lattice points in and around the target (§29 of the
-DDSCAT 7.3 guide) and along a line (§30, the post-processor).
+"""Near fields: E (and B) at lattice points in and around the target (§29 of
+the DDSCAT 7.3 guide) and along a line (§30, the post-processor).
+
+Test infrastructure: only the tests, the smoke check and the benchmark's CPU
+baseline use this package.
 
 For a solved polarization P the field at a lattice point q, the dipole at q
 itself excluded, is (d = 1, the Green tensor of ``interaction``)
@@ -80,3 +83,40 @@ def field_on_line(field_at, positions):
     uniq, inv = np.unique(flat, axis=0, return_inverse=True)
     vals = field_at(uniq)[inv.ravel()].reshape(corners.shape[0], 8, 3)
     return np.einsum("nk,nka->na", weights, vals)
+
+
+def magnetic_field(sites, kd, P, points, khat, e, origin=(0.0, 0.0, 0.0)):
+    """B_inc + B_sca at real-valued points, complex128 [len(points), 3].
+
+    §29 stores, with E, the magnetic field B_sca of all the oscillating dipoles
+    except one sitting at the point, and the incident B_inc (nonmagnetic
+    material: B is both the micro- and the macroscopic field).  In the units of
+    ``interaction`` (Gaussian, time factor exp(-i omega t), d = 1) the field of
+    a point dipole p at distance R along the unit vector n (source to point) is
+    the textbook one,
+
+        B = k^2 (exp(ikR) / R) (1 - 1 / (ikR)) n x p,
+
+    and the plane wave E_inc = e exp(ik khat . r) carries B_inc = khat x E_inc.
+    Direct sum over the dipoles.
+    """
+    sites = np.asarray(sites, dtype=float)
+    points = np.asarray(points, dtype=float)
+    P = np.asarray(P, dtype=complex)
+    out = np.empty((len(points), 3), dtype=complex)
+    block = max(1, 500_000 // max(1, len(sites)))
+    for i0 in range(0, len(points), block):
+        q = points[i0:i0 + block]
+        R = q[:, None, :] - sites[None, :, :]                      # [b, N, 3]
+        r = np.sqrt(np.sum(R * R, axis=-1))
+        self_term = r == 0.0
+        r = np.where(self_term, 1.0, r)
+        n = R / r[..., None]
+        f = kd * kd * np.exp(1j * kd * r) / r * (1.0 - 1.0 / (1j * kd * r))
+        f = np.where(self_term, 0.0, f)
+        out[i0:i0 + block] = np.sum(f[..., None] * np.cross(n, P[None, :, :]), axis=1)
+    rr = points - np.asarray(origin, dtype=float)[None, :]
+    kh = np.asarray(khat, dtype=float)
+    phase = np.exp(1j * kd * (rr @ kh))
+    binc = np.cross(kh, np.asarray(e, dtype=complex))
+    return out + phase[:, None] * binc[None, :]

@@ -516,6 +516,69 @@ def test_near_field_at_sites_is_the_dipole_equation():
     assert np.allclose(near_field.lattice_field(one, kd, p1, q, khat, e)[0], want, rtol=0, atol=1e-15)
 
 
+def _electric_field_at(sites, kd, P, x, khat, e):
+    """E_inc + sum_l G(x - r_l) P_l at real points x (no point on a site)."""
+    R = np.asarray(x, dtype=float)[:, None, :] - np.asarray(sites, dtype=float)[None, :, :]
+    Es = np.einsum("qnab,nb->qa", interaction.green_tensor(R, kd), P)
+    return Es + np.exp(1j * kd * (np.asarray(x, dtype=float) @ khat))[:, None] * e[None, :]
+
+
+def test_magnetic_near_field_is_the_curl_of_the_electric_field():
+    # Faraday's law for exp(-i omega t) in Gaussian units: curl E = ik B, for
+    # the scattered and the incident field alike.  The curl of the oracle's E
+    # by central differences (step 1e-5) at points from half a spacing to 40
+    # spacings away from the dipoles fixes B_sca and B_inc completely: a
+    # wrong sign, a dropped (1 - 1/(ikR)) term or a swapped cross product
+    # fails by far more than the tolerance.
+    rng = np.random.default_rng(29)
+    sites = np.array([[0, 0, 0], [1, 0, 0], [0, 2, 1], [-1, 1, 3], [2, -2, 0], [0, 0, -2]])
+    P = rng.standard_normal((6, 3)) + 1j * rng.standard_normal((6, 3))
+    kd = 0.7
+    khat = np.array([0.0, 0.6, 0.8])
+    e = np.array([1.0, 0.3j, -0.3 * 0.6 / 0.8 * 1j])            # khat . e = 0
+    pts = np.array([[0.5, 0.1, -0.2], [1.3, 0.7, 0.4], [0.4, 1.5, 2.2], [3.1, -1.2, 1.7], [40.0, 3.0, -7.0],
+                    [-9.3, 12.1, 25.4]])
+    B = near_field.magnetic_field(sites, kd, P, pts, khat, e)
+    h = 1e-5
+    curl = np.zeros((len(pts), 3), dtype=complex)
+    dE = []
+    for a in range(3):
+        step = np.zeros(3)
+        step[a] = h
+        dE.append((_electric_field_at(sites, kd, P, pts + step, khat, e)
+                   - _electric_field_at(sites, kd, P, pts - step, khat, e)) / (2 * h))   # dE / dx_a
+    for a in range(3):
+        b, c = (a + 1) % 3, (a + 2) % 3
+        curl[:, a] = dE[b][:, c] - dE[c][:, b]
+    want = curl / (1j * kd)
+    scale = np.abs(want).max(axis=1, keepdims=True)
+    assert (np.abs(B - want) / scale).max() < 1e-7
+
+
+def test_magnetic_near_field_special_cases():
+    kd = 0.9
+    khat, e = np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0])
+    # incident wave alone: B = khat x e exp(ik x) = z_hat exp(ik x)
+    pts = np.array([[0.0, 0.0, 0.0], [1.7, -2.0, 0.5]])
+    B0 = near_field.magnetic_field(np.zeros((0, 3)), kd, np.zeros((0, 3)), pts, khat, e)
+    assert np.allclose(B0, np.exp(1j * kd * pts[:, 0])[:, None] * np.array([0.0, 0.0, 1.0]), rtol=0, atol=1e-15)
+    # far from one dipole the scattered fields form an outgoing wave: B = n x E
+    # and |B| = |E| up to terms of relative order 1/(kR)
+    p = np.array([[0.2 + 0.4j, 1.0, -0.5j]])
+    n = np.array([0.36, 0.48, 0.8])
+    far = 4000.0 * n[None, :]
+    zero = np.zeros(3)
+    Bs = near_field.magnetic_field(np.zeros((1, 3)), kd, p, far, khat, zero)[0]
+    Es = _electric_field_at(np.zeros((1, 3)), kd, p, far, khat, zero)[0]
+    assert np.abs(Bs - np.cross(n, Es)).max() < 2.0 / (kd * 4000.0) * np.abs(Es).max()
+    # a point on a site leaves that site's dipole out
+    sites = np.array([[0, 0, 0], [2, 1, 0], [-1, 0, 3]])
+    P = np.array([[1.0, 0.5j, 0.2], [0.1j, -0.3, 1.0], [0.7, 0.0, -0.4j]])
+    on = near_field.magnetic_field(sites, kd, P, sites[:1], khat, e)
+    rest = near_field.magnetic_field(sites[1:], kd, P[1:], sites[:1], khat, e)
+    assert np.array_equal(on, rest)
+
+
 # ------------------------------------------------------- scattering matrix --
 
 def test_scattering_matrix_of_one_dipole_is_rayleigh():
