@@ -297,6 +297,19 @@ int dda_scattering_matrix(dda_target *t, const dda_rhs rhs[2], const void *p_dev
 int dda_near_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const void *p_dev,
                    const int32_t margin[3], int32_t macroscopic, void *e_dev, void *stream);
 
+/* E and/or the magnetic field B at the same points (§29: the NRFLD = 2 option,
+ * which stores B with E; nonmagnetic material, so B is both the micro- and the
+ * macroscopic field).  Arguments as dda_near_field; e_dev or b_dev may be NULL
+ * (not both).  b_dev: device [nrhs][Z][Y][X][3] dda_c64, the layout of e_dev,
+ *   B(q) = B_inc(q) + sum_{l, r_l != q} k^2 (e^{ikR}/R) (1 - 1/(ikR)) n x P_l,
+ * R = |r_q - r_l|, n = (r_q - r_l)/R, B_inc = khat x E_inc (Gaussian units,
+ * d = 1).  The sum is a convolution computed with full FP64 3-D FFTs of the
+ * padded extended box (two grids of 3 components held during the call, one
+ * RHS at a time).  Errors as dda_near_field. */
+int dda_near_field_eb(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const void *p_dev,
+                      const int32_t margin[3], int32_t macroscopic, void *e_dev, void *b_dev,
+                      void *stream);
+
 /* The product AP = A P for nrhs vectors (device [nrhs][N][3] in and out, may
  * not alias), in DDA_FP64 or DDA_MIXED (FP32 FFT convolution, FP64 diagonal
  * and output).  The polarizabilities are those of the given RHS.  Queued on

@@ -216,19 +216,27 @@ class Target:
         M = np.array([[list(o.mueller[i]) for i in range(4)] for o in out])
         return f, S, M
 
-    def near_field(self, rhs, P, margin=(0, 0, 0), macroscopic=False, stream=None):
+    def near_field(self, rhs, P, margin=(0, 0, 0), macroscopic=False, magnetic=False, stream=None):
         """E at every lattice point of the box extended by ``margin`` points on
         both sides of each axis: complex128 [nrhs, Z, Y, X, 3] on the device,
-        point (i, j, k) at site coordinate (i, j, k) - margin."""
+        point (i, j, k) at site coordinate (i, j, k) - margin.  With
+        magnetic=True returns (E, B), B the magnetic field at the same points."""
         import torch
         mg = [int(v) for v in margin]
         box = self.info()["box"]
         X, Y, Z = (box[a] + 2 * mg[a] for a in range(3))
         out = torch.empty((len(rhs), Z, Y, X, 3), dtype=torch.complex128, device=f"cuda:{self.device}")
-        L.check(self._lib.dda_near_field(self._h, _rhs_array(rhs), len(rhs), ctypes.c_void_p(P.data_ptr()),
-                                         (ctypes.c_int32 * 3)(*mg), int(bool(macroscopic)),
-                                         ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
-        return out
+        if not magnetic:
+            L.check(self._lib.dda_near_field(self._h, _rhs_array(rhs), len(rhs), ctypes.c_void_p(P.data_ptr()),
+                                             (ctypes.c_int32 * 3)(*mg), int(bool(macroscopic)),
+                                             ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+            return out
+        outb = torch.empty_like(out)
+        L.check(self._lib.dda_near_field_eb(self._h, _rhs_array(rhs), len(rhs), ctypes.c_void_p(P.data_ptr()),
+                                            (ctypes.c_int32 * 3)(*mg), int(bool(macroscopic)),
+                                            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(outb.data_ptr()),
+                                            _stream_ptr(stream)))
+        return out, outb
 
     def apply(self, rhs, P, precision="fp64", stream=None):
         out = self._vec(len(rhs))

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "dda_internal.hpp"
+#include "nearfield.hpp"
 #include "reduce.hpp"
 
 using namespace dda;
@@ -1112,8 +1113,14 @@ int dda_scattering_matrix(dda_target *t, const dda_rhs rhs[2], const void *p_dev
 
 int dda_near_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const void *p_dev, const int32_t margin[3],
                    int32_t macroscopic, void *e_dev, void *stream) {
+  if (!e_dev) return guarded([&]() -> int { throw Error{DDA_EINVAL, "NULL argument"}; });
+  return dda_near_field_eb(t, rhs, nrhs, p_dev, margin, macroscopic, e_dev, nullptr, stream);
+}
+
+int dda_near_field_eb(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const void *p_dev, const int32_t margin[3],
+                      int32_t macroscopic, void *e_dev, void *b_dev, void *stream) {
   return guarded([&]() -> int {
-    DDA_REQUIRE(t && rhs && p_dev && margin && e_dev, "NULL argument");
+    DDA_REQUIRE(t && rhs && p_dev && margin && (e_dev || b_dev), "NULL argument");
     DDA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
     DDA_REQUIRE(margin[0] >= 0 && margin[1] >= 0 && margin[2] >= 0, "margins must be >= 0");
     const int mg[3] = {margin[0], margin[1], margin[2]};
@@ -1189,11 +1196,38 @@ int dda_near_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const void *
       DDA_HIP(hipMemcpy(d_cellc, cellc.data(), cellc.size() * sizeof(int), hipMemcpyHostToDevice));
       DDA_HIP(hipMemcpy(d_fac, fac.data(), fac.size() * sizeof(c64), hipMemcpyHostToDevice));
       KrylovState &k = ext->k;
-      DDA_HIP(hipMemsetAsync(k.x, 0, (size_t)nrhs * ne * 3 * sizeof(c64), s));
-      launch_near_field_embed(static_cast<const c64 *>(p_dev), n, d_map, k.x, ne, nrhs, s);
-      matvec(ext, DDA_FP64, k.x, k.v, nrhs, nullptr, s);
-      launch_near_field_combine(k.v, ne, X, Y, mg, ext->d_rhs, nrhs, t->kd, d_cellc, macroscopic ? d_fac : nullptr,
-                                static_cast<c64 *>(e_dev), s);
+      if (e_dev) {
+        DDA_HIP(hipMemsetAsync(k.x, 0, (size_t)nrhs * ne * 3 * sizeof(c64), s));
+        launch_near_field_embed(static_cast<const c64 *>(p_dev), n, d_map, k.x, ne, nrhs, s);
+        matvec(ext, DDA_FP64, k.x, k.v, nrhs, nullptr, s);
+        launch_near_field_combine(k.v, ne, X, Y, mg, ext->d_rhs, nrhs, t->kd, d_cellc,
+                                  macroscopic ? d_fac : nullptr, static_cast<c64 *>(e_dev), s);
+      }
+      if (b_dev) {
+        // B = B_inc + h (*) P on the full padded grid of the extended box, one
+        // RHS at a time: h transformed once, P embedded and transformed, the
+        // cross product, the inverse transform (scaled by 1/M)
+        const Geometry &ge = ext->g;
+        const int64_t M = (int64_t)ge.Mx * ge.My * ge.Mz;
+        std::vector<int64_t> mapM((size_t)n);
+        for (int64_t i = 0; i < n; ++i)
+          mapM[i] = ((int64_t)(sites[3 * i + 2] + mg[2]) * ge.My + (sites[3 * i + 1] + mg[1])) * ge.Mx +
+                    (sites[3 * i] + mg[0]);
+        int64_t *d_mapM = ext->alloc<int64_t>(mapM.size() * sizeof(int64_t));
+        DDA_HIP(hipMemcpy(d_mapM, mapM.data(), mapM.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+        c64 *h = ext->alloc<c64>((size_t)3 * M * sizeof(c64));
+        c64 *full = ext->alloc<c64>((size_t)3 * M * sizeof(c64));
+        launch_magnetic_kernel(ge, t->kd, h, ext->tx, ext->ty, ext->tz, ext->px, ext->py, ext->pz, s);
+        for (int r = 0; r < nrhs; ++r) {
+          DDA_HIP(hipMemsetAsync(full, 0, (size_t)3 * M * sizeof(c64), s));
+          launch_magnetic_embed(static_cast<const c64 *>(p_dev) + (size_t)r * n * 3, n, d_mapM, full, M, s);
+          launch_fft3_full64(full, 3, ge, ext->tx, ext->ty, ext->tz, ext->px, ext->py, ext->pz, -1, s);
+          launch_magnetic_cross(h, full, M, 1.0 / double(M), s);
+          launch_fft3_full64(full, 3, ge, ext->tx, ext->ty, ext->tz, ext->px, ext->py, ext->pz, 1, s);
+          launch_magnetic_field(full, ge, X, Y, ne, mg, ext->d_rhs + r, t->kd,
+                                static_cast<c64 *>(b_dev) + (size_t)r * ne * 3, s);
+        }
+      }
     }
     return DDA_OK;
   });

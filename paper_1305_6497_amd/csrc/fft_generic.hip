@@ -4,6 +4,7 @@
 
 #include "dda_internal.hpp"
 #include "fft_lds.hpp"
+#include "nearfield.hpp"
 
 namespace dda {
 
@@ -100,6 +101,41 @@ __global__ void k_green_fill(c64 *__restrict__ full, int nx, int ny, int nz, int
   for (int c = 0; c < 6; ++c) full[c * M + i] = g[c];
 }
 
+// The magnetic field of a dipole p at offset R = R n (source to point),
+//   B = k^2 (e^{ikR}/R) (1 - 1/(ikR)) n x p = h(R) x p,  h = k^2 (e^{ikR}/R) (1 + i/(kR)) n,
+// as the three components of h on the same periodic grid (zero at the origin
+// and outside the band), so that B_sca = h (*) P is a convolution with a cross
+// product in place of the matrix product.
+__global__ void k_magnetic_fill(c64 *__restrict__ full, int nx, int ny, int nz, int Mx, int My, int Mz, double kd) {
+  const int64_t M = (int64_t)Mx * My * Mz;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const int x = (int)(i % Mx);
+  const int y = (int)((i / Mx) % My);
+  const int z = (int)(i / ((int64_t)Mx * My));
+  auto delta = [](int idx, int n, int m, bool &ok) {
+    if (idx < n) return idx;
+    if (idx > m - n) return idx - m;
+    ok = false;
+    return 0;
+  };
+  bool ok = true;
+  const int dx = delta(x, nx, Mx, ok), dy = delta(y, ny, My, ok), dz = delta(z, nz, Mz, ok);
+  c64 h[3] = {{0, 0}, {0, 0}, {0, 0}};
+  if (ok && (dx | dy | dz) != 0) {
+    const double R = sqrt(double(dx) * dx + double(dy) * dy + double(dz) * dz);
+    double sn, cs;
+    sincos(kd * R, &sn, &cs);
+    const c64 pref = {cs / R, sn / R};                                   // e^{ikR}/R
+    const c64 f = (kd * kd) * (pref * c64{1.0, 1.0 / (kd * R)});        // k^2 e^{ikR}/R (1 + i/(kR))
+    const double n[3] = {dx / R, dy / R, dz / R};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) h[c] = n[c] * f;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) full[c * M + i] = h[c];
+}
+
 __global__ void k_green_octant(const c64 *__restrict__ full, c64 *__restrict__ o64, c32 *__restrict__ o32, int Mx,
                                int My, int Mz, int Mxh, int Myh, int Mzh, double scale) {
   const int64_t moct = (int64_t)Mxh * Myh * Mzh;
@@ -173,8 +209,9 @@ template void launch_fft_rows<float>(const c32 *, c32 *, int64_t, const AxisPlan
 template void launch_fft_rows<double>(const c64 *, c64 *, int64_t, const AxisPlan &, const c64 *, int, double,
                                       hipStream_t);
 
-static void fft_strided_fwd64(c64 *data, const AxisPlan &p, const c64 *tw, int64_t outer, int64_t inner,
-                              hipStream_t s) {
+template <int DIR>
+static void fft_strided64(c64 *data, const AxisPlan &p, const c64 *tw, int64_t outer, int64_t inner,
+                          hipStream_t s) {
   // 8 pencils per block, 4 for the longest axes (LDS budget of row_budget)
   const bool wide = (size_t)8 * p.L <= (size_t)row_budget<double>();
   const int np = wide ? 8 : 4;
@@ -183,16 +220,44 @@ static void fft_strided_fwd64(c64 *data, const AxisPlan &p, const c64 *tw, int64
   const size_t lds = (elems + p.L) * sizeof(c64);
   DDA_EPT_SWITCH(pick_ept_gen(elems), {
     if (wide) {
-      allow_lds(k_fft_strided<double, E, -1, 3>, lds);
-      hipLaunchKernelGGL((k_fft_strided<double, E, -1, 3>), dim3((unsigned)(outer * tiles)), dim3(kNT), lds, s,
+      allow_lds(k_fft_strided<double, E, DIR, 3>, lds);
+      hipLaunchKernelGGL((k_fft_strided<double, E, DIR, 3>), dim3((unsigned)(outer * tiles)), dim3(kNT), lds, s,
                          data, p, tw, inner, tiles);
     } else {
-      allow_lds(k_fft_strided<double, E, -1, 2>, lds);
-      hipLaunchKernelGGL((k_fft_strided<double, E, -1, 2>), dim3((unsigned)(outer * tiles)), dim3(kNT), lds, s,
+      allow_lds(k_fft_strided<double, E, DIR, 2>, lds);
+      hipLaunchKernelGGL((k_fft_strided<double, E, DIR, 2>), dim3((unsigned)(outer * tiles)), dim3(kNT), lds, s,
                          data, p, tw, inner, tiles);
     }
   });
   DDA_HIP(hipGetLastError());
+}
+static void fft_strided_fwd64(c64 *data, const AxisPlan &p, const c64 *tw, int64_t outer, int64_t inner,
+                              hipStream_t s) {
+  fft_strided64<-1>(data, p, tw, outer, inner, s);
+}
+
+void launch_fft3_full64(c64 *data, int ncomp, const Geometry &g, const Twiddles &tx, const Twiddles &ty,
+                        const Twiddles &tz, const AxisPlan &px, const AxisPlan &py, const AxisPlan &pz, int dir,
+                        hipStream_t s) {
+  // x: contiguous rows; y: stride Mx; z: stride Mx*My (unnormalised)
+  launch_fft_rows<double>(data, data, (int64_t)ncomp * g.Mz * g.My, px, tx.d64, dir, 1.0, s);
+  if (dir < 0) {
+    fft_strided64<-1>(data, py, ty.d64, (int64_t)ncomp * g.Mz, g.Mx, s);
+    fft_strided64<-1>(data, pz, tz.d64, ncomp, (int64_t)g.Mx * g.My, s);
+  } else {
+    fft_strided64<1>(data, py, ty.d64, (int64_t)ncomp * g.Mz, g.Mx, s);
+    fft_strided64<1>(data, pz, tz.d64, ncomp, (int64_t)g.Mx * g.My, s);
+  }
+}
+
+void launch_magnetic_kernel(const Geometry &g, double kd, c64 *h, const Twiddles &tx, const Twiddles &ty,
+                            const Twiddles &tz, const AxisPlan &px, const AxisPlan &py, const AxisPlan &pz,
+                            hipStream_t s) {
+  const int64_t M = (int64_t)g.Mx * g.My * g.Mz;
+  hipLaunchKernelGGL(k_magnetic_fill, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, h, g.nx, g.ny, g.nz,
+                     g.Mx, g.My, g.Mz, kd);
+  DDA_HIP(hipGetLastError());
+  launch_fft3_full64(h, 3, g, tx, ty, tz, px, py, pz, -1, s);
 }
 
 void launch_green_build(const Geometry &g, double kd, c64 *full, c64 *oct64, c32 *oct32, const Twiddles &tx,

@@ -568,6 +568,37 @@ def test_near_field_au_sphere_matches_printed_line(dda):
     assert np.abs(Ef[:, [0, 2]]).max() < 1e-5
 
 
+@pytest.mark.parametrize("shape,shpar,margin", [
+    ("ELLIPSOID", (9.5, 8.0, 6.5), (2, 1, 3)),
+    ("RCTGLPRSM", (5, 1, 1), (3, 2, 0)),
+    ("HEX_PRISM", (6, 9, 2), (1, 0, 2)),
+])
+def test_magnetic_near_field_matches_oracle_direct_sum(dda, shape, shpar, margin):
+    # B_inc + B_sca at every extended point against the oracle's direct sum
+    # (pinned by Faraday's law), two RHS; E from the same call equals E alone
+    from oracle import near_field
+    sites, box = dda.make_sites(shape, shpar)
+    osites = targets.make(shape, shpar)
+    n = len(sites)
+    kd = 0.57
+    t = dda.Target(sites, box, m=1.7 + 0.2j, kd=kd)
+    rhs = [dda.orient_rhs(0.3, 1.1, 2.0, which=1), dda.orient_rhs(0.7, 0.4, 5.0, which=2)]
+    P = inputs.random_polarization(n, 2, seed=31)
+    Pt = torch.tensor(P, dtype=torch.complex128, device="cuda")
+    E, B = t.near_field(rhs, Pt, margin=margin, magnetic=True)
+    E0 = t.near_field(rhs, Pt, margin=margin)
+    t.close()
+    assert torch.equal(E, E0)
+    B = B.cpu().numpy()
+    X, Y, Z = (box[a] + 2 * margin[a] for a in range(3))
+    assert B.shape == (2, Z, Y, X, 3)
+    zz, yy, xx = np.meshgrid(np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    pts = np.stack([xx.ravel() - margin[0], yy.ravel() - margin[1], zz.ravel() - margin[2]], axis=1)
+    for r in range(2):
+        ref = near_field.magnetic_field(osites, kd, P[r], pts, *rhs[r])
+        assert _rel(B[r].reshape(-1, 3), ref) < 1e-11
+
+
 def test_near_field_errors(dda):
     sites, box = dda.make_sites("ELLIPSOID", (6, 5, 4))
     t = dda.Target(sites, box, m=1.5, kd=0.4)
