@@ -25,6 +25,20 @@ intensity |F_perp(n)|^2 with cos theta = n . khat:
 
     g = <cos theta>,   <cos^2 theta>.
 
+§3.1 also lists Q_bk, the differential scattering cross section for
+backscattering (area per steradian) over pi a_eff^2, and §3.2 Q_pha, the
+phase-shift cross section over pi a_eff^2 (defined in Draine 1988, cited).
+Readings:
+
+    dC_sca/dOmega (n) = k^4 | sum_j (I - n n) P_j e^{-i k n.r_j} |^2,
+    Q_bk = dC_sca/dOmega (n = -khat) / (pi a_eff^2),
+    C_pha = 2 pi k sum_j Re( conj(E_inc,j) . P_j ),
+
+the last being the phase delay per unit column density that the real part of
+the response imposes on the transmitted wave, as C_ext is (twice) the
+amplitude attenuation (for one dipole C_pha = 2 pi k Re alpha, the
+dilute-medium refractive index n - 1 = 2 pi N alpha in these units).
+
 The guide chooses its scattering directions by the parameter ETASCA (number
 of directions proportional to [(3 + x)/ETASCA]^2) without printing the rule.
 Reading: Gauss-Legendre in cos theta with n_theta = ceil((3 + x)/ETASCA) + 1
@@ -41,6 +55,20 @@ import scipy.special as ssp
 
 def c_ext(kd, E_inc, P):
     return 4.0 * math.pi * kd * float(np.sum(np.imag(np.conj(E_inc) * P)))
+
+
+def c_pha(kd, E_inc, P):
+    """Phase-shift cross section (module docstring)."""
+    return 2.0 * math.pi * kd * float(np.sum(np.real(np.conj(E_inc) * P)))
+
+
+def dc_sca_domega(sites, kd, P, n):
+    """Differential scattering cross section in direction(s) n [..., 3] (unit)."""
+    sites = np.asarray(sites, dtype=float)
+    n = np.asarray(n, dtype=float).reshape(-1, 3)
+    F = np.exp(-1j * kd * (n @ sites.T)) @ np.asarray(P, dtype=complex)          # [m, 3]
+    Fperp = F - np.sum(n * F, axis=1, keepdims=True) * n
+    return kd ** 4 * np.sum(np.abs(Fperp) ** 2, axis=1)
 
 
 def c_abs(kd, alpha_inv_sites, P):
@@ -127,10 +155,10 @@ def far_field(sites, kd, P, khat, n_theta, n_phi):
 
 
 def efficiencies(n_sites, kd, E_inc, alpha_inv_sites, P, sites=None, exact_sca=False):
-    """Dict of Q_ext, Q_abs, Q_sca (= Q_ext - Q_abs unless exact_sca) and a_eff."""
+    """Dict of Q_ext, Q_abs, Q_sca (= Q_ext - Q_abs unless exact_sca), Q_pha and a_eff."""
     aeff = (3.0 * n_sites / (4.0 * math.pi)) ** (1.0 / 3.0)
     geo = math.pi * aeff * aeff
     ce = c_ext(kd, E_inc, P)
     ca = c_abs(kd, alpha_inv_sites, P)
     cs = c_sca_exact(sites, kd, P) if exact_sca else ce - ca
-    return dict(qext=ce / geo, qabs=ca / geo, qsca=cs / geo, aeff=aeff)
+    return dict(qext=ce / geo, qabs=ca / geo, qsca=cs / geo, qpha=c_pha(kd, E_inc, P) / geo, aeff=aeff)
