@@ -143,6 +143,8 @@ typedef struct {
 typedef struct {
   double qext, qabs, qsca; /* efficiencies Q = C / (pi a_eff^2) (§3.1); qsca = qext - qabs */
   double aeff;             /* effective radius in lattice units (§2) */
+  double qpha;             /* phase-shift efficiency (§3.2, defined in Draine 1988):
+                              C_pha = 2 pi k sum_j Re(conj(E_inc,j) . P_j) */
 } dda_q;
 
 /* Far-field averages of one solved RHS (§3.1 outputs). */
@@ -152,6 +154,8 @@ typedef struct {
   double g;                /* <cos theta>, theta the scattering angle from khat */
   double cos2;             /* <cos^2 theta> */
   int32_t n_theta, n_phi;  /* quadrature: Gauss-Legendre nodes in cos theta, uniform phi */
+  double qbk;              /* backscattering: k^4 |F_perp(-khat)|^2 / (pi a_eff^2), the differential
+                              cross section (per sr) at theta = 180 deg over pi a_eff^2 (§3.1) */
 } dda_far;
 
 typedef struct {

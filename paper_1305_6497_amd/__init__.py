@@ -188,15 +188,15 @@ class Target:
         q = (L.Q * nrhs)()
         L.check(self._lib.dda_cross_sections(self._h, _rhs_array(rhs), nrhs, ctypes.c_void_p(P.data_ptr()), None,
                                              _stream_ptr(stream), q))
-        return [dict(qext=v.qext, qabs=v.qabs, qsca=v.qsca, aeff=v.aeff) for v in q]
+        return [dict(qext=v.qext, qabs=v.qabs, qsca=v.qsca, aeff=v.aeff, qpha=v.qpha) for v in q]
 
     def far_field(self, rhs, P, etasca=0.5, stream=None):
-        """Q_sca by far-field quadrature, <cos theta>, <cos^2 theta> per RHS."""
+        """Q_sca by far-field quadrature, <cos theta>, <cos^2 theta> and Q_bk per RHS."""
         nrhs = len(rhs)
         out = (L.Far * nrhs)()
         L.check(self._lib.dda_far_field(self._h, _rhs_array(rhs), nrhs, ctypes.c_void_p(P.data_ptr()),
                                         float(etasca), _stream_ptr(stream), out))
-        return [dict(qsca=v.qsca, g=v.g, cos2=v.cos2, n_theta=v.n_theta, n_phi=v.n_phi) for v in out]
+        return [dict(qsca=v.qsca, g=v.g, cos2=v.cos2, n_theta=v.n_theta, n_phi=v.n_phi, qbk=v.qbk) for v in out]
 
     def scattering_matrix(self, rhs, P, lab, theta_phi, stream=None):
         """Amplitude and Mueller matrices for the two polarizations rhs[0], rhs[1]

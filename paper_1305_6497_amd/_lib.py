@@ -60,7 +60,7 @@ class SolveStats(ctypes.Structure):
 
 class Far(ctypes.Structure):
     _fields_ = [("qsca", ctypes.c_double), ("g", ctypes.c_double), ("cos2", ctypes.c_double),
-                ("n_theta", ctypes.c_int32), ("n_phi", ctypes.c_int32)]
+                ("n_theta", ctypes.c_int32), ("n_phi", ctypes.c_int32), ("qbk", ctypes.c_double)]
 
 
 class Scat(ctypes.Structure):
@@ -69,7 +69,7 @@ class Scat(ctypes.Structure):
 
 class Q(ctypes.Structure):
     _fields_ = [("qext", ctypes.c_double), ("qabs", ctypes.c_double), ("qsca", ctypes.c_double),
-                ("aeff", ctypes.c_double)]
+                ("aeff", ctypes.c_double), ("qpha", ctypes.c_double)]
 
 
 class TargetInfo(ctypes.Structure):

@@ -311,7 +311,7 @@ void ensure_krylov(dda_target *t, int nrhs, hipStream_t s) {
   t->d_restart = t->alloc<int>(nrhs * sizeof(int));
   t->d_ainv = t->alloc<c64>((size_t)nrhs * t->ncomp * sizeof(c64));
   t->d_rhs = t->alloc<RhsDev>(nrhs * sizeof(RhsDev));
-  t->d_sums = t->alloc<double>(2 * nrhs * sizeof(double));
+  t->d_sums = t->alloc<double>(3 * nrhs * sizeof(double));
   t->kr_nrhs = nrhs;
   k.nrhs = nrhs;
   ++t->buffer_gen;
@@ -1255,11 +1255,12 @@ int dda_far_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const void *p
         mu[(size_t)i * nf + j] = gx[i];
         w[(size_t)i * nf + j] = gw[i] * 2.0 * pi / nf;
       }
-    const size_t scratch = far_field_scratch_bytes(t->g, ndir);
-    const size_t bytes = (size_t)ndir * 5 * sizeof(double) + scratch + 3 * sizeof(double);
+    // scratch for the quadrature and for the single backscattering direction
+    const size_t scratch = std::max(far_field_scratch_bytes(t->g, ndir), far_field_scratch_bytes(t->g, 1));
+    const size_t bytes = (size_t)ndir * 5 * sizeof(double) + scratch + 8 * sizeof(double);
     double *buf = t->alloc<double>(bytes);
     double *d_dirs = buf, *d_mu = buf + (size_t)ndir * 3, *d_w = d_mu + ndir, *d_scr = d_w + ndir;
-    double *d_sums = d_scr + scratch / sizeof(double);
+    double *d_sums = d_scr + scratch / sizeof(double), *d_bk = d_sums + 3;
     std::vector<double> sums(3);
     try {
       DDA_HIP(hipMemcpyAsync(d_mu, mu.data(), (size_t)ndir * sizeof(double), hipMemcpyHostToDevice, s));
@@ -1296,6 +1297,14 @@ int dda_far_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const void *p
         out[r].cos2 = sums[0] > 0.0 ? sums[2] / sums[0] : 0.0;
         out[r].n_theta = nt;
         out[r].n_phi = nf;
+        // backscattering: the same phase sum in the one direction -khat (weight 1)
+        const double bk[5] = {-k[0], -k[1], -k[2], -1.0, 1.0};
+        double bsum = 0.0;
+        DDA_HIP(hipMemcpyAsync(d_bk, bk, sizeof(bk), hipMemcpyHostToDevice, s));
+        launch_far_field(t->g, t->d_cell_site, P, t->kd, d_bk, d_bk + 3, d_bk + 4, 1, d_scr, d_sums, s);
+        DDA_HIP(hipMemcpyAsync(&bsum, d_sums, sizeof(double), hipMemcpyDeviceToHost, s));
+        DDA_HIP(hipStreamSynchronize(s));
+        out[r].qbk = k4 * bsum / (pi * t->aeff * t->aeff);
       }
     } catch (...) {
       (void)hipStreamSynchronize(s);
@@ -1328,18 +1337,20 @@ int dda_cross_sections(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const vo
     }
     launch_cross_sums(t->g, t->d_ijk, t->d_rhs, nrhs, t->kd, P, t->d_ainv, t->ncomp, t->d_comp, t->k.partial,
                       t->d_sums, s);
-    std::vector<double> sums(2 * nrhs);
+    std::vector<double> sums(3 * nrhs);
     DDA_HIP(hipMemcpyAsync(sums.data(), t->d_sums, sums.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     DDA_HIP(hipStreamSynchronize(s));
     const double pi = 3.14159265358979323846;
     const double geo = pi * t->aeff * t->aeff;
     for (int r = 0; r < nrhs; ++r) {
-      const double cext = 4.0 * pi * t->kd * sums[2 * r];
-      const double cabs = 4.0 * pi * t->kd * sums[2 * r + 1];
+      const double cext = 4.0 * pi * t->kd * sums[3 * r];
+      const double cabs = 4.0 * pi * t->kd * sums[3 * r + 1];
+      const double cpha = 2.0 * pi * t->kd * sums[3 * r + 2];
       out[r].qext = cext / geo;
       out[r].qabs = cabs / geo;
       out[r].qsca = (cext - cabs) / geo;
       out[r].aeff = t->aeff;
+      out[r].qpha = cpha / geo;
     }
     return DDA_OK;
   });

@@ -590,7 +590,7 @@ __global__ void kk_cross(const int32_t *ijk, int64_t n, const RhsDev *rhs, doubl
   const int r = blockIdx.y;
   const RhsDev R = rhs[r];
   const double rr = (2.0 / 3.0) * kd * kd * kd;
-  double acc[2] = {0.0, 0.0};
+  double acc[3] = {0.0, 0.0, 0.0};
   for (int64_t j = blockIdx.x * (int64_t)KNT + threadIdx.x; j < n; j += (int64_t)nblk * KNT) {
     const double ph = kd * (R.khat[0] * ijk[3 * j] + R.khat[1] * ijk[3 * j + 1] + R.khat[2] * ijk[3 * j + 2]);
     double sn, cs;
@@ -604,22 +604,25 @@ __global__ void kk_cross(const int32_t *ijk, int64_t n, const RhsDev *rhs, doubl
       const c64 ec = w * R.e[c];
       const c64 pc = pj[c];
       acc[0] += ec.x * pc.y - ec.y * pc.x;        // Im(conj(E) P)
+      acc[2] += ec.x * pc.x + ec.y * pc.y;        // Re(conj(E) P)
       p2 += pc.x * pc.x + pc.y * pc.y;
     }
     acc[1] += (-ai.y - rr) * p2;
   }
-  double out[2];
-  block_sum<2>(acc, out);
-  if (threadIdx.x == 0) write_record<2>(partial, r, nblk, blockIdx.x, out);
+  double out[3];
+  block_sum<3>(acc, out);
+  if (threadIdx.x == 0) write_record<3>(partial, r, nblk, blockIdx.x, out);
 }
 
+// sums[3 r + i]: sum Im(conj(E) P), the absorption sum, sum Re(conj(E) P)
 __global__ void kk_cross_final(const double *partial, int nblk, double *sums) {
   const int r = blockIdx.x;
-  double s[2];
-  sum_partials<2>(partial, nblk, r, s);
+  double s[3];
+  sum_partials<3>(partial, nblk, r, s);
   if (threadIdx.x == 0) {
-    sums[2 * r] = s[0];
-    sums[2 * r + 1] = s[1];
+    sums[3 * r] = s[0];
+    sums[3 * r + 1] = s[1];
+    sums[3 * r + 2] = s[2];
   }
 }
 

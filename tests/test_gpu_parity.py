@@ -225,7 +225,7 @@ def test_solve_matches_dense_lu(dda, m, alpha, solver):
         Po = solvers.lu_solve(A, E.ravel()).reshape(-1, 3)
         assert _rel(Pg[r], Po) < 1e-8
         qo = cross_sections.efficiencies(len(osites), kd, E, ai, Po)
-        for key in ("qext", "qabs", "qsca"):
+        for key in ("qext", "qabs", "qsca", "qpha"):
             assert abs(q[r][key] - qo[key]) <= 1e-9 * qo["qext"], key
 
 
@@ -484,6 +484,8 @@ def test_far_field_matches_oracle_quadrature(dda, shape, shpar, khat):
         assert (far[r]["n_theta"], far[r]["n_phi"]) == (nt, nf)
         assert abs(far[r]["qsca"] * math.pi * aeff ** 2 - ref["c_sca"]) <= 1e-11 * ref["c_sca"]
         assert abs(far[r]["g"] - ref["g"]) <= 1e-11 and abs(far[r]["cos2"] - ref["cos2"]) <= 1e-11
+        bk = cross_sections.dc_sca_domega(osites, kd, P[r], -khat)[0]
+        assert abs(far[r]["qbk"] * math.pi * aeff ** 2 - bk) <= 1e-11 * bk
 
 
 @pytest.mark.parametrize("name", ["au_block_16x32x32", "block_64"])
