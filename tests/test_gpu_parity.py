@@ -671,6 +671,7 @@ def test_scattering_matrix_au_block_matches_printed(dda):
     tp = np.radians(rows[:, :2])
     f, S, M = t.scattering_matrix(rhs, P, lab, np.vstack([tp, [[0.0, 0.0]]]))
     q = t.cross_sections(rhs, P)
+    far = t.far_field(rhs, P, etasca=0.5)
     t.close()
     S0 = S[-1]
     aeff = q[0]["aeff"]
@@ -683,6 +684,16 @@ def test_scattering_matrix_au_block_matches_printed(dda):
     pol_ = np.sqrt(M[:, 1, 0] ** 2 + M[:, 2, 0] ** 2) / M[:, 0, 0]
     assert np.abs(pol_ - rows[:, 2]).max() < 0.05
     assert np.all(np.abs(M[:, 0, 1] - rows[:, 4]) < 0.1 * rows[:, 3])
+    # the printed efficiencies: Q_ext, Q_abs, Q_sca within 1%, Q_bk within 2%
+    # and Q_pha within 15% with its sign (the oracle pin's LDR-vs-GKDLDR
+    # tolerances)
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_printed.json")) as fh:
+        pr = json.load(fh)["au_block_example"]
+    for i in range(2):
+        for key in ("qext", "qabs", "qsca"):
+            assert abs(q[i][key] / pr[key] - 1) < 0.01, (i, key)
+        assert far[i]["qbk"] > 0 and abs(far[i]["qbk"] / pr["qbk"] - 1) < 0.02
+        assert q[i]["qpha"] < 0 and abs(q[i]["qpha"] / pr["qpha"] - 1) < 0.15
 
 
 def test_scattering_matrix_errors(dda):
