@@ -6,6 +6,11 @@ whose size is exact (copy of B bytes: B read, B written).
 
     python -m paper_1305_6497_amd.profile_matvec block_64 --reps 20 --precision mixed
 
+``solve`` runs whole solves of a workload instead (kernel statistics of the
+iteration):
+
+    python -m paper_1305_6497_amd.profile_matvec solve sphere_d133 --nrhs 2 --solver cocg
+
 ``summarize`` turns two rocprofv3 counter runs of that command (one with
 --pmc FETCH_SIZE, one with --pmc WRITE_SIZE, both -f csv) into HBM bytes per
 launch of each kernel, each counter scaled so that the copy reads and writes
@@ -86,7 +91,41 @@ def summarize(args):
     return 0
 
 
+def solve(args):
+    """Solves of a named workload (its first RHS, or both polarizations), for
+    kernel statistics of the whole iteration."""
+    import torch
+
+    import inputs
+    import paper_1305_6497_amd as dda
+
+    w = inputs.WORKLOADS[args.workload]
+    sites, box = dda.make_sites(w["shape"], w["shpar"])
+    kd = dda.kd_from_x(w["x"], len(sites))
+    t = dda.Target(sites, box, m=w["m"], kd=kd)
+    rhs = [dda.orient_rhs(0.0, 0.0, 0.0, which=1 + k) for k in range(args.nrhs)]
+    P = torch.empty((len(rhs), len(sites), 3), dtype=torch.complex128, device="cuda")
+    for rep in range(args.reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = t.solve(rhs, tol=args.tol, precision=args.precision, out=P, solver=args.solver)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(workload=args.workload, solver=args.solver, precision=args.precision, rep=rep,
+                              seconds=time.perf_counter() - t0, iters=[x["iters"] for x in st])), flush=True)
+    t.close()
+    return 0
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "solve":
+        ap = argparse.ArgumentParser(prog="profile_matvec solve")
+        ap.add_argument("workload")
+        ap.add_argument("--solver", default="bicgstab")
+        ap.add_argument("--precision", default="mixed")
+        ap.add_argument("--nrhs", type=int, default=1, choices=(1, 2))
+        ap.add_argument("--tol", type=float, default=1e-5)
+        ap.add_argument("--reps", type=int, default=1)
+        return solve(ap.parse_args(sys.argv[2:]))
     if len(sys.argv) > 1 and sys.argv[1] == "summarize":
         ap = argparse.ArgumentParser(prog="profile_matvec summarize")
         ap.add_argument("fetch_dir")
