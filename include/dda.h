@@ -238,16 +238,16 @@ int dda_target_get_info(const dda_target *t, dda_target_info *info);
 int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_opts *opts,
               void *p_dev, dda_c64 *p_host, void *stream, dda_solve_stats *stats);
 
-/* Q_ext, Q_abs, Q_sca (= Q_ext - Q_abs) of solved polarizations P, from FP64
- * sums over the sites (cross sections of Draine 1988 / Draine & Flatau 1994,
- * efficiencies of §3.1).  P is read from p_dev (device) if non-NULL, else from
+/* Q_ext, Q_abs, Q_sca (= Q_ext - Q_abs) and Q_pha of solved polarizations P,
+ * from FP64 sums over the sites (cross sections of Draine 1988 / Draine &
+ * Flatau 1994, efficiencies of §3.1 and §3.2).  P is read from p_dev (device) if non-NULL, else from
  * p_host (host).  out: host [nrhs].  Synchronous. */
 int dda_cross_sections(dda_target *t, const dda_rhs *rhs, int32_t nrhs,
                        const void *p_dev, const dda_c64 *p_host, void *stream, dda_q *out);
 
-/* Q_sca, <cos theta> and <cos^2 theta> of solved polarizations P (device
- * [nrhs][N][3]) from the far field F(n) = sum_j P_j exp(-i k n.r_j), weighted
- * by |F_perp|^2 (§3.1).  Directions: Gauss-Legendre in cos theta about khat
+/* Q_sca, <cos theta>, <cos^2 theta> and Q_bk of solved polarizations P
+ * (device [nrhs][N][3]) from the far field F(n) = sum_j P_j exp(-i k n.r_j),
+ * weighted by |F_perp|^2 (§3.1); Q_bk from F(-khat) alone.  Directions: Gauss-Legendre in cos theta about khat
  * with n_theta = ceil((3 + x)/etasca) + 1 nodes and 2 n_theta uniform phi,
  * x = k a_eff (the guide's ETASCA resolution parameter, §9: the number of
  * directions grows as [(3 + x)/ETASCA]^2; 0.5 is its recommended value).
