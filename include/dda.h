@@ -129,6 +129,11 @@ typedef struct {
                               kernel that needs its step length (BiCGSTAB alpha and omega, COCG
                               and QMR alpha) sum the records itself; above, one block computes
                               it first.  0 => 1024; < 0 => never */
+  const void *x0;          /* NULL: the guide's start P = 0 (§12).  Otherwise a device
+                              [nrhs][N][3] dda_c64 initial guess (read only): its FP64 true
+                              residual is checked first (one product, counted as one outer
+                              pass); an RHS already within tol returns x0 unchanged, the others
+                              iterate from it as from a refinement restart */
 } dda_solve_opts;
 
 typedef struct {

@@ -119,6 +119,15 @@ def footprint_bytes(box, n_sites, m=1.5, kd=0.5, nrhs=1, alpha="LATTDR"):
     return out.value
 
 
+def _checked_vec(v, nrhs, n):
+    """A device vector argument [nrhs, n, 3] complex128, contiguous."""
+    import torch
+    if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.complex128 and v.is_contiguous()
+            and tuple(v.shape) == (nrhs, n, 3)):
+        raise ValueError(f"expected a contiguous complex128 CUDA tensor of shape ({nrhs}, {n}, 3)")
+    return v
+
+
 class Target:
     """A target handle: sites, refractive indices and wavenumber on one GPU."""
 
@@ -161,7 +170,7 @@ class Target:
         return torch.empty((nrhs, self.n, 3), dtype=torch.complex128, device=f"cuda:{self.device}")
 
     def solve(self, rhs, tol=1e-5, max_iter=1000, precision="fp64", inner_tol=0.0, max_outer=20, check_every=0,
-              out=None, stream=None, use_graph=False, solver="bicgstab", fold_records=0):
+              out=None, stream=None, use_graph=False, solver="bicgstab", fold_records=0, x0=None):
         """Solve A P = E for every (khat, e) in rhs.  Returns (P, stats).
 
         solver: "bicgstab" (the guide's PBCGST), "bicgstab2" (BiCGstab(2), the
@@ -169,12 +178,14 @@ class Target:
         QMRCCG).  check_every: iterations between host convergence checks; 0
         picks them from the residual decay after a first block of 8, -n does
         the same after a first block of n.  fold_records: tuning only (results
-        are bit-identical), see dda_solve_opts."""
+        are bit-identical), see dda_solve_opts.  x0: optional initial guess,
+        a contiguous complex128 [nrhs, N, 3] device tensor (default P = 0)."""
         nrhs = len(rhs)
         P = self._vec(nrhs) if out is None else out
         opts = L.SolveOpts(tol=tol, max_iter=max_iter, precision=PRECISION[precision], inner_tol=inner_tol,
                            max_outer=max_outer, check_every=check_every, use_graph=int(bool(use_graph)),
-                           solver=SOLVER[solver], fold_records=fold_records)
+                           solver=SOLVER[solver], fold_records=fold_records,
+                           x0=None if x0 is None else _checked_vec(x0, nrhs, self.n).data_ptr())
         st = (L.SolveStats * nrhs)()
         code = L.check(self._lib.dda_solve(self._h, _rhs_array(rhs), nrhs, ctypes.byref(opts),
                                            ctypes.c_void_p(P.data_ptr()), None, _stream_ptr(stream), st),

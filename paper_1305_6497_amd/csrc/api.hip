@@ -891,11 +891,19 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     const double tol = opts->tol;
     const double inner = opts->precision == DDA_MIXED ? opts->inner_tol : 0.0;
     // P = 0 start: an RHS with E = 0 is already solved (its status says so
-    // after the first block; the first block is queued without a read)
+    // after the first block; the first block is queued without a read).
+    // With an initial guess every RHS starts stopped: the check below takes
+    // the true residual of x0 and restarts the recurrence from it, or keeps
+    // x0 when it is already within tol.
+    const bool warm = opts->x0 != nullptr;
+    if (warm) {
+      DDA_HIP(hipMemcpyAsync(k.x, opts->x0, (size_t)k.n3 * nrhs * sizeof(c64), hipMemcpyDeviceToDevice, s));
+      DDA_HIP(hipMemsetAsync(k.active, 0, nrhs * sizeof(int), s));
+    }
     bool first = true;
     while (true) {
       if (first) {
-        std::fill(status.begin(), status.end(), (int)ST_RUN);
+        std::fill(status.begin(), status.end(), warm ? (int)ST_CONV : (int)ST_RUN);
       } else {
         DDA_HIP(hipMemcpyAsync(t->h_status, k.status, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
         if (adaptive)

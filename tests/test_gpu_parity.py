@@ -746,6 +746,30 @@ def test_orientation_averaged_efficiencies_match_oracle(dda):
 
 
 @pytest.mark.parametrize("solver", SOLVERS)
+def test_initial_guess(dda, solver):
+    # x0 within tol is returned unchanged after one true-residual check; x0
+    # from a loose solve continues to the tight tolerance in fewer iterations
+    # than a cold start, to the same solution; a bad shape is rejected
+    sites, box = dda.make_sites("ELLIPSOID", (12, 9, 7))
+    rhs = [dda.orient_rhs(0.3, 0.8, 1.1, which=1), dda.orient_rhs(0.3, 0.8, 1.1, which=2)]
+    t = dda.Target(sites, box, m=1.8 + 0.05j, kd=0.5)
+    cold, sc = t.solve(rhs, tol=1e-9, precision="fp64", solver=solver)
+    same, ss = t.solve(rhs, tol=1e-8, precision="fp64", solver=solver, x0=cold)
+    assert all(x["status"] == 0 and x["iters"] == 0 and x["outer"] == 1 for x in ss)
+    assert torch.equal(same, cold)
+    _, scm = t.solve(rhs, tol=1e-9, precision="mixed", solver=solver)
+    loose, sl = t.solve(rhs, tol=1e-2, precision="mixed", solver=solver)
+    warm, sw = t.solve(rhs, tol=1e-9, precision="mixed", solver=solver, x0=loose)
+    for i in range(2):
+        assert sw[i]["status"] == 0 and sw[i]["rel_resid"] <= 1e-9
+        assert sw[i]["iters"] <= scm[i]["iters"], (sw[i], scm[i])
+    assert _rel(warm.cpu().numpy(), cold.cpu().numpy()) < 1e-7
+    with pytest.raises(ValueError):
+        t.solve(rhs, tol=1e-5, x0=cold[:1])
+    t.close()
+
+
+@pytest.mark.parametrize("solver", SOLVERS)
 def test_where_step_lengths_are_summed_does_not_change_results(dda, solver):
     # alpha and omega come from the same records summed in the same order
     # whether every block of the kernel that uses them sums the records
