@@ -764,6 +764,11 @@ def test_initial_guess(dda, solver):
         assert sw[i]["status"] == 0 and sw[i]["rel_resid"] <= 1e-9
         assert sw[i]["iters"] <= scm[i]["iters"], (sw[i], scm[i])
     assert _rel(warm.cpu().numpy(), cold.cpu().numpy()) < 1e-7
+    # the same warm start with the iterations captured in a HIP graph
+    warm_g, swg = t.solve(rhs, tol=1e-9, precision="mixed", solver=solver, x0=loose, use_graph=True, check_every=8)
+    warm_e, swe = t.solve(rhs, tol=1e-9, precision="mixed", solver=solver, x0=loose, check_every=8)
+    assert torch.equal(warm_g, warm_e)
+    assert [x["iters"] for x in swg] == [x["iters"] for x in swe]
     with pytest.raises(ValueError):
         t.solve(rhs, tol=1e-5, x0=cold[:1])
     t.close()
