@@ -478,7 +478,8 @@ void cycle2(dda_target *t, int precision, hipStream_t s) {
   k_scalar_rho(k, s, 2, -1.0);
 }
 
-// One COCG / QMR iteration (one product) for every active RHS: 7 kernels.
+// One COCG / QMR iteration (one product) for every active RHS: 7 kernels
+// (8 when the product has more than fold_records records).
 //   p = r + beta p (fused into the x-forward pass), q = A p -> v with p^T q
 //   (x-inverse records); alpha, x and r (QMR: the smoothing first); next
 //   beta, QMR's weight and the convergence status.
