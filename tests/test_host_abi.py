@@ -155,3 +155,13 @@ def test_footprint_grows_with_rhs_and_grid(dda):
     c = dda.footprint_bytes((96, 64, 48), 154424, nrhs=64)
     assert 0 < a < b < c
     assert c < 288 * 2 ** 30
+
+
+def test_vector_arguments_are_checked_before_the_library(dda):
+    # an initial guess must be a contiguous complex128 device tensor [nrhs, N, 3]
+    import torch
+    from paper_1305_6497_amd import _checked_vec
+    with pytest.raises(ValueError):
+        _checked_vec(torch.zeros((2, 5, 3), dtype=torch.complex128), 2, 5)          # host tensor
+    with pytest.raises(ValueError):
+        _checked_vec(np.zeros((2, 5, 3), dtype=complex), 2, 5)                     # not a tensor
