@@ -46,12 +46,12 @@ def algorithmic_bytes(box, grid, n_sites, fp32=True, nrhs=1):
     return total, zpass
 
 
-def measured_traffic(kernel_prefix):
+def measured_traffic(kernel_prefix, workload=None):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated on a plain copy),
     or None when the kernel sources changed since the counters were taken."""
     from paper_1305_6497_amd import profile_matvec
-    path = os.path.join(ROOT, "profiles", f"{kernel_prefix}_{WORKLOAD}_hbm_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel_prefix}_{workload or WORKLOAD}_hbm_traffic.json")
     if not os.path.exists(path):
         return None, "no counter summary"
     with open(path) as f:
@@ -233,6 +233,16 @@ def extra_workloads(dda, inputs, torch, tol):
     d133["cocg"] = dict(solves_per_s=len(rhs) / t3, iters=[x["iters"] for x in st3],
                         rel_resid=[x["rel_resid"] for x in st3],
                         q_rel_err_vs_mie=[_rel_err(v, mie) for v in q3] if mie else None)
+    # the HBM-bound configuration's roofline: the z-pass of one RHS, HIP-event timed
+    prof = t.profile_matvec(rhs[:1], P[:1].contiguous(), precision="mixed", reps=5)
+    info = t.info()
+    _, z_b = algorithmic_bytes(info["box"], info["grid"], len(sites), fp32=True)
+    traffic, traffic_src = measured_traffic("k_zpass", "sphere_d133")
+    achieved = z_b / (prof["z_pass"] * 1e-3) / 1e9
+    d133["roofline"] = {"bound": "hbm", "kernel": "z_pass", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                        "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                        "traffic_source": traffic_src, "algorithmic_bytes_per_launch": z_b,
+                        "pass_ms": prof}
     out["sphere_d133"] = d133
     t.close()
 
