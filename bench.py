@@ -184,6 +184,17 @@ def extra_workloads(dda, inputs, torch, tol):
         "q_rel_err_vs_oracle_first_rhs": errs,
         "config": {"n_sites": len(sites), "fft_grid": list(t.info()["grid"]), "precision": "mixed",
                    "orientations": "PCG64 seed 1305, uniform on SO(3)"}}
+    # roofline of one batched z-pass launch (all 64 RHS), HIP-event timed
+    prof = t.profile_matvec(rhs, P, precision="mixed", reps=3)
+    info = t.info()
+    _, z_b = algorithmic_bytes(info["box"], info["grid"], len(sites), fp32=True, nrhs=len(rhs))
+    z_launch = z_b * len(rhs)
+    traffic, traffic_src = measured_traffic("k_zpass", "ellipsoid_96x64x48")
+    achieved = z_launch / (prof["z_pass"] * 1e-3) / 1e9
+    out["ellipsoid_96x64x48_batched"]["roofline"] = {
+        "bound": "hbm", "kernel": "z_pass", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+        "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "traffic_source": traffic_src,
+        "algorithmic_bytes_per_launch": z_launch, "rhs_per_launch": len(rhs), "pass_ms": prof}
     t.close()
 
     # Sphere D = 133 (N = 1,232,177, grid 270^3), 2 polarizations batched, mixed, against Mie.
