@@ -119,12 +119,23 @@ def footprint_bytes(box, n_sites, m=1.5, kd=0.5, nrhs=1, alpha="LATTDR"):
     return out.value
 
 
-def _checked_vec(v, nrhs, n):
-    """A device vector argument [nrhs, n, 3] complex128, contiguous."""
+def _checked_vec(v, nrhs, n, device=None):
+    """A device vector argument: a contiguous complex128 CUDA tensor [nrhs, n, 3]
+    (on cuda:device when given).  Raises ValueError naming what is wrong, before
+    any pointer reaches the library."""
     import torch
-    if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.complex128 and v.is_contiguous()
-            and tuple(v.shape) == (nrhs, n, 3)):
-        raise ValueError(f"expected a contiguous complex128 CUDA tensor of shape ({nrhs}, {n}, 3)")
+    if not isinstance(v, torch.Tensor):
+        raise ValueError(f"expected a torch tensor, got {type(v).__name__}")
+    if v.dtype != torch.complex128:
+        raise ValueError(f"expected dtype complex128, got {v.dtype}")
+    if tuple(v.shape) != (nrhs, n, 3):
+        raise ValueError(f"expected shape ({nrhs}, {n}, 3), got {tuple(v.shape)}")
+    if not v.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if not v.is_cuda:
+        raise ValueError("expected a CUDA (device) tensor, got a host tensor")
+    if device is not None and (v.device.index or 0) != device:
+        raise ValueError(f"expected a tensor on cuda:{device}, got {v.device}")
     return v
 
 
@@ -169,6 +180,10 @@ class Target:
         import torch
         return torch.empty((nrhs, self.n, 3), dtype=torch.complex128, device=f"cuda:{self.device}")
 
+    def _checked(self, v, nrhs):
+        """A device vector argument: contiguous complex128 [nrhs, N, 3] on this target's device."""
+        return _checked_vec(v, nrhs, self.n, self.device)
+
     def solve(self, rhs, tol=1e-5, max_iter=1000, precision="fp64", inner_tol=0.0, max_outer=20, check_every=0,
               out=None, stream=None, use_graph=False, solver="bicgstab", fold_records=0, x0=None):
         """Solve A P = E for every (khat, e) in rhs.  Returns (P, stats).
@@ -181,11 +196,12 @@ class Target:
         are bit-identical), see dda_solve_opts.  x0: optional initial guess,
         a contiguous complex128 [nrhs, N, 3] device tensor (default P = 0)."""
         nrhs = len(rhs)
-        P = self._vec(nrhs) if out is None else out
+        x0 = None if x0 is None else self._checked(x0, nrhs)
+        P = self._vec(nrhs) if out is None else self._checked(out, nrhs)
         opts = L.SolveOpts(tol=tol, max_iter=max_iter, precision=PRECISION[precision], inner_tol=inner_tol,
                            max_outer=max_outer, check_every=check_every, use_graph=int(bool(use_graph)),
                            solver=SOLVER[solver], fold_records=fold_records,
-                           x0=None if x0 is None else _checked_vec(x0, nrhs, self.n).data_ptr())
+                           x0=None if x0 is None else x0.data_ptr())
         st = (L.SolveStats * nrhs)()
         code = L.check(self._lib.dda_solve(self._h, _rhs_array(rhs), nrhs, ctypes.byref(opts),
                                            ctypes.c_void_p(P.data_ptr()), None, _stream_ptr(stream), st),
@@ -196,6 +212,7 @@ class Target:
 
     def cross_sections(self, rhs, P, stream=None):
         nrhs = len(rhs)
+        P = self._checked(P, nrhs)
         q = (L.Q * nrhs)()
         L.check(self._lib.dda_cross_sections(self._h, _rhs_array(rhs), nrhs, ctypes.c_void_p(P.data_ptr()), None,
                                              _stream_ptr(stream), q))
@@ -204,6 +221,7 @@ class Target:
     def far_field(self, rhs, P, etasca=0.5, stream=None):
         """Q_sca by far-field quadrature, <cos theta>, <cos^2 theta> and Q_bk per RHS."""
         nrhs = len(rhs)
+        P = self._checked(P, nrhs)
         out = (L.Far * nrhs)()
         L.check(self._lib.dda_far_field(self._h, _rhs_array(rhs), nrhs, ctypes.c_void_p(P.data_ptr()),
                                         float(etasca), _stream_ptr(stream), out))
@@ -215,6 +233,9 @@ class Target:
         as NumPy arrays; lab = (x_LF, y_LF, z_LF) in the target frame,
         theta_phi [ndir, 2] in radians."""
         import numpy as np
+        if len(rhs) != 2:
+            raise ValueError("scattering_matrix takes the two polarizations of one incidence")
+        P = self._checked(P, 2)
         tp = np.ascontiguousarray(theta_phi, dtype=np.float64).reshape(-1, 2)
         lb = np.ascontiguousarray(lab, dtype=np.float64).reshape(9)
         out = (L.Scat * len(tp))()
@@ -233,6 +254,7 @@ class Target:
         point (i, j, k) at site coordinate (i, j, k) - margin.  With
         magnetic=True returns (E, B), B the magnetic field at the same points."""
         import torch
+        P = self._checked(P, len(rhs))
         mg = [int(v) for v in margin]
         box = self.info()["box"]
         X, Y, Z = (box[a] + 2 * mg[a] for a in range(3))
@@ -250,14 +272,17 @@ class Target:
         return out, outb
 
     def apply(self, rhs, P, precision="fp64", stream=None):
-        out = self._vec(len(rhs))
-        L.check(self._lib.dda_apply(self._h, _rhs_array(rhs), len(rhs), PRECISION[precision],
+        nrhs = len(rhs)
+        P = self._checked(P, nrhs)
+        out = self._vec(nrhs)
+        L.check(self._lib.dda_apply(self._h, _rhs_array(rhs), nrhs, PRECISION[precision],
                                     ctypes.c_void_p(P.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                     _stream_ptr(stream)))
         return out
 
     def profile_matvec(self, rhs, P, precision="mixed", reps=20, stream=None):
         """Average ms of each FFT pass (and the whole product) over reps products."""
+        P = self._checked(P, len(rhs))
         out = self._vec(len(rhs))
         ms = (ctypes.c_double * 6)()
         L.check(self._lib.dda_profile_matvec(self._h, _rhs_array(rhs), len(rhs), PRECISION[precision], int(reps),

@@ -158,10 +158,59 @@ def test_footprint_grows_with_rhs_and_grid(dda):
 
 
 def test_vector_arguments_are_checked_before_the_library(dda):
-    # an initial guess must be a contiguous complex128 device tensor [nrhs, N, 3]
+    # a device vector must be a contiguous complex128 CUDA tensor [nrhs, N, 3]
     import torch
     from paper_1305_6497_amd import _checked_vec
-    with pytest.raises(ValueError):
-        _checked_vec(torch.zeros((2, 5, 3), dtype=torch.complex128), 2, 5)          # host tensor
-    with pytest.raises(ValueError):
-        _checked_vec(np.zeros((2, 5, 3), dtype=complex), 2, 5)                     # not a tensor
+    with pytest.raises(ValueError, match="host tensor"):
+        _checked_vec(torch.zeros((2, 5, 3), dtype=torch.complex128), 2, 5)
+    with pytest.raises(ValueError, match="torch tensor"):
+        _checked_vec(np.zeros((2, 5, 3), dtype=complex), 2, 5)
+    with pytest.raises(ValueError, match="complex128"):
+        _checked_vec(torch.zeros((2, 5, 3), dtype=torch.complex64), 2, 5)
+    with pytest.raises(ValueError, match="shape"):
+        _checked_vec(torch.zeros((2, 4, 3), dtype=torch.complex128), 2, 5)
+    with pytest.raises(ValueError, match="contiguous"):
+        _checked_vec(torch.zeros((2, 3, 5), dtype=torch.complex128).transpose(1, 2), 2, 5)
+
+
+def _unbound_target(dda, n=5):
+    # a Target whose handle was never made: any call that reached the library
+    # would fail on the NULL handle, so a ValueError shows the binding's check
+    t = object.__new__(dda.Target)
+    t._lib = None
+    t._h = None
+    t.n = n
+    t.device = 0
+    return t
+
+
+@pytest.mark.parametrize("bad", ["host", "dtype", "shape"])
+def test_every_entry_point_checks_its_vectors(dda, bad):
+    import torch
+    n = 5
+    t = _unbound_target(dda, n)
+    rhs1 = [(np.array([1.0, 0, 0]), np.array([0, 1.0, 0]))]
+    rhs2 = rhs1 + [(np.array([1.0, 0, 0]), np.array([0, 0, 1.0]))]
+
+    def vec(nrhs):
+        if bad == "host":
+            return torch.zeros((nrhs, n, 3), dtype=torch.complex128)
+        if bad == "dtype":
+            return torch.zeros((nrhs, n, 3), dtype=torch.complex64)
+        return torch.zeros((nrhs, n + 1, 3), dtype=torch.complex128)
+
+    calls = {
+        "solve(out)": lambda: t.solve(rhs1, out=vec(1)),
+        "solve(x0)": lambda: t.solve(rhs1, x0=vec(1)),
+        "cross_sections": lambda: t.cross_sections(rhs1, vec(1)),
+        "far_field": lambda: t.far_field(rhs1, vec(1)),
+        "scattering_matrix": lambda: t.scattering_matrix(rhs2, vec(2), np.eye(3), [[0.0, 0.0]]),
+        "near_field": lambda: t.near_field(rhs1, vec(1)),
+        "apply": lambda: t.apply(rhs1, vec(1)),
+        "profile_matvec": lambda: t.profile_matvec(rhs1, vec(1)),
+    }
+    if hasattr(t, "apply_noalloc"):
+        calls["apply_noalloc(P)"] = lambda: t.apply_noalloc(rhs1, vec(1), vec(1))
+    for name, call in calls.items():
+        with pytest.raises(ValueError):
+            call()
