@@ -40,6 +40,7 @@
 #ifndef DDA_H
 #define DDA_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -325,6 +326,31 @@ int dda_near_field_eb(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const voi
  * the stream; not synchronous. */
 int dda_apply(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t precision,
               const void *p_dev, void *ap_dev, void *stream);
+
+/* Allocation-free variant of dda_apply, for callers that cannot allocate
+ * device memory during the call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same product, same kernels, same
+ * results as dda_apply (bit for bit), but the FFT work buffers and the per-RHS
+ * 1/alpha live in one static device array of DDA_NOALLOC_SCRATCH_BYTES per GPU
+ * (held by every process that loads the library, until it ends) instead of
+ * the handle's workspaces; the call makes no device or pinned allocation and
+ * creates no HIP object (the 1/alpha values reach the device as a kernel
+ * argument).
+ * Limits: nrhs * n_comp <= 64, and the work buffers of nrhs products,
+ * nrhs * (3 nz nxt ny W + My nxt 3 nz W) * (8 B DDA_MIXED, 16 B DDA_FP64) with
+ * W = 16 (MIXED) or 8 (FP64) and nxt = ceil(Mx / W), plus 4 KiB must fit in
+ * DDA_NOALLOC_SCRATCH_BYTES (a 64^3 block: 37.7 MB per RHS MIXED, 75.5 MB
+ * FP64); otherwise DDA_ENOTSUP, nothing queued.
+ * Every call on one GPU shares that GPU's array, whichever handle it is made
+ * with, and the array keeps the last call's contents: calls that overlap in
+ * time on one GPU (other streams, other threads) race and must be ordered by
+ * the caller.  Nothing in the array needs to start at zero.  dda_free_target
+ * must not run before the work this call queued has finished (synchronize the
+ * stream, unless the handle has already queued other work on it).
+ * Arguments and errors otherwise as dda_apply.  Queued on the stream. */
+#define DDA_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int dda_apply_noalloc(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t precision,
+                      const void *p_dev, void *ap_dev, void *stream);
 
 /* Incident field E_j = e exp(i kd khat . r_j) at the sites (eq. AP=E),
  * device [nrhs][N][3] out.  Queued on the stream. */

@@ -280,6 +280,17 @@ class Target:
                                     _stream_ptr(stream)))
         return out
 
+    def apply_noalloc(self, rhs, P, out, precision="fp64", stream=None):
+        """A P into the caller's ``out`` through dda_apply_noalloc: the library
+        allocates nothing (its work buffers are a static device array)."""
+        nrhs = len(rhs)
+        P = self._checked(P, nrhs)
+        out = self._checked(out, nrhs)
+        L.check(self._lib.dda_apply_noalloc(self._h, _rhs_array(rhs), nrhs, PRECISION[precision],
+                                            ctypes.c_void_p(P.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                            _stream_ptr(stream)))
+        return out
+
     def profile_matvec(self, rhs, P, precision="mixed", reps=20, stream=None):
         """Average ms of each FFT pass (and the whole product) over reps products."""
         P = self._checked(P, len(rhs))

@@ -108,6 +108,7 @@ SIGNATURES = [
     ("dda_near_field_eb", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), ctypes.c_int32, _VP,
                                          ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, _VP, _VP, _VP]),
     ("dda_apply", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP]),
+    ("dda_apply_noalloc", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP]),
     ("dda_incident_field", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), ctypes.c_int32, _VP, _VP]),
     ("dda_free_target", None, [_VP]),
     ("dda_profile_matvec", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,

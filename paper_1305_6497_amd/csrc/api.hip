@@ -6,6 +6,7 @@
 #include <complex>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -317,26 +318,30 @@ void ensure_krylov(dda_target *t, int nrhs, hipStream_t s) {
   ++t->buffer_gen;
 }
 
+// Validate and normalise one RHS.
+void check_rhs(const dda_rhs &q, RhsDev &rd) {
+  const double kn = std::sqrt(q.khat[0] * q.khat[0] + q.khat[1] * q.khat[1] + q.khat[2] * q.khat[2]);
+  DDA_REQUIRE(std::fabs(kn - 1.0) <= 1e-12, "khat must be a unit vector");
+  double en = 0.0;
+  for (int a = 0; a < 3; ++a) en += q.e[a].re * q.e[a].re + q.e[a].im * q.e[a].im;
+  en = std::sqrt(en);
+  DDA_REQUIRE(en > 0.0 && std::isfinite(en), "polarization must be non-zero and finite");
+  std::complex<double> dot = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    rd.khat[a] = q.khat[a];
+    rd.e[a] = c64{q.e[a].re / en, q.e[a].im / en};
+    dot += q.khat[a] * std::complex<double>(rd.e[a].x, rd.e[a].y);
+  }
+  DDA_REQUIRE(std::abs(dot) <= 1e-9, "polarization must be transverse (khat . e = 0)");
+}
+
 // Validate and normalise the RHS; fill per-RHS descriptions and 1/alpha.
 void prepare_rhs(dda_target *t, const dda_rhs *rhs, int nrhs, std::vector<RhsDev> &rd, std::vector<c64> &ainv) {
   DDA_REQUIRE(rhs != nullptr, "rhs is NULL");
   rd.resize(nrhs);
   ainv.resize((size_t)nrhs * t->ncomp);
   for (int r = 0; r < nrhs; ++r) {
-    const dda_rhs &q = rhs[r];
-    const double kn = std::sqrt(q.khat[0] * q.khat[0] + q.khat[1] * q.khat[1] + q.khat[2] * q.khat[2]);
-    DDA_REQUIRE(std::fabs(kn - 1.0) <= 1e-12, "khat must be a unit vector");
-    double en = 0.0;
-    for (int a = 0; a < 3; ++a) en += q.e[a].re * q.e[a].re + q.e[a].im * q.e[a].im;
-    en = std::sqrt(en);
-    DDA_REQUIRE(en > 0.0 && std::isfinite(en), "polarization must be non-zero and finite");
-    std::complex<double> dot = 0.0;
-    for (int a = 0; a < 3; ++a) {
-      rd[r].khat[a] = q.khat[a];
-      rd[r].e[a] = c64{q.e[a].re / en, q.e[a].im / en};
-      dot += q.khat[a] * std::complex<double>(rd[r].e[a].x, rd[r].e[a].y);
-    }
-    DDA_REQUIRE(std::abs(dot) <= 1e-9, "polarization must be transverse (khat . e = 0)");
+    check_rhs(rhs[r], rd[r]);
     for (int c = 0; c < t->ncomp; ++c) ainv[(size_t)r * t->ncomp + c] = alpha_inverse(t->alpha_kind, t->m[c], t->kd, rd[r].khat, rd[r].e);
   }
 }
@@ -351,21 +356,23 @@ void upload_rhs(dda_target *t, const std::vector<RhsDev> &rd, const std::vector<
   DDA_HIP(hipEventRecord(t->upload_done, s));
 }
 
-void matvec(dda_target *t, int precision, const c64 *in, c64 *out, int nrhs, const int *mask, hipStream_t s,
-            const hipEvent_t *ev = nullptr, int only_pass = -1, int reps = 1, const FuseArgs *fuse = nullptr) {
+// The product on explicit 1/alpha and work buffers (see MatvecArgs).
+void matvec_on(dda_target *t, int precision, const c64 *in, c64 *out, int nrhs, const int *mask, const c64 *ainv,
+               void *bufA, void *bufB, hipStream_t s, const hipEvent_t *ev = nullptr, int only_pass = -1,
+               int reps = 1, const FuseArgs *fuse = nullptr) {
   MatvecArgs a{};
   if (fuse) a.fuse = *fuse;
   a.in = in;
   a.out = out;
   a.nrhs = nrhs;
   a.mask = mask;
-  a.ainv = t->d_ainv;
+  a.ainv = ainv;
   a.ncomp = t->ncomp;
   a.comp = t->d_comp;
   a.cell_site = t->d_cell_site;
   a.rowtab = t->d_rowtab;
-  a.bufA = t->d_bufA;
-  a.bufB = t->d_bufB;
+  a.bufA = bufA;
+  a.bufB = bufB;
   a.px = t->px;
   a.py = t->py;
   a.pz = t->pz;
@@ -382,6 +389,11 @@ void matvec(dda_target *t, int precision, const c64 *in, c64 *out, int nrhs, con
     a.twz = t->tz.d64;
     launch_matvec<double>(t->g, a, s, ev, only_pass, reps);
   }
+}
+
+void matvec(dda_target *t, int precision, const c64 *in, c64 *out, int nrhs, const int *mask, hipStream_t s,
+            const hipEvent_t *ev = nullptr, int only_pass = -1, int reps = 1, const FuseArgs *fuse = nullptr) {
+  matvec_on(t, precision, in, out, nrhs, mask, t->d_ainv, t->d_bufA, t->d_bufB, s, ev, only_pass, reps, fuse);
 }
 
 // One BiCGSTAB iteration for every active RHS of the block: 12 kernels
@@ -558,6 +570,49 @@ void run_iterations(dda_target *t, int precision, int solver, int K, bool use_gr
   DDA_HIP(hipGraphLaunch(t->graph, t->stream));
   DDA_HIP(hipEventRecord(t->ev_out, t->stream));
   DDA_HIP(hipStreamWaitEvent(s, t->ev_out, 0));
+}
+
+// ------------------------------------------------- allocation-free product --
+// dda_apply_noalloc keeps its work buffers in one static device array per GPU
+// (the loader places it with the code object; it lives until the process
+// ends): the per-RHS 1/alpha values first, then the two FFT work buffers.
+constexpr int kNoAllocMaxAinv = 64;                 // nrhs * n_comp per call
+constexpr size_t kNoAllocAinvBytes = 4096;          // >= kNoAllocMaxAinv * 16, keeps A 256-byte aligned
+constexpr int kMaxDevices = 64;
+
+// 1/alpha values travel as a kernel argument, so the call needs no host
+// staging buffer and no copy node.
+struct AinvArg {
+  c64 v[kNoAllocMaxAinv];
+  int n;
+};
+
+__global__ void k_fill_ainv(c64 *dst, AinvArg a) {
+  if ((int)threadIdx.x < a.n) dst[threadIdx.x] = a.v[threadIdx.x];
+}
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[DDA_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (which must be `device`).
+// The host-side name of a __device__ array is only a stand-in; each GPU holds
+// its own copy, looked up once per device and kept.
+unsigned char *scratch_address(int device) {
+  DDA_REQUIRE(device >= 0 && device < kMaxDevices, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void *p = nullptr;
+    DDA_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    DDA_REQUIRE(p != nullptr, "scratch array has no device address");
+    g_scratch_dev[device] = p;
+  }
+  return static_cast<unsigned char *>(g_scratch_dev[device]);
 }
 
 }  // namespace
@@ -789,6 +844,49 @@ int dda_apply(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t precision
     ensure_workspace(t, nrhs, s);
     upload_rhs(t, rd, ai, s);
     matvec(t, precision, static_cast<const c64 *>(p_dev), static_cast<c64 *>(ap_dev), nrhs, nullptr, s);
+    return DDA_OK;
+  });
+}
+
+int dda_apply_noalloc(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t precision, const void *p_dev,
+                      void *ap_dev, void *stream) {
+  return guarded([&]() -> int {
+    DDA_REQUIRE(t && rhs && p_dev && ap_dev, "NULL argument");
+    DDA_REQUIRE(p_dev != ap_dev, "p_dev and ap_dev must not alias");
+    DDA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    DDA_REQUIRE(precision == DDA_FP64 || precision == DDA_MIXED, "unknown precision");
+    DDA_REQUIRE((int64_t)nrhs * t->ncomp <= kNoAllocMaxAinv, "nrhs * n_comp exceeds 64 (allocation-free product)");
+    const bool f32 = precision == DDA_MIXED;
+    const size_t cs = f32 ? sizeof(c32) : sizeof(c64);
+    const size_t a = t->g.a_elems(f32) * cs * nrhs;
+    const size_t b = t->g.b_elems(f32) * cs * nrhs;
+    const size_t a_pad = (a + 255) / 256 * 256;
+    const size_t need = kNoAllocAinvBytes + a_pad + b;
+    if (need > (size_t)DDA_NOALLOC_SCRATCH_BYTES)
+      throw Error{DDA_ENOTSUP, "allocation-free product needs " + std::to_string(need) + " bytes of scratch, " +
+                                   "more than the " + std::to_string((size_t)DDA_NOALLOC_SCRATCH_BYTES) +
+                                   " available (fewer RHS, or dda_apply)"};
+    AinvArg av{};
+    av.n = nrhs * t->ncomp;
+    for (int r = 0; r < nrhs; ++r) {
+      RhsDev rd;
+      check_rhs(rhs[r], rd);
+      for (int c = 0; c < t->ncomp; ++c) av.v[r * t->ncomp + c] = alpha_inverse(t->alpha_kind, t->m[c], t->kd, rd.khat, rd.e);
+    }
+    DDA_HIP(hipSetDevice(t->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned char *base = scratch_address(t->device);
+    c64 *d_ainv = reinterpret_cast<c64 *>(base);
+    void *bufA = base + kNoAllocAinvBytes;
+    void *bufB = base + kNoAllocAinvBytes + a_pad;
+    hipLaunchKernelGGL(k_fill_ainv, dim3(1), dim3(kNoAllocMaxAinv), 0, s, d_ainv, av);
+    DDA_HIP(hipGetLastError());
+    matvec_on(t, precision, static_cast<const c64 *>(p_dev), static_cast<c64 *>(ap_dev), nrhs, nullptr, d_ainv, bufA,
+              bufB, s);
+    // the handle's release waits for this stream if it already tracks it
+    // (creating a tracking event here would allocate)
+    for (auto &u : t->uses)
+      if (u.first == s) (void)hipEventRecord(u.second, s);
     return DDA_OK;
   });
 }
