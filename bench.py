@@ -1,17 +1,23 @@
 """Benchmark of the DDA hot path on one MI355X.
 
-A step is one whole pass of the path over the mixed-precision single-solve
-workload (64 x 64 x 64 block of dipoles, m = 1.5 + 0.1i, x = 10, FFT grid
-128^3, k along x, polarization along y): incident field, BiCGSTAB with the
-complex FP32 FFT product and FP64 Krylov vectors, FP64 true-residual
-refinement to 1e-5, and the FP64 cross-section sums.  The Green-tensor
-transform of the target is built once before timing (it depends only on the
-target and k, not on the right-hand side).
+A step is one whole pass of the path over the largest single-GPU workload: a
+sphere of diameter 133 dipoles (ELLIPSOID SHPAR 133, N = 1,232,177, FFT grid
+270^3), m = 1.33 + 0.001i, x = 25, incidence along x, both polarizations (e
+along y and z) as one batch of two right-hand sides.  The step is the
+incident field, COCG with the complex FP32 FFT product and FP64 Krylov
+vectors and inner products, FP64 true-residual refinement to 1e-5, and the
+FP64 cross-section sums.  The Green-tensor transform of the target is built
+once before timing (it depends on the target and k only).
 
-Prints one JSON line.  `value` is solves per second.  Extra fields carry the
-FFT-product rate, p50/p99 step latency, the plain FP64 solver on the same GPU,
-the per-pass event timing and roofline of the dominant kernel, and the FP64
-CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line on stdout (progress goes to stderr).  `value` is solves
+per second (a batch of two RHS is two solves).  Extra fields: products/s,
+p50/p99 step latency, the other solvers and the plain FP64 single-RHS solver
+on the same workload, the Q error of every result against the FP64 oracle's
+stored solution (tests/golden), a tolerance scan, per-pass HIP-event timing,
+the roofline of the dominant kernel and of the whole product, and the FP64 CPU
+oracle timed on a bounded sample of the same solve.  The other workloads
+(64^3 block, D = 20 sphere, 64-RHS ellipsoid, the guide's worked example and
+near field, the 1000-request serving mix) are under `workloads`.
 """
 
 import argparse
@@ -24,34 +30,60 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKLOAD = "block_64"
+WORKLOAD = "sphere_d133"
+SOLVER = "cocg"
 PEAK_HBM_GBS = 8000.0
+# FP32 / FP64 vector issue without packed math: 256 CUs x 4 SIMDs, one wave
+# instruction per SIMD every 4 cycles at 2.4 GHz
+PEAK_VALU_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def algorithmic_bytes(box, grid, n_sites, fp32=True, nrhs=1):
-    """Bytes the FFT product must move (per RHS), and those of its z-pass.
+    """Bytes the FFT product must move per launch of a block of nrhs RHS, and
+    those of its z-pass.
 
     P in and AP out in FP64 (48 B per site each); each transform stage writes
     its output once and the next stage reads it once: x-forward output
     3*Mx*ny*nz, y-forward output 3*Mx*My*nz, the z-pass reads and writes the
     latter, the inverse stages mirror the forward ones; the octant Green
-    transform (6 components) is read once per product of a block of RHS.
+    transform (6 components) is read once per launch, whatever nrhs.
     """
     nx, ny, nz = box
     Mx, My, Mz = grid
     c = 8 if fp32 else 16
     moct = (Mx // 2 + 1) * (My // 2 + 1) * (Mz // 2 + 1)
-    total = 2 * 48 * n_sites + 3 * c * (4 * Mx * ny * nz + 4 * Mx * My * nz) + 6 * c * moct / nrhs
-    zpass = 2 * 3 * c * Mx * My * nz + 6 * c * moct / nrhs
-    return total, zpass
+    per_rhs = 2 * 48 * n_sites + 3 * c * (4 * Mx * ny * nz + 4 * Mx * My * nz)
+    zpass_rhs = 2 * 3 * c * Mx * My * nz
+    green = 6 * c * moct
+    return nrhs * per_rhs + green, nrhs * zpass_rhs + green
 
 
-def measured_traffic(kernel_prefix, workload=None):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated on a plain copy),
-    or None when the kernel sources changed since the counters were taken."""
+def pass_bytes(box, grid, n_sites, fp32=True, nrhs=1):
+    """Algorithmic bytes of each of the five passes for one launch of nrhs RHS."""
+    nx, ny, nz = box
+    Mx, My, Mz = grid
+    c = 8 if fp32 else 16
+    a_b = 3 * c * Mx * ny * nz
+    b_b = 3 * c * Mx * My * nz
+    _, z = algorithmic_bytes(box, grid, n_sites, fp32, nrhs)
+    return dict(x_forward=nrhs * (48 * n_sites + a_b), y_forward=nrhs * (a_b + b_b), z_pass=z,
+                y_inverse=nrhs * (a_b + b_b), x_inverse=nrhs * (a_b + 2 * 48 * n_sites))
+
+
+KERNEL_PREFIX = dict(x_forward="k_xfwd", y_forward="k_yfwd", z_pass="k_zpass", y_inverse="k_yinv",
+                     x_inverse="k_xinv")
+
+
+def measured_traffic(kernel_prefix, workload):
+    """HBM bytes per launch of a kernel from the committed counter summary
+    (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated on a plain copy), or None
+    when the kernel sources changed since the counters were taken."""
     from paper_1305_6497_amd import profile_matvec
-    path = os.path.join(ROOT, "profiles", f"{kernel_prefix}_{workload or WORKLOAD}_hbm_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel_prefix}_{workload}_hbm_traffic.json")
     if not os.path.exists(path):
         return None, "no counter summary"
     with open(path) as f:
@@ -61,34 +93,52 @@ def measured_traffic(kernel_prefix, workload=None):
     return rec["traffic_bytes"], os.path.relpath(path, ROOT)
 
 
+def roofline(prof, box, grid, n_sites, nrhs, workload, fp32=True):
+    """Roofline of the dominant pass (by event time) and of the whole product."""
+    pb = pass_bytes(box, grid, n_sites, fp32, nrhs)
+    dom = max(pb, key=lambda k: prof[k])
+    achieved = pb[dom] / (prof[dom] * 1e-3) / 1e9
+    traffic, src = measured_traffic(KERNEL_PREFIX[dom], workload)
+    tot, _ = algorithmic_bytes(box, grid, n_sites, fp32, nrhs)
+    prod = tot / (prof["total"] * 1e-3) / 1e9
+    return ({"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+             "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "traffic_source": src,
+             "algorithmic_bytes_per_launch": pb[dom], "rhs_per_launch": nrhs, "launch_ms": prof[dom]},
+            {"bound": "hbm", "achieved": prod, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": prod / PEAK_HBM_GBS,
+             "algorithmic_bytes_per_launch": tot, "rhs_per_launch": nrhs, "product_ms": prof["total"],
+             "pass_ms": prof, "pass_frac": {k: pb[k] / (prof[k] * 1e-3) / 1e9 / PEAK_HBM_GBS for k in pb}})
+
+
 def cpu_baseline(sites, kd, m, rhs, gpu_fp64_iters, budget_s=20.0):
-    """FP64 CPU oracle on a bounded sample of the same solve."""
-    import numpy as np
+    """FP64 CPU oracle (COCG on its SciPy FFT product) on a bounded sample of
+    the same solve: s per iteration x the iteration count of the identical
+    FP64 algorithm."""
     from oracle import incident, interaction, polarizability, solvers
+    workers = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     t0 = time.perf_counter()
     khat, e = rhs
     ai = polarizability.alpha_inv_ldr(m, kd, khat, e)
     E = incident.incident_field(sites, kd, khat, e)
-    op = interaction.FFTOperator(sites, kd, ai)
+    op = interaction.FFTOperator(sites, kd, ai, workers=workers)
     setup = time.perf_counter() - t0
-    # time BiCGSTAB iterations until the budget is used (at least 2)
-    its = 2
+    its = 1
     t0 = time.perf_counter()
-    solvers.bicgstab(op.matvec, E, tol=1e-30, maxiter=its)
+    solvers.cocg(op.matvec, E, tol=1e-30, maxiter=its)
     dt = time.perf_counter() - t0
     while dt < budget_s * 0.5 and its < 64:
         its *= 2
         t0 = time.perf_counter()
-        solvers.bicgstab(op.matvec, E, tol=1e-30, maxiter=its)
+        solvers.cocg(op.matvec, E, tol=1e-30, maxiter=its)
         dt = time.perf_counter() - t0
     per_iter = dt / its
     solve_s = per_iter * gpu_fp64_iters
-    return dict(value=1.0 / solve_s, unit="solves/s", cores=os.cpu_count(), kind="oracle",
-                sample=(f"{its} FP64 BiCGSTAB iterations ({2 * its} SciPy FFT products, workers=all cores) of the "
-                        f"same block_64 solve in {dt:.2f} s; solves/s = 1 / (s per iteration x {gpu_fp64_iters} "
-                        f"iterations, the count the identical FP64 algorithm needs on this system); "
-                        f"Green-transform setup {setup:.2f} s excluded"),
-                matvecs_per_s=2 * its / dt)
+    return dict(value=1.0 / solve_s, unit="solves/s", cores=workers, kind="oracle",
+                sample=(f"{its} FP64 COCG iterations ({its} SciPy FFT products of the 266^3 grid, "
+                        f"scipy.fft workers={workers}; element-wise NumPy work single-threaded) of the same "
+                        f"{WORKLOAD} solve (first polarization) in {dt:.2f} s; solves/s = 1 / (s per iteration x "
+                        f"{gpu_fp64_iters} iterations, the count of the identical FP64 COCG on this GPU); "
+                        f"Green-transform setup {setup:.1f} s excluded"),
+                matvecs_per_s=its / dt, setup_s=setup)
 
 
 def _reference(name):
@@ -104,6 +154,16 @@ def _rel_err(q, ref):
     return {k: abs(q[k] - ref[k]) / abs(ref[k]) for k in ("qext", "qabs", "qsca")}
 
 
+def _ref_errors(q, ref):
+    """Per-RHS relative errors against the stored oracle results (by RHS index)."""
+    if not ref or not ref.get("results"):
+        return None
+    by = {r["rhs"]: r for r in ref["results"]}
+    errs = [dict(rhs=i, **_rel_err(q[i], by[i])) for i in range(len(q)) if i in by]
+    worst = max((max(e["qext"], e["qabs"], e["qsca"]) for e in errs), default=None)
+    return dict(n_compared=len(errs), n_results=len(q), max_rel_err=worst, per_rhs=errs)
+
+
 def _rhs_list(dda, inputs, w):
     """(khat, e) of the workload: fixed incidence along x, or seeded SO(3) orientations."""
     if w["orientations"] == 1:
@@ -113,12 +173,61 @@ def _rhs_list(dda, inputs, w):
             for k in range(w["polarizations"])]
 
 
-def extra_workloads(dda, inputs, torch, tol):
-    """The other configurations: latency-bound sphere, batched RHS, large sphere."""
+def _timed_solves(t, torch, rhs, reps, **kw):
+    t.solve(rhs, **kw)
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    for _ in range(reps):
+        P, st = t.solve(rhs, **kw)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - s0) / reps, P, st
+
+
+def block64_workload(dda, inputs, torch, tol):
+    """64^3 block, one RHS: mixed against FP64, every solver (Infinity-Cache resident)."""
+    w = inputs.WORKLOADS["block_64"]
+    sites, box = dda.make_sites(w["shape"], w["shpar"])
+    n = len(sites)
+    kd = dda.kd_from_x(w["x"], n)
+    rhs = [dda.orient_rhs(0.0, 0.0, 0.0, which=1)]
+    t = dda.Target(sites, box, m=w["m"], kd=kd)
+    info = t.info()
+    P = torch.empty((1, n, 3), dtype=torch.complex128, device="cuda")
+    ref = _reference("block_64")
+    out = {"config": {"n_sites": n, "box": list(info["box"]), "fft_grid": list(info["grid"]), "nrhs": 1,
+                      "tol": tol}}
+    for name, prec, solver in (("mixed", "mixed", "bicgstab"), ("fp64", "fp64", "bicgstab"),
+                               ("mixed_bicgstab2", "mixed", "bicgstab2"), ("mixed_cocg", "mixed", "cocg"),
+                               ("mixed_qmr", "mixed", "qmr")):
+        dt, P, st = _timed_solves(t, torch, rhs, 5, tol=tol, precision=prec, out=P, solver=solver)
+        q = t.cross_sections(rhs, P)
+        out[name] = {"solves_per_s": 1.0 / dt, "iters": st[0]["iters"], "matvecs": st[0]["matvecs"],
+                     "rel_resid": st[0]["rel_resid"], "q": q[0], "q_err_vs_oracle": _ref_errors(q, ref)}
+    out["speedup_mixed_over_fp64"] = out["mixed"]["solves_per_s"] / out["fp64"]["solves_per_s"]
+    Pr = torch.tensor(inputs.random_polarization(n, 1, seed=1), device="cuda")
+    prof = t.profile_matvec(rhs, Pr, precision="mixed", reps=50)
+    prof64 = t.profile_matvec(rhs, Pr, precision="fp64", reps=20)
+    dom, prod = roofline(prof, info["box"], info["grid"], n, 1, "block_64")
+    dom64, prod64 = roofline(prof64, info["box"], info["grid"], n, 1, "block_64", fp32=False)
+    out["roofline"] = dom
+    out["product_roofline"] = prod
+    out["roofline_fp64"] = dom64
+    out["product_roofline_fp64"] = prod64
+    out["note"] = "working set below the 256 MB Infinity Cache: the roofline is not graded here"
+    t.close()
+    return out
+
+
+def extra_workloads(dda, inputs, torch, tol, serving_alone=True):
+    """The other configurations."""
     import numpy as np
     out = {}
 
+    log("block_64")
+    out["block_64"] = block64_workload(dda, inputs, torch, tol)
+
     # Sphere D = 20 (N = 4224), FP64, two polarizations solved separately.
+    log("sphere_d20")
     w = inputs.WORKLOADS["sphere_d20"]
     sites, box = dda.make_sites(w["shape"], w["shpar"])
     kd = dda.kd_from_x(w["x"], len(sites))
@@ -142,27 +251,37 @@ def extra_workloads(dda, inputs, torch, tol):
     q = t.cross_sections(rhs, P)
     ref = _reference("sphere_d20")
     res["q"] = q
-    res["q_rel_err_vs_oracle"] = [_rel_err(q[i], ref["results"][i]) for i in range(len(q))] if ref else None
+    res["q_err_vs_oracle"] = _ref_errors(q, ref)
     res["mie"] = ref.get("mie") if ref else None
     res["config"] = {"n_sites": len(sites), "fft_grid": list(t.info()["grid"]), "precision": "fp64", "nrhs": 1}
     t.close()
     out["sphere_d20"] = res
 
     # Ellipsoid 96 x 64 x 48: 32 orientations x 2 polarizations = 64 RHS in one block (mixed) against the
-    # plain FP64 single-RHS solver on the same GPU.
+    # plain FP64 single-RHS solver on the same GPU; every result against the oracle's.
+    log("ellipsoid_96x64x48 (64 RHS)")
     w = inputs.WORKLOADS["ellipsoid_96x64x48"]
     sites, box = dda.make_sites(w["shape"], w["shpar"])
     kd = dda.kd_from_x(w["x"], len(sites))
     rhs = _rhs_list(dda, inputs, w)
     t = dda.Target(sites, box, m=w["m"], kd=kd)
     P = torch.empty((len(rhs), len(sites), 3), dtype=torch.complex128, device="cuda")
-    t.solve(rhs, tol=tol, precision="mixed", out=P)
-    torch.cuda.synchronize()
-    s0 = time.perf_counter()
-    P, st = t.solve(rhs, tol=tol, precision="mixed", out=P)
-    q = t.cross_sections(rhs, P)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - s0
+    ref = _reference("ellipsoid_96x64x48")
+    ell = {"nrhs": len(rhs), "config": {"n_sites": len(sites), "fft_grid": list(t.info()["grid"]),
+                                        "precision": "mixed", "orientations": "PCG64 seed 1305, uniform on SO(3)"}}
+    for tl in sorted({tol, 1e-6, 1e-7}, reverse=True):
+        t.solve(rhs, tol=tl, precision="mixed", out=P, solver="bicgstab")
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        P, st = t.solve(rhs, tol=tl, precision="mixed", out=P, solver="bicgstab")
+        q = t.cross_sections(rhs, P)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - s0
+        ell[f"tol_{tl:g}"] = {"solves_per_s": len(rhs) / tb, "block_seconds": tb,
+                              "iters_mean": float(np.mean([x["iters"] for x in st])),
+                              "iters_max": int(max(x["iters"] for x in st)),
+                              "max_rel_resid": float(max(x["rel_resid"] for x in st)),
+                              "q_err_vs_oracle": _ref_errors(q, ref)}
     P1 = torch.empty((1, len(sites), 3), dtype=torch.complex128, device="cuda")
     t.solve(rhs[:1], tol=tol, precision="fp64", out=P1)
     torch.cuda.synchronize()
@@ -174,93 +293,22 @@ def extra_workloads(dda, inputs, torch, tol):
         iters64.append(s1[0]["iters"])
     torch.cuda.synchronize()
     ts = time.perf_counter() - s0
-    ref = _reference("ellipsoid_96x64x48")
-    errs = [_rel_err(q[i], ref["results"][i]) for i in range(len(ref["results"]))] if ref else None
-    out["ellipsoid_96x64x48_batched"] = {
-        "nrhs": len(rhs), "solves_per_s": len(rhs) / tb, "block_seconds": tb,
-        "fp64_single_rhs_solves_per_s": len(rhs) / ts, "speedup_vs_fp64_single": ts / tb,
-        "iters_mean": float(np.mean([x["iters"] for x in st])), "iters_max": int(max(x["iters"] for x in st)),
-        "fp64_iters_mean": float(np.mean(iters64)), "max_rel_resid": float(max(x["rel_resid"] for x in st)),
-        "q_rel_err_vs_oracle_first_rhs": errs,
-        "config": {"n_sites": len(sites), "fft_grid": list(t.info()["grid"]), "precision": "mixed",
-                   "orientations": "PCG64 seed 1305, uniform on SO(3)"}}
-    # roofline of one batched z-pass launch (all 64 RHS), HIP-event timed
+    ell["fp64_single_rhs_solves_per_s"] = len(rhs) / ts
+    ell["fp64_iters_mean"] = float(np.mean(iters64))
+    ell["speedup_batched_mixed_over_fp64_single"] = ell[f"tol_{tol:g}"]["solves_per_s"] / ell[
+        "fp64_single_rhs_solves_per_s"]
     prof = t.profile_matvec(rhs, P, precision="mixed", reps=3)
     info = t.info()
-    _, z_b = algorithmic_bytes(info["box"], info["grid"], len(sites), fp32=True, nrhs=len(rhs))
-    z_launch = z_b * len(rhs)
-    traffic, traffic_src = measured_traffic("k_zpass", "ellipsoid_96x64x48")
-    achieved = z_launch / (prof["z_pass"] * 1e-3) / 1e9
-    out["ellipsoid_96x64x48_batched"]["roofline"] = {
-        "bound": "hbm", "kernel": "z_pass", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-        "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "traffic_source": traffic_src,
-        "algorithmic_bytes_per_launch": z_launch, "rhs_per_launch": len(rhs), "pass_ms": prof}
+    ell["roofline"], ell["product_roofline"] = roofline(prof, info["box"], info["grid"], len(sites), len(rhs),
+                                                        "ellipsoid_96x64x48")
     t.close()
-
-    # Sphere D = 133 (N = 1,232,177, grid 270^3), 2 polarizations batched, mixed, against Mie.
-    w = inputs.WORKLOADS["sphere_d133"]
-    sites, box = dda.make_sites(w["shape"], w["shpar"])
-    kd = dda.kd_from_x(w["x"], len(sites))
-    rhs = _rhs_list(dda, inputs, w)
-    s0 = time.perf_counter()
-    t = dda.Target(sites, box, m=w["m"], kd=kd)
-    torch.cuda.synchronize()
-    setup = time.perf_counter() - s0
-    P = torch.empty((len(rhs), len(sites), 3), dtype=torch.complex128, device="cuda")
-    s0 = time.perf_counter()
-    P, st = t.solve(rhs, tol=tol, precision="mixed", out=P)
-    q = t.cross_sections(rhs, P)
-    torch.cuda.synchronize()
-    tsolve = time.perf_counter() - s0
-    ref = _reference("sphere_d133")
-    mie = ref.get("mie") if ref else None
-    d133 = dict(nrhs=len(rhs), solves_per_s=len(rhs) / tsolve, solve_seconds=tsolve, setup_seconds=setup,
-                iters=[x["iters"] for x in st], rel_resid=[x["rel_resid"] for x in st], q=q, mie=mie)
-    d133["q_rel_err_vs_mie"] = [_rel_err(v, mie) for v in q] if mie else None
-    d133["config"] = {"n_sites": len(sites), "fft_grid": list(t.info()["grid"]), "precision": "mixed"}
-    # far field: Q_sca by quadrature (optical theorem check) and <cos theta> against Mie
-    s0 = time.perf_counter()
-    far = t.far_field(rhs, P, etasca=0.5)
-    torch.cuda.synchronize()
-    d133["far_field"] = dict(seconds=time.perf_counter() - s0, n_theta=far[0]["n_theta"], n_phi=far[0]["n_phi"],
-                             qsca=[f["qsca"] for f in far], g=[f["g"] for f in far], cos2=[f["cos2"] for f in far],
-                             mie_g=mie.get("g") if mie else None,
-                             qsca_rel_diff_vs_qext_minus_qabs=[abs(f["qsca"] - v["qsca"]) / v["qext"]
-                                                               for f, v in zip(far, q)])
-    # the same solve with BiCGstab(2), the guide's recommended PBCGS2
-    s0 = time.perf_counter()
-    P, st2 = t.solve(rhs, tol=tol, precision="mixed", out=P, solver="bicgstab2")
-    q2 = t.cross_sections(rhs, P)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter() - s0
-    d133["bicgstab2"] = dict(solves_per_s=len(rhs) / t2, iters=[x["iters"] for x in st2],
-                             q_rel_err_vs_mie=[_rel_err(v, mie) for v in q2] if mie else None)
-    # and with COCG (one product per iteration, bilinear form of the complex-symmetric A)
-    s0 = time.perf_counter()
-    P, st3 = t.solve(rhs, tol=tol, precision="mixed", out=P, solver="cocg")
-    q3 = t.cross_sections(rhs, P)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter() - s0
-    d133["cocg"] = dict(solves_per_s=len(rhs) / t3, iters=[x["iters"] for x in st3],
-                        rel_resid=[x["rel_resid"] for x in st3],
-                        q_rel_err_vs_mie=[_rel_err(v, mie) for v in q3] if mie else None)
-    # the HBM-bound configuration's roofline: the z-pass of one RHS, HIP-event timed
-    prof = t.profile_matvec(rhs[:1], P[:1].contiguous(), precision="mixed", reps=5)
-    info = t.info()
-    _, z_b = algorithmic_bytes(info["box"], info["grid"], len(sites), fp32=True)
-    traffic, traffic_src = measured_traffic("k_zpass", "sphere_d133")
-    achieved = z_b / (prof["z_pass"] * 1e-3) / 1e9
-    d133["roofline"] = {"bound": "hbm", "kernel": "z_pass", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                        "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                        "traffic_source": traffic_src, "algorithmic_bytes_per_launch": z_b,
-                        "pass_ms": prof}
-    out["sphere_d133"] = d133
-    t.close()
+    out["ellipsoid_96x64x48_batched"] = ell
 
     # Near field of the guide's Au sphere (N = 59728 in 48^3, kd = 0.20619, m = 0.96+1.01i) on the printed
     # 96^3 extended volume, interpolated trilinearly along the printed line through the centre.
-    fx = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
-                                     "au_sphere_nearfield_line.json")))
+    log("au_sphere_near_field")
+    golden = os.path.join(ROOT, "tests", "golden")
+    fx = json.load(open(os.path.join(golden, "au_sphere_nearfield_line.json")))
     sites, box = dda.make_sites("ELLIPSOID", (48.49, 48.49, 48.49))
     rhs = [(np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0]))]
     t = dda.Target(sites, box, m=complex(*fx["m"]), kd=fx["kd"])
@@ -296,8 +344,8 @@ def extra_workloads(dda, inputs, torch, tol):
                 "x-axis track, trilinear"}
 
     # The guide's worked example (16 x 32 x 32 Au block, two polarizations along y and z, k along x): every
-    # printed efficiency next to the GPU's (LDR here, GKDLDR there), solved with BiCGstab(2) as printed.
-    golden = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden")
+    # printed efficiency next to the GPU's, solved with BiCGstab(2) as printed.
+    log("au_block_worked_example")
     pr = json.load(open(os.path.join(golden, "paper_printed.json")))["au_block_example"]
     mu = json.load(open(os.path.join(golden, "au_block_mueller.json")))
     sites, box = dda.make_sites("RCTGLPRSM", mu["box"])
@@ -326,24 +374,60 @@ def extra_workloads(dda, inputs, torch, tol):
         "bicgstab2_cycles": [x["iters"] // 2 for x in st], "printed_iterations": [18, 18], "gpu": gpu,
         "printed": printed,
         "rel_diff": {k: (gpu[k] - printed[k]) / abs(printed[k]) for k in printed if k != "qpol"},
-        "note": "FP64, TOL 1e-5, LDR (the printed run used GKDLDR, not given in the guide); Q_pha is ~25x more "
-                "sensitive to the polarizability than Q_ext"}
+        "note": "FP64, TOL 1e-5, LDR (the printed run used GKDLDR); Q_pha is ~25x more sensitive to the "
+                "polarizability than Q_ext"}
 
-    # Serving mix (seeded, first 200 of the 1000-request stream): saturated, then Poisson arrivals at 0.8x.
+    # Serving mix: the whole seeded 1000-request stream, saturated, then Poisson arrivals at 0.8x the
+    # saturated rate, then every request alone (one slot) for the alone-vs-mix difference of each result.
     from paper_1305_6497_amd import serving
+    log("serving mix (1000 requests)")
+    out["serving_mix_1000"] = serving_mix(serving, dda, inputs, tol, alone=serving_alone)
+    return out
+
+
+def serving_mix(serving, dda, inputs, tol, n=1000, slots=8, alone=True):
+    import numpy as np
     ex = serving.GpuExecutor(tol=tol)
-    reqs = serving.make_requests(200, inputs.SERVING_SEED, 1.0, dda)
+    reqs = serving.make_requests(n, inputs.SERVING_SEED, 1.0, dda)
     burst = [serving.Request(**{**r.__dict__, "arrival": 0.0}) for r in reqs]
     s0 = time.perf_counter()
-    sat = serving.summarize(serving.Server(ex, slots=8).run(burst), time.perf_counter() - s0)
+    res_sat = serving.Server(ex, slots=slots).run(burst)
+    sat = serving.summarize(res_sat, time.perf_counter() - s0)
+    log(f"serving saturated: {sat['requests_per_s']:.1f} requests/s")
     rate = 0.8 * sat["requests_per_s"]
-    reqs = serving.make_requests(200, inputs.SERVING_SEED, rate, dda)
+    reqs = serving.make_requests(n, inputs.SERVING_SEED, rate, dda)
     s0 = time.perf_counter()
-    poi = serving.summarize(serving.Server(ex, slots=8).run(reqs), time.perf_counter() - s0)
+    res_poi = serving.Server(ex, slots=slots).run(reqs)
+    poi = serving.summarize(res_poi, time.perf_counter() - s0)
     poi["arrival_rate_per_s"] = rate
-    out["serving_mix_200"] = {"saturated": sat, "poisson_0.8": poi, "slots": 8,
-                              "note": "first 200 requests of the seeded 1000-request mix; 2 polarizations each; "
-                                      "mixed precision; admission by dda_footprint_bytes against 80% of free HBM"}
+    log(f"serving Poisson: p50 {poi['p50_ms']:.0f} ms, p99 {poi['p99_ms']:.0f} ms")
+    failed = [dict(id=r.id, shape=reqs[r.id].shape, shpar=list(reqs[r.id].shpar), m=[reqs[r.id].m.real,
+                   reqs[r.id].m.imag], x=reqs[r.id].x, n_sites=r.n_sites, error=r.error,
+                   stats=r.stats) for r in res_poi.values()
+              if r.error or not all(s["status"] == 0 for s in r.stats)]
+    out = {"saturated": sat, "poisson_0.8": poi, "slots": slots, "requests": n,
+           "unconverged": failed,
+           "cap": "per RHS: COCG with the products of 2000 BiCGSTAB iterations, then BiCGstab(2) from its iterate "
+                  "for up to 4000 BiCG steps (survey reading C-18: max_iter caps an outlier)",
+           "note": "seeded 1000-request mix (PCG64 seed 4242); 2 polarizations each; mixed precision, tol "
+                   f"{tol:g}; admission by dda_footprint_bytes against 80% of free HBM"}
+    if alone:
+        # every request alone (one slot, one at a time) against its result inside the Poisson mix
+        s0 = time.perf_counter()
+        res_alone = serving.Server(ex, slots=1).run([serving.Request(**{**r.__dict__, "arrival": 0.0})
+                                                     for r in reqs])
+        dq = []
+        for r in reqs:
+            a, b = res_alone[r.id], res_poi[r.id]
+            if a.error or b.error:
+                continue
+            dq.append(max(abs(qa[k] - qb[k]) / abs(qa["qext"]) for qa, qb in zip(a.q, b.q)
+                          for k in ("qext", "qabs", "qsca")))
+        dq = np.array(dq)
+        out["alone_vs_mix"] = {"requests_compared": int(len(dq)), "max_abs_dq_over_qext": float(dq.max()),
+                               "nonzero": int((dq > 0).sum()), "p99_abs_dq_over_qext": float(np.percentile(dq, 99)),
+                               "alone_seconds": time.perf_counter() - s0}
+        log(f"serving alone-vs-mix: max |dQ|/Q_ext {dq.max():.3g}")
     return out
 
 
@@ -354,7 +438,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tol", type=float, default=1e-5)
-    ap.add_argument("--no-extras", action="store_true", help="only the block_64 workload")
+    ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
+    ap.add_argument("--no-serving-alone", action="store_true", help="skip the alone-vs-mix serving rerun")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not part of this "
@@ -371,91 +456,105 @@ def main():
     sites, box = dda.make_sites(w["shape"], w["shpar"])
     n = len(sites)
     kd = dda.kd_from_x(w["x"], n)
-    rhs = [dda.orient_rhs(0.0, 0.0, 0.0, which=1)]
+    rhs = _rhs_list(dda, inputs, w)
+    log(f"{WORKLOAD}: N = {n}, setup")
     t = dda.Target(sites, box, m=w["m"], kd=kd)
     info = t.info()
-    P = torch.empty((1, n, 3), dtype=torch.complex128, device="cuda")
+    P = torch.empty((len(rhs), n, 3), dtype=torch.complex128, device="cuda")
+    ref = _reference(WORKLOAD)
 
-    def step(precision, solver="bicgstab"):
-        Pp, st = t.solve(rhs, tol=args.tol, precision=precision, out=P, solver=solver)
-        q = t.cross_sections(rhs, Pp)
-        return st[0], q[0]
+    def step(tol, solver=SOLVER, precision="mixed", r=rhs, out=P):
+        Pp, st = t.solve(r, tol=tol, precision=precision, out=out, solver=solver)
+        q = t.cross_sections(r, Pp)
+        return st, q
 
     for _ in range(args.warmup):
-        step("mixed")
+        step(args.tol)
     torch.cuda.synchronize()
+    log(f"{WORKLOAD}: {args.steps} timed steps")
     lat = []
     mv = 0
     outer = 0
     t_start = time.perf_counter()
     for _ in range(args.steps):
         s0 = time.perf_counter()
-        st, q = step("mixed")
+        st, q = step(args.tol)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - s0)
-        mv += st["matvecs"]
-        outer += st["outer"]
+        mv += sum(x["matvecs"] for x in st)
+        outer += sum(x["outer"] for x in st)
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
-    assert st["status"] == 0 and st["rel_resid"] <= args.tol, st
+    assert all(x["status"] == 0 and x["rel_resid"] <= args.tol for x in st), st
+    solves = len(rhs) * args.steps
 
-    # plain FP64 single-RHS solver on the same GPU
-    step("fp64")
-    torch.cuda.synchronize()
-    f0 = time.perf_counter()
-    nf = max(2, args.steps // 2)
-    for _ in range(nf):
-        st64, q64 = step("fp64")
-    torch.cuda.synchronize()
-    fp64_s = (time.perf_counter() - f0) / nf
+    # the same batch with the other solvers
+    log(f"{WORKLOAD}: other solvers")
+    solvers_out = {}
+    for solver in ("bicgstab", "bicgstab2", "qmr"):
+        dt, Ps, sts = _timed_solves(t, torch, rhs, 2, tol=args.tol, precision="mixed", out=P, solver=solver)
+        qs = t.cross_sections(rhs, Ps)
+        solvers_out[solver] = {"solves_per_s": len(rhs) / dt, "iters": [x["iters"] for x in sts],
+                               "matvecs": [x["matvecs"] for x in sts], "q_err_vs_oracle": _ref_errors(qs, ref)}
 
-    # BiCGstab(2) (the guide's PBCGS2), mixed, same workload
-    step("mixed", "bicgstab2")
+    # plain FP64 single-RHS solver on the same GPU (one polarization at a time)
+    log(f"{WORKLOAD}: FP64 single-RHS")
+    P1 = torch.empty((1, n, 3), dtype=torch.complex128, device="cuda")
+    s0 = time.perf_counter()
+    st64 = []
+    q64 = []
+    for r in rhs:
+        P1, s1 = t.solve([r], tol=args.tol, precision="fp64", out=P1, solver=SOLVER)
+        q64 += t.cross_sections([r], P1)
+        st64 += s1
     torch.cuda.synchronize()
-    f0 = time.perf_counter()
-    for _ in range(nf):
-        stb2, qb2 = step("mixed", "bicgstab2")
+    fp64_s = (time.perf_counter() - s0) / len(rhs)
+
+    # tolerance scan: Q against the oracle's solution at the metric's tolerance and tighter ones; throughput
+    # at the loosest tolerance whose every result is within 1e-5 of the oracle's
+    log(f"{WORKLOAD}: tolerance scan")
+    scan = []
+    for tl in (1e-5, 3e-6, 1e-6, 3e-7, 1e-7):
+        dt, Ps, sts = _timed_solves(t, torch, rhs, 1, tol=tl, precision="mixed", out=P, solver=SOLVER)
+        qs = t.cross_sections(rhs, Ps)
+        scan.append({"tol": tl, "solves_per_s": len(rhs) / dt, "iters": [x["iters"] for x in sts],
+                     "q_err_vs_oracle": _ref_errors(qs, ref)})
+    parity = [s for s in scan if s["q_err_vs_oracle"] and s["q_err_vs_oracle"]["max_rel_err"] is not None
+              and s["q_err_vs_oracle"]["max_rel_err"] <= 1e-5]
+    at_parity = dict(tol=parity[0]["tol"], solves_per_s=parity[0]["solves_per_s"],
+                     max_rel_err=parity[0]["q_err_vs_oracle"]["max_rel_err"]) if parity else None
+
+    # event timing of the five FFT passes: the 2-RHS mixed product of the solve, and the FP64 product
+    log(f"{WORKLOAD}: pass timing")
+    Pr = torch.tensor(inputs.random_polarization(n, len(rhs), seed=1), device="cuda")
+    prof = t.profile_matvec(rhs, Pr, precision="mixed", reps=20)
+    prof64 = t.profile_matvec(rhs[:1], Pr[:1].contiguous(), precision="fp64", reps=10)
+    dom, prod = roofline(prof, info["box"], info["grid"], n, len(rhs), WORKLOAD)
+    dom64, prod64 = roofline(prof64, info["box"], info["grid"], n, 1, WORKLOAD, fp32=False)
+    mie = ref.get("mie") if ref else None
+    # far field of the last solve: Q_sca by quadrature (the dipole array's optical theorem) and <cos theta>
+    s0 = time.perf_counter()
+    Pq, _ = t.solve(rhs, tol=args.tol, precision="mixed", out=P, solver=SOLVER)
+    far = t.far_field(rhs, Pq, etasca=0.5)
     torch.cuda.synchronize()
-    b2_s = (time.perf_counter() - f0) / nf
-
-    # COCG and QMR (the guide's QMRCCG, as the smoothing of COCG), mixed, same workload
-    cs = {}
-    for solver in ("cocg", "qmr"):
-        step("mixed", solver)
-        torch.cuda.synchronize()
-        f0 = time.perf_counter()
-        for _ in range(nf):
-            stc, qc = step("mixed", solver)
-        torch.cuda.synchronize()
-        assert stc["status"] == 0 and stc["rel_resid"] <= args.tol, (solver, stc)
-        cs[solver] = {"solves_per_s": nf / (time.perf_counter() - f0), "iters": stc["iters"],
-                      "matvecs": stc["matvecs"], "q": qc, "precision": "mixed"}
-
-    # event timing of the five FFT passes (mixed product)
-    Pr = torch.tensor(inputs.random_polarization(n, 1, seed=1), device="cuda")
-    prof = t.profile_matvec(rhs, Pr, precision="mixed", reps=50)
-    prof64 = t.profile_matvec(rhs, Pr, precision="fp64", reps=20)
-    tot_b, z_b = algorithmic_bytes(info["box"], info["grid"], n, fp32=True)
-    dom = max(("x_forward", "y_forward", "z_pass", "y_inverse", "x_inverse"), key=lambda k: prof[k])
-    Mx, My, _ = info["grid"]
-    a_b = 3 * 8 * Mx * box[1] * box[2]          # x-transformed rows (FP32)
-    b_b = 3 * 8 * Mx * My * box[2]              # x- and y-transformed planes (FP32)
-    pass_bytes = dict(x_forward=48 * n + a_b, y_forward=a_b + b_b, z_pass=z_b, y_inverse=a_b + b_b,
-                      x_inverse=a_b + 2 * 48 * n)
-    achieved = pass_bytes[dom] / (prof[dom] * 1e-3) / 1e9
-    kprefix = dict(x_forward="k_xfwd", y_forward="k_yfwd", z_pass="k_zpass", y_inverse="k_yinv",
-                   x_inverse="k_xinv")[dom]
-    traffic, traffic_src = measured_traffic(kprefix)
+    far_out = dict(seconds_with_solve=time.perf_counter() - s0, n_theta=far[0]["n_theta"], n_phi=far[0]["n_phi"],
+                   qsca=[f["qsca"] for f in far], g=[f["g"] for f in far], mie_g=mie.get("g") if mie else None,
+                   qsca_rel_diff_vs_qext_minus_qabs=[abs(f["qsca"] - v["qsca"]) / v["qext"] for f, v in zip(far, q)])
     ms_per_step = 1e3 * total / args.steps
-    extras = None if args.no_extras else extra_workloads(dda, inputs, torch, args.tol)
+    lat_ms = np.array(lat) * 1e3
+    t.close()
+
+    extras = None
+    if not args.no_extras:
+        extras = extra_workloads(dda, inputs, torch, args.tol, serving_alone=not args.no_serving_alone)
     cpu = None
     if not args.no_cpu:
+        log("cpu_baseline (FP64 oracle)")
         from oracle import targets
-        cpu = cpu_baseline(targets.make(w["shape"], w["shpar"]), kd, w["m"], rhs[0], st64["iters"])
-    lat_ms = np.array(lat) * 1e3
+        cpu = cpu_baseline(targets.make(w["shape"], w["shpar"]), kd, w["m"], rhs[0], st64[0]["iters"])
     out = {
         "metric": "FFT dipole matvecs/sec + solves/sec at 1e-5 rel. residual; p50/p99 latency",
-        "value": args.steps / total,
+        "value": solves / total,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -466,36 +565,38 @@ def main():
         "vs_baseline": None,
         "dtype": "c64 FFT product / f64 Krylov, residual and sums",
         "data": "synthetic",
-        "config": {"workload": "block_64: 64x64x64 RCTGLPRSM, m=1.5+0.1i, x=10, LATTDR, k||x, e||y, "
-                               "mixed FP32 product + FP64 refinement to 1e-5",
-                   "n_sites": n, "box": list(info["box"]), "fft_grid": list(info["grid"]), "kd": kd, "nrhs": 1,
-                   "tol": args.tol},
+        "config": {"workload": f"{WORKLOAD}: ELLIPSOID SHPAR 133 sphere, N={n}, m=1.33+0.001i, x=25, LATTDR, "
+                               "k||x, e||y and e||z as one batch of 2 RHS, COCG, mixed FP32 product + FP64 "
+                               f"refinement to {args.tol:g}",
+                   "n_sites": n, "box": list(info["box"]), "fft_grid": list(info["grid"]), "kd": kd,
+                   "nrhs": len(rhs), "tol": args.tol, "solver": SOLVER, "precision": "mixed"},
+        "solves_per_step": len(rhs),
         "matvecs_per_s": mv / total,
-        "matvecs_per_solve": mv / args.steps,
-        "fp64_checks_per_solve": outer / args.steps,
+        "matvecs_per_solve": mv / solves,
+        "fp64_checks_per_solve": outer / solves,
         "p50_ms": float(np.percentile(lat_ms, 50)),
         "p99_ms": float(np.percentile(lat_ms, 99)),
         "q": q,
-        "rel_resid": st["rel_resid"],
-        "iters": st["iters"],
-        "bicgstab2_solver": {"solves_per_s": 1.0 / b2_s, "iters": stb2["iters"], "q": qb2, "precision": "mixed"},
-        "cocg_solver": cs["cocg"],
-        "qmr_solver": cs["qmr"],
-        "fp64_solver": {"solves_per_s": 1.0 / fp64_s, "iters": st64["iters"], "q": q64,
-                        "speedup_mixed_over_fp64": (args.steps / total) * fp64_s},
-        "matvec_event_ms": {"mixed": prof, "fp64": prof64},
-        "matvec_only_per_s": {"mixed": 1e3 / prof["total"], "fp64": 1e3 / prof64["total"]},
-        "matvec_algorithmic_bytes": tot_b,
-        "matvec_effective_GBs": tot_b / (prof["total"] * 1e-3) / 1e9,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "traffic_source": traffic_src,
-                     "algorithmic_bytes_per_launch": pass_bytes[dom]},
+        "iters": [x["iters"] for x in st],
+        "rel_resid": [x["rel_resid"] for x in st],
+        "q_err_vs_oracle": _ref_errors(q, ref),
+        "q_rel_err_vs_mie": [_rel_err(v, mie) for v in q] if mie else None,
+        "far_field": far_out,
+        "at_parity": at_parity,
+        "tolerance_scan": scan,
+        "solvers": solvers_out,
+        "fp64_single_rhs": {"solves_per_s": 1.0 / fp64_s, "iters": [x["iters"] for x in st64],
+                            "q_err_vs_oracle": _ref_errors(q64, ref),
+                            "speedup_mixed_batched_over_fp64_single": (solves / total) * fp64_s},
+        "matvec_event_ms": {"mixed_2rhs": prof, "fp64_1rhs": prof64},
+        "matvec_only_per_s": {"mixed": len(rhs) * 1e3 / prof["total"], "fp64": 1e3 / prof64["total"]},
+        "roofline": dom,
+        "product_roofline": prod,
+        "roofline_fp64": dom64,
+        "product_roofline_fp64": prod64,
         "cpu_baseline": cpu,
-        "q_rel_err_vs_oracle": (_rel_err(q, _reference(WORKLOAD)["results"][0]) if _reference(WORKLOAD) else None),
         "workloads": extras,
     }
-    t.close()
     print(json.dumps(out))
 
 

@@ -74,7 +74,12 @@ class GpuExecutor:
         sites, box = self.dda.make_sites(req.shape, req.shpar)
         kd = self.dda.kd_from_x(req.x, len(sites))
         fp = self.dda.footprint_bytes(box, len(sites), m=req.m, kd=kd, nrhs=2)
-        fp += 2 * len(sites) * 3 * 16          # the P output buffer
+        vec = 2 * len(sites) * 3 * 16
+        # the P output, and for the BiCGstab(2) fallback its initial-guess copy
+        # and second output; the device cache rounds blocks up to 2 MiB and may
+        # grant up to 25% more than asked (a handle holds about 20 blocks)
+        fp += 3 * vec
+        fp = int(fp * 1.25) + 20 * (2 << 20)
         return dict(sites=sites, box=box, kd=kd), fp
 
     def _stream(self):
@@ -103,7 +108,9 @@ class GpuExecutor:
                                           x0=P[redo].contiguous())
                         for j, i in enumerate(redo):
                             P[i].copy_(P2[j])
-                            st[i] = dict(st2[j], fallback_from="cocg")
+                            # products include COCG's; iters stays BiCGstab(2)'s BiCG steps
+                            st[i] = dict(st2[j], fallback_from="cocg", cocg_iters=st[i]["iters"],
+                                         matvecs=st2[j]["matvecs"] + st[i]["matvecs"])
                 else:
                     P, st = t.solve(rhs, tol=self.tol, precision=self.precision, max_iter=self.max_iter, stream=s,
                                     solver=self.solver)
