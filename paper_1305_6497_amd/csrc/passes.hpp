@@ -416,6 +416,34 @@ __global__ __launch_bounds__(kNT) void k_yfwd(const int *__restrict__ mask, cons
 }
 
 // ------------------------------------------------------------------ z-pass --
+template <typename T>
+__device__ __forceinline__ T fmaT(T a, T b, T c) {
+  if constexpr (sizeof(T) == 4) return __builtin_fmaf(a, b, c);
+  else return __builtin_fma(a, b, c);
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<T> neg(cpx<T> a) { return {-a.x, -a.y}; }
+
+// g0 p0 + g1 p1 + g2 p2 as two chains of one multiply and five fused
+// multiply-adds (one per real product), instead of three complex products
+// and two complex sums.
+template <typename T>
+__device__ __forceinline__ cpx<T> dot3(cpx<T> g0, cpx<T> p0, cpx<T> g1, cpx<T> p1, cpx<T> g2, cpx<T> p2) {
+  T re = -g2.y * p2.y, im = g2.y * p2.x;
+  re = fmaT(g2.x, p2.x, re);
+  im = fmaT(g2.x, p2.y, im);
+  re = fmaT(-g1.y, p1.y, re);
+  im = fmaT(g1.y, p1.x, im);
+  re = fmaT(g1.x, p1.x, re);
+  im = fmaT(g1.x, p1.y, im);
+  re = fmaT(-g0.y, p0.y, re);
+  im = fmaT(g0.y, p0.x, im);
+  re = fmaT(g0.x, p0.x, re);
+  im = fmaT(g0.x, p0.y, im);
+  return {re, im};
+}
+
 // Fold a frequency index into the stored octant: k <= M/2 is kept (sign +1),
 // k > M/2 maps to M - k (sign -1 for components odd along this axis).
 __device__ __forceinline__ int fold(int k, int M, int &sgn) {
@@ -545,35 +573,32 @@ __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx
   for (int i = 0; i < NQ; ++i) {
     const int q = threadIdx.x + i * kNT;
     if (q < nq) {
-      const int oz = q >> LOGP, p = q & (NP - 1), kx = (xt << LOGW) + h * NP + p;
+      // lanes past Mx (the last x tile) hold zeros, which the x-forward pass
+      // wrote there; any Green value keeps them zero, so their index is clamped
+      const int oz = q >> LOGP, p = q & (NP - 1), kx = min((xt << LOGW) + h * NP + p, d.Mx - 1);
       const bool mir = oz != 0 && 2 * oz != Mz;
-      const int zb = ((Mz - oz) << LOGP) + p;
-      cpx<T> qa0 = {0, 0}, qa1 = {0, 0}, qa2 = {0, 0}, qb0 = {0, 0}, qb1 = {0, 0}, qb2 = {0, 0};
-      if (kx < d.Mx) {
-        int sx;
-        const int ox = fold(kx, d.Mx, sx);
-        const cpx<T> *g = ghat + (size_t)(mul24(mul24(oz, d.Myh) + oy, d.Mxh) + ox);
-        const cpx<T> gxx = g[0], gyy = g[d.moct], gzz = g[2 * d.moct];
-        const cpx<T> gxy = T(sx * sy) * g[3 * d.moct], gxz = T(sx) * g[4 * d.moct], gyz = T(sy) * g[5 * d.moct];
-        const cpx<T> a2 = buf[q];
-        qa0 = gxx * a0[i] + gxy * a1[i] + gxz * a2;
-        qa1 = gxy * a0[i] + gyy * a1[i] + gyz * a2;
-        qa2 = gxz * a0[i] + gyz * a1[i] + gzz * a2;
-        if (mir) {
-          const cpx<T> b2 = buf[zb];
-          qb0 = gxx * b0[i] + gxy * b1[i] - gxz * b2;
-          qb1 = gxy * b0[i] + gyy * b1[i] - gyz * b2;
-          qb2 = gzz * b2 - gxz * b0[i] - gyz * b1[i];
-        }
-      }
+      // without a mirror (oz = 0 or Mz/2) the mirror products are computed on
+      // the cell itself and discarded
+      const int zb = mir ? ((Mz - oz) << LOGP) + p : q;
+      int sx;
+      const int ox = fold(kx, d.Mx, sx);
+      const cpx<T> *g = ghat + (size_t)(mul24(mul24(oz, d.Myh) + oy, d.Mxh) + ox);
+      const cpx<T> gxx = g[0], gyy = g[d.moct], gzz = g[2 * d.moct];
+      const cpx<T> gxy = T(sx * sy) * g[3 * d.moct], gxz = T(sx) * g[4 * d.moct], gyz = T(sy) * g[5 * d.moct];
+      const cpx<T> a2 = buf[q], b2 = buf[zb];
+      const cpx<T> qa0 = dot3(gxx, a0[i], gxy, a1[i], gxz, a2);
+      const cpx<T> qa1 = dot3(gxy, a0[i], gyy, a1[i], gyz, a2);
+      const cpx<T> qa2 = dot3(gxz, a0[i], gyz, a1[i], gzz, a2);
+      // the mirror frequency Mz - oz: the z-odd components change sign
+      const cpx<T> qb0 = dot3(gxx, b0[i], gxy, b1[i], neg(gxz), b2);
+      const cpx<T> qb1 = dot3(gxy, b0[i], gyy, b1[i], neg(gyz), b2);
+      const cpx<T> qb2 = dot3(neg(gxz), b0[i], neg(gyz), b1[i], gzz, b2);
       a0[i] = qa0;
       a1[i] = qa1;
+      b0[i] = qb0;
+      b1[i] = qb1;
       buf[q] = qa2;
-      if (mir) {
-        b0[i] = qb0;
-        b1[i] = qb1;
-        buf[zb] = qb2;
-      }
+      if (mir) buf[zb] = qb2;
     }
   }
   __syncthreads();
