@@ -7,6 +7,8 @@ that give C from the dipole moments are cited (Draine 1988; Draine & Flatau
 
     C_ext = 4 pi k sum_j Im( conj(E_inc,j) . P_j )
     C_abs = 4 pi k sum_j [ Im( P_j . conj(1/alpha_j) conj(P_j) ) - (2/3) k^3 |P_j|^2 ]
+
+(for a diagonal 1/alpha tensor the first term is sum_c Im(conj(1/alpha_jc)) |P_jc|^2)
     C_sca = k^4 * integral dOmega | sum_j (I - n n) P_j e^{-i k n.r_j} |^2
           = 4 pi k^4 sum_j sum_l conj(P_j) . K(k R_jl) . P_l
 
@@ -52,6 +54,8 @@ import math
 import numpy as np
 import scipy.special as ssp
 
+from . import interaction
+
 
 def c_ext(kd, E_inc, P):
     return 4.0 * math.pi * kd * float(np.sum(np.imag(np.conj(E_inc) * P)))
@@ -72,8 +76,9 @@ def dc_sca_domega(sites, kd, P, n):
 
 
 def c_abs(kd, alpha_inv_sites, P):
-    ai = np.asarray(alpha_inv_sites, dtype=complex)
-    p2 = np.sum(np.abs(P) ** 2, axis=-1)
+    P = np.asarray(P, dtype=complex)
+    ai = interaction.alpha_inv_diag(alpha_inv_sites, P.shape[0])
+    p2 = np.abs(P) ** 2
     term = np.imag(np.conj(ai)) * p2 - (2.0 / 3.0) * kd ** 3 * p2
     return 4.0 * math.pi * kd * float(np.sum(term))
 

@@ -8,8 +8,12 @@ for j != l, with R = r_j - r_l, R = |R|, n = R/R,
     A_jl = -G_jl,
     G_jl = (e^{ikR}/R) [ k^2 (I - n n) + ((ikR - 1)/R^2) (I - 3 n n) ],
 
-the field at r_j radiated by a unit dipole at r_l; and A_jj = (1/alpha_j) I.
-So (A P)_j = P_j / alpha_j - sum_{l != j} G_jl P_l.
+the field at r_j radiated by a unit dipole at r_l; and A_jj = 1/alpha_j, a
+multiple of I, or for the GKDLDR polarizability of §14 a diagonal tensor.
+So (A P)_j = alpha_j^{-1} P_j - sum_{l != j} G_jl P_l.
+
+The inverse polarizabilities may be given as one scalar, one per site [N],
+or as tensor diagonals, one for all sites [1, 3] or one per site [N, 3].
 
 Two products are given:
 
@@ -26,6 +30,17 @@ Two products are given:
 
 import numpy as np
 import scipy.fft as sfft
+
+
+def alpha_inv_diag(alpha_inv_sites, n):
+    """1/alpha as the diagonal of each site's tensor, complex [n, 3].
+
+    A scalar or a 1-D array (one value per site) is a multiple of I; a 2-D
+    array [1, 3] or [n, 3] holds tensor diagonals."""
+    ai = np.asarray(alpha_inv_sites, dtype=complex)
+    if ai.ndim <= 1:
+        return np.repeat(np.broadcast_to(ai, (n,))[:, None], 3, axis=1)
+    return np.broadcast_to(ai, (n, 3)).copy()
 
 
 def green_tensor(R, kd):
@@ -54,9 +69,9 @@ def dense_matrix(sites, kd, alpha_inv_sites):
     G = np.zeros((n, n, 3, 3), dtype=complex)
     G[off] = green_tensor(R[off], kd)
     A = -G
-    ai = np.broadcast_to(np.asarray(alpha_inv_sites, dtype=complex), (n,))
+    ai = alpha_inv_diag(alpha_inv_sites, n)
     for j in range(n):
-        A[j, j] = ai[j] * np.eye(3)
+        A[j, j] = np.diag(ai[j])
     return A.transpose(0, 2, 1, 3).reshape(3 * n, 3 * n)
 
 
@@ -65,8 +80,7 @@ def direct_matvec(sites, kd, alpha_inv_sites, P, block=256):
     sites = np.asarray(sites, dtype=float)
     P = np.asarray(P, dtype=complex)
     n = sites.shape[0]
-    ai = np.broadcast_to(np.asarray(alpha_inv_sites, dtype=complex), (n,))
-    out = ai[:, None] * P
+    out = alpha_inv_diag(alpha_inv_sites, n) * P
     for j0 in range(0, n, block):
         j1 = min(n, j0 + block)
         R = sites[j0:j1, None, :] - sites[None, :, :]
@@ -127,7 +141,7 @@ class FFTOperator:
         self.M = tuple(2 * b for b in self.box)
         self.kd = kd
         self.n = self.sites.shape[0]
-        self.alpha_inv = np.broadcast_to(np.asarray(alpha_inv_sites, dtype=complex), (self.n,)).copy()
+        self.alpha_inv = alpha_inv_diag(alpha_inv_sites, self.n)
         self.workers = workers if workers is not None else -1
         G = green_grid(self.box, kd, self.M)
         self.Ghat = sfft.fftn(G, axes=(1, 2, 3), workers=self.workers)
@@ -154,4 +168,4 @@ class FFTOperator:
 
     def matvec(self, P):
         P = np.asarray(P, dtype=complex)
-        return self.alpha_inv[:, None] * P - self.field(P)
+        return self.alpha_inv * P - self.field(P)

@@ -11,11 +11,28 @@
                                                - (2/3) i (kd)^3 ])
 
   with b1 = -1.891531, b2 = 0.1648469, b3 = -1.7700004 and
-  S = sum_l (khat_l e_l)^2 over the three Target-Frame components of the unit
-  propagation vector khat and polarization vector e.  The -(2/3) i (kd)^3
+  S = sum_l khat_l^2 |e_l|^2 over the three Target-Frame components of the
+  unit propagation vector khat and polarization vector e.  For a linear
+  polarization (e real up to a phase) this is the cited sum_l (khat_l e_l)^2;
+  written with |e_l|^2 it does not change when e is multiplied by a phase
+  factor, which leaves every physical quantity unchanged.  The -(2/3) i (kd)^3
   term is the radiative reaction; its sign is pinned by the requirement that
-  a lossless (real m) target absorbs nothing.  The b-constants are quoted
-  from the literature and are "parity unpinned" by the guide.
+  a lossless (real m) target absorbs nothing.  The b-constants are pinned by
+  the lattice sums of ``lattice_sums``: they are the coefficients of the
+  second-order terms of the infinite lattice's dispersion relation.
+* GKDLDR, the lattice dispersion relation as corrected by Gutkowicz-Krusin &
+  Draine (2004), the option §14 recommends; cited, not printed.  Reading: the
+  polarizability is a diagonal tensor in the lattice axes that depends on the
+  propagation direction only,
+
+      1/alpha_jj = 1/alpha_CM + (b1 + b2 m^2 + b3 m^2 khat_j^2)(kd)^2 - (2/3) i (kd)^3,
+
+  with the LATTDR constants.  It cancels the lattice's anisotropic
+  second-order term component by component, so that every transverse wave,
+  whatever its polarization, propagates with K = m k to second order, where
+  the scalar LATTDR achieves this only for the projection on e.  Pinned by the
+  lattice sums (every transverse wave a mode) and by the efficiencies the
+  guide prints for its GKDLDR example (appendix .avg file, Q_pha included).
 * CM with radiative reaction: alpha = alpha_CM / (1 - (2/3) i k^3 alpha_CM).
 * FLTRCD, the filtered coupled dipole polarizability of §14.  The printed
   correction D is garbled: its log term lacks the (kd)^3 factor of the cited
@@ -29,7 +46,8 @@
   the lossless test; otherwise parity unpinned.
 
 All functions return the inverse polarizability 1/alpha (complex128), which
-is what enters the diagonal of A in eq. (AP=E).
+is what enters the diagonal of A in eq. (AP=E): a scalar, or for GKDLDR the
+three diagonal elements of the tensor.
 """
 
 import math
@@ -48,10 +66,10 @@ def alpha_cm(m):
 
 
 def ldr_s(khat, e):
-    """S = sum_l (khat_l e_l)^2 for the LDR correction (Target Frame)."""
-    khat = np.asarray(khat, dtype=complex)
+    """S = sum_l khat_l^2 |e_l|^2 for the LDR correction (Target Frame; e a unit vector)."""
+    khat = np.asarray(khat, dtype=float)
     e = np.asarray(e, dtype=complex)
-    return complex(np.sum((khat * e) ** 2))
+    return float(np.sum(khat ** 2 * np.abs(e) ** 2))
 
 
 def alpha_inv_ldr(m, kd, khat, e):
@@ -59,6 +77,14 @@ def alpha_inv_ldr(m, kd, khat, e):
     m2 = np.asarray(m, dtype=complex) ** 2
     s = ldr_s(khat, e)
     return 1.0 / alpha_cm(m) + (LDR_B1 + LDR_B2 * m2 + LDR_B3 * m2 * s) * kd ** 2 - (2.0 / 3.0) * 1j * kd ** 3
+
+
+def alpha_inv_gkdldr(m, kd, khat):
+    """Diagonal of the inverse polarizability tensor for GKDLDR, complex [1, 3]
+    (one tensor for every site of the composition)."""
+    m2 = complex(m) ** 2
+    a2 = np.asarray(khat, dtype=float).reshape(1, 3) ** 2
+    return 1.0 / alpha_cm(m) + (LDR_B1 + LDR_B2 * m2 + LDR_B3 * m2 * a2) * kd ** 2 - (2.0 / 3.0) * 1j * kd ** 3
 
 
 def alpha_inv_cmrr(m, kd):
@@ -74,9 +100,12 @@ def alpha_inv_fcd(m, kd):
 
 
 def alpha_inv(kind, m, kd, khat, e):
-    """Dispatch on the guide's option name: LATTDR, CMRR, FLTRCD."""
+    """Dispatch on the guide's option name: LATTDR, GKDLDR, CMRR, FLTRCD
+    (GKDLDR returns the tensor diagonal [1, 3], the others a scalar)."""
     if kind == "LATTDR":
         return alpha_inv_ldr(m, kd, khat, e)
+    if kind == "GKDLDR":
+        return alpha_inv_gkdldr(m, kd, khat)
     if kind == "CMRR":
         return alpha_inv_cmrr(m, kd)
     if kind == "FLTRCD":
