@@ -61,6 +61,7 @@ extern "C" {
 #define DDA_ALPHA_LDR 0       /* LATTDR: lattice dispersion relation (Draine & Goodman 1993) */
 #define DDA_ALPHA_CMRR 1      /* Clausius-Mossotti with radiative reaction */
 #define DDA_ALPHA_FCD 2       /* FLTRCD polarizability (requires kd < pi) */
+#define DDA_ALPHA_GKDLDR 3    /* GKDLDR: lattice dispersion relation of Gutkowicz-Krusin & Draine 2004 */
 
 /* Arithmetic of the FFT product inside the Krylov iteration. */
 #define DDA_FP64 0            /* complex FP64 throughout */
@@ -94,9 +95,24 @@ typedef struct {
   int32_t n_comp;          /* number of compositions, 1..255 */
   const dda_c64 *m;        /* host [n_comp] refractive index relative to the medium (§3.2) */
   double kd;               /* k d > 0 (wavenumber in the medium times lattice spacing) */
-  int32_t alpha_kind;      /* DDA_ALPHA_* */
+  int32_t alpha_kind;      /* DDA_ALPHA_* (below) */
   int32_t device;          /* HIP device ordinal */
 } dda_target_desc;
+
+/* Polarizabilities (§14; d = 1, m the composition's index, kd, and the RHS's
+ * khat, e; alpha_CM = (3/4pi)(m^2-1)/(m^2+2) as printed in §14):
+ *   DDA_ALPHA_LDR     1/alpha = 1/alpha_CM + (b1 + b2 m^2 + b3 m^2 S) kd^2 - (2/3) i kd^3,
+ *                     S = sum_l khat_l^2 |e_l|^2, b1 = -1.891531, b2 = 0.1648469,
+ *                     b3 = -1.7700004 (cited LATTDR; the b's are the second-order
+ *                     coefficients of the dipole lattice's dispersion relation);
+ *   DDA_ALPHA_GKDLDR  a diagonal tensor, 1/alpha_jj = 1/alpha_CM + (b1 + b2 m^2 +
+ *                     b3 m^2 khat_j^2) kd^2 - (2/3) i kd^3 (the corrected lattice
+ *                     dispersion relation §14 recommends, cited: every transverse
+ *                     wave then propagates with K = m k to second order);
+ *   DDA_ALPHA_CMRR    1/alpha = 1/alpha_CM - (2/3) i kd^3;
+ *   DDA_ALPHA_FCD     1/alpha = 1/alpha_CM - [(4/3) kd^2 + (2/(3 pi)) ln((pi - kd)/(pi + kd)) kd^3
+ *                     + (2/3) i kd^3] (the FLTRCD print of §14 read with the
+ *                     kd^3 factor of its source and the radiative sign). */
 
 typedef struct dda_target dda_target;   /* opaque handle; owns its device memory */
 
@@ -336,7 +352,7 @@ int dda_apply(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t precision
  * the handle's workspaces; the call makes no device or pinned allocation and
  * creates no HIP object (the 1/alpha values reach the device as a kernel
  * argument).
- * Limits: nrhs * n_comp <= 64, and the work buffers of nrhs products,
+ * Limits: nrhs * n_comp <= 32, and the work buffers of nrhs products,
  * nrhs * (3 nz nxt ny W + My nxt 3 nz W) * (8 B DDA_MIXED, 16 B DDA_FP64) with
  * W = 16 (MIXED) or 8 (FP64) and nxt = ceil(Mx / W), plus 4 KiB must fit in
  * DDA_NOALLOC_SCRATCH_BYTES (a 64^3 block: 37.7 MB per RHS MIXED, 75.5 MB

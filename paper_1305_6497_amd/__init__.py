@@ -24,7 +24,7 @@ from ._lib import DDAError  # noqa: F401
 
 SHAPES = {"ELLIPSOID": L.DDA_SHAPE_ELLIPSOID, "RCTGLPRSM": L.DDA_SHAPE_RCTGLPRSM,
           "CYLINDER1": L.DDA_SHAPE_CYLINDER1, "HEX_PRISM": L.DDA_SHAPE_HEX_PRISM}
-ALPHA = {"LATTDR": L.DDA_ALPHA_LDR, "LDR": L.DDA_ALPHA_LDR, "CMRR": L.DDA_ALPHA_CMRR,
+ALPHA = {"LATTDR": L.DDA_ALPHA_LDR, "LDR": L.DDA_ALPHA_LDR, "GKDLDR": L.DDA_ALPHA_GKDLDR, "CMRR": L.DDA_ALPHA_CMRR,
          "FLTRCD": L.DDA_ALPHA_FCD, "FCD": L.DDA_ALPHA_FCD}
 SOLVER = {"bicgstab": 0, "bicgstab2": 1, "cocg": 2, "qmr": 3}
 PRECISION = {"fp64": L.DDA_FP64, "mixed": L.DDA_MIXED}

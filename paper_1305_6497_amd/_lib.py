@@ -17,6 +17,7 @@ DDA_WVALIDITY = 2
 DDA_ALPHA_LDR = 0
 DDA_ALPHA_CMRR = 1
 DDA_ALPHA_FCD = 2
+DDA_ALPHA_GKDLDR = 3
 
 DDA_FP64 = 0
 DDA_MIXED = 1

@@ -194,7 +194,8 @@ void validate_desc(const dda_target_desc *d, bool need_sites) {
   DDA_REQUIRE(d->n_comp >= 1 && d->n_comp <= 255, "n_comp must be in 1..255");
   DDA_REQUIRE(d->m != nullptr, "m is NULL");
   DDA_REQUIRE(std::isfinite(d->kd) && d->kd > 0.0, "kd must be finite and > 0");
-  DDA_REQUIRE(d->alpha_kind == DDA_ALPHA_LDR || d->alpha_kind == DDA_ALPHA_CMRR || d->alpha_kind == DDA_ALPHA_FCD,
+  DDA_REQUIRE(d->alpha_kind == DDA_ALPHA_LDR || d->alpha_kind == DDA_ALPHA_CMRR || d->alpha_kind == DDA_ALPHA_FCD ||
+                  d->alpha_kind == DDA_ALPHA_GKDLDR,
               "unknown alpha_kind");
   if (d->alpha_kind == DDA_ALPHA_FCD) DDA_REQUIRE(d->kd < 3.14159265358979323846, "FCD requires kd < pi");
   for (int c = 0; c < d->n_comp; ++c) {
@@ -245,7 +246,7 @@ size_t krylov_bytes(const Geometry &g, int nrhs) {
   const int nblk = std::max(krylov_blocks(n3), std::max(xpass_blocks(g, true), xpass_blocks(g, false)));
   return 9 * vec + 2 * (size_t)nrhs * nblk * kPart * sizeof(double) + (size_t)nrhs * kScal * sizeof(c64) +
          4 * (size_t)nrhs * sizeof(int) + (size_t)nrhs * (sizeof(RhsDev) + 2 * sizeof(double)) +
-         (size_t)nrhs * 255 * sizeof(c64);
+         (size_t)nrhs * 255 * 3 * sizeof(c64);
 }
 
 // Workspaces grow on demand.  Work already queued on s may still use the old
@@ -310,7 +311,7 @@ void ensure_krylov(dda_target *t, int nrhs, hipStream_t s) {
   k.status = t->alloc<int>(nrhs * sizeof(int));
   k.check = t->alloc<int>(nrhs * sizeof(int));
   t->d_restart = t->alloc<int>(nrhs * sizeof(int));
-  t->d_ainv = t->alloc<c64>((size_t)nrhs * t->ncomp * sizeof(c64));
+  t->d_ainv = t->alloc<c64>((size_t)nrhs * t->ncomp * 3 * sizeof(c64));
   t->d_rhs = t->alloc<RhsDev>(nrhs * sizeof(RhsDev));
   t->d_sums = t->alloc<double>(3 * nrhs * sizeof(double));
   t->kr_nrhs = nrhs;
@@ -339,10 +340,11 @@ void check_rhs(const dda_rhs &q, RhsDev &rd) {
 void prepare_rhs(dda_target *t, const dda_rhs *rhs, int nrhs, std::vector<RhsDev> &rd, std::vector<c64> &ainv) {
   DDA_REQUIRE(rhs != nullptr, "rhs is NULL");
   rd.resize(nrhs);
-  ainv.resize((size_t)nrhs * t->ncomp);
+  ainv.resize((size_t)nrhs * t->ncomp * 3);
   for (int r = 0; r < nrhs; ++r) {
     check_rhs(rhs[r], rd[r]);
-    for (int c = 0; c < t->ncomp; ++c) ainv[(size_t)r * t->ncomp + c] = alpha_inverse(t->alpha_kind, t->m[c], t->kd, rd[r].khat, rd[r].e);
+    for (int c = 0; c < t->ncomp; ++c)
+      alpha_inverse(t->alpha_kind, t->m[c], t->kd, rd[r].khat, rd[r].e, &ainv[((size_t)r * t->ncomp + c) * 3]);
   }
 }
 
@@ -576,7 +578,8 @@ void run_iterations(dda_target *t, int precision, int solver, int K, bool use_gr
 // dda_apply_noalloc keeps its work buffers in one static device array per GPU
 // (the loader places it with the code object; it lives until the process
 // ends): the per-RHS 1/alpha values first, then the two FFT work buffers.
-constexpr int kNoAllocMaxAinv = 64;                 // nrhs * n_comp per call
+constexpr int kNoAllocMaxRhsComp = 32;              // nrhs * n_comp per call
+constexpr int kNoAllocMaxAinv = 3 * kNoAllocMaxRhsComp;   // tensor diagonals
 constexpr size_t kNoAllocAinvBytes = 4096;          // >= kNoAllocMaxAinv * 16, keeps A 256-byte aligned
 constexpr int kMaxDevices = 64;
 
@@ -855,7 +858,7 @@ int dda_apply_noalloc(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t p
     DDA_REQUIRE(p_dev != ap_dev, "p_dev and ap_dev must not alias");
     DDA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
     DDA_REQUIRE(precision == DDA_FP64 || precision == DDA_MIXED, "unknown precision");
-    DDA_REQUIRE((int64_t)nrhs * t->ncomp <= kNoAllocMaxAinv, "nrhs * n_comp exceeds 64 (allocation-free product)");
+    DDA_REQUIRE((int64_t)nrhs * t->ncomp <= kNoAllocMaxRhsComp, "nrhs * n_comp exceeds 32 (allocation-free product)");
     const bool f32 = precision == DDA_MIXED;
     const size_t cs = f32 ? sizeof(c32) : sizeof(c64);
     const size_t a = t->g.a_elems(f32) * cs * nrhs;
@@ -867,11 +870,12 @@ int dda_apply_noalloc(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t p
                                    "more than the " + std::to_string((size_t)DDA_NOALLOC_SCRATCH_BYTES) +
                                    " available (fewer RHS, or dda_apply)"};
     AinvArg av{};
-    av.n = nrhs * t->ncomp;
+    av.n = 3 * nrhs * t->ncomp;
     for (int r = 0; r < nrhs; ++r) {
       RhsDev rd;
       check_rhs(rhs[r], rd);
-      for (int c = 0; c < t->ncomp; ++c) av.v[r * t->ncomp + c] = alpha_inverse(t->alpha_kind, t->m[c], t->kd, rd.khat, rd.e);
+      for (int c = 0; c < t->ncomp; ++c)
+        alpha_inverse(t->alpha_kind, t->m[c], t->kd, rd.khat, rd.e, &av.v[3 * (r * t->ncomp + c)]);
     }
     DDA_HIP(hipSetDevice(t->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -879,7 +883,7 @@ int dda_apply_noalloc(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t p
     c64 *d_ainv = reinterpret_cast<c64 *>(base);
     void *bufA = base + kNoAllocAinvBytes;
     void *bufB = base + kNoAllocAinvBytes + a_pad;
-    hipLaunchKernelGGL(k_fill_ainv, dim3(1), dim3(kNoAllocMaxAinv), 0, s, d_ainv, av);
+    hipLaunchKernelGGL(k_fill_ainv, dim3(1), dim3(128), 0, s, d_ainv, av);
     DDA_HIP(hipGetLastError());
     matvec_on(t, precision, static_cast<const c64 *>(p_dev), static_cast<c64 *>(ap_dev), nrhs, nullptr, d_ainv, bufA,
               bufB, s);

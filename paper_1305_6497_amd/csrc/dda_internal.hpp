@@ -174,7 +174,7 @@ struct MatvecArgs {
   c64 *out;
   int nrhs;
   const int *mask;                // device [nrhs] (nonzero = process) or nullptr
-  const c64 *ainv;                // device [nrhs][ncomp]
+  const c64 *ainv;                // device [nrhs][ncomp][3]: diagonal of 1/alpha per composition
   int ncomp;
   const uint8_t *comp;            // device [N] or nullptr
   const int *cell_site;           // device [nz][ny][nx], -1 = empty
@@ -283,7 +283,8 @@ void k_restart(const KrylovState &k, const int *restart, double tol, double inne
 
 void launch_incident(const Geometry &g, const int32_t *ijk, const RhsDev *rhs, int nrhs, double kd,
                      c64 *e, hipStream_t s);
-// Sums per RHS: [0] = sum Im(conj(E) . P), [1] = sum (-Im(ainv) - (2/3) kd^3) |P|^2
+// Sums per RHS: [0] = sum Im(conj(E) . P), [1] = sum_c (-Im(ainv_c) - (2/3) kd^3) |P_c|^2
+// (ainv [nrhs][ncomp][3])
 void launch_cross_sums(const Geometry &g, const int32_t *ijk, const RhsDev *rhs, int nrhs, double kd,
                        const c64 *P, const c64 *ainv, int ncomp, const uint8_t *comp, double *partial,
                        double *sums, hipStream_t s);
@@ -326,6 +327,8 @@ void orient_rhs(double beta, double theta, double phi, const c64 e01[3], int whi
 // (end points included), midpoints with equal weights for even n.
 void periodic_rule(double lo, double hi, int n, std::vector<double> &x, std::vector<double> &w);
 void cos_theta_rule(double lo, double hi, int n, std::vector<double> &theta, std::vector<double> &w);
-c64 alpha_inverse(int kind, c64 m, double kd, const double khat[3], const c64 e[3]);
+// Diagonal of the inverse polarizability tensor (a multiple of I except for
+// GKDLDR) of one composition for one RHS.
+void alpha_inverse(int kind, c64 m, double kd, const double khat[3], const c64 e[3], c64 out[3]);
 
 }  // namespace dda

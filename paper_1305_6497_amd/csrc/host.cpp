@@ -230,29 +230,31 @@ void orient_rhs(double beta, double theta, double phi, const c64 e01[3], int whi
 // FLTRCD (reading of the garbled print: kd^3 on the log term, sign such that
 // a lossless target does not absorb):
 //   1/alpha = 1/alpha_CM - [(4/3) kd^2 + (2/(3 pi)) ln((pi-kd)/(pi+kd)) kd^3 + (2/3) i kd^3].
-c64 alpha_inverse(int kind, c64 mc, double kd, const double khat[3], const c64 e[3]) {
+void alpha_inverse(int kind, c64 mc, double kd, const double khat[3], const c64 e[3], c64 out[3]) {
   using C = std::complex<double>;
   const C m(mc.x, mc.y);
   const C m2 = m * m;
   const double pi = 3.14159265358979323846;
   const C acm_inv = (4.0 * pi / 3.0) * (m2 + 2.0) / (m2 - 1.0);
   const double k2 = kd * kd, k3 = kd * kd * kd;
-  C r;
+  const double b1 = -1.891531, b2 = 0.1648469, b3 = -1.7700004;
+  C r[3];
   if (kind == DDA_ALPHA_LDR) {
-    const double b1 = -1.891531, b2 = 0.1648469, b3 = -1.7700004;
-    C S = 0.0;
-    for (int l = 0; l < 3; ++l) {
-      const C ke = khat[l] * C(e[l].x, e[l].y);
-      S += ke * ke;
-    }
-    r = acm_inv + (b1 + b2 * m2 + b3 * m2 * S) * k2 - C(0.0, 2.0 / 3.0) * k3;
+    double S = 0.0;                       // sum_l khat_l^2 |e_l|^2
+    for (int l = 0; l < 3; ++l) S += khat[l] * khat[l] * (e[l].x * e[l].x + e[l].y * e[l].y);
+    r[0] = acm_inv + (b1 + b2 * m2 + b3 * m2 * S) * k2 - C(0.0, 2.0 / 3.0) * k3;
+    r[1] = r[2] = r[0];
+  } else if (kind == DDA_ALPHA_GKDLDR) {
+    for (int l = 0; l < 3; ++l)
+      r[l] = acm_inv + (b1 + b2 * m2 + b3 * m2 * (khat[l] * khat[l])) * k2 - C(0.0, 2.0 / 3.0) * k3;
   } else if (kind == DDA_ALPHA_CMRR) {
-    r = acm_inv - C(0.0, 2.0 / 3.0) * k3;
+    r[0] = r[1] = r[2] = acm_inv - C(0.0, 2.0 / 3.0) * k3;
   } else {
     const double lg = std::log((pi - kd) / (pi + kd));
-    r = acm_inv - ((4.0 / 3.0) * k2 + (2.0 / (3.0 * pi)) * lg * k3 + C(0.0, 2.0 / 3.0) * k3);
+    r[0] = acm_inv - ((4.0 / 3.0) * k2 + (2.0 / (3.0 * pi)) * lg * k3 + C(0.0, 2.0 / 3.0) * k3);
+    r[1] = r[2] = r[0];
   }
-  return c64{r.real(), r.imag()};
+  for (int l = 0; l < 3; ++l) out[l] = c64{r[l].real(), r[l].imag()};
 }
 
 // --------------------------------------------------------------- FFT plans --

@@ -584,7 +584,7 @@ void launch_incident(const Geometry &g, const int32_t *ijk, const RhsDev *rhs, i
 }
 
 // --------------------------------------------------------- cross sections --
-// per site: Im(conj(E_j) . P_j)  and  (-Im(ainv_j) - (2/3) kd^3) |P_j|^2
+// per site: Im(conj(E_j) . P_j)  and  sum_c (-Im(ainv_jc) - (2/3) kd^3) |P_jc|^2
 __global__ void kk_cross(const int32_t *ijk, int64_t n, const RhsDev *rhs, double kd, const c64 *P, const c64 *ainv,
                          int ncomp, const uint8_t *comp, double *partial, int nblk) {
   const int r = blockIdx.y;
@@ -597,17 +597,15 @@ __global__ void kk_cross(const int32_t *ijk, int64_t n, const RhsDev *rhs, doubl
     sincos(ph, &sn, &cs);
     const c64 w = {cs, sn};
     const c64 *pj = P + ((size_t)r * n + j) * 3;
-    const c64 ai = ainv[(size_t)r * ncomp + (comp ? comp[j] : 0)];
-    double p2 = 0.0;
+    const c64 *ai = ainv + ((size_t)r * ncomp + (comp ? comp[j] : 0)) * 3;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const c64 ec = w * R.e[c];
       const c64 pc = pj[c];
       acc[0] += ec.x * pc.y - ec.y * pc.x;        // Im(conj(E) P)
       acc[2] += ec.x * pc.x + ec.y * pc.y;        // Re(conj(E) P)
-      p2 += pc.x * pc.x + pc.y * pc.y;
+      acc[1] += (-ai[c].y - rr) * (pc.x * pc.x + pc.y * pc.y);
     }
-    acc[1] += (-ai.y - rr) * p2;
   }
   double out[3];
   block_sum<3>(acc, out);

@@ -693,7 +693,7 @@ __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *_
   __syncthreads();
   fft_rows<T, EPT, +1, LC>(buf, tw, px, 3 * nrows);
   const size_t off = (size_t)r * n3;
-  const c64 *ai = ainv + (size_t)r * ncomp;
+  const c64 *ai = ainv + (size_t)r * ncomp * 3;      // [ncomp][3] of this RHS
   double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   // out = ainv P - (G P) at one element; x is rh (out_mode 1) or r0 (out_mode 3)
   auto finish = [&](size_t j, c64 a, c64 pv, cpx<T> fv, c64 x) {
@@ -742,7 +742,8 @@ __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *_
         if (e < n) {
           pv[i] = in[j0 + e];
           xv[i] = xsrc ? xsrc[j0 + e] : c64{0, 0};
-          av[i] = ai[comp ? comp[rr.first + e / 3] : 0];
+          const int st = e / 3;
+          av[i] = ai[(comp ? 3 * comp[rr.first + st] : 0) + (e - 3 * st)];
         }
       }
 #pragma unroll
@@ -779,11 +780,11 @@ __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *_
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
       if (site[i] >= 0) {
-        const c64 a = ai[comp ? comp[site[i]] : 0];
+        const c64 *a = ai + (comp ? 3 * comp[site[i]] : 0);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const size_t j = off + (size_t)3 * site[i] + c;
-          finish(j, a, pv[i][c], buf[c * ne + bi[i]], xsrc ? xsrc[j] : c64{0, 0});
+          finish(j, a[c], pv[i][c], buf[c * ne + bi[i]], xsrc ? xsrc[j] : c64{0, 0});
         }
       }
     }

@@ -188,6 +188,28 @@ def test_matvec_multi_composition(dda):
     assert _rel(out, ref) < 1e-12
 
 
+@pytest.mark.parametrize("alpha", ["GKDLDR", "LATTDR"])
+def test_matvec_multi_composition_tensor_polarizability(dda, alpha):
+    # three compositions and an oblique incidence: GKDLDR's diagonal tensor
+    # differs per component, LATTDR's scalar depends on the polarization
+    sites, box = dda.make_sites("ELLIPSOID", (12, 10, 9))
+    comp = (np.arange(len(sites)) % 3).astype(np.uint8)
+    ms = [1.5 + 0.1j, 1.33 + 0.0j, 2.0 + 0.5j]
+    kd = 0.3
+    b, th, ph = inputs.orientation_angles(2, seed=11)
+    rhs = [dda.orient_rhs(b[i], th[i], ph[i], which=1 + i) for i in range(2)]
+    t = dda.Target(sites, box, m=ms, kd=kd, comp=comp, alpha=alpha)
+    P = inputs.random_polarization(len(sites), 2, seed=9)
+    for prec, tol in (("fp64", 1e-12), ("mixed", 5e-6)):
+        out = t.apply(rhs, torch.tensor(P, device="cuda"), prec).cpu().numpy()
+        for r in range(2):
+            ai = np.array([np.broadcast_to(polarizability.alpha_inv(alpha, mm, kd, *rhs[r]), (1, 3))[0]
+                           for mm in ms])[comp]
+            ref = interaction.direct_matvec(targets.ellipsoid(12, 10, 9), kd, ai, P[r])
+            assert _rel(out[r], ref) < tol, (alpha, prec, r)
+    t.close()
+
+
 def test_incident_field(dda):
     sites, box = dda.make_sites("ELLIPSOID", (15, 12, 9))
     kd = 0.37
@@ -204,7 +226,7 @@ def test_incident_field(dda):
 # ------------------------------------------------------------------ solves --
 @pytest.mark.parametrize("solver", SOLVERS)
 @pytest.mark.parametrize("m,alpha", [(1.33 + 0.01j, "LATTDR"), (1.7 + 0.3j, "LATTDR"), (2.5 + 0.5j, "CMRR"),
-                                     (1.5 + 0.0j, "FLTRCD")])
+                                     (1.5 + 0.0j, "FLTRCD"), (1.7 + 0.3j, "GKDLDR")])
 def test_solve_matches_dense_lu(dda, m, alpha, solver):
     shpar = (9.5, 8.0, 6.5)
     sites, box = dda.make_sites("ELLIPSOID", shpar)
@@ -653,19 +675,25 @@ def test_scattering_matrix_matches_oracle(dda, shape, shpar, angles):
     assert _rel(M, Mo) < 1e-12
 
 
-def test_scattering_matrix_au_block_matches_printed(dda):
-    # GPU solve (FP64) of the printed Au block and its Mueller matrix in the
-    # printed directions: the oracle pin's tolerances (LDR against the printed
-    # GKDLDR run), and the optical theorem against the GPU cross sections.
+@pytest.mark.parametrize("solver", ["bicgstab2", "cocg"])
+def test_scattering_matrix_au_block_matches_printed(dda, solver):
+    # GPU solve (FP64, GKDLDR as printed) of the printed Au block: the printed
+    # efficiencies at their digits (one unit of the last printed digit; the
+    # printed run stopped at TOL 1e-5), Q_bk to 1e-4, the printed Mueller
+    # table (S_11 and S_12 to 2e-4 of S_11, P to 1e-4), the optical theorem
+    # against the GPU cross sections, and g, <cos^2> within the 0.5% that the
+    # printing program's own angular sampling leaves.
     import json
     import os
     fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "au_block_mueller.json")))
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_printed.json")) as fh:
+        pr = json.load(fh)["au_block_example"]
     sites, box = dda.make_sites("RCTGLPRSM", fx["box"])
     kd, m = fx["kd"], complex(*fx["m"])
     lab = np.eye(3)
     rhs = [(lab[0], np.array([0, 1.0, 0])), (lab[0], np.array([0, 0, 1.0]))]
-    t = dda.Target(sites, box, m=m, kd=kd)
-    P, st = t.solve(rhs, tol=1e-7, precision="fp64")
+    t = dda.Target(sites, box, m=m, kd=kd, alpha="GKDLDR")
+    P, st = t.solve(rhs, tol=1e-8, precision="fp64", solver=solver)
     assert all(x["status"] == 0 for x in st)
     rows = np.array(fx["rows"])
     tp = np.radians(rows[:, :2])
@@ -678,22 +706,18 @@ def test_scattering_matrix_au_block_matches_printed(dda):
     assert abs(4 * np.pi / kd ** 2 * S0[1].real / (np.pi * aeff ** 2) - q[0]["qext"]) < 1e-10 * q[0]["qext"]
     assert abs(4 * np.pi / kd ** 2 * S0[0].real / (np.pi * aeff ** 2) - q[1]["qext"]) < 1e-10 * q[1]["qext"]
     M = M[:-1]
-    rel = np.abs(M[:, 0, 0] / rows[:, 3] - 1)
-    off_min = (rows[:, 0] < 40) | (rows[:, 0] > 75)
-    assert rel.max() < 0.06 and rel[off_min].max() < 0.02
+    assert np.abs(M[:, 0, 0] / rows[:, 3] - 1).max() < 2e-4
     pol_ = np.sqrt(M[:, 1, 0] ** 2 + M[:, 2, 0] ** 2) / M[:, 0, 0]
-    assert np.abs(pol_ - rows[:, 2]).max() < 0.05
-    assert np.all(np.abs(M[:, 0, 1] - rows[:, 4]) < 0.1 * rows[:, 3])
-    # the printed efficiencies: Q_ext, Q_abs, Q_sca within 1%, Q_bk within 2%
-    # and Q_pha within 15% with its sign (the oracle pin's LDR-vs-GKDLDR
-    # tolerances)
-    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_printed.json")) as fh:
-        pr = json.load(fh)["au_block_example"]
+    assert np.abs(pol_ - rows[:, 2]).max() < 1e-4
+    assert np.all(np.abs(M[:, 0, 1] - rows[:, 4]) < 2e-4 * rows[:, 3])
     for i in range(2):
         for key in ("qext", "qabs", "qsca"):
-            assert abs(q[i][key] / pr[key] - 1) < 0.01, (i, key)
-        assert far[i]["qbk"] > 0 and abs(far[i]["qbk"] / pr["qbk"] - 1) < 0.02
-        assert q[i]["qpha"] < 0 and abs(q[i]["qpha"] / pr["qpha"] - 1) < 0.15
+            assert abs(q[i][key] - pr[key]) <= 1e-4, (i, key, q[i][key])
+        assert abs(q[i]["qpha"] - pr["qpha"]) <= 1e-5, (i, q[i]["qpha"])
+        assert abs(far[i]["qbk"] / pr["qbk"] - 1) < 1e-4, (i, far[i]["qbk"])
+    g = 0.5 * (far[0]["g"] + far[1]["g"])
+    c2 = 0.5 * (far[0]["cos2"] + far[1]["cos2"])
+    assert abs(g / fx["g"] - 1) < 0.005 and abs(c2 / fx["cos2"] - 1) < 0.005
 
 
 def test_scattering_matrix_errors(dda):

@@ -69,8 +69,8 @@ def test_noalloc_rejects_sizes_beyond_the_scratch():
     assert torch.equal(out[:1], ref)
     t.close()
     t, n = _setup(dda, "RCTGLPRSM", (6, 6, 6), 1.5 + 0.1j, 1.0)
-    rhs = [dda.orient_rhs(0.0, 0.0, 0.0, which=1)] * 65
-    P = torch.zeros((65, n, 3), dtype=torch.complex128, device="cuda")
-    with pytest.raises(dda.DDAError):                      # nrhs * n_comp > 64
+    rhs = [dda.orient_rhs(0.0, 0.0, 0.0, which=1)] * 33
+    P = torch.zeros((33, n, 3), dtype=torch.complex128, device="cuda")
+    with pytest.raises(dda.DDAError):                      # nrhs * n_comp > 32
         t.apply_noalloc(rhs, P, torch.zeros_like(P), "mixed")
     t.close()
