@@ -30,3 +30,55 @@ def test_results_identical_alone_and_in_the_mix():
             assert all(s["status"] == 0 for s in a.stats + b.stats)
             for qa, qb in zip(a.q, b.q):
                 assert qa == qb, (rep, r.id, qa, qb)   # bit-identical: deterministic reductions, private buffers
+
+
+def _oracle_q(req, tol=1e-10):
+    # the FP64 oracle's efficiencies of one request, both polarizations
+    import numpy as np
+
+    from oracle import cross_sections, incident, interaction, polarizability, solvers, targets
+    sites = targets.make(req.shape, req.shpar)
+    kd = targets.kd_from_x(req.x, len(sites))
+    out = []
+    for e in (np.array([0.0, 1.0, 0.0]), np.array([0.0, 0.0, 1.0])):
+        khat = np.array([1.0, 0.0, 0.0])
+        ai = polarizability.alpha_inv_ldr(req.m, kd, khat, e)
+        E = incident.incident_field(sites, kd, khat, e)
+        P, info = solvers.bicgstab(interaction.FFTOperator(sites, kd, ai).matvec, E, tol=tol, maxiter=20000)
+        assert info["converged"]
+        out.append(cross_sections.efficiencies(len(sites), kd, E, ai, P))
+    return out
+
+
+def test_served_results_match_oracle_solves():
+    # A few requests of the mix's shapes served concurrently (mixed precision,
+    # tol 1e-7), each result against the FP64 oracle's solve of the same
+    # request to 1e-10: within 1e-5 of Q_ext.  The same requests are then
+    # served with an iteration budget that stops COCG about halfway for the
+    # slowest one, so it goes through the BiCGstab(2) continuation, and must
+    # give the same efficiencies.
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1305_6497_amd.serving import GpuExecutor, Request, Server
+    reqs = [Request(id=0, arrival=0.0, shape="CYLINDER1", shpar=(14, 10, 1), m=1.6 + 0.05j, x=3.0),
+            Request(id=1, arrival=0.002, shape="HEX_PRISM", shpar=(12, 13, 1), m=1.4 + 0.2j, x=2.5),
+            Request(id=2, arrival=0.004, shape="ELLIPSOID", shpar=(14, 11, 9), m=2.0 + 0.3j, x=2.0),
+            Request(id=3, arrival=0.006, shape="ELLIPSOID", shpar=(13, 13, 13), m=1.9 + 0.01j, x=3.3)]
+    ref = {r.id: _oracle_q(r) for r in reqs}
+
+    def check(res, label):
+        for r in reqs:
+            x = res[r.id]
+            assert not x.error and all(s["status"] == 0 for s in x.stats), (label, r.id, x.error, x.stats)
+            for qg, qo in zip(x.q, ref[r.id]):
+                for key in ("qext", "qabs", "qsca"):
+                    assert abs(qg[key] - qo[key]) <= 1e-5 * qo["qext"], (label, r.id, key, qg[key], qo[key])
+
+    res = Server(GpuExecutor(tol=1e-7), slots=4).run(reqs)
+    check(res, "cocg")
+    slowest = max(reqs, key=lambda r: max(s["iters"] for s in res[r.id].stats))
+    need = max(s["iters"] for s in res[slowest.id].stats)
+    assert need >= 40, need
+    res2 = Server(GpuExecutor(tol=1e-7, max_iter=need // 4), slots=4).run(reqs)
+    check(res2, "fallback")
+    assert any(s.get("fallback_from") == "cocg" for s in res2[slowest.id].stats)
