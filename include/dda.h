@@ -186,6 +186,9 @@ typedef struct {
   int64_t n_sites;
   double kd, aeff;
   uint64_t device_bytes;   /* device memory currently held by the handle */
+  int32_t zpass_variant[2];/* radix-plan variant of the z-pass (0..3) in DDA_MIXED [0] and DDA_FP64
+                              [1]: the autotuner's measured choice for Mz, or the one forced by
+                              dda_set_zpass_variant; 0 is the cost model's plan */
 } dda_target_info;
 
 /* ---- target geometry (host arithmetic) ------------------------------- */
@@ -246,6 +249,27 @@ int dda_footprint_bytes(const dda_target_desc *desc, int32_t nrhs,
                         const dda_solve_opts *opts, uint64_t *bytes);
 
 int dda_target_get_info(const dda_target *t, dda_target_info *info);
+
+/* Plan autotuning (§13 "Choice of FFT Algorithm": the guide picks among FFT
+ * implementations; here the choice is among radix plans of one transform
+ * length).  Forces the radix plan of the z-pass for this handle: 0 the cost
+ * model's plan (fewest LDS stages, then fewest flops, largest radix first,
+ * radices bounded so that at least half the threads of a block hold a
+ * butterfly), 1 the same with radices up to 16 whatever that bound, 2 the
+ * cheapest plan with one stage more than 0, 3 the radices of 0 smallest
+ * first; -1 restores the measured
+ * choice of the built-in table (written by autotune.py; variant 0 for
+ * lengths it has not timed).  Variants exist for compile-time lengths of 96
+ * and above; others always use variant 0.  Results of every variant agree to
+ * rounding.  Errors: DDA_EINVAL (NULL, variant out of range). */
+int dda_set_zpass_variant(dda_target *t, int32_t variant);
+
+/* The radices, in execution order, of z-pass plan `variant` for the
+ * compile-time length L in `precision` (zeros after the last); returns the
+ * number of stages, or a negative DDA_E* code (L not 2/3/5-smooth or above
+ * 512, variant not 0..3).  Lengths without a compile-time plan use the
+ * run-time radix-8/4/2/5/3 plan in the product instead. */
+int dda_zpass_plan(int32_t L, int32_t precision, int32_t variant, int32_t radices[8]);
 
 /* Solve A P = E for nrhs right-hand sides as one block (shared FFT grid and
  * Green transform, per-RHS polarizabilities, scalars and convergence).

@@ -108,6 +108,13 @@ def fft_pencils(x, sign=-1, scale=1.0, stream=None):
     return out
 
 
+def zpass_plan(length, precision="mixed", variant=0):
+    """Radices (execution order) of z-pass plan `variant` for a padded length."""
+    r = (ctypes.c_int32 * 8)()
+    n = L.check(L.lib().dda_zpass_plan(int(length), PRECISION[precision], int(variant), r), ok=tuple(range(9)))
+    return [r[i] for i in range(n)]
+
+
 def footprint_bytes(box, n_sites, m=1.5, kd=0.5, nrhs=1, alpha="LATTDR"):
     """Device bytes a target and a solve of nrhs right-hand sides would hold."""
     mlist = m if isinstance(m, (list, tuple)) else [m]
@@ -174,7 +181,12 @@ class Target:
         i = L.TargetInfo()
         L.check(self._lib.dda_target_get_info(self._h, ctypes.byref(i)))
         return dict(box=tuple(i.box), grid=tuple(i.grid), n_sites=i.n_sites, kd=i.kd, aeff=i.aeff,
-                    device_bytes=i.device_bytes)
+                    device_bytes=i.device_bytes, zpass_variant=dict(mixed=i.zpass_variant[0],
+                                                                    fp64=i.zpass_variant[1]))
+
+    def set_zpass_variant(self, variant):
+        """Force the z-pass radix-plan variant (0..3), or -1 for the tuned table's."""
+        L.check(self._lib.dda_set_zpass_variant(self._h, int(variant)))
 
     def _vec(self, nrhs):
         import torch

@@ -25,6 +25,7 @@ SOURCES = {
     "api.hip": [],
     "host.cpp": ["-ffp-contract=off"],
     "devmem.cpp": [],
+    "tuned.cpp": [],
 }
 
 

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "dda_internal.hpp"
+#include "fft_lds.hpp"
 #include "nearfield.hpp"
 #include "reduce.hpp"
 
@@ -70,6 +71,8 @@ struct dda_target {
   // scalar (alpha, omega) to the consuming kernel, which computes it in every
   // block; larger ones get a one-block kernel first (set by each solve)
   int fold_records = kFoldRecords;
+  // z-pass plan variant forced by dda_set_zpass_variant (-1: the tuned table's)
+  int zvar = -1;
   uint64_t graph_gen = 0;
   uint64_t buffer_gen = 0;        // bumped whenever workspaces are reallocated
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -378,6 +381,7 @@ void matvec_on(dda_target *t, int precision, const c64 *in, c64 *out, int nrhs, 
   a.px = t->px;
   a.py = t->py;
   a.pz = t->pz;
+  a.zvar = t->zvar;
   if (precision == DDA_MIXED) {
     a.ghat = t->d_ghat32;
     a.twx = t->tx.d32;
@@ -807,11 +811,38 @@ int dda_target_get_info(const dda_target *t, dda_target_info *info) {
     info->kd = t->kd;
     info->aeff = t->aeff;
     info->device_bytes = t->bytes;
+    for (int p = 0; p < 2; ++p)
+      info->zpass_variant[p] = t->zvar >= 0 ? t->zvar : tuned_zpass_variant(t->g.Mz, p == 0);
     return DDA_OK;
   });
 }
 
 void dda_free_target(dda_target *t) { delete t; }
+
+int dda_zpass_plan(int32_t L, int32_t precision, int32_t variant, int32_t radices[8]) {
+  return guarded([&]() -> int {
+    DDA_REQUIRE(radices != nullptr, "NULL argument");
+    DDA_REQUIRE(precision == DDA_FP64 || precision == DDA_MIXED, "unknown precision");
+    DDA_REQUIRE(variant >= 0 && variant < kPlanVariants, "variant must be 0..3");
+    DDA_REQUIRE(L >= 2 && L <= kMaxLen && next_smooth(L) == L, "L must be 2/3/5-smooth and <= 512");
+    // pencils per z-pass block: a 128-byte tile row, halved for long columns
+    const bool f32 = precision == DDA_MIXED;
+    const int logw = f32 ? 4 : 3, half = L * (1 << logw) > (f32 ? 2048 : 1024) ? 1 : 0;
+    const StaticPlan p = plan_variant(L, pen_rmax(L, logw - half), L >= kTunedMinLen ? variant : 0);
+    for (int i = 0; i < 8; ++i) radices[i] = i < p.n ? p.radix[i] : 0;
+    return p.n;
+  });
+}
+
+int dda_set_zpass_variant(dda_target *t, int32_t variant) {
+  return guarded([&]() -> int {
+    DDA_REQUIRE(t != nullptr, "NULL argument");
+    DDA_REQUIRE(variant >= -1 && variant < kPlanVariantsHost, "variant must be -1..3");
+    t->zvar = variant;
+    ++t->buffer_gen;                  // a captured iteration graph holds the old kernels
+    return DDA_OK;
+  });
+}
 
 int dda_incident_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, void *e_dev, void *stream) {
   return guarded([&]() -> int {

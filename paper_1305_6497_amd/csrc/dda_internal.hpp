@@ -187,7 +187,15 @@ struct MatvecArgs {
   const void *twx, *twy, *twz;    // twiddles of the T precision
   AxisPlan px, py, pz;
   FuseArgs fuse;
+  int zvar = -1;                  // z-pass plan variant (0..3), or -1: the tuned table's choice
 };
+
+// Plan variants of the z-pass (plan_variant in fft_lds.hpp) exist for the
+// compile-time lengths from kTunedMinLen up; the autotuner's measured choice
+// per length and precision (zpass_tuned.inc), 0 for lengths it has not timed.
+constexpr int kTunedMinLen = 96;
+constexpr int kPlanVariantsHost = 4;     // = kPlanVariants of fft_lds.hpp
+int tuned_zpass_variant(int L, bool fp32);
 
 // The x passes keep 3 * rows * Mx <= kXBudget elements per block (EPT <= 8):
 // more, lighter blocks keep more loads in flight than few heavy ones.

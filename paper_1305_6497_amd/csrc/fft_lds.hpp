@@ -384,6 +384,65 @@ constexpr StaticPlan static_plan(int L, int rmax = 8) {
   return p;
 }
 
+// The cheapest plan (by the cost model) with exactly n stages.
+constexpr StaticPlan search_plan_n(int L, int rmax, int n) {
+  StaticPlan best{};
+  best.cost = 1e30;
+  if (n == 0) {
+    if (L == 1) best.cost = 0.0;
+    return best;
+  }
+  const int set[11] = {16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
+  for (int i = 0; i < 11; ++i) {
+    const int R = set[i];
+    if (R > rmax || L % R != 0) continue;
+    StaticPlan c = search_plan_n(L / R, rmax, n - 1);
+    if (c.cost >= 1e29) continue;
+    c.radix[c.n++] = R;
+    c.cost += radix_flops(R) + 6.0 * (R - 1) / R;
+    if (c.cost < best.cost) best = c;
+  }
+  return best;
+}
+
+// Radices sorted (largest first, or smallest first) and their Ns filled in.
+constexpr StaticPlan order_plan(StaticPlan p, bool largest_first) {
+  for (int i = 0; i < p.n; ++i)
+    for (int j = i + 1; j < p.n; ++j)
+      if (largest_first ? p.radix[j] > p.radix[i] : p.radix[j] < p.radix[i]) {
+        const int t = p.radix[i];
+        p.radix[i] = p.radix[j];
+        p.radix[j] = t;
+      }
+  int ns = 1;
+  for (int i = 0; i < p.n; ++i) {
+    p.ns[i] = ns;
+    ns *= p.radix[i];
+  }
+  return p;
+}
+
+// Alternative plans of one length, for the plan autotuner:
+//   0  the cost model's plan (static_plan with the caller's radix bound:
+//      fewest stages, then fewest flops, largest radix first),
+//   1  the same with radices up to 16 whatever the bound (fewer LDS stages
+//      at the price of idle threads in the large-radix stages),
+//   2  the cheapest plan with one stage more than 0 (smaller radices, fewer
+//      registers per butterfly), largest radix first,
+//   3  the radices of 0, smallest first.
+// Variant 2 falls back to 0 where no such plan exists.
+constexpr int kPlanVariants = 4;
+
+constexpr StaticPlan plan_variant(int L, int rmax, int V) {
+  const StaticPlan p0 = search_plan(L, rmax);
+  if (V == 1) return order_plan(search_plan(L, 16), true);
+  if (V == 2) {
+    const StaticPlan p2 = p0.n + 1 <= kMaxStages ? search_plan_n(L, rmax, p0.n + 1) : p0;
+    return order_plan(p2.cost < 1e29 ? p2 : p0, true);
+  }
+  return order_plan(p0, V != 3);
+}
+
 // Largest radix of a pen plan over 2^LOGP pencils: a radix-R stage keeps
 // L NPEN / R butterflies, and at least half the threads should get one.
 constexpr int pen_rmax(int L, int LOGP) {
@@ -393,22 +452,22 @@ constexpr int pen_rmax(int L, int LOGP) {
 
 constexpr int cdiv_c(int a, int b) { return (a + b - 1) / b; }
 
-template <typename T, int DIR, int LOGP, int L, int S, int SEND = 64>
+template <typename T, int DIR, int LOGP, int L, int S, int SEND = 64, int V = 0>
 __device__ __forceinline__ void fft_pen_c(cpx<T> *buf, const cpx<T> *tw) {
-  constexpr StaticPlan P = static_plan(L, pen_rmax(L, LOGP));
+  constexpr StaticPlan P = plan_variant(L, pen_rmax(L, LOGP), V);
   if constexpr (S < P.n && S < SEND) {
     constexpr int R = P.radix[S], Ns = P.ns[S];
     constexpr int NB = cdiv_c((L / R) << LOGP, kNT);
     stage_pen<T, R, NB, DIR, LOGP>(buf, tw, L / R, Ns, L / (Ns * R), ConstDiv<Ns>{});
-    fft_pen_c<T, DIR, LOGP, L, S + 1, SEND>(buf, tw);
+    fft_pen_c<T, DIR, LOGP, L, S + 1, SEND, V>(buf, tw);
   }
 }
 
 // First and last stage of a compile-time pen plan, for transforms whose input
 // comes from (or whose output goes to) global memory directly.
-template <int L, int LOGP>
+template <int L, int LOGP, int V = 0>
 struct PenEnds {
-  static constexpr StaticPlan P = static_plan(L, pen_rmax(L, LOGP));
+  static constexpr StaticPlan P = plan_variant(L, pen_rmax(L, LOGP), V);
   static constexpr int R0 = P.radix[0];                  // first stage
   static constexpr int NBF0 = (L / R0) << LOGP;          // its butterflies
   static constexpr int NB0 = cdiv_c(NBF0, kNT);          // ... per thread
@@ -421,10 +480,10 @@ struct PenEnds {
 // v[i][k] = element b + k * NBF0 of the buffer for butterfly b = tid + i kNT.
 // buf must be free on entry (no thread still reading it); on exit the result
 // is in buf and a barrier has been passed.
-template <typename T, int DIR, int LOGP, int L>
+template <typename T, int DIR, int LOGP, int L, int V = 0>
 __device__ __forceinline__ void fft_pen_from_regs(cpx<T> *buf, const cpx<T> *tw,
-                                                  cpx<T> (&v)[PenEnds<L, LOGP>::NB0][PenEnds<L, LOGP>::R0]) {
-  using E = PenEnds<L, LOGP>;
+                                                  cpx<T> (&v)[PenEnds<L, LOGP, V>::NB0][PenEnds<L, LOGP, V>::R0]) {
+  using E = PenEnds<L, LOGP, V>;
 #pragma unroll
   for (int i = 0; i < E::NB0; ++i) {
     const int b = threadIdx.x + i * kNT;
@@ -432,18 +491,18 @@ __device__ __forceinline__ void fft_pen_from_regs(cpx<T> *buf, const cpx<T> *tw,
       pen_butterfly<T, E::R0, DIR, LOGP>(v[i], b, tw, 1, 0, ConstDiv<1>{}, [&](int o, cpx<T> x) { buf[o] = x; });
   }
   __syncthreads();
-  fft_pen_c<T, DIR, LOGP, L, 1>(buf, tw);
+  fft_pen_c<T, DIR, LOGP, L, 1, 64, V>(buf, tw);
 }
 
 // Pen transform of buf whose last-stage outputs go to put(e, value), e the
 // element index in the pen layout, instead of back to LDS.  Data must be
 // visible to all threads on entry; no barrier follows the last stage, so the
 // caller synchronises before writing buf again.
-template <typename T, int DIR, int LOGP, int L, typename Put>
+template <typename T, int DIR, int LOGP, int L, int V = 0, typename Put>
 __device__ __forceinline__ void fft_pen_to_store(cpx<T> *buf, const cpx<T> *tw, Put &&put) {
-  using E = PenEnds<L, LOGP>;
+  using E = PenEnds<L, LOGP, V>;
   constexpr int S = E::P.n - 1, R = E::RL, Ns = E::P.ns[S];
-  fft_pen_c<T, DIR, LOGP, L, 0, S>(buf, tw);
+  fft_pen_c<T, DIR, LOGP, L, 0, S, V>(buf, tw);
   cpx<T> v[E::NBL][R];
 #pragma unroll
   for (int i = 0; i < E::NBL; ++i) {

@@ -462,8 +462,9 @@ __device__ __forceinline__ int fold(int k, int M, int &sgn) {
 // frequency Mz - oz of the same pencil: one read of the six Green values
 // serves both, with the z-odd components (xz, yz) negated for the mirror.
 // Forward spectra of components 0 and 1 are parked in registers, component 2
-// stays in LDS.
-template <typename T, int EPT, int LC, int HALF>
+// stays in LDS.  V selects one of the alternative radix plans of a
+// compile-time length (plan_variant); the plan autotuner picks it per length.
+template <typename T, int EPT, int LC, int HALF, int V>
 __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx<T> *__restrict__ B, size_t b_elems,
                                                 const cpx<T> *__restrict__ ghat, const cpx<T> *__restrict__ twz,
                                                 AxisPlan pz, PassDims d) {
@@ -521,7 +522,7 @@ __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx
     // registers of the first stage (rows >= (Mz + 1) / 2 >= nz are known
     // zeros), in a two-slot ring so component c + 1 is in flight while c is
     // transformed.
-    using PE = PenEnds<LC, LOGP>;
+    using PE = PenEnds<LC, LOGP, V>;
     constexpr int MB = (LC + 1) / 2;
     cpx<T> pre[2][PE::NB0][PE::R0];
     auto fetch = [&](int c, cpx<T>(&dst)[PE::NB0][PE::R0]) {
@@ -540,7 +541,7 @@ __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (c < 2) fetch(c + 1, pre[(c + 1) & 1]);
-      fft_pen_from_regs<T, -1, LOGP, LC>(buf, tw, pre[c & 1]);
+      fft_pen_from_regs<T, -1, LOGP, LC, V>(buf, tw, pre[c & 1]);
       if (c < 2) park(c);
     }
   } else {
@@ -620,7 +621,7 @@ __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx
     cpx<T> *dst = tile + c * nzW;
     if constexpr (LC > 0) {
       // the last stage writes the nz kept rows straight to global memory
-      fft_pen_to_store<T, +1, LOGP, LC>(buf, tw, [&](int e, cpx<T> v) {
+      fft_pen_to_store<T, +1, LOGP, LC, V>(buf, tw, [&](int e, cpx<T> v) {
         if ((e >> LOGP) < d.nz) dst[toff(e)] = v;
       });
     } else {
@@ -926,22 +927,35 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
         // the registers a thread needs for the parked spectra
         constexpr int kHalfAbove = sizeof(T) == 4 ? 2048 : 1024;
         const int half = g.Mz * W > kHalfAbove ? 1 : 0;
-        auto launch = [&](auto e, auto lc, auto hf) {
+        auto launch = [&](auto e, auto lc, auto hf, auto vv) {
           constexpr int LC = decltype(lc)::value, H = decltype(hf)::value, E = decltype(e)::value;
+          constexpr int V = decltype(vv)::value;
           const size_t lds = (((size_t)g.Mz * W >> H) + g.Mz) * cs;
-          allow_lds(k_zpass<T, E, LC, H>, lds);
-          hipLaunchKernelGGL((k_zpass<T, E, LC, H>), dim3((g.My * nxt) << H, a.nrhs), dim3(kNT), lds, s, a.mask, B,
-                             be, static_cast<const cpx<T> *>(a.ghat), twz, a.pz, d);
+          allow_lds(k_zpass<T, E, LC, H, V>, lds);
+          hipLaunchKernelGGL((k_zpass<T, E, LC, H, V>), dim3((g.My * nxt) << H, a.nrhs), dim3(kNT), lds, s, a.mask,
+                             B, be, static_cast<const cpx<T> *>(a.ghat), twz, a.pz, d);
         };
+        // plan variant: forced by the caller, else the autotuner's table, else the cost model's
+        const int zv = a.zvar >= 0 ? a.zvar : tuned_zpass_variant(g.Mz, f32);
         with_len(g.Mz, [&](auto lc) {
           constexpr int LC = decltype(lc)::value;
           if constexpr (LC > 0) {
             constexpr int H = LC * W > kHalfAbove ? 1 : 0;
-            launch(IC<pick_ept_c((size_t)(LC * W) >> H, false)>{}, lc, IC<H>{});
+            constexpr int E = pick_ept_c((size_t)(LC * W) >> H, false);
+            if constexpr (LC >= kTunedMinLen) {
+              switch (zv) {
+                case 1: launch(IC<E>{}, lc, IC<H>{}, IC<1>{}); break;
+                case 2: launch(IC<E>{}, lc, IC<H>{}, IC<2>{}); break;
+                case 3: launch(IC<E>{}, lc, IC<H>{}, IC<3>{}); break;
+                default: launch(IC<E>{}, lc, IC<H>{}, IC<0>{}); break;
+              }
+            } else {
+              launch(IC<E>{}, lc, IC<H>{}, IC<0>{});
+            }
           } else if (half) {
-            with_ept<16>((size_t)g.Mz * W / 2, [&](auto e) { launch(e, lc, IC<1>{}); });
+            with_ept<16>((size_t)g.Mz * W / 2, [&](auto e) { launch(e, lc, IC<1>{}, IC<0>{}); });
           } else {
-            with_ept<8>((size_t)g.Mz * W, [&](auto e) { launch(e, lc, IC<0>{}); });
+            with_ept<8>((size_t)g.Mz * W, [&](auto e) { launch(e, lc, IC<0>{}, IC<0>{}); });
           }
         });
       } break;
