@@ -53,7 +53,8 @@ struct PassDims {
   int nrows;                      // rows per block of the x passes
   int Mxh, Myh;                   // octant extents M/2 + 1 (Green table)
   int64_t moct;                   // Mxh * Myh * Mzh
-  FastDiv d_mx, d_nx, d_ny, d_nxt, d_nrows;
+  int nrhs;                       // right-hand sides of the launch
+  FastDiv d_mx, d_nx, d_ny, d_nxt, d_nrows, d_nrhs;
 };
 
 // Fill LDS from global memory: every global load of a thread is issued before
@@ -474,7 +475,17 @@ __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx
   // thread, nz NP <= (Mz + 1) NP / 2 <= NL kNT (exact when Mz = LC is known)
   constexpr int NQ = LC > 0 ? cdiv_c((LC / 2 + 1) << LOGP, kNT) : EPT / 2 + 1;
   constexpr int NL = LC > 0 ? cdiv_c(((LC + 1) / 2) << LOGP, kNT) : EPT / 2 + 1;
-  const int r = blockIdx.y;
+  // XCD-aware order.  Workgroups are dispatched to the 8 XCDs round-robin
+  // (XCD = b mod 8), and each XCD has its own L2.  Logical index li runs
+  // through contiguous ranges per XCD; consecutive li take the right-hand
+  // sides of one column (so a batch reads the column's Green values from HBM
+  // once), then the halves of a tile, ky and My - ky, and the x tiles t and
+  // nxt - 1 - t: the (up to) four columns that read the same octant Green
+  // values, and the two halves of a tile, share one L2.
+  const int b = blockIdx.x;
+  const int nb = ((d.My * d.nxt) << HALF) * d.nrhs, per = nb >> 3;
+  const int lr = b < (per << 3) ? (b & 7) * per + (b >> 3) : b;
+  const int li = (int)d.d_nrhs((uint32_t)lr), r = lr - li * d.nrhs;
   if (mask && !mask[r]) return;
   const int Mz = LC > 0 ? LC : pz.L;
   const int n = Mz << LOGP;
@@ -484,15 +495,6 @@ __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx
   cpx<T> *buf = reinterpret_cast<cpx<T> *>(dda_smem);
   cpx<T> *tw = buf + n;
   load_twiddles(tw, twz, Mz);
-  // XCD-aware order.  Workgroups are dispatched to the 8 XCDs round-robin
-  // (XCD = b mod 8), and each XCD has its own L2.  Logical index li runs
-  // through contiguous ranges per XCD, and consecutive li visit the halves of
-  // a tile, ky and My - ky, and the x tiles t and nxt - 1 - t next to each
-  // other: the (up to) four columns that read the same octant Green values,
-  // and the two halves of a tile, share one L2.
-  const int b = blockIdx.x;
-  const int nb = (d.My * d.nxt) << HALF, per = nb >> 3;
-  const int li = b < (per << 3) ? (b & 7) * per + (b >> 3) : b;
   const int h = li & HALF, lt = li >> HALF;
   const int iy = (int)d.d_nxt((uint32_t)lt), ix = lt - iy * d.nxt;
   const int ky = (iy & 1) ? d.My - ((iy + 1) >> 1) : (iy >> 1);
@@ -900,6 +902,12 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
   d.d_ny = make_fastdiv(g.ny);
   d.d_nxt = make_fastdiv(nxt);
   d.d_nrows = make_fastdiv(nrows);
+  d.nrhs = a.nrhs;
+  d.d_nrhs = make_fastdiv(a.nrhs);
+  // the z-pass divides its block index (< blocks * nrhs) by nrhs with d_nrhs,
+  // exact while that index times nrhs stays below 2^32
+  DDA_REQUIRE((uint64_t)((g.My * nxt) << 1) * a.nrhs * a.nrhs < (uint64_t(1) << 32),
+              "too many right-hand sides in one product for this grid");
   const FuseArgs &f = a.fuse;
   const size_t xlds = ((size_t)3 * nrows * g.Mx + g.Mx) * cs + (size_t)3 * nrows * sizeof(int);
   auto pass = [&](int k) {
@@ -932,8 +940,8 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
           constexpr int V = decltype(vv)::value;
           const size_t lds = (((size_t)g.Mz * W >> H) + g.Mz) * cs;
           allow_lds(k_zpass<T, E, LC, H, V>, lds);
-          hipLaunchKernelGGL((k_zpass<T, E, LC, H, V>), dim3((g.My * nxt) << H, a.nrhs), dim3(kNT), lds, s, a.mask,
-                             B, be, static_cast<const cpx<T> *>(a.ghat), twz, a.pz, d);
+          hipLaunchKernelGGL((k_zpass<T, E, LC, H, V>), dim3(((g.My * nxt) << H) * a.nrhs), dim3(kNT), lds, s,
+                             a.mask, B, be, static_cast<const cpx<T> *>(a.ghat), twz, a.pz, d);
         };
         // plan variant: forced by the caller, else the autotuner's table, else the cost model's
         const int zv = a.zvar >= 0 ? a.zvar : tuned_zpass_variant(g.Mz, f32);
