@@ -188,7 +188,9 @@ typedef struct {
   uint64_t device_bytes;   /* device memory currently held by the handle */
   int32_t zpass_variant[2];/* radix-plan variant of the z-pass (0..3) in DDA_MIXED [0] and DDA_FP64
                               [1]: the autotuner's measured choice for Mz, or the one forced by
-                              dda_set_zpass_variant; 0 is the cost model's plan */
+                              dda_set_plan_variant; 0 is the cost model's plan */
+  int32_t xfwd_variant[2]; /* the same for the x-forward pass (0..1, for Mx) */
+  int32_t xinv_variant[2]; /* the same for the x-inverse pass (0..1, for Mx) */
 } dda_target_info;
 
 /* ---- target geometry (host arithmetic) ------------------------------- */
@@ -252,23 +254,31 @@ int dda_target_get_info(const dda_target *t, dda_target_info *info);
 
 /* Plan autotuning (§13 "Choice of FFT Algorithm": the guide picks among FFT
  * implementations; here the choice is among radix plans of one transform
- * length).  Forces the radix plan of the z-pass for this handle: 0 the cost
- * model's plan (fewest LDS stages, then fewest flops, largest radix first,
- * radices bounded so that at least half the threads of a block hold a
- * butterfly), 1 the same with radices up to 16 whatever that bound, 2 the
- * cheapest plan with one stage more than 0, 3 the radices of 0 smallest
- * first; -1 restores the measured
- * choice of the built-in table (written by autotune.py; variant 0 for
- * lengths it has not timed).  Variants exist for compile-time lengths of 96
- * and above; others always use variant 0.  Results of every variant agree to
- * rounding.  Errors: DDA_EINVAL (NULL, variant out of range). */
+ * length).  The product's passes are numbered as in dda_profile_matvec:
+ * 0 x-forward, 2 z-pass, 4 x-inverse (the y passes have one plan per length).
+ * z-pass variants: 0 the cost model's plan (fewest LDS stages, then fewest
+ * flops, largest radix first, radices bounded so that at least half the
+ * threads of a block hold a butterfly), 1 the same with radices up to 16
+ * whatever that bound, 2 the cheapest plan with one stage more than 0, 3 the
+ * radices of 0 smallest first.  x-pass variants: 0 radices up to 8, 1 radices
+ * up to 16.  Variants exist for compile-time lengths of 96 and above; others
+ * always use variant 0.  Every variant gives the product to rounding.
+ *
+ * dda_set_plan_variant forces a pass's variant for this handle; -1 restores
+ * the measured choice of the built-in table (written by autotune.py; variant
+ * 0 for lengths it has not timed).  Errors: DDA_EINVAL (NULL, pass not 0, 2
+ * or 4, variant out of range).  dda_set_zpass_variant(t, v) is
+ * dda_set_plan_variant(t, 2, v). */
+int dda_set_plan_variant(dda_target *t, int32_t pass, int32_t variant);
 int dda_set_zpass_variant(dda_target *t, int32_t variant);
 
-/* The radices, in execution order, of z-pass plan `variant` for the
+/* The radices, in execution order, of plan `variant` of pass 0, 2 or 4 for the
  * compile-time length L in `precision` (zeros after the last); returns the
  * number of stages, or a negative DDA_E* code (L not 2/3/5-smooth or above
- * 512, variant not 0..3).  Lengths without a compile-time plan use the
- * run-time radix-8/4/2/5/3 plan in the product instead. */
+ * 512, pass or variant out of range).  Lengths without a compile-time plan use
+ * the run-time radix-8/4/2/5/3 plan in the product instead.
+ * dda_zpass_plan(L, p, v, r) is dda_pass_plan(2, L, p, v, r). */
+int dda_pass_plan(int32_t pass, int32_t L, int32_t precision, int32_t variant, int32_t radices[8]);
 int dda_zpass_plan(int32_t L, int32_t precision, int32_t variant, int32_t radices[8]);
 
 /* Solve A P = E for nrhs right-hand sides as one block (shared FFT grid and

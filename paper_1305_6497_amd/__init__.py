@@ -108,11 +108,21 @@ def fft_pencils(x, sign=-1, scale=1.0, stream=None):
     return out
 
 
+PASSES = {"x_forward": 0, "z_pass": 2, "x_inverse": 4}
+
+
+def pass_plan(pass_name, length, precision="mixed", variant=0):
+    """Radices (execution order) of plan `variant` of a pass ("x_forward",
+    "z_pass" or "x_inverse") for a padded length."""
+    r = (ctypes.c_int32 * 8)()
+    n = L.check(L.lib().dda_pass_plan(PASSES[pass_name], int(length), PRECISION[precision], int(variant), r),
+                ok=tuple(range(9)))
+    return [r[i] for i in range(n)]
+
+
 def zpass_plan(length, precision="mixed", variant=0):
     """Radices (execution order) of z-pass plan `variant` for a padded length."""
-    r = (ctypes.c_int32 * 8)()
-    n = L.check(L.lib().dda_zpass_plan(int(length), PRECISION[precision], int(variant), r), ok=tuple(range(9)))
-    return [r[i] for i in range(n)]
+    return pass_plan("z_pass", length, precision, variant)
 
 
 def footprint_bytes(box, n_sites, m=1.5, kd=0.5, nrhs=1, alpha="LATTDR"):
@@ -181,12 +191,19 @@ class Target:
         i = L.TargetInfo()
         L.check(self._lib.dda_target_get_info(self._h, ctypes.byref(i)))
         return dict(box=tuple(i.box), grid=tuple(i.grid), n_sites=i.n_sites, kd=i.kd, aeff=i.aeff,
-                    device_bytes=i.device_bytes, zpass_variant=dict(mixed=i.zpass_variant[0],
-                                                                    fp64=i.zpass_variant[1]))
+                    device_bytes=i.device_bytes,
+                    plan_variant={name: dict(mixed=arr[0], fp64=arr[1]) for name, arr in
+                                  (("x_forward", i.xfwd_variant), ("z_pass", i.zpass_variant),
+                                   ("x_inverse", i.xinv_variant))})
+
+    def set_plan_variant(self, pass_name, variant):
+        """Force the radix-plan variant of "x_forward", "z_pass" or "x_inverse",
+        or -1 for the tuned table's."""
+        L.check(self._lib.dda_set_plan_variant(self._h, PASSES[pass_name], int(variant)))
 
     def set_zpass_variant(self, variant):
         """Force the z-pass radix-plan variant (0..3), or -1 for the tuned table's."""
-        L.check(self._lib.dda_set_zpass_variant(self._h, int(variant)))
+        self.set_plan_variant("z_pass", variant)
 
     def _vec(self, nrhs):
         import torch

@@ -77,7 +77,8 @@ class Q(ctypes.Structure):
 class TargetInfo(ctypes.Structure):
     _fields_ = [("box", ctypes.c_int32 * 3), ("grid", ctypes.c_int32 * 3), ("n_sites", ctypes.c_int64),
                 ("kd", ctypes.c_double), ("aeff", ctypes.c_double), ("device_bytes", ctypes.c_uint64),
-                ("zpass_variant", ctypes.c_int32 * 2)]
+                ("zpass_variant", ctypes.c_int32 * 2), ("xfwd_variant", ctypes.c_int32 * 2),
+                ("xinv_variant", ctypes.c_int32 * 2)]
 
 
 # (name, restype, argtypes) for every entry point declared in include/dda.h
@@ -96,7 +97,10 @@ SIGNATURES = [
     ("dda_footprint_bytes", ctypes.c_int, [ctypes.POINTER(TargetDesc), ctypes.c_int32, ctypes.POINTER(SolveOpts),
                                            ctypes.POINTER(ctypes.c_uint64)]),
     ("dda_target_get_info", ctypes.c_int, [_VP, ctypes.POINTER(TargetInfo)]),
+    ("dda_set_plan_variant", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     ("dda_set_zpass_variant", ctypes.c_int, [_VP, ctypes.c_int32]),
+    ("dda_pass_plan", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_int32)]),
     ("dda_zpass_plan", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     ("dda_solve", ctypes.c_int, [_VP, ctypes.POINTER(Rhs), ctypes.c_int32, ctypes.POINTER(SolveOpts), _VP,
                                  ctypes.POINTER(C64), _VP, ctypes.POINTER(SolveStats)]),

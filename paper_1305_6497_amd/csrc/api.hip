@@ -71,8 +71,9 @@ struct dda_target {
   // scalar (alpha, omega) to the consuming kernel, which computes it in every
   // block; larger ones get a one-block kernel first (set by each solve)
   int fold_records = kFoldRecords;
-  // z-pass plan variant forced by dda_set_zpass_variant (-1: the tuned table's)
+  // plan variants forced by dda_set_plan_variant (-1: the tuned table's)
   int zvar = -1;
+  int xvar[2] = {-1, -1};
   uint64_t graph_gen = 0;
   uint64_t buffer_gen = 0;        // bumped whenever workspaces are reallocated
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -382,6 +383,8 @@ void matvec_on(dda_target *t, int precision, const c64 *in, c64 *out, int nrhs, 
   a.py = t->py;
   a.pz = t->pz;
   a.zvar = t->zvar;
+  a.xvar[0] = t->xvar[0];
+  a.xvar[1] = t->xvar[1];
   if (precision == DDA_MIXED) {
     a.ghat = t->d_ghat32;
     a.twx = t->tx.d32;
@@ -811,38 +814,58 @@ int dda_target_get_info(const dda_target *t, dda_target_info *info) {
     info->kd = t->kd;
     info->aeff = t->aeff;
     info->device_bytes = t->bytes;
-    for (int p = 0; p < 2; ++p)
-      info->zpass_variant[p] = t->zvar >= 0 ? t->zvar : tuned_zpass_variant(t->g.Mz, p == 0);
+    for (int p = 0; p < 2; ++p) {
+      info->zpass_variant[p] = t->zvar >= 0 ? t->zvar : tuned_variant(kPassZ, t->g.Mz, p == 0);
+      info->xfwd_variant[p] = t->xvar[0] >= 0 ? t->xvar[0] : tuned_variant(kPassXfwd, t->g.Mx, p == 0);
+      info->xinv_variant[p] = t->xvar[1] >= 0 ? t->xvar[1] : tuned_variant(kPassXinv, t->g.Mx, p == 0);
+    }
     return DDA_OK;
   });
 }
 
 void dda_free_target(dda_target *t) { delete t; }
 
-int dda_zpass_plan(int32_t L, int32_t precision, int32_t variant, int32_t radices[8]) {
+int dda_pass_plan(int32_t pass, int32_t L, int32_t precision, int32_t variant, int32_t radices[8]) {
   return guarded([&]() -> int {
     DDA_REQUIRE(radices != nullptr, "NULL argument");
     DDA_REQUIRE(precision == DDA_FP64 || precision == DDA_MIXED, "unknown precision");
-    DDA_REQUIRE(variant >= 0 && variant < kPlanVariants, "variant must be 0..3");
+    DDA_REQUIRE(pass == kPassXfwd || pass == kPassZ || pass == kPassXinv, "pass must be 0, 2 or 4");
+    const int nvar = pass == kPassZ ? kPlanVariants : kRowPlanVariants;
+    DDA_REQUIRE(variant >= 0 && variant < nvar, "variant out of range for this pass");
     DDA_REQUIRE(L >= 2 && L <= kMaxLen && next_smooth(L) == L, "L must be 2/3/5-smooth and <= 512");
-    // pencils per z-pass block: a 128-byte tile row, halved for long columns
-    const bool f32 = precision == DDA_MIXED;
-    const int logw = f32 ? 4 : 3, half = L * (1 << logw) > (f32 ? 2048 : 1024) ? 1 : 0;
-    const StaticPlan p = plan_variant(L, pen_rmax(L, logw - half), L >= kTunedMinLen ? variant : 0);
+    const int v = L >= kTunedMinLen ? variant : 0;
+    StaticPlan p{};
+    if (pass == kPassZ) {
+      // pencils per z-pass block: a 128-byte tile row, halved for long columns
+      const bool f32 = precision == DDA_MIXED;
+      const int logw = f32 ? 4 : 3, half = L * (1 << logw) > (f32 ? 2048 : 1024) ? 1 : 0;
+      p = plan_variant(L, pen_rmax(L, logw - half), v);
+    } else {
+      p = rows_plan(L, v);
+    }
     for (int i = 0; i < 8; ++i) radices[i] = i < p.n ? p.radix[i] : 0;
     return p.n;
   });
 }
 
-int dda_set_zpass_variant(dda_target *t, int32_t variant) {
+int dda_zpass_plan(int32_t L, int32_t precision, int32_t variant, int32_t radices[8]) {
+  return dda_pass_plan(kPassZ, L, precision, variant, radices);
+}
+
+int dda_set_plan_variant(dda_target *t, int32_t pass, int32_t variant) {
   return guarded([&]() -> int {
     DDA_REQUIRE(t != nullptr, "NULL argument");
-    DDA_REQUIRE(variant >= -1 && variant < kPlanVariantsHost, "variant must be -1..3");
-    t->zvar = variant;
+    DDA_REQUIRE(pass == kPassXfwd || pass == kPassZ || pass == kPassXinv, "pass must be 0, 2 or 4");
+    const int nvar = pass == kPassZ ? kPlanVariantsHost : kRowPlanVariantsHost;
+    DDA_REQUIRE(variant >= -1 && variant < nvar, "variant out of range for this pass");
+    if (pass == kPassZ) t->zvar = variant;
+    else t->xvar[pass == kPassXfwd ? 0 : 1] = variant;
     ++t->buffer_gen;                  // a captured iteration graph holds the old kernels
     return DDA_OK;
   });
 }
+
+int dda_set_zpass_variant(dda_target *t, int32_t variant) { return dda_set_plan_variant(t, kPassZ, variant); }
 
 int dda_incident_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, void *e_dev, void *stream) {
   return guarded([&]() -> int {

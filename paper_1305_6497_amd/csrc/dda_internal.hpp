@@ -188,14 +188,18 @@ struct MatvecArgs {
   AxisPlan px, py, pz;
   FuseArgs fuse;
   int zvar = -1;                  // z-pass plan variant (0..3), or -1: the tuned table's choice
+  int xvar[2] = {-1, -1};         // x-forward / x-inverse rows-plan variant (0..1), or -1
 };
 
-// Plan variants of the z-pass (plan_variant in fft_lds.hpp) exist for the
-// compile-time lengths from kTunedMinLen up; the autotuner's measured choice
-// per length and precision (zpass_tuned.inc), 0 for lengths it has not timed.
+// Plan variants exist for the compile-time lengths from kTunedMinLen up: four
+// for the z-pass (plan_variant in fft_lds.hpp), two for the x passes
+// (rows_plan).  tuned_variant returns the autotuner's measured choice per
+// pass, length and precision (plan_tuned.inc), 0 for lengths it has not timed.
 constexpr int kTunedMinLen = 96;
 constexpr int kPlanVariantsHost = 4;     // = kPlanVariants of fft_lds.hpp
-int tuned_zpass_variant(int L, bool fp32);
+constexpr int kRowPlanVariantsHost = 2;  // = kRowPlanVariants of fft_lds.hpp
+enum : int { kPassXfwd = 0, kPassZ = 2, kPassXinv = 4 };
+int tuned_variant(int pass, int L, bool fp32);
 
 // The x passes keep 3 * rows * Mx <= kXBudget elements per block (EPT <= 8):
 // more, lighter blocks keep more loads in flight than few heavy ones.

@@ -544,14 +544,21 @@ __device__ __forceinline__ void fft_pen(cpx<T> *buf, const cpx<T> *tw, const Axi
   else fft_pen_rt<T, EPT, DIR, LOGP>(buf, tw, pl);
 }
 
-template <typename T, int EPT, int DIR, int L, int S>
+// Plans of the rows layout (the x passes): 0 radices up to 8 (the cost
+// model's bound for contiguous rows), 1 radices up to 16 (fewer LDS stages).
+constexpr int kRowPlanVariants = 2;
+static_assert(kRowPlanVariants == kRowPlanVariantsHost, "rows plan variant count");
+
+constexpr StaticPlan rows_plan(int L, int V) { return static_plan(L, V == 1 ? 16 : 8); }
+
+template <typename T, int EPT, int DIR, int L, int S, int V = 0>
 __device__ __forceinline__ void fft_rows_c(cpx<T> *buf, const cpx<T> *tw, int npen) {
-  constexpr StaticPlan P = static_plan(L);
+  constexpr StaticPlan P = rows_plan(L, V);
   if constexpr (S < P.n) {
     constexpr int R = P.radix[S], Ns = P.ns[S];
     stage_rows<T, R, cdiv_c(EPT, R), DIR>(buf, tw, L, L / R, Ns, L / (Ns * R), ConstDiv<L / R>{}, ConstDiv<Ns>{},
                                           npen);
-    fft_rows_c<T, EPT, DIR, L, S + 1>(buf, tw, npen);
+    fft_rows_c<T, EPT, DIR, L, S + 1, V>(buf, tw, npen);
   }
 }
 
@@ -572,9 +579,9 @@ __device__ __forceinline__ void fft_rows_rt(cpx<T> *buf, const cpx<T> *tw, const
 }
 
 // Transform npen contiguous pencils in buf (rows layout); npen * L <= EPT * kNT.
-template <typename T, int EPT, int DIR, int LC>
+template <typename T, int EPT, int DIR, int LC, int V = 0>
 __device__ __forceinline__ void fft_rows(cpx<T> *buf, const cpx<T> *tw, const AxisPlan &pl, int npen) {
-  if constexpr (LC > 0) fft_rows_c<T, EPT, DIR, LC, 0>(buf, tw, npen);
+  if constexpr (LC > 0) fft_rows_c<T, EPT, DIR, LC, 0, V>(buf, tw, npen);
   else fft_rows_rt<T, EPT, DIR>(buf, tw, pl, npen);
 }
 

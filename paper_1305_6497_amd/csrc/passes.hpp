@@ -237,7 +237,7 @@ __device__ __forceinline__ bool block_alpha(const FuseArgs &f, int r, c64 &alpha
 // f.in_mode (see FuseArgs): 0 transforms `in`; 1 and 2 first form the BiCGSTAB
 // vector p or s from r, v (and the old p) and store it, so the vector update
 // costs no pass of its own.  LC > 0: Mx = LC, known at compile time.
-template <typename T, int EPT, int LC>
+template <typename T, int EPT, int LC, int V>
 __global__ __launch_bounds__(kNT) void k_xfwd(const c64 *__restrict__ in, int64_t n3, const int *__restrict__ mask,
                                                const int *__restrict__ cell_site, const int4 *__restrict__ rowtab,
                                                cpx<T> *__restrict__ A,
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(kNT) void k_xfwd(const c64 *__restrict__ in, int64_
     }
   }
   __syncthreads();
-  fft_rows<T, EPT, -1, LC>(buf, tw, px, 3 * nrows);
+  fft_rows<T, EPT, -1, LC, V>(buf, tw, px, 3 * nrows);
   cpx<T> *Ar = A + (size_t)r * a_elems;
   const int nyW = d.ny * W;
   const int nseg = 3 * nrows * nxt;
@@ -663,7 +663,7 @@ __global__ __launch_bounds__(kNT) void k_yinv(const int *__restrict__ mask, cons
 // --------------------------------------------------------------- x-inverse --
 // f.out_mode (see FuseArgs): 0 only writes out = ainv * in - G*in; 1 and 2 also
 // write per-block partial sums of the BiCGSTAB inner products of `out`.
-template <typename T, int EPT, int LC>
+template <typename T, int EPT, int LC, int V>
 __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *__restrict__ out, int64_t n3,
                                                const int *__restrict__ mask, const c64 *__restrict__ ainv,
                                                int ncomp, const uint8_t *__restrict__ comp,
@@ -694,7 +694,7 @@ __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *_
     return ro >= 0 ? Ar[ro + (kx >> LOGW) * nyW + (kx & (W - 1))] : cpx<T>{0, 0};
   });
   __syncthreads();
-  fft_rows<T, EPT, +1, LC>(buf, tw, px, 3 * nrows);
+  fft_rows<T, EPT, +1, LC, V>(buf, tw, px, 3 * nrows);
   const size_t off = (size_t)r * n3;
   const c64 *ai = ainv + (size_t)r * ncomp * 3;      // [ncomp][3] of this RHS
   double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -909,6 +909,9 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
   DDA_REQUIRE((uint64_t)((g.My * nxt) << 1) * a.nrhs * a.nrhs < (uint64_t(1) << 32),
               "too many right-hand sides in one product for this grid");
   const FuseArgs &f = a.fuse;
+  // rows-plan variants of the x-forward and x-inverse passes (forced or tuned)
+  const int xv[2] = {a.xvar[0] >= 0 ? a.xvar[0] : tuned_variant(kPassXfwd, g.Mx, f32),
+                     a.xvar[1] >= 0 ? a.xvar[1] : tuned_variant(kPassXinv, g.Mx, f32)};
   const size_t xlds = ((size_t)3 * nrows * g.Mx + g.Mx) * cs + (size_t)3 * nrows * sizeof(int);
   auto pass = [&](int k) {
     switch (k) {
@@ -916,8 +919,16 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
         with_pass<8>(g.Mx, (size_t)3 * nrows * g.Mx, [&](auto e, auto lc) {
           constexpr int LC = decltype(lc)::value;
           constexpr int E = LC > 0 ? pick_ept_c((size_t)3 * xpass_rows(LC) * LC, true) : decltype(e)::value;
-          hipLaunchKernelGGL((k_xfwd<T, E, LC>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s, a.in, n3, a.mask,
-                             a.cell_site, a.rowtab, A, ae, twx, a.px, d, f);
+          auto go = [&](auto vv) {
+            hipLaunchKernelGGL((k_xfwd<T, E, LC, decltype(vv)::value>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s,
+                               a.in, n3, a.mask, a.cell_site, a.rowtab, A, ae, twx, a.px, d, f);
+          };
+          if constexpr (LC >= kTunedMinLen) {
+            if (xv[0] == 1) go(IC<1>{});
+            else go(IC<0>{});
+          } else {
+            go(IC<0>{});
+          }
         });
         break;
       case 1:
@@ -944,7 +955,7 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
                              a.mask, B, be, static_cast<const cpx<T> *>(a.ghat), twz, a.pz, d);
         };
         // plan variant: forced by the caller, else the autotuner's table, else the cost model's
-        const int zv = a.zvar >= 0 ? a.zvar : tuned_zpass_variant(g.Mz, f32);
+        const int zv = a.zvar >= 0 ? a.zvar : tuned_variant(kPassZ, g.Mz, f32);
         with_len(g.Mz, [&](auto lc) {
           constexpr int LC = decltype(lc)::value;
           if constexpr (LC > 0) {
@@ -981,8 +992,17 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
         with_pass<8>(g.Mx, (size_t)3 * nrows * g.Mx, [&](auto e, auto lc) {
           constexpr int LC = decltype(lc)::value;
           constexpr int E = LC > 0 ? pick_ept_c((size_t)3 * xpass_rows(LC) * LC, true) : decltype(e)::value;
-          hipLaunchKernelGGL((k_xinv<T, E, LC>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s, a.in, a.out, n3,
-                             a.mask, a.ainv, a.ncomp, a.comp, a.cell_site, a.rowtab, A, ae, twx, a.px, d, f);
+          auto go = [&](auto vv) {
+            hipLaunchKernelGGL((k_xinv<T, E, LC, decltype(vv)::value>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s,
+                               a.in, a.out, n3, a.mask, a.ainv, a.ncomp, a.comp, a.cell_site, a.rowtab, A, ae, twx,
+                               a.px, d, f);
+          };
+          if constexpr (LC >= kTunedMinLen) {
+            if (xv[1] == 1) go(IC<1>{});
+            else go(IC<0>{});
+          } else {
+            go(IC<0>{});
+          }
         });
         break;
     }

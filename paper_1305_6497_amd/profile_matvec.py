@@ -35,7 +35,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # Sources the FFT-product kernels are compiled from: a traffic figure measured
 # on other sources no longer describes the kernel.
 KERNEL_SOURCES = ("passes.hpp", "fft_lds.hpp", "dda_internal.hpp", "reduce.hpp", "matvec_f32.hip",
-                  "matvec_f64.hip", "zpass_tuned.inc")
+                  "matvec_f64.hip", "plan_tuned.inc")
 
 
 def kernel_source_hash():

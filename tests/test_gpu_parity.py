@@ -211,28 +211,33 @@ def test_matvec_multi_composition_tensor_polarizability(dda, alpha):
 
 
 @pytest.mark.parametrize("length", [96, 128, 192, 270])
-def test_zpass_plan_variants_agree_with_the_oracle(dda, length):
-    # every radix plan the autotuner may pick gives the product of the FP64
-    # oracle (FFT convolution on its own grid) to rounding
+def test_plan_variants_agree_with_the_oracle(dda, length):
+    # every radix plan the autotuner may pick (z-pass and x passes) gives the
+    # product of the FP64 oracle (FFT convolution on its own grid) to rounding
     nz = (length + 1) // 2
-    sites, box = dda.make_sites("RCTGLPRSM", (9, 7, nz))
+    sites, box = dda.make_sites("RCTGLPRSM", (nz, 7, nz))
     kd, m = 0.3, 1.5 + 0.1j
     rhs = [dda.orient_rhs(0.2, 0.9, 0.4, which=1), dda.orient_rhs(0.2, 0.9, 0.4, which=2)]
     t = dda.Target(sites, box, m=m, kd=kd)
-    assert t.info()["grid"][2] == length
+    assert t.info()["grid"][0] == length and t.info()["grid"][2] == length
     P = inputs.random_polarization(len(sites), 2, seed=21)
     Pd = torch.tensor(P, device="cuda")
-    osites = targets.rctglprsm(9, 7, nz)
+    osites = targets.rctglprsm(nz, 7, nz)
     refs = [interaction.FFTOperator(osites, kd, _oracle_ainv(m, kd, *rhs[r])).matvec(P[r]) for r in range(2)]
     for v in range(4):
         t.set_zpass_variant(v)
+        t.set_plan_variant("x_forward", v % 2)
+        t.set_plan_variant("x_inverse", (v // 2) % 2)
         for prec, tol in (("fp64", 1e-12), ("mixed", 5e-6)):
             out = t.apply(rhs, Pd, prec).cpu().numpy()
             for r in range(2):
                 assert _rel(out[r], refs[r]) < tol, (length, v, prec, r, dda.zpass_plan(length, prec, v))
-    t.set_zpass_variant(-1)
+    for name in ("z_pass", "x_forward", "x_inverse"):
+        t.set_plan_variant(name, -1)
     with pytest.raises(dda.DDAError):
         t.set_zpass_variant(4)
+    with pytest.raises(dda.DDAError):
+        t.set_plan_variant("x_forward", 2)
     t.close()
 
 

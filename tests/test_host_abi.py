@@ -216,7 +216,7 @@ def test_every_entry_point_checks_its_vectors(dda, bad):
             call()
 
 
-def test_zpass_plans_factor_their_length(dda):
+def test_pass_plans_factor_their_length(dda):
     # every plan variant of every tuned length is a factorization of the
     # length into the engine's radices, with at most 8 stages
     import functools
@@ -224,28 +224,33 @@ def test_zpass_plans_factor_their_length(dda):
     radices = {2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16}
     for L in (96, 100, 108, 120, 125, 128, 135, 144, 150, 160, 162, 180, 192, 256, 270):
         for prec in ("mixed", "fp64"):
-            for v in range(4):
-                p = dda.zpass_plan(L, prec, v)
-                assert 1 <= len(p) <= 8 and set(p) <= radices
-                assert functools.reduce(operator.mul, p, 1) == L, (L, prec, v, p)
+            for name, nvar in (("z_pass", 4), ("x_forward", 2), ("x_inverse", 2)):
+                for v in range(nvar):
+                    p = dda.pass_plan(name, L, prec, v)
+                    assert 1 <= len(p) <= 8 and set(p) <= radices
+                    assert functools.reduce(operator.mul, p, 1) == L, (L, prec, name, v, p)
             p0, p3 = dda.zpass_plan(L, prec, 0), dda.zpass_plan(L, prec, 3)
             assert sorted(p0) == sorted(p3) and p0 == sorted(p0, reverse=True)
+            assert max(dda.pass_plan("x_forward", L, prec, 0)) <= 8
     with pytest.raises(dda.DDAError):
         dda.zpass_plan(97, "mixed", 0)                   # not 2/3/5-smooth
     with pytest.raises(dda.DDAError):
         dda.zpass_plan(128, "mixed", 4)
+    with pytest.raises(dda.DDAError):
+        dda.pass_plan("x_forward", 128, "mixed", 2)
 
 
-def test_tuned_zpass_table_names_other_plans(dda):
+def test_tuned_plan_table_names_other_plans(dda):
     # the autotuner's table (compiled into the library) only lists lengths
     # whose chosen plan differs from the cost model's
     import re
     path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1305_6497_amd", "csrc",
-                        "zpass_tuned.inc")
+                        "plan_tuned.inc")
+    names = {0: "x_forward", 2: "z_pass", 4: "x_inverse"}
     for line in open(path):
-        mt = re.match(r"\{(\d+), ([01]), (\d)\}", line.strip())
+        mt = re.match(r"\{(\d), (\d+), ([01]), (\d)\}", line.strip())
         if not mt:
             continue
-        L, f32, v = int(mt.group(1)), int(mt.group(2)), int(mt.group(3))
+        ps, L, f32, v = (int(mt.group(i)) for i in range(1, 5))
         prec = "mixed" if f32 else "fp64"
-        assert 1 <= v <= 3 and dda.zpass_plan(L, prec, v) != dda.zpass_plan(L, prec, 0), line
+        assert v >= 1 and dda.pass_plan(names[ps], L, prec, v) != dda.pass_plan(names[ps], L, prec, 0), line
