@@ -109,10 +109,9 @@ def roofline(prof, box, grid, n_sites, nrhs, workload, fp32=True):
              "pass_ms": prof, "pass_frac": {k: pb[k] / (prof[k] * 1e-3) / 1e9 / PEAK_HBM_GBS for k in pb}})
 
 
-def cpu_baseline(sites, kd, m, rhs, gpu_fp64_iters, budget_s=20.0):
-    """FP64 CPU oracle (COCG on its SciPy FFT product) on a bounded sample of
-    the same solve: s per iteration x the iteration count of the identical
-    FP64 algorithm."""
+def _oracle_rate(sites, kd, m, rhs, budget_s):
+    """Time FP64 COCG iterations of the oracle (one SciPy FFT product each) on one RHS: doubling the count
+    until the run takes half the budget.  Returns (iterations, seconds, setup seconds, workers)."""
     from oracle import incident, interaction, polarizability, solvers
     workers = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     t0 = time.perf_counter()
@@ -130,6 +129,14 @@ def cpu_baseline(sites, kd, m, rhs, gpu_fp64_iters, budget_s=20.0):
         t0 = time.perf_counter()
         solvers.cocg(op.matvec, E, tol=1e-30, maxiter=its)
         dt = time.perf_counter() - t0
+    return its, dt, setup, workers
+
+
+def cpu_baseline(sites, kd, m, rhs, gpu_fp64_iters, budget_s=20.0):
+    """FP64 CPU oracle (COCG on its SciPy FFT product) on a bounded sample of
+    the same solve: s per iteration x the iteration count of the identical
+    FP64 algorithm."""
+    its, dt, setup, workers = _oracle_rate(sites, kd, m, rhs, budget_s)
     per_iter = dt / its
     solve_s = per_iter * gpu_fp64_iters
     return dict(value=1.0 / solve_s, unit="solves/s", cores=workers, kind="oracle",
@@ -139,6 +146,26 @@ def cpu_baseline(sites, kd, m, rhs, gpu_fp64_iters, budget_s=20.0):
                         f"{gpu_fp64_iters} iterations, the count of the identical FP64 COCG on this GPU); "
                         f"Green-transform setup {setup:.1f} s excluded"),
                 matvecs_per_s=its / dt, setup_s=setup)
+
+
+def cpu_per_config(dda, inputs, extras, budget_s=6.0):
+    """The oracle's FP64 product rate on every other configuration (first RHS), and its solve rate as
+    s per product x the products of the same configuration's FP64 solve on this GPU."""
+    from oracle import targets
+    legs = (("block_64", lambda e: e["block_64"]["fp64"]["matvecs"]),
+            ("sphere_d20", lambda e: e["sphere_d20"]["fp64_matvecs"]),
+            ("ellipsoid_96x64x48", lambda e: e["ellipsoid_96x64x48_batched"]["fp64_matvecs_mean"]))
+    out = {}
+    for name, gpu_mv in legs:
+        w = inputs.WORKLOADS[name]
+        sites = targets.make(w["shape"], w["shpar"])
+        kd = dda.kd_from_x(w["x"], len(sites))
+        its, dt, setup, workers = _oracle_rate(sites, kd, w["m"], _rhs_list(dda, inputs, w)[0], budget_s)
+        mv = gpu_mv(extras)
+        out[name] = dict(matvecs_per_s=its / dt, solves_per_s=its / dt / mv, cores=workers,
+                         gpu_fp64_matvecs_per_solve=mv, setup_s=setup,
+                         sample=f"{its} FP64 COCG iterations of the oracle in {dt:.2f} s (first RHS)")
+    return out
 
 
 def _reference(name):
@@ -246,11 +273,13 @@ def extra_workloads(dda, inputs, torch, tol, serving_alone=True):
                 lat.append(time.perf_counter() - s0)
         res["graph" if graph else "eager"] = {"solves_per_s": len(lat) / sum(lat),
                                              "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                                             "p99_ms": float(np.percentile(lat, 99) * 1e3), "iters": st[0]["iters"]}
+                                             "p99_ms": float(np.percentile(lat, 99) * 1e3), "iters": st[0]["iters"],
+                                             "matvecs": st[0]["matvecs"]}
     P, st = t.solve(rhs, tol=tol, precision="fp64")
     q = t.cross_sections(rhs, P)
     ref = _reference("sphere_d20")
     res["q"] = q
+    res["fp64_matvecs"] = float(np.mean([x["matvecs"] for x in st]))
     res["q_err_vs_oracle"] = _ref_errors(q, ref)
     res["mie"] = ref.get("mie") if ref else None
     res["config"] = {"n_sites": len(sites), "fft_grid": list(t.info()["grid"]), "precision": "fp64", "nrhs": 1}
@@ -287,14 +316,17 @@ def extra_workloads(dda, inputs, torch, tol, serving_alone=True):
     torch.cuda.synchronize()
     s0 = time.perf_counter()
     iters64 = []
+    mv64 = []
     for r in rhs:
         P1, s1 = t.solve([r], tol=tol, precision="fp64", out=P1)
         t.cross_sections([r], P1)
         iters64.append(s1[0]["iters"])
+        mv64.append(s1[0]["matvecs"])
     torch.cuda.synchronize()
     ts = time.perf_counter() - s0
     ell["fp64_single_rhs_solves_per_s"] = len(rhs) / ts
     ell["fp64_iters_mean"] = float(np.mean(iters64))
+    ell["fp64_matvecs_mean"] = float(np.mean(mv64))
     ell["speedup_batched_mixed_over_fp64_single"] = ell[f"tol_{tol:g}"]["solves_per_s"] / ell[
         "fp64_single_rhs_solves_per_s"]
     prof = t.profile_matvec(rhs, P, precision="mixed", reps=3)
@@ -554,6 +586,9 @@ def main():
         log("cpu_baseline (FP64 oracle)")
         from oracle import targets
         cpu = cpu_baseline(targets.make(w["shape"], w["shpar"]), kd, w["m"], rhs[0], st64[0]["iters"])
+        if extras:
+            log("per-configuration oracle rates")
+            cpu["per_config"] = cpu_per_config(dda, inputs, extras)
     out = {
         "metric": "FFT dipole matvecs/sec + solves/sec at 1e-5 rel. residual; p50/p99 latency",
         "value": solves / total,
