@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOAD = "sphere_d133"
+PASS_TIMING_EVERY = 4
 SOLVER = "cocg"
 PEAK_HBM_GBS = 8000.0
 # FP32 / FP64 vector issue without packed math: 256 CUs x 4 SIMDs, one wave
@@ -72,6 +73,23 @@ def pass_bytes(box, grid, n_sites, fp32=True, nrhs=1):
     _, z = algorithmic_bytes(box, grid, n_sites, fp32, nrhs)
     return dict(x_forward=nrhs * (48 * n_sites + a_b), y_forward=nrhs * (a_b + b_b), z_pass=z,
                 y_inverse=nrhs * (a_b + b_b), x_inverse=nrhs * (a_b + 2 * 48 * n_sites))
+
+
+# FP32 vector peak without packed math (this build keeps packed FP32 off): 256 CUs x 4 SIMDs x 16 lanes x
+# 2 flops per fused multiply-add x 2.4 GHz
+PEAK_FP32_UNPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def zpass_alu_roofline(grid, nrhs, ms):
+    """The z-pass against the vector-ALU bound: algorithmic flops per launch (per column and RHS three
+    forward and three inverse complex transforms of length Mz at 5 Mz log2 Mz flops each, and the 3x3
+    complex multiply at 72 flops per frequency) over the launch time."""
+    Mx, My, Mz = grid
+    flops = nrhs * Mx * My * (6 * 5 * Mz * math.log2(Mz) + 72 * Mz)
+    achieved = flops / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": "z_pass", "achieved": achieved, "peak": PEAK_FP32_UNPACKED_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_UNPACKED_TFLOPS, "algorithmic_flops_per_launch": flops,
+            "rhs_per_launch": nrhs, "launch_ms": ms}
 
 
 KERNEL_PREFIX = dict(x_forward="k_xfwd", y_forward="k_yfwd", z_pass="k_zpass", y_inverse="k_yinv",
@@ -504,6 +522,8 @@ def main():
         step(args.tol)
     torch.cuda.synchronize()
     log(f"{WORKLOAD}: {args.steps} timed steps")
+    # HIP events around the five passes of every PASS_TIMING_EVERY-th product the timed solves launch
+    t.set_pass_timing(PASS_TIMING_EVERY)
     lat = []
     mv = 0
     outer = 0
@@ -517,6 +537,8 @@ def main():
         outer += sum(x["outer"] for x in st)
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
+    in_solve, n_timed = t.pass_timing("mixed")
+    t.set_pass_timing(0)
     assert all(x["status"] == 0 and x["rel_resid"] <= args.tol for x in st), st
     solves = len(rhs) * args.steps
 
@@ -563,7 +585,9 @@ def main():
     Pr = torch.tensor(inputs.random_polarization(n, len(rhs), seed=1), device="cuda")
     prof = t.profile_matvec(rhs, Pr, precision="mixed", reps=20)
     prof64 = t.profile_matvec(rhs[:1], Pr[:1].contiguous(), precision="fp64", reps=10)
-    dom, prod = roofline(prof, info["box"], info["grid"], n, len(rhs), WORKLOAD)
+    dom, prod = roofline(in_solve, info["box"], info["grid"], n, len(rhs), WORKLOAD)
+    dom_alu = zpass_alu_roofline(info["grid"], len(rhs), in_solve["z_pass"])
+    dom_iso, prod_iso = roofline(prof, info["box"], info["grid"], n, len(rhs), WORKLOAD)
     dom64, prod64 = roofline(prof64, info["box"], info["grid"], n, 1, WORKLOAD, fp32=False)
     mie = ref.get("mie") if ref else None
     # far field of the last solve: Q_sca by quadrature (the dipole array's optical theorem) and <cos theta>
@@ -625,7 +649,13 @@ def main():
         "fp64_single_rhs": {"solves_per_s": 1.0 / fp64_s, "iters": [x["iters"] for x in st64],
                             "q_err_vs_oracle": _ref_errors(q64, ref),
                             "speedup_mixed_batched_over_fp64_single": (solves / total) * fp64_s},
+        "pass_timing_in_solve": {"every": PASS_TIMING_EVERY, "products_timed": n_timed, "ms": in_solve,
+                                 "note": "HIP events on the solve's stream around each pass of the sampled "
+                                         "products of the timed steps; roofline and product_roofline use it"},
         "matvec_event_ms": {"mixed_2rhs": prof, "fp64_1rhs": prof64},
+        "roofline_alu": dom_alu,
+        "roofline_isolated_passes": {"roofline": dom_iso, "product_roofline": prod_iso,
+                                     "note": "each pass launched alone 20 times back to back"},
         "matvec_only_per_s": {"mixed": len(rhs) * 1e3 / prof["total"], "fp64": 1e3 / prof64["total"]},
         "roofline": dom,
         "product_roofline": prod,

@@ -417,6 +417,26 @@ void dda_free_target(dda_target *t);
 int dda_profile_matvec(dda_target *t, const dda_rhs *rhs, int32_t nrhs, int32_t precision, int32_t reps,
                        const void *p_dev, void *ap_dev, void *stream, double ms_per_pass[6]);
 
+/* Timing of the FFT passes of the products inside dda_solve (the products of
+ * the Krylov iterations and of the FP64 residual checks, §13), as they run in
+ * the solve.  With every >= 1, every every-th product that a dda_solve on this
+ * handle launches eagerly records a HIP event on the solve's stream before each
+ * of its five passes and after the last (at most 512 products between two host
+ * synchronisations of the solve; products replayed from a captured graph are
+ * not timed); the solve reads the events back at its own synchronisations and
+ * adds each pass's duration to per-precision sums.  every = 0 stops timing.
+ * Each call resets the sums.  The first call with every >= 1 creates the
+ * handle's 3072 events, which live as long as the handle.  Errors: DDA_EINVAL
+ * (NULL, every < 0), DDA_EHIP. */
+int dda_set_pass_timing(dda_target *t, int32_t every);
+
+/* The sums of dda_set_pass_timing for the products in `precision` (DDA_MIXED:
+ * the FP32 products; DDA_FP64: the FP64 ones): ms (host [5]) the total
+ * milliseconds of each pass (x-forward, y-forward, z-pass, y-inverse,
+ * x-inverse) and *products the number of timed products.  Errors: DDA_EINVAL
+ * (NULL, unknown precision). */
+int dda_get_pass_timing(const dda_target *t, int32_t precision, double ms[5], int64_t *products);
+
 /* ---- diagnostics --------------------------------------------------------- */
 
 /* Batched 1-D complex FFT (in_dev may equal out_dev) of length n (2/3/5-smooth, <= 512) on

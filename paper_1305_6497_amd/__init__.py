@@ -320,6 +320,22 @@ class Target:
                                             _stream_ptr(stream)))
         return out
 
+    def set_pass_timing(self, every=1):
+        """Time the FFT passes of every `every`-th product inside solve() with HIP events (0: off);
+        resets the sums."""
+        L.check(self._lib.dda_set_pass_timing(self._h, int(every)))
+
+    def pass_timing(self, precision="mixed"):
+        """Average ms per launch of each pass over the products timed inside solves since
+        set_pass_timing, and their count."""
+        ms = (ctypes.c_double * 5)()
+        n = ctypes.c_int64()
+        L.check(self._lib.dda_get_pass_timing(self._h, PRECISION[precision], ms, ctypes.byref(n)))
+        names = ("x_forward", "y_forward", "z_pass", "y_inverse", "x_inverse")
+        avg = {k: (v / n.value if n.value else None) for k, v in zip(names, list(ms))}
+        avg["total"] = sum(ms) / n.value if n.value else None
+        return avg, n.value
+
     def profile_matvec(self, rhs, P, precision="mixed", reps=20, stream=None):
         """Average ms of each FFT pass (and the whole product) over reps products."""
         P = self._checked(P, len(rhs))

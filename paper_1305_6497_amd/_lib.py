@@ -99,6 +99,9 @@ SIGNATURES = [
     ("dda_target_get_info", ctypes.c_int, [_VP, ctypes.POINTER(TargetInfo)]),
     ("dda_set_plan_variant", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     ("dda_set_zpass_variant", ctypes.c_int, [_VP, ctypes.c_int32]),
+    ("dda_set_pass_timing", ctypes.c_int, [_VP, ctypes.c_int32]),
+    ("dda_get_pass_timing", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_int64)]),
     ("dda_pass_plan", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_int32)]),
     ("dda_zpass_plan", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),

@@ -77,6 +77,17 @@ struct dda_target {
   uint64_t graph_gen = 0;
   uint64_t buffer_gen = 0;        // bumped whenever workspaces are reallocated
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // per-pass event timing of the products inside dda_solve (dda_set_pass_timing):
+  // every pt_every-th eager product records six events (before each pass and
+  // after the last); the call reads them back at its host synchronisations
+  static constexpr int kPassTimingSets = 512;
+  int pt_every = 0, pt_used = 0;
+  int64_t pt_seen = 0;
+  bool pt_active = false;          // inside dda_solve, not under graph capture
+  std::vector<hipEvent_t> pt_ev;   // kPassTimingSets * 6
+  std::vector<int> pt_prec;
+  double pt_ms[2][5] = {};
+  int64_t pt_n[2] = {};
   uint64_t bytes = 0;
   struct Block {
     void *p;
@@ -110,6 +121,31 @@ struct dda_target {
     (void)hipEventRecord(e, s);
     uses.push_back({s, e});
   }
+  // event sets for this product, or nullptr (timing off, not sampled, all sets in use)
+  const hipEvent_t *pt_next(int precision) {
+    if (!pt_active || pt_every <= 0 || pt_used >= kPassTimingSets) return nullptr;
+    if (pt_seen++ % pt_every != 0) return nullptr;
+    pt_prec[pt_used] = precision;
+    return &pt_ev[(size_t)6 * pt_used++];
+  }
+  // add the recorded sets to the sums; called once the stream they were
+  // recorded on has been synchronised
+  void pt_harvest() {
+    for (int i = 0; i < pt_used; ++i) {
+      float ms[5];
+      bool ok = true;
+      for (int k = 0; k < 5 && ok; ++k)
+        ok = hipEventElapsedTime(&ms[k], pt_ev[(size_t)6 * i + k], pt_ev[(size_t)6 * i + k + 1]) == hipSuccess;
+      if (!ok) {
+        (void)hipGetLastError();
+        continue;
+      }
+      const int p = pt_prec[i] == DDA_MIXED ? 1 : 0;
+      for (int k = 0; k < 5; ++k) pt_ms[p][k] += ms[k];
+      ++pt_n[p];
+    }
+    pt_used = 0;
+  }
   // wait for every piece of work this handle has queued
   void quiesce() {
     for (auto &u : uses) (void)hipEventSynchronize(u.second);
@@ -133,12 +169,24 @@ struct dda_target {
     if (graph) (void)hipGraphExecDestroy(graph);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
+    for (hipEvent_t e : pt_ev) (void)hipEventDestroy(e);
     for (auto &a : allocs) dev_release(device, a.p, a.granted);
     for (auto &u : uses) (void)hipEventDestroy(u.second);
     if (upload_done) (void)hipEventDestroy(upload_done);
     pinned_release(h_status, h_status_granted);
     pinned_release(h_scal, h_scal_granted);
     if (stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+// Pass timing is on inside dda_solve only; sets not read back when the call
+// ends (an error path) are dropped.
+struct PassTimingScope {
+  dda_target *t;
+  explicit PassTimingScope(dda_target *t_) : t(t_) { t->pt_active = true; }
+  ~PassTimingScope() {
+    t->pt_active = false;
+    t->pt_used = 0;
   }
 };
 
@@ -366,6 +414,7 @@ void upload_rhs(dda_target *t, const std::vector<RhsDev> &rd, const std::vector<
 void matvec_on(dda_target *t, int precision, const c64 *in, c64 *out, int nrhs, const int *mask, const c64 *ainv,
                void *bufA, void *bufB, hipStream_t s, const hipEvent_t *ev = nullptr, int only_pass = -1,
                int reps = 1, const FuseArgs *fuse = nullptr) {
+  if (!ev && only_pass < 0) ev = t->pt_next(precision);
   MatvecArgs a{};
   if (fuse) a.fuse = *fuse;
   a.in = in;
@@ -556,13 +605,17 @@ void run_iterations(dda_target *t, int precision, int solver, int K, bool use_gr
     }
     hipGraph_t g = nullptr;
     DDA_HIP(hipStreamBeginCapture(t->stream, hipStreamCaptureModeThreadLocal));
+    const bool timing = t->pt_active;
+    t->pt_active = false;        // no timing events inside the captured block
     try {
       for (int it = 0; it < K; ++it) step(t, precision, solver, t->stream);
     } catch (...) {
+      t->pt_active = timing;
       (void)hipStreamEndCapture(t->stream, &g);
       if (g) (void)hipGraphDestroy(g);
       throw;
     }
+    t->pt_active = timing;
     DDA_HIP(hipStreamEndCapture(t->stream, &g));
     hipError_t e = hipGraphInstantiate(&t->graph, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -867,6 +920,46 @@ int dda_set_plan_variant(dda_target *t, int32_t pass, int32_t variant) {
 
 int dda_set_zpass_variant(dda_target *t, int32_t variant) { return dda_set_plan_variant(t, kPassZ, variant); }
 
+int dda_set_pass_timing(dda_target *t, int32_t every) {
+  return guarded([&]() -> int {
+    DDA_REQUIRE(t != nullptr, "NULL argument");
+    DDA_REQUIRE(every >= 0, "every must be >= 0");
+    DDA_HIP(hipSetDevice(t->device));
+    if (every > 0 && t->pt_ev.empty()) {
+      std::vector<hipEvent_t> ev((size_t)6 * dda_target::kPassTimingSets, nullptr);
+      for (auto &e : ev) {
+        const hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) {
+          for (hipEvent_t x : ev)
+            if (x) (void)hipEventDestroy(x);
+          DDA_HIP(err);
+        }
+      }
+      t->pt_ev.swap(ev);
+      t->pt_prec.assign(dda_target::kPassTimingSets, 0);
+    }
+    t->pt_every = every;
+    t->pt_used = 0;
+    t->pt_seen = 0;
+    for (int p = 0; p < 2; ++p) {
+      t->pt_n[p] = 0;
+      for (int k = 0; k < 5; ++k) t->pt_ms[p][k] = 0.0;
+    }
+    return DDA_OK;
+  });
+}
+
+int dda_get_pass_timing(const dda_target *t, int32_t precision, double ms[5], int64_t *products) {
+  return guarded([&]() -> int {
+    DDA_REQUIRE(t && ms && products, "NULL argument");
+    DDA_REQUIRE(precision == DDA_FP64 || precision == DDA_MIXED, "unknown precision");
+    const int p = precision == DDA_MIXED ? 1 : 0;
+    for (int k = 0; k < 5; ++k) ms[k] = t->pt_ms[p][k];
+    *products = t->pt_n[p];
+    return DDA_OK;
+  });
+}
+
 int dda_incident_field(dda_target *t, const dda_rhs *rhs, int32_t nrhs, void *e_dev, void *stream) {
   return guarded([&]() -> int {
     DDA_REQUIRE(t && e_dev, "NULL argument");
@@ -1008,6 +1101,7 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     DDA_HIP(hipSetDevice(t->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     StreamUse use_{t, s};
+    PassTimingScope timing_{t};
     // iterations between host checks: fixed, or (check_every <= 0, eager
     // launches) a first block of 8 (or -check_every) iterations, then blocks
     // predicted from the recursive residual's decay since the last check, so
@@ -1066,6 +1160,7 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
         if (adaptive)
           DDA_HIP(hipMemcpyAsync(t->h_scal, k.scal, scal.size() * sizeof(c64), hipMemcpyDeviceToHost, s));
         DDA_HIP(hipStreamSynchronize(s));
+        t->pt_harvest();
         std::copy(t->h_status, t->h_status + nrhs, status.begin());
         if (adaptive) std::copy(t->h_scal, t->h_scal + scal.size(), scal.begin());
       }
@@ -1107,6 +1202,7 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
         k_true_residual(k, k.t, s);
         DDA_HIP(hipMemcpyAsync(t->h_scal, k.scal, scal.size() * sizeof(c64), hipMemcpyDeviceToHost, s));
         DDA_HIP(hipStreamSynchronize(s));
+        t->pt_harvest();
         std::copy(t->h_scal, t->h_scal + scal.size(), scal.begin());
         bool any_restart = false;
         for (int r = 0; r < nrhs; ++r) {
@@ -1149,6 +1245,7 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     if (p_dev) DDA_HIP(hipMemcpyAsync(p_dev, k.x, vec, hipMemcpyDeviceToDevice, s));
     if (p_host) DDA_HIP(hipMemcpyAsync(p_host, k.x, vec, hipMemcpyDeviceToHost, s));
     DDA_HIP(hipStreamSynchronize(s));
+    t->pt_harvest();
     std::copy(t->h_scal, t->h_scal + scal.size(), scal.begin());
     bool all_ok = true;
     for (int r = 0; r < nrhs; ++r) {
