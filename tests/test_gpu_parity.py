@@ -457,6 +457,35 @@ def test_full_size_efficiencies_against_oracle(dda, name, prec, solver):
             assert abs(q[i][key] - r[key]) <= 1e-7 * abs(r["qext"]), (name, prec, i, key, q[i][key], r[key])
 
 
+# The largest configuration (D = 133 sphere, N = 1232177, grid 270^3) as the
+# timed solve runs it: both polarizations in one batch, COCG, here to 1e-9;
+# every RHS with a stored oracle solve is compared to 1e-7 of Q_ext.
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_sphere_d133_efficiencies_against_oracle(dda, prec):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "reference_sphere_d133.json")) as f:
+        ref = json.load(f)
+    if not ref["results"]:
+        pytest.skip("no stored oracle solve of sphere_d133")
+    w = inputs.WORKLOADS["sphere_d133"]
+    sites, box = dda.make_sites(w["shape"], w["shpar"])
+    assert len(sites) == ref["n_sites"]
+    kd = dda.kd_from_x(w["x"], len(sites))
+    assert abs(kd - ref["kd"]) <= 1e-15 * kd
+    rhs = [dda.orient_rhs(0.0, 0.0, 0.0, which=k + 1) for k in range(w["polarizations"])]
+    t = dda.Target(sites, box, m=w["m"], kd=kd)
+    P, st = t.solve(rhs, tol=1e-9, precision=prec, max_iter=20000, solver="cocg")
+    q = t.cross_sections(rhs, P)
+    t.close()
+    assert all(s["status"] == 0 and s["rel_resid"] <= 1e-9 for s in st), st
+    for r in ref["results"]:
+        i = r["rhs"]
+        assert np.allclose(r["khat"], rhs[i][0], atol=1e-15) and np.allclose(r["e_re"], np.real(rhs[i][1]), atol=1e-15)
+        for key in ("qext", "qabs", "qsca"):
+            assert abs(q[i][key] - r[key]) <= 1e-7 * abs(r["qext"]), (prec, i, key, q[i][key], r[key])
+
+
 def test_bicgstab2_follows_the_oracle_recurrence(dda):
     # Same algorithm, same FP64 arithmetic up to rounding order (and the
     # normal equations of the 2x2 minimal-residual step instead of a QR): the
