@@ -149,8 +149,17 @@ typedef struct {
   const void *x0;          /* NULL: the guide's start P = 0 (§12).  Otherwise a device
                               [nrhs][N][3] dda_c64 initial guess (read only): its FP64 true
                               residual is checked first (one product, counted as one outer
-                              pass); an RHS already within tol returns x0 unchanged, the others
-                              iterate from it as from a refinement restart */
+                              pass); an RHS already within tol returns x0 unchanged (up to
+                              rounding with jacobi), the others iterate from it as from a
+                              refinement restart */
+  int32_t jacobi;          /* 1: symmetric diagonal (Jacobi) scaling, the diagonal
+                              preconditioning of the PIM solvers §12 cites: the iterations solve
+                              (S A S) y = S E with S = diag(alpha)^(1/2) (principal root, one
+                              value per composition and component, so S A S has unit diagonal
+                              and stays complex symmetric) and return P = S y; tol and
+                              rel_resid then refer to |S (E - A P)| / |S E|, which for one
+                              composition with a scalar alpha (LDR, CMRR, FCD) is |E - A P| / |E|.
+                              0: none */
 } dda_solve_opts;
 
 typedef struct {

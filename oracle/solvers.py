@@ -74,7 +74,25 @@
       d_n = (v_n - zeta_n d_{n-1} - eps_n d_{n-2}) / gamma_n,   x_n = x_{n-1} + tau_n d_n.
   The quasi-residual |phi_{n+1}| bounds the true residual by
   sqrt(n+1) |phi_{n+1}|; when |phi_{n+1}| <= tol |E| the true residual is
-  computed and, if it does not pass, the method restarts from the current x.
+  computed and, if it does not pass, the run goes on until |phi| has fallen
+  by the factor the true residual still misses, and is checked again (a
+  restart from the true residual would begin with a quasi-residual already
+  near the threshold, check after one step and stall); it restarts only on
+  a Lanczos breakdown.
+* ``jacobi_scaled``: symmetric diagonal (Jacobi) scaling around any of the
+  solvers above.  The guide's PBCGST option comes from a package of
+  preconditioned iterative methods (§12) and says no more about the
+  preconditioner; diagonal scaling is the simplest one.  Written symmetrically
+  it keeps the matrix complex symmetric, which COCG and QMR need: with
+  D = diag(A) (1/alpha of every site and component) and S = D^(-1/2)
+  (principal root),
+
+      (S A S) y = S E,   P = S y,
+
+  and S A S has unit diagonal.  The stopping rule then applies to the scaled
+  system, |S (E - A P)| / |S E|; when S is a multiple of the identity (one
+  composition, scalar 1/alpha) that is |E - A P| / |E| and the iterates are
+  those of the unscaled solver.
 """
 
 import numpy as np
@@ -331,6 +349,7 @@ def qmr_cs(matvec, b, tol=1e-10, maxiter=10000, x0=None, trace=None):
     first = True
     while it < maxiter:
         # one Lanczos run from the residual r of the current x
+        thr = tol * nb
         rho = np.linalg.norm(r)
         v = r / rho
         v_old = np.zeros_like(b)
@@ -371,13 +390,18 @@ def qmr_cs(matvec, b, tol=1e-10, maxiter=10000, x0=None, trace=None):
             c2, s2, c1, s1 = c1, s1, c, sn
             if first and trace is not None:
                 trace.append((x.copy(), abs(phi)))
-            if abs(phi) <= tol * nb or rho_next == 0.0:
+            if abs(phi) <= thr or rho_next == 0.0:
                 r = b - mv(x)
                 nmv += 1
                 rel = np.linalg.norm(r) / nb
                 if rel <= tol:
                     return x.reshape(shape), dict(iters=it, matvecs=nmv, rel_resid=rel, converged=True)
-                break                        # restart from the true residual
+                if rho_next == 0.0:
+                    break                    # Krylov space exhausted: restart from the true residual
+                # the quasi-residual passed but the true residual did not:
+                # the same run goes on until the quasi-residual has fallen
+                # by the factor still missing
+                thr = abs(phi) * tol / rel
             v_old = v
             v = w / rho_next
             delta_old = delta
@@ -385,3 +409,12 @@ def qmr_cs(matvec, b, tol=1e-10, maxiter=10000, x0=None, trace=None):
         first = False
     rel = np.linalg.norm(b - mv(x)) / nb
     return x.reshape(shape), dict(iters=it, matvecs=nmv + 1, rel_resid=rel, converged=rel <= tol)
+
+
+def jacobi_scaled(solver, matvec, b, diag, x0=None, **kw):
+    """Solve A x = b by ``solver`` on (S A S) y = S b, S = diag^(-1/2); returns (S y, info).
+
+    diag: the diagonal of A, complex [3N] (1/alpha per site and component)."""
+    s = 1.0 / np.sqrt(np.asarray(diag, dtype=complex))
+    y, info = solver(lambda v: s * matvec(s * v), s * b, x0=None if x0 is None else x0 / s, **kw)
+    return s * y, info

@@ -214,7 +214,7 @@ class Target:
         return _checked_vec(v, nrhs, self.n, self.device)
 
     def solve(self, rhs, tol=1e-5, max_iter=1000, precision="fp64", inner_tol=0.0, max_outer=20, check_every=0,
-              out=None, stream=None, use_graph=False, solver="bicgstab", fold_records=0, x0=None):
+              out=None, stream=None, use_graph=False, solver="bicgstab", fold_records=0, x0=None, jacobi=False):
         """Solve A P = E for every (khat, e) in rhs.  Returns (P, stats).
 
         solver: "bicgstab" (the guide's PBCGST), "bicgstab2" (BiCGstab(2), the
@@ -223,14 +223,17 @@ class Target:
         picks them from the residual decay after a first block of 8, -n does
         the same after a first block of n.  fold_records: tuning only (results
         are bit-identical), see dda_solve_opts.  x0: optional initial guess,
-        a contiguous complex128 [nrhs, N, 3] device tensor (default P = 0)."""
+        a contiguous complex128 [nrhs, N, 3] device tensor (default P = 0).
+        jacobi: symmetric diagonal scaling S A S with S = diag(alpha)^(1/2)
+        (tol then bounds |S(E - A P)| / |S E|, the same as |E - A P| / |E| for
+        one composition with a scalar polarizability)."""
         nrhs = len(rhs)
         x0 = None if x0 is None else self._checked(x0, nrhs)
         P = self._vec(nrhs) if out is None else self._checked(out, nrhs)
         opts = L.SolveOpts(tol=tol, max_iter=max_iter, precision=PRECISION[precision], inner_tol=inner_tol,
                            max_outer=max_outer, check_every=check_every, use_graph=int(bool(use_graph)),
                            solver=SOLVER[solver], fold_records=fold_records,
-                           x0=None if x0 is None else x0.data_ptr())
+                           x0=None if x0 is None else x0.data_ptr(), jacobi=int(bool(jacobi)))
         st = (L.SolveStats * nrhs)()
         code = L.check(self._lib.dda_solve(self._h, _rhs_array(rhs), nrhs, ctypes.byref(opts),
                                            ctypes.c_void_p(P.data_ptr()), None, _stream_ptr(stream), st),

@@ -52,7 +52,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("solver", ctypes.c_int32), ("fold_records", ctypes.c_int32),
-                ("x0", ctypes.c_void_p)]
+                ("x0", ctypes.c_void_p), ("jacobi", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):

@@ -50,6 +50,8 @@ struct dda_target {
   int kr_nrhs = 0;
   KrylovState k;
   c64 *d_ainv = nullptr;
+  c64 *d_scl = nullptr;            // Jacobi scaling s per RHS, composition, component
+  bool jacobi_active = false;      // inside a dda_solve with opts->jacobi
   RhsDev *d_rhs = nullptr;
   double *d_sums = nullptr;
   int *d_restart = nullptr;
@@ -57,6 +59,7 @@ struct dda_target {
   // reads them has completed (upload_done)
   std::vector<RhsDev> h_rhs;
   std::vector<c64> h_ainv;
+  std::vector<c64> h_scl;
   hipEvent_t upload_done = nullptr;
   // pinned host copies of the per-RHS status and scalars read at every host
   // check of a solve (a pinned copy returns sooner than a pageable one)
@@ -66,7 +69,7 @@ struct dda_target {
   int h_nrhs = 0;
   // captured block of BiCGSTAB iterations (see run_iterations)
   hipGraphExec_t graph = nullptr;
-  int graph_nrhs = 0, graph_prec = -1, graph_k = 0, graph_solver = -1, graph_fold = -1;
+  int graph_nrhs = 0, graph_prec = -1, graph_k = 0, graph_solver = -1, graph_fold = -1, graph_jacobi = -1;
   // products with at most this many partial records per RHS hand their
   // scalar (alpha, omega) to the consuming kernel, which computes it in every
   // block; larger ones get a one-block kernel first (set by each solve)
@@ -190,6 +193,13 @@ struct PassTimingScope {
   }
 };
 
+// The products of a dda_solve with opts->jacobi use the scaling; others never.
+struct JacobiScope {
+  dda_target *t;
+  JacobiScope(dda_target *t_, bool on) : t(t_) { t->jacobi_active = on; }
+  ~JacobiScope() { t->jacobi_active = false; }
+};
+
 // Records, when the call returns, that the handle queued work on stream s.
 struct StreamUse {
   dda_target *t;
@@ -298,7 +308,7 @@ size_t krylov_bytes(const Geometry &g, int nrhs) {
   const int nblk = std::max(krylov_blocks(n3), std::max(xpass_blocks(g, true), xpass_blocks(g, false)));
   return 9 * vec + 2 * (size_t)nrhs * nblk * kPart * sizeof(double) + (size_t)nrhs * kScal * sizeof(c64) +
          4 * (size_t)nrhs * sizeof(int) + (size_t)nrhs * (sizeof(RhsDev) + 2 * sizeof(double)) +
-         (size_t)nrhs * 255 * 3 * sizeof(c64);
+         2 * (size_t)nrhs * 255 * 3 * sizeof(c64);
 }
 
 // Workspaces grow on demand.  Work already queued on s may still use the old
@@ -339,6 +349,7 @@ void ensure_krylov(dda_target *t, int nrhs, hipStream_t s) {
   t->release(k.status);
   t->release(k.check);
   t->release(t->d_ainv);
+  t->release(t->d_scl);
   t->release(t->d_rhs);
   t->release(t->d_sums);
   t->release(t->d_restart);
@@ -364,6 +375,7 @@ void ensure_krylov(dda_target *t, int nrhs, hipStream_t s) {
   k.check = t->alloc<int>(nrhs * sizeof(int));
   t->d_restart = t->alloc<int>(nrhs * sizeof(int));
   t->d_ainv = t->alloc<c64>((size_t)nrhs * t->ncomp * 3 * sizeof(c64));
+  t->d_scl = t->alloc<c64>((size_t)nrhs * t->ncomp * 3 * sizeof(c64));
   t->d_rhs = t->alloc<RhsDev>(nrhs * sizeof(RhsDev));
   t->d_sums = t->alloc<double>(3 * nrhs * sizeof(double));
   t->kr_nrhs = nrhs;
@@ -400,14 +412,33 @@ void prepare_rhs(dda_target *t, const dda_rhs *rhs, int nrhs, std::vector<RhsDev
   }
 }
 
-void upload_rhs(dda_target *t, const std::vector<RhsDev> &rd, const std::vector<c64> &ainv, hipStream_t s) {
+void upload_rhs(dda_target *t, const std::vector<RhsDev> &rd, const std::vector<c64> &ainv, hipStream_t s,
+                const std::vector<c64> *scl = nullptr) {
   if (!t->upload_done) DDA_HIP(hipEventCreateWithFlags(&t->upload_done, hipEventDisableTiming));
   DDA_HIP(hipEventSynchronize(t->upload_done));      // previous upload has read the staging
   t->h_rhs = rd;
   t->h_ainv = ainv;
   DDA_HIP(hipMemcpyAsync(t->d_rhs, t->h_rhs.data(), rd.size() * sizeof(RhsDev), hipMemcpyHostToDevice, s));
   DDA_HIP(hipMemcpyAsync(t->d_ainv, t->h_ainv.data(), ainv.size() * sizeof(c64), hipMemcpyHostToDevice, s));
+  if (scl) {
+    t->h_scl = *scl;
+    DDA_HIP(hipMemcpyAsync(t->d_scl, t->h_scl.data(), scl->size() * sizeof(c64), hipMemcpyHostToDevice, s));
+  }
   DDA_HIP(hipEventRecord(t->upload_done, s));
+}
+
+// Symmetric diagonal (Jacobi) scaling of the system: s = (1/alpha)^(-1/2)
+// (principal root) per RHS, composition and component; 1/alpha is replaced by
+// the diagonal of S A S, s (1/alpha) s (= 1 up to rounding).
+void jacobi_scaling(std::vector<c64> &ainv, std::vector<c64> &scl) {
+  scl.resize(ainv.size());
+  for (size_t i = 0; i < ainv.size(); ++i) {
+    const std::complex<double> a(ainv[i].x, ainv[i].y);
+    const std::complex<double> sv = 1.0 / std::sqrt(a);
+    const std::complex<double> dg = sv * a * sv;
+    scl[i] = c64{sv.real(), sv.imag()};
+    ainv[i] = c64{dg.real(), dg.imag()};
+  }
 }
 
 // The product on explicit 1/alpha and work buffers (see MatvecArgs).
@@ -416,6 +447,11 @@ void matvec_on(dda_target *t, int precision, const c64 *in, c64 *out, int nrhs, 
                int reps = 1, const FuseArgs *fuse = nullptr) {
   if (!ev && only_pass < 0) ev = t->pt_next(precision);
   MatvecArgs a{};
+  if (t->jacobi_active) {
+    a.scl.s = t->d_scl;
+    a.scl.comp = t->d_comp;
+    a.scl.ncomp = t->ncomp;
+  }
   if (fuse) a.fuse = *fuse;
   a.in = in;
   a.out = out;
@@ -598,7 +634,8 @@ void run_iterations(dda_target *t, int precision, int solver, int K, bool use_gr
     DDA_HIP(hipEventCreateWithFlags(&t->ev_out, hipEventDisableTiming));
   }
   if (!t->graph || t->graph_nrhs != t->k.nrhs || t->graph_prec != precision || t->graph_k != K ||
-      t->graph_solver != solver || t->graph_fold != t->fold_records || t->graph_gen != t->buffer_gen) {
+      t->graph_solver != solver || t->graph_fold != t->fold_records || t->graph_gen != t->buffer_gen ||
+      t->graph_jacobi != (int)t->jacobi_active) {
     if (t->graph) {
       DDA_HIP(hipGraphExecDestroy(t->graph));
       t->graph = nullptr;
@@ -624,6 +661,7 @@ void run_iterations(dda_target *t, int precision, int solver, int K, bool use_gr
     t->graph_prec = precision;
     t->graph_solver = solver;
     t->graph_fold = t->fold_records;
+    t->graph_jacobi = (int)t->jacobi_active;
     t->graph_k = K;
     t->graph_gen = t->buffer_gen;
   }
@@ -1112,13 +1150,18 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     const bool adaptive = opts->check_every <= 0 && opts->use_graph == 0;
     const int max_outer = opts->max_outer > 0 ? opts->max_outer : 20;
     std::vector<RhsDev> rd;
-    std::vector<c64> ai;
+    std::vector<c64> ai, scl;
     prepare_rhs(t, rhs, nrhs, rd, ai);
+    const bool jacobi = opts->jacobi != 0;
+    if (jacobi) jacobi_scaling(ai, scl);
     ensure_krylov(t, nrhs, s);
     ensure_workspace(t, nrhs, s);
     KrylovState &k = t->k;
-    upload_rhs(t, rd, ai, s);
+    upload_rhs(t, rd, ai, s, jacobi ? &scl : nullptr);
     launch_incident(t->g, t->d_ijk, t->d_rhs, nrhs, t->kd, k.b, s);
+    // with Jacobi scaling the iterations solve (S A S) y = S E, and P = S y
+    JacobiScope jacobi_{t, jacobi};
+    if (jacobi) launch_scale(t->g, k.b, nrhs, t->d_scl, t->ncomp, t->d_comp, false, s);
     k_init_state(k, opts->tol, opts->max_iter, opts->solver, s);
 
     if (t->h_nrhs < nrhs) {
@@ -1149,6 +1192,7 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     const bool warm = opts->x0 != nullptr;
     if (warm) {
       DDA_HIP(hipMemcpyAsync(k.x, opts->x0, (size_t)k.n3 * nrhs * sizeof(c64), hipMemcpyDeviceToDevice, s));
+      if (jacobi) launch_scale(t->g, k.x, nrhs, t->d_scl, t->ncomp, t->d_comp, true, s);
       DDA_HIP(hipMemsetAsync(k.active, 0, nrhs * sizeof(int), s));
     }
     bool first = true;
@@ -1242,6 +1286,7 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     }
     DDA_HIP(hipMemcpyAsync(t->h_scal, k.scal, scal.size() * sizeof(c64), hipMemcpyDeviceToHost, s));
     const size_t vec = (size_t)k.n3 * nrhs * sizeof(c64);
+    if (jacobi) launch_scale(t->g, k.x, nrhs, t->d_scl, t->ncomp, t->d_comp, false, s);
     if (p_dev) DDA_HIP(hipMemcpyAsync(p_dev, k.x, vec, hipMemcpyDeviceToDevice, s));
     if (p_host) DDA_HIP(hipMemcpyAsync(p_host, k.x, vec, hipMemcpyDeviceToHost, s));
     DDA_HIP(hipStreamSynchronize(s));

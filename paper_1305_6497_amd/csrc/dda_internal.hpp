@@ -137,6 +137,21 @@ struct RhsDev {
 };
 
 // ------------------------------------------------------------ kernel API --
+// Symmetric diagonal (Jacobi) scaling of the product: with s non-null the
+// passes compute S A S y = S (1/alpha) S y - S G S y, S = diag(s) of one value
+// per RHS, composition and component ([nrhs][ncomp][3]): the x-forward
+// transforms s y and the x-inverse writes ainv y - s (G s y), ainv then
+// holding s (1/alpha) s.
+struct Scaling {
+  const c64 *s = nullptr;
+  const uint8_t *comp = nullptr;  // device [N] composition index, or nullptr (all 0)
+  int ncomp = 1;
+  __device__ __forceinline__ const c64 *rhs(int r) const { return s + (size_t)r * ncomp * 3; }
+  __device__ __forceinline__ c64 at(const c64 *sr, int site, int c) const {
+    return sr[(comp ? 3 * comp[site] : 0) + c];
+  }
+};
+
 // BiCGSTAB work fused into the first and last pass of a product.
 struct FuseArgs {
   int in_mode = 0;     // 0: transform `in` as given
@@ -187,6 +202,7 @@ struct MatvecArgs {
   const void *twx, *twy, *twz;    // twiddles of the T precision
   AxisPlan px, py, pz;
   FuseArgs fuse;
+  Scaling scl;                    // Jacobi scaling (s = nullptr: none)
   int zvar = -1;                  // z-pass plan variant (0..3), or -1: the tuned table's choice
   int xvar[2] = {-1, -1};         // x-forward / x-inverse rows-plan variant (0..1), or -1
 };
@@ -293,6 +309,9 @@ void k_true_residual(const KrylovState &k, const c64 *ax, hipStream_t s);
 void k_restart(const KrylovState &k, const int *restart, double tol, double inner_tol, int solver,
                hipStream_t s);
 
+// v <- S v (inverse: S^-1 v) for the Jacobi-scaled solve (see Scaling)
+void launch_scale(const Geometry &g, c64 *v, int nrhs, const c64 *scl, int ncomp, const uint8_t *comp, bool inverse,
+                  hipStream_t s);
 void launch_incident(const Geometry &g, const int32_t *ijk, const RhsDev *rhs, int nrhs, double kd,
                      c64 *e, hipStream_t s);
 // Sums per RHS: [0] = sum Im(conj(E) . P), [1] = sum_c (-Im(ainv_c) - (2/3) kd^3) |P_c|^2

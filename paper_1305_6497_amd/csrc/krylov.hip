@@ -583,6 +583,27 @@ void launch_incident(const Geometry &g, const int32_t *ijk, const RhsDev *rhs, i
   DDA_HIP(hipGetLastError());
 }
 
+// ------------------------------------------------------ Jacobi scaling --
+// v <- s v (inverse: v <- v / s), s per RHS, composition and component
+__global__ void kk_scale(c64 *v, int64_t n, const c64 *scl, int ncomp, const uint8_t *comp, int inverse) {
+  const int r = blockIdx.y;
+  const c64 *sr = scl + (size_t)r * ncomp * 3;
+  for (int64_t j = blockIdx.x * (int64_t)KNT + threadIdx.x; j < n; j += (int64_t)gridDim.x * KNT) {
+    const c64 *sj = sr + (comp ? 3 * comp[j] : 0);
+    c64 *vj = v + ((size_t)r * n + j) * 3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vj[c] = inverse ? cdiv(vj[c], sj[c]) : sj[c] * vj[c];
+  }
+}
+
+void launch_scale(const Geometry &g, c64 *v, int nrhs, const c64 *scl, int ncomp, const uint8_t *comp, bool inverse,
+                  hipStream_t s) {
+  const int64_t n = g.n_sites;
+  const unsigned nb = (unsigned)std::min<int64_t>((n + KNT - 1) / KNT, 2048);
+  hipLaunchKernelGGL(kk_scale, dim3(nb, nrhs), dim3(KNT), 0, s, v, n, scl, ncomp, comp, inverse ? 1 : 0);
+  DDA_HIP(hipGetLastError());
+}
+
 // --------------------------------------------------------- cross sections --
 // per site: Im(conj(E_j) . P_j)  and  sum_c (-Im(ainv_jc) - (2/3) kd^3) |P_jc|^2
 __global__ void kk_cross(const int32_t *ijk, int64_t n, const RhsDev *rhs, double kd, const c64 *P, const c64 *ainv,

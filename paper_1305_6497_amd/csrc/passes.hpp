@@ -240,7 +240,7 @@ __device__ __forceinline__ bool block_alpha(const FuseArgs &f, int r, c64 &alpha
 template <typename T, int EPT, int LC, int V>
 __global__ __launch_bounds__(kNT) void k_xfwd(const c64 *__restrict__ in, int64_t n3, const int *__restrict__ mask,
                                                const int *__restrict__ cell_site, const int4 *__restrict__ rowtab,
-                                               cpx<T> *__restrict__ A,
+                                               Scaling sc, cpx<T> *__restrict__ A,
                                                size_t a_elems, const cpx<T> *__restrict__ twx, AxisPlan px,
                                                PassDims d, FuseArgs f) {
   constexpr int W = kW<T>, LOGW = kLogW<T>;
@@ -297,12 +297,14 @@ __global__ __launch_bounds__(kNT) void k_xfwd(const c64 *__restrict__ in, int64_
         if (f.nax > 1) runs_axpy(u, n, f.ax_a[1] + j0, f.ax_b[1] + j0, f.ax_d[1] + j0, cf[1]);
         if (f.nax > 2) runs_axpy(u, n, f.ax_a[2] + j0, f.ax_b[2] + j0, f.ax_d[2] + j0, cf[2]);
       }
+      const c64 *sr = sc.s ? sc.rhs(r) : nullptr;
 #pragma unroll
       for (int i = 0; i < ER; ++i) {
         const int e = threadIdx.x + i * kNT;
         if (e < n) {
           const int st = e / 3;
-          buf[(e - 3 * st) * ne + rr.pos(st)] = to_t<T>(v[i]);
+          const c64 x = sr ? sc.at(sr, rr.first + st, e - 3 * st) * v[i] : v[i];
+          buf[(e - 3 * st) * ne + rr.pos(st)] = to_t<T>(x);
         }
       }
       for (int e = threadIdx.x; e < ne; e += kNT) {
@@ -362,6 +364,15 @@ __global__ __launch_bounds__(kNT) void k_xfwd(const c64 *__restrict__ in, int64_
             f.w[j] = val;
           }
           v[i][c] = val;
+        }
+    }
+    if (sc.s) {
+      const c64 *sr = sc.rhs(r);
+#pragma unroll
+      for (int i = 0; i < NE; ++i)
+        if (site[i] >= 0) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) v[i][c] = sc.at(sr, site[i], c) * v[i][c];
         }
     }
 #pragma unroll
@@ -668,7 +679,7 @@ __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *_
                                                const int *__restrict__ mask, const c64 *__restrict__ ainv,
                                                int ncomp, const uint8_t *__restrict__ comp,
                                                const int *__restrict__ cell_site, const int4 *__restrict__ rowtab,
-                                               const cpx<T> *__restrict__ A, size_t a_elems,
+                                               Scaling sc, const cpx<T> *__restrict__ A, size_t a_elems,
                                                const cpx<T> *__restrict__ twx, AxisPlan px, PassDims d, FuseArgs f) {
   constexpr int W = kW<T>, LOGW = kLogW<T>;
   constexpr int NE = (EPT + 2) / 3;
@@ -698,6 +709,13 @@ __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *_
   const size_t off = (size_t)r * n3;
   const c64 *ai = ainv + (size_t)r * ncomp * 3;      // [ncomp][3] of this RHS
   double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const c64 *sr = sc.s ? sc.rhs(r) : nullptr;
+  // with scaling the field term becomes s (G s P): each thread scales the
+  // transformed values it is about to read
+  auto scale_at = [&](int idx, int site, int c) {
+    const cpx<T> g = buf[idx];
+    buf[idx] = to_t<T>(sc.at(sr, site, c) * c64{double(g.x), double(g.y)});
+  };
   // out = ainv P - (G P) at one element; x is rh (out_mode 1) or r0 (out_mode 3)
   auto finish = [&](size_t j, c64 a, c64 pv, cpx<T> fv, c64 x) {
     const c64 dd = a * pv;
@@ -738,6 +756,16 @@ __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *_
       const RowRuns<NR> rr(rowtab, row0, nrow, LC);
       const int n = 3 * rr.count;
       const size_t j0 = off + (size_t)3 * rr.first;
+      if (sr) {
+#pragma unroll
+        for (int i = 0; i < ER; ++i) {
+          const int e = threadIdx.x + i * kNT;
+          if (e < n) {
+            const int st = e / 3;
+            scale_at((e - 3 * st) * ne + rr.pos(st), rr.first + st, e - 3 * st);
+          }
+        }
+      }
       c64 pv[ER], xv[ER], av[ER];
 #pragma unroll
       for (int i = 0; i < ER; ++i) {
@@ -774,6 +802,14 @@ __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *_
         const int q = (int)d.d_nx((uint32_t)e);
         bi[i] = q * Mx + (e - q * d.nx);
       }
+    }
+    if (sr) {
+#pragma unroll
+      for (int i = 0; i < NE; ++i)
+        if (site[i] >= 0) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) scale_at(c * ne + bi[i], site[i], c);
+        }
     }
     c64 pv[NE][3];
 #pragma unroll
@@ -921,7 +957,7 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
           constexpr int E = LC > 0 ? pick_ept_c((size_t)3 * xpass_rows(LC) * LC, true) : decltype(e)::value;
           auto go = [&](auto vv) {
             hipLaunchKernelGGL((k_xfwd<T, E, LC, decltype(vv)::value>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s,
-                               a.in, n3, a.mask, a.cell_site, a.rowtab, A, ae, twx, a.px, d, f);
+                               a.in, n3, a.mask, a.cell_site, a.rowtab, a.scl, A, ae, twx, a.px, d, f);
           };
           if constexpr (LC >= kTunedMinLen) {
             if (xv[0] == 1) go(IC<1>{});
@@ -994,8 +1030,8 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
           constexpr int E = LC > 0 ? pick_ept_c((size_t)3 * xpass_rows(LC) * LC, true) : decltype(e)::value;
           auto go = [&](auto vv) {
             hipLaunchKernelGGL((k_xinv<T, E, LC, decltype(vv)::value>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s,
-                               a.in, a.out, n3, a.mask, a.ainv, a.ncomp, a.comp, a.cell_site, a.rowtab, A, ae, twx,
-                               a.px, d, f);
+                               a.in, a.out, n3, a.mask, a.ainv, a.ncomp, a.comp, a.cell_site, a.rowtab, a.scl, A,
+                               ae, twx, a.px, d, f);
           };
           if constexpr (LC >= kTunedMinLen) {
             if (xv[1] == 1) go(IC<1>{});

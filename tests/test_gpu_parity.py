@@ -486,6 +486,72 @@ def test_sphere_d133_efficiencies_against_oracle(dda, prec):
             assert abs(q[i][key] - r[key]) <= 1e-7 * abs(r["qext"]), (prec, i, key, q[i][key], r[key])
 
 
+def _core_shell(dda):
+    # a 9 x 8 x 7 ellipsoid whose core (composition 1, m = 3 + i) has a ten
+    # times larger 1/alpha than its shell (composition 0, m = 1.3 + 0.01i)
+    sites, box = dda.make_sites("ELLIPSOID", (9, 8, 7))
+    osites = targets.ellipsoid(9, 8, 7)
+    assert np.array_equal(np.asarray(sites), osites)
+    c = (osites - osites.mean(axis=0)) / np.array([4.5, 4.0, 3.5])
+    comp = (np.sum(c * c, axis=1) < 0.35).astype(np.uint8)
+    return sites, box, osites, comp, [1.3 + 0.01j, 3.0 + 1.0j], 0.4
+
+
+@pytest.mark.parametrize("solver", SOLVERS)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_jacobi_scaled_solve_matches_dense_lu(dda, solver, prec):
+    # symmetric diagonal scaling on a two-composition target: the solution of
+    # A P = E (dense LU of the oracle's matrix) in fewer iterations than
+    # without scaling; in FP64, COCG and BiCGSTAB take the oracle's
+    # Jacobi-scaled iteration count
+    sites, box, osites, comp, ms, kd = _core_shell(dda)
+    rhs = [dda.orient_rhs(0.0, 0.0, 0.0, which=1)]
+    t = dda.Target(sites, box, m=ms, kd=kd, comp=comp)
+    Pj, sj = t.solve(rhs, tol=1e-10, precision=prec, solver=solver, jacobi=True, max_iter=2000)
+    Pj = Pj.cpu().numpy()[0]
+    _, sn = t.solve(rhs, tol=1e-10, precision=prec, solver=solver, max_iter=2000)
+    t.close()
+    # sites in another order: the x passes' per-cell path with the composition of each site
+    perm = np.random.default_rng(29).permutation(len(sites))
+    t = dda.Target(np.ascontiguousarray(sites[perm]), box, m=ms, kd=kd, comp=np.ascontiguousarray(comp[perm]))
+    Pp, sp = t.solve(rhs, tol=1e-10, precision=prec, solver=solver, jacobi=True, max_iter=2000)
+    Pp = Pp.cpu().numpy()[0]
+    t.close()
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(len(perm))
+    assert sp[0]["status"] == 0, sp
+    assert _rel(Pp[inv], Pj) < 1e-7
+    ai = np.array([_oracle_ainv(mm, kd, *rhs[0]) for mm in ms])[comp]
+    E = incident.incident_field(osites, kd, *rhs[0])
+    A = interaction.dense_matrix(osites, kd, ai)
+    P_lu = solvers.lu_solve(A, E.ravel()).reshape(-1, 3)
+    assert sj[0]["status"] == 0 and sn[0]["status"] == 0, (sj, sn)
+    assert _rel(Pj, P_lu) < 1e-7, (solver, prec)
+    assert sj[0]["iters"] < sn[0]["iters"], (sj, sn)
+    if prec == "fp64" and solver in ("cocg", "bicgstab"):
+        op = interaction.FFTOperator(osites, kd, ai)
+        diag = interaction.alpha_inv_diag(ai, len(osites)).ravel()
+        _, info = solvers.jacobi_scaled(getattr(solvers, solver), lambda v: op.matvec(v.reshape(-1, 3)).ravel(),
+                                        E.ravel(), diag, tol=1e-10)
+        assert abs(sj[0]["iters"] - info["iters"]) <= 2, (sj[0]["iters"], info["iters"])
+
+
+def test_jacobi_scaling_of_one_composition_keeps_the_solve(dda):
+    # one composition, scalar 1/alpha: S is a multiple of I, the criterion is
+    # the unscaled one and the iterations are the same
+    sites, box = dda.make_sites("ELLIPSOID", (13, 11, 9))
+    rhs = [dda.orient_rhs(0.4, 0.9, 1.3, which=2)]
+    t = dda.Target(sites, box, m=1.6 + 0.02j, kd=0.55)
+    for solver in SOLVERS:
+        P0, s0 = t.solve(rhs, tol=1e-9, precision="fp64", solver=solver)
+        P0 = P0.cpu().numpy()
+        P1, s1 = t.solve(rhs, tol=1e-9, precision="fp64", solver=solver, jacobi=True)
+        assert s0[0]["status"] == 0 and s1[0]["status"] == 0
+        assert abs(s0[0]["iters"] - s1[0]["iters"]) <= 2, (solver, s0, s1)
+        assert _rel(P1.cpu().numpy(), P0) < 1e-7, solver
+    t.close()
+
+
 def test_bicgstab2_follows_the_oracle_recurrence(dda):
     # Same algorithm, same FP64 arithmetic up to rounding order (and the
     # normal equations of the 2x2 minimal-residual step instead of a QR): the

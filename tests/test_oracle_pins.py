@@ -453,6 +453,68 @@ def test_complex_symmetric_solvers_zero_rhs_and_scaled_identity(name):
     assert np.abs(x - E / c).max() < 1e-14 * np.abs(E / c).max()
 
 
+def _two_composition_system():
+    # core-shell ellipsoid: strong contrast between the compositions, so the
+    # diagonal 1/alpha differs by an order of magnitude between sites
+    s = targets.ellipsoid(9, 8, 7)
+    kd = 0.4
+    khat, e = np.array([1.0, 0, 0]), np.array([0, 1.0, 0])
+    c = (s - s.mean(axis=0)) / np.array([4.5, 4.0, 3.5])
+    core = np.sum(c * c, axis=1) < 0.35
+    ai = np.where(core, pol.alpha_inv_ldr(3.0 + 1.0j, kd, khat, e), pol.alpha_inv_ldr(1.3 + 0.01j, kd, khat, e))
+    E = incident.incident_field(s, kd, khat, e)
+    return s, kd, ai, E
+
+
+def test_jacobi_scaled_operator_has_unit_diagonal_and_stays_symmetric():
+    # the scaled matrix S A S, read back column by column through the matvec
+    # the wrapped solver receives: unit diagonal, complex symmetric, and its
+    # right-hand side is S E with S^2 = 1 / diag(A)
+    s, kd, ai, E = _two_composition_system()
+    A = interaction.dense_matrix(s, kd, ai)
+    diag = np.diag(A).copy()
+    cap = {}
+
+    def capture(mv, b, x0=None, **kw):
+        cap["mv"], cap["b"] = mv, b
+        return np.zeros_like(b), {}
+
+    solvers.jacobi_scaled(capture, lambda v: A @ v, E.ravel(), diag)
+    n = A.shape[0]
+    B = np.stack([cap["mv"](np.eye(n, dtype=complex)[:, j]) for j in range(n)], axis=1)
+    assert np.abs(np.diag(B) - 1.0).max() < 1e-13
+    assert np.abs(B - B.T).max() < 1e-13 * np.abs(B).max()
+    assert np.abs(cap["b"] ** 2 * diag - E.ravel() ** 2).max() < 1e-13 * np.abs(E).max() ** 2 * np.abs(diag).max()
+
+
+@pytest.mark.parametrize("name", ["bicgstab", "cocg", "qmr_cs"])
+def test_jacobi_scaled_solvers_match_dense_lu(name):
+    s, kd, ai, E = _two_composition_system()
+    A = interaction.dense_matrix(s, kd, ai)
+    P_lu = solvers.lu_solve(A, E.ravel())
+    op = interaction.FFTOperator(s, kd, ai)
+    diag = interaction.alpha_inv_diag(ai, len(s)).ravel()
+    P, info = solvers.jacobi_scaled(getattr(solvers, name), lambda v: op.matvec(v.reshape(-1, 3)).ravel(),
+                                    E.ravel(), diag, tol=1e-12)
+    assert info["converged"]
+    assert np.abs(P - P_lu).max() < 1e-9 * np.abs(P_lu).max()
+
+
+def test_jacobi_scaling_by_a_multiple_of_identity_keeps_the_iterates():
+    # one composition with a scalar 1/alpha: S = s I, so COCG on s^2 A with
+    # s E takes the unscaled iterates divided by s and stops at the same step
+    s = targets.ellipsoid(10, 8, 7)
+    kd, m = 0.5, 1.7 + 0.05j
+    khat, e = np.array([1.0, 0, 0]), np.array([0, 1.0, 0])
+    ai = pol.alpha_inv_ldr(m, kd, khat, e)
+    E = incident.incident_field(s, kd, khat, e)
+    op = interaction.FFTOperator(s, kd, ai)
+    P0, i0 = solvers.cocg(op.matvec, E, tol=1e-10)
+    P1, i1 = solvers.jacobi_scaled(solvers.cocg, op.matvec, E, np.full(E.shape, ai), tol=1e-10)
+    assert i0["converged"] and i1["converged"] and abs(i0["iters"] - i1["iters"]) <= 1
+    assert np.abs(P1 - P0).max() < 1e-8 * np.abs(P0).max()
+
+
 # -------------------------------------------------------------- near field --
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
