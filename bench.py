@@ -316,7 +316,7 @@ def extra_workloads(dda, inputs, torch, tol, serving_alone=True):
     ref = _reference("ellipsoid_96x64x48")
     ell = {"nrhs": len(rhs), "config": {"n_sites": len(sites), "fft_grid": list(t.info()["grid"]),
                                         "precision": "mixed", "orientations": "PCG64 seed 1305, uniform on SO(3)"}}
-    for tl in sorted({tol, 1e-6, 1e-7}, reverse=True):
+    for tl in sorted({tol, 3e-6, 1e-6, 1e-7}, reverse=True):
         t.solve(rhs, tol=tl, precision="mixed", out=P, solver="bicgstab")
         torch.cuda.synchronize()
         s0 = time.perf_counter()
@@ -329,6 +329,12 @@ def extra_workloads(dda, inputs, torch, tol, serving_alone=True):
                               "iters_max": int(max(x["iters"] for x in st)),
                               "max_rel_resid": float(max(x["rel_resid"] for x in st)),
                               "q_err_vs_oracle": _ref_errors(q, ref)}
+    # the loosest tolerance whose every result is within 1e-5 of the oracle's
+    ok = [k for k in sorted((k for k in ell if k.startswith("tol_")), key=lambda k: -float(k[4:]))
+          if ell[k]["q_err_vs_oracle"] and ell[k]["q_err_vs_oracle"]["max_rel_err"] is not None
+          and ell[k]["q_err_vs_oracle"]["max_rel_err"] <= 1e-5]
+    ell["at_parity"] = dict(tol=float(ok[0][4:]), solves_per_s=ell[ok[0]]["solves_per_s"],
+                            max_rel_err=ell[ok[0]]["q_err_vs_oracle"]["max_rel_err"]) if ok else None
     P1 = torch.empty((1, len(sites), 3), dtype=torch.complex128, device="cuda")
     t.solve(rhs[:1], tol=tol, precision="fp64", out=P1)
     torch.cuda.synchronize()
