@@ -512,6 +512,7 @@ void iteration(dda_target *t, int precision, hipStream_t s) {
   f.active = k.active;
   f.status = k.status;
   f.partial = k.partial;
+  f.rec_cap = k.nrec;
   f.in_mode = 1;
   f.out_mode = 1;
   f.w = k.p;
@@ -549,6 +550,7 @@ void cycle2(dda_target *t, int precision, hipStream_t s) {
   f.active = k.active;
   f.status = k.status;
   f.partial = k.partial;
+  f.rec_cap = k.nrec;
   f.in_mode = 3;
   auto ax = [&](int i, c64 *d, const c64 *a, const c64 *b, int slot, int neg) {
     f.ax_d[i] = d;
@@ -597,6 +599,7 @@ void cocg_iteration(dda_target *t, int precision, bool qmr, hipStream_t s) {
   f.active = k.active;
   f.status = k.status;
   f.partial = k.partial;
+  f.rec_cap = k.nrec;
   f.in_mode = 3;
   f.nax = 1;
   f.ax_d[0] = k.p;

@@ -170,6 +170,7 @@ struct FuseArgs {
   c64 *scal = nullptr;
   int *active = nullptr, *status = nullptr;
   double *partial = nullptr;      // records [nrhs][kPart][x-pass blocks] (see reduce.hpp)
+  int rec_cap = 0;                // records per value and RHS that `partial` holds
   // in_mode 2 with fold_alpha: every block computes alpha = rho / <rh, v> from
   // the nrec records in `partial` of the product that made v (no separate
   // scalar kernel); block 0 stores it

@@ -501,7 +501,16 @@ static dim3 vgrid(const KrylovState &k) { return dim3(k.nblk, k.nrhs); }
 
 static bool bilinear_solver(int solver) { return solver == DDA_SOLVER_COCG || solver == DDA_SOLVER_QMR; }
 
+// Records stay inside their buffers: k.partial holds k.nrec records per value
+// and RHS (the products' x-inverse blocks and the vector kernels' blocks),
+// k.partial2 k.nblk; nrec is the count a product wrote.
+static void check_records(const KrylovState &k, int nrec) {
+  DDA_REQUIRE(k.nblk >= 1 && k.nblk <= k.nrec, "vector-kernel records exceed their buffer");
+  DDA_REQUIRE(nrec >= 1 && nrec <= k.nrec, "product records exceed their buffer");
+}
+
 void k_init_state(const KrylovState &k, double tol, int max_iter, int solver, hipStream_t s) {
+  check_records(k, k.nblk);
   const bool qmr = solver == DDA_SOLVER_QMR;
   hipLaunchKernelGGL(kk_init, vgrid(k), dim3(KNT), 0, s, k.x, k.r, k.rh, k.p, k.v, qmr ? k.s : nullptr,
                      qmr ? k.t : nullptr, k.b, k.n3, k.partial, k.nblk);
@@ -510,6 +519,7 @@ void k_init_state(const KrylovState &k, double tol, int max_iter, int solver, hi
   DDA_HIP(hipGetLastError());
 }
 void k_cocg_update(const KrylovState &k, hipStream_t s, int nrec, bool fold, bool qmr) {
+  check_records(k, nrec);
   if (!fold)
     hipLaunchKernelGGL(kk_cocg_alpha, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, nrec, k.scal, k.active);
   hipLaunchKernelGGL(kk_cocg_update, vgrid(k), dim3(KNT), 0, s, k.active, k.x, k.r, k.p, k.v, qmr ? k.s : nullptr,
@@ -520,9 +530,11 @@ void k_cocg_scalar(const KrylovState &k, hipStream_t s, bool qmr) {
                      qmr ? 1 : 0);
 }
 void k_scalar_alpha(const KrylovState &k, hipStream_t s, int nrec) {
+  check_records(k, nrec);
   hipLaunchKernelGGL(kk_scalar_alpha, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, nrec, k.scal, k.active, k.status);
 }
 void k_update_xr(const KrylovState &k, hipStream_t s, int nrec, bool fold) {
+  check_records(k, nrec);
   if (!fold)
     hipLaunchKernelGGL(kk_scalar_omega, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, nrec, k.scal, k.active);
   hipLaunchKernelGGL(kk_update_xr, vgrid(k), dim3(KNT), 0, s, k.active, k.x, k.r, k.rh, k.p, k.s, k.t, k.scal, k.n3,
@@ -534,9 +546,11 @@ void k_scalar_rho(const KrylovState &k, hipStream_t s, int step, double bsign) {
                      k.scal, k.active, k.status, step, bsign);
 }
 void k2_scalar_rho1(const KrylovState &k, hipStream_t s, int nrec) {
+  check_records(k, nrec);
   hipLaunchKernelGGL(kk2_scalar_rho1, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, nrec, k.scal, k.active, k.status);
 }
 void k2_scalar_mr(const KrylovState &k, hipStream_t s, int nrec) {
+  check_records(k, nrec);
   hipLaunchKernelGGL(kk2_scalar_mr, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, nrec, k.scal, k.active, k.status);
 }
 void k2_update_mr(const KrylovState &k, hipStream_t s) {

@@ -945,6 +945,9 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
   DDA_REQUIRE((uint64_t)((g.My * nxt) << 1) * a.nrhs * a.nrhs < (uint64_t(1) << 32),
               "too many right-hand sides in one product for this grid");
   const FuseArgs &f = a.fuse;
+  // the x-inverse writes one record per block; a folding x-forward reads nrec
+  DDA_REQUIRE(f.out_mode == 0 || (f.partial && nrowblk <= f.rec_cap), "product records exceed their buffer");
+  DDA_REQUIRE(!f.fold_alpha || (f.nrec >= 1 && f.nrec <= f.rec_cap), "folded records exceed their buffer");
   // rows-plan variants of the x-forward and x-inverse passes (forced or tuned)
   const int xv[2] = {a.xvar[0] >= 0 ? a.xvar[0] : tuned_variant(kPassXfwd, g.Mx, f32),
                      a.xvar[1] >= 0 ? a.xvar[1] : tuned_variant(kPassXinv, g.Mx, f32)};
