@@ -33,6 +33,9 @@ sys.path.insert(0, ROOT)
 WORKLOAD = "sphere_d133"
 PASS_TIMING_EVERY = 4
 SOLVER = "cocg"
+# FP32 products and FP32 search directions (p, A p); residual, iterate, sums and the true-residual
+# refinement in FP64
+PRECISION = "mixed32"
 PEAK_HBM_GBS = 8000.0
 # FP32 / FP64 vector issue without packed math: 256 CUs x 4 SIMDs, one wave
 # instruction per SIMD every 4 cycles at 2.4 GHz
@@ -519,7 +522,7 @@ def main():
     P = torch.empty((len(rhs), n, 3), dtype=torch.complex128, device="cuda")
     ref = _reference(WORKLOAD)
 
-    def step(tol, solver=SOLVER, precision="mixed", r=rhs, out=P):
+    def step(tol, solver=SOLVER, precision=PRECISION, r=rhs, out=P):
         Pp, st = t.solve(r, tol=tol, precision=precision, out=out, solver=solver, max_iter=20000)
         q = t.cross_sections(r, Pp)
         return st, q
@@ -551,11 +554,11 @@ def main():
     # the same batch with the other solvers
     log(f"{WORKLOAD}: other solvers")
     solvers_out = {}
-    for solver in ("bicgstab", "bicgstab2", "qmr"):
-        dt, Ps, sts = _timed_solves(t, torch, rhs, 2, tol=args.tol, precision="mixed", out=P, solver=solver,
+    for solver, prec in (("cocg", "mixed"), ("bicgstab", "mixed"), ("bicgstab2", "mixed"), ("qmr", "mixed")):
+        dt, Ps, sts = _timed_solves(t, torch, rhs, 2, tol=args.tol, precision=prec, out=P, solver=solver,
                                     max_iter=20000)
         qs = t.cross_sections(rhs, Ps)
-        solvers_out[solver] = {"solves_per_s": len(rhs) / dt, "iters": [x["iters"] for x in sts],
+        solvers_out[f"{solver}_{prec}"] = {"solves_per_s": len(rhs) / dt, "iters": [x["iters"] for x in sts],
                                "matvecs": [x["matvecs"] for x in sts], "q_err_vs_oracle": _ref_errors(qs, ref)}
 
     # plain FP64 single-RHS solver on the same GPU (one polarization at a time)
@@ -576,7 +579,7 @@ def main():
     log(f"{WORKLOAD}: tolerance scan")
     scan = []
     for tl in (1e-5, 3e-6, 1e-6, 3e-7, 1e-7):
-        dt, Ps, sts = _timed_solves(t, torch, rhs, 1, tol=tl, precision="mixed", out=P, solver=SOLVER,
+        dt, Ps, sts = _timed_solves(t, torch, rhs, 1, tol=tl, precision=PRECISION, out=P, solver=SOLVER,
                                     max_iter=20000)
         qs = t.cross_sections(rhs, Ps)
         scan.append({"tol": tl, "solves_per_s": len(rhs) / dt, "iters": [x["iters"] for x in sts],
@@ -598,7 +601,7 @@ def main():
     mie = ref.get("mie") if ref else None
     # far field of the last solve: Q_sca by quadrature (the dipole array's optical theorem) and <cos theta>
     s0 = time.perf_counter()
-    Pq, _ = t.solve(rhs, tol=args.tol, precision="mixed", out=P, solver=SOLVER, max_iter=20000)
+    Pq, _ = t.solve(rhs, tol=args.tol, precision=PRECISION, out=P, solver=SOLVER, max_iter=20000)
     far = t.far_field(rhs, Pq, etasca=0.5)
     torch.cuda.synchronize()
     far_out = dict(seconds_with_solve=time.perf_counter() - s0, n_theta=far[0]["n_theta"], n_phi=far[0]["n_phi"],
@@ -630,13 +633,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 FFT product / f64 Krylov, residual and sums",
+        "dtype": "c64 FFT product and search directions / f64 residual, iterate, sums and refinement",
         "data": "synthetic",
         "config": {"workload": f"{WORKLOAD}: ELLIPSOID SHPAR 133 sphere, N={n}, m=1.33+0.001i, x=25, LATTDR, "
-                               "k||x, e||y and e||z as one batch of 2 RHS, COCG, mixed FP32 product + FP64 "
-                               f"refinement to {args.tol:g}",
+                               "k||x, e||y and e||z as one batch of 2 RHS, COCG, FP32 product and search "
+                               f"directions + FP64 residual and refinement to {args.tol:g}",
                    "n_sites": n, "box": list(info["box"]), "fft_grid": list(info["grid"]), "kd": kd,
-                   "nrhs": len(rhs), "tol": args.tol, "solver": SOLVER, "precision": "mixed"},
+                   "nrhs": len(rhs), "tol": args.tol, "solver": SOLVER, "precision": PRECISION},
         "solves_per_step": len(rhs),
         "matvecs_per_s": mv / total,
         "matvecs_per_solve": mv / solves,

@@ -27,7 +27,7 @@ SHAPES = {"ELLIPSOID": L.DDA_SHAPE_ELLIPSOID, "RCTGLPRSM": L.DDA_SHAPE_RCTGLPRSM
 ALPHA = {"LATTDR": L.DDA_ALPHA_LDR, "LDR": L.DDA_ALPHA_LDR, "GKDLDR": L.DDA_ALPHA_GKDLDR, "CMRR": L.DDA_ALPHA_CMRR,
          "FLTRCD": L.DDA_ALPHA_FCD, "FCD": L.DDA_ALPHA_FCD}
 SOLVER = {"bicgstab": 0, "bicgstab2": 1, "cocg": 2, "qmr": 3}
-PRECISION = {"fp64": L.DDA_FP64, "mixed": L.DDA_MIXED}
+PRECISION = {"fp64": L.DDA_FP64, "mixed": L.DDA_MIXED, "mixed32": L.DDA_MIXED_V32}
 
 
 def make_sites(shape, shpar):
@@ -224,6 +224,8 @@ class Target:
         the same after a first block of n.  fold_records: tuning only (results
         are bit-identical), see dda_solve_opts.  x0: optional initial guess,
         a contiguous complex128 [nrhs, N, 3] device tensor (default P = 0).
+        precision: "fp64", "mixed" (FP32 products, FP64 vectors) or "mixed32"
+        (COCG only: also COCG's search direction p and A p stored in FP32).
         jacobi: symmetric diagonal scaling S A S with S = diag(alpha)^(1/2)
         (tol then bounds |S(E - A P)| / |S E|, the same as |E - A P| / |E| for
         one composition with a scalar polarizability)."""

@@ -17,6 +17,7 @@ DEVICE_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
                 "-Wno-unused-command-line-argument"]
 SOURCES = {
     "matvec_f32.hip": [],
+    "matvec_f32v.hip": [],
     "matvec_f64.hip": [],
     "fft_generic.hip": [],
     "krylov.hip": [],

@@ -21,6 +21,7 @@ DDA_ALPHA_GKDLDR = 3
 
 DDA_FP64 = 0
 DDA_MIXED = 1
+DDA_MIXED_V32 = 2
 
 DDA_SHAPE_ELLIPSOID = 1
 DDA_SHAPE_RCTGLPRSM = 2

@@ -69,7 +69,8 @@ struct dda_target {
   int h_nrhs = 0;
   // captured block of BiCGSTAB iterations (see run_iterations)
   hipGraphExec_t graph = nullptr;
-  int graph_nrhs = 0, graph_prec = -1, graph_k = 0, graph_solver = -1, graph_fold = -1, graph_jacobi = -1;
+  int graph_nrhs = 0, graph_prec = -1, graph_k = 0, graph_solver = -1, graph_fold = -1, graph_jacobi = -1,
+      graph_vec32 = -1;
   // products with at most this many partial records per RHS hand their
   // scalar (alpha, omega) to the consuming kernel, which computes it in every
   // block; larger ones get a one-block kernel first (set by each solve)
@@ -191,6 +192,13 @@ struct PassTimingScope {
     t->pt_active = false;
     t->pt_used = 0;
   }
+};
+
+// COCG's p and q in FP32 for the duration of a DDA_MIXED_V32 solve.
+struct Vec32Scope {
+  dda_target *t;
+  Vec32Scope(dda_target *t_, bool on) : t(t_) { t->k.vec32 = on; }
+  ~Vec32Scope() { t->k.vec32 = false; }
 };
 
 // The products of a dda_solve with opts->jacobi use the scaling; others never.
@@ -447,6 +455,7 @@ void matvec_on(dda_target *t, int precision, const c64 *in, c64 *out, int nrhs, 
                int reps = 1, const FuseArgs *fuse = nullptr) {
   if (!ev && only_pass < 0) ev = t->pt_next(precision);
   MatvecArgs a{};
+  a.vec32 = t->k.vec32 && precision == DDA_MIXED;   // only the iterations' products run in FP32
   if (t->jacobi_active) {
     a.scl.s = t->d_scl;
     a.scl.comp = t->d_comp;
@@ -638,7 +647,7 @@ void run_iterations(dda_target *t, int precision, int solver, int K, bool use_gr
   }
   if (!t->graph || t->graph_nrhs != t->k.nrhs || t->graph_prec != precision || t->graph_k != K ||
       t->graph_solver != solver || t->graph_fold != t->fold_records || t->graph_gen != t->buffer_gen ||
-      t->graph_jacobi != (int)t->jacobi_active) {
+      t->graph_jacobi != (int)t->jacobi_active || t->graph_vec32 != (int)t->k.vec32) {
     if (t->graph) {
       DDA_HIP(hipGraphExecDestroy(t->graph));
       t->graph = nullptr;
@@ -665,6 +674,7 @@ void run_iterations(dda_target *t, int precision, int solver, int K, bool use_gr
     t->graph_solver = solver;
     t->graph_fold = t->fold_records;
     t->graph_jacobi = (int)t->jacobi_active;
+    t->graph_vec32 = (int)t->k.vec32;
     t->graph_k = K;
     t->graph_gen = t->buffer_gen;
   }
@@ -1136,7 +1146,12 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     DDA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
     DDA_REQUIRE(std::isfinite(opts->tol) && opts->tol > 0.0, "tol must be > 0");
     DDA_REQUIRE(opts->max_iter >= 1, "max_iter must be >= 1");
-    DDA_REQUIRE(opts->precision == DDA_FP64 || opts->precision == DDA_MIXED, "unknown precision");
+    DDA_REQUIRE(opts->precision == DDA_FP64 || opts->precision == DDA_MIXED || opts->precision == DDA_MIXED_V32,
+                "unknown precision");
+    DDA_REQUIRE(opts->precision != DDA_MIXED_V32 || opts->solver == DDA_SOLVER_COCG,
+                "DDA_MIXED_V32 is built for DDA_SOLVER_COCG only");
+    // the products run in FP32 for both mixed modes; V32 also keeps COCG's p and q in FP32
+    const int prec = opts->precision == DDA_MIXED_V32 ? DDA_MIXED : opts->precision;
     DDA_REQUIRE(opts->inner_tol >= 0.0 && opts->inner_tol < 1.0, "inner_tol must be in [0, 1)");
     DDA_REQUIRE(opts->solver >= DDA_SOLVER_BICGSTAB && opts->solver <= DDA_SOLVER_QMR, "unknown solver");
     DDA_HIP(hipSetDevice(t->device));
@@ -1164,6 +1179,7 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     launch_incident(t->g, t->d_ijk, t->d_rhs, nrhs, t->kd, k.b, s);
     // with Jacobi scaling the iterations solve (S A S) y = S E, and P = S y
     JacobiScope jacobi_{t, jacobi};
+    Vec32Scope vec32_{t, opts->precision == DDA_MIXED_V32};
     if (jacobi) launch_scale(t->g, k.b, nrhs, t->d_scl, t->ncomp, t->d_comp, false, s);
     k_init_state(k, opts->tol, opts->max_iter, opts->solver, s);
 
@@ -1186,7 +1202,7 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     std::vector<double> ref_r2(nrhs, -1.0), ref_it(nrhs, 0.0);
     const double steps_per_k = opts->solver == DDA_SOLVER_BICGSTAB2 ? 2.0 : 1.0;
     const double tol = opts->tol;
-    const double inner = opts->precision == DDA_MIXED ? opts->inner_tol : 0.0;
+    const double inner = prec == DDA_MIXED ? opts->inner_tol : 0.0;
     // P = 0 start: an RHS with E = 0 is already solved (its status says so
     // after the first block; the first block is queued without a read).
     // With an initial guess every RHS starts stopped: the check below takes
@@ -1285,7 +1301,7 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
         }
       }
       if (!any_run) break;
-      run_iterations(t, opts->precision, opts->solver, K, opts->use_graph != 0, s);
+      run_iterations(t, prec, opts->solver, K, opts->use_graph != 0, s);
     }
     DDA_HIP(hipMemcpyAsync(t->h_scal, k.scal, scal.size() * sizeof(c64), hipMemcpyDeviceToHost, s));
     const size_t vec = (size_t)k.n3 * nrhs * sizeof(c64);

@@ -62,6 +62,24 @@ __host__ __device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
 using c64 = cpx<double>;
 using c32 = cpx<float>;
 
+// Krylov vectors are complex FP64 (c64), or FP32 (c32) for the search
+// direction and its product in a DDA_MIXED_V32 COCG solve; arithmetic on them
+// is FP64.
+__host__ __device__ __forceinline__ c64 vld(const c64 *p) { return *p; }
+__host__ __device__ __forceinline__ c64 vld(const c32 *p) {
+  const c32 v = *p;
+  return {double(v.x), double(v.y)};
+}
+__host__ __device__ __forceinline__ void vst(c64 *p, c64 v) { *p = v; }
+__host__ __device__ __forceinline__ void vst(c32 *p, c64 v) { *p = c32{float(v.x), float(v.y)}; }
+// the value a vector of type VT holds after storing v (so that a product
+// transforms exactly the vector it stores)
+template <typename VT>
+__host__ __device__ __forceinline__ c64 vround(c64 v) {
+  if constexpr (sizeof(VT) == sizeof(c32)) return {double(float(v.x)), double(float(v.y))};
+  else return v;
+}
+
 // ---------------------------------------------------------------- FFT plan --
 constexpr int kMaxStages = 8;     // a 2/3/5-smooth L <= 512 needs at most 6 stages
 constexpr int kMaxLen = 512;      // largest supported padded extent
@@ -204,6 +222,9 @@ struct MatvecArgs {
   AxisPlan px, py, pz;
   FuseArgs fuse;
   Scaling scl;                    // Jacobi scaling (s = nullptr: none)
+  // in, out and the updated vector of the x-forward are c32 (COCG's p and
+  // q = A p in a DDA_MIXED_V32 solve; FP32 product only), else c64
+  bool vec32 = false;
   int zvar = -1;                  // z-pass plan variant (0..3), or -1: the tuned table's choice
   int xvar[2] = {-1, -1};         // x-forward / x-inverse rows-plan variant (0..1), or -1
 };
@@ -262,6 +283,9 @@ struct KrylovState {
   int *check = nullptr;           // [nrhs]
   int nblk = 0;
   int nrec = 0;                   // records per RHS in `partial` (max of Krylov and x-pass blocks)
+  // DDA_MIXED_V32 COCG: p and v hold c32 values (in the first half of their
+  // buffers); x, r, b, t and every sum stay FP64
+  bool vec32 = false;
 };
 
 // scalar slots per RHS

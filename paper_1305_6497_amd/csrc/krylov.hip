@@ -64,8 +64,10 @@ __device__ __forceinline__ void sum_partials(const double *partial, int nblk, in
   const size_t off = (size_t)r * n3;
 
 // ------------------------------------------------------------- init/restart --
-// xs, ss: QMR's raw iterate (set to 0) and smoothed residual (set to b), or null
-__global__ void kk_init(c64 *x, c64 *rr, c64 *rh, c64 *p, c64 *v, c64 *xs, c64 *ss, const c64 *b, int64_t n3,
+// xs, ss: QMR's raw iterate (set to 0) and smoothed residual (set to b), or
+// null; rh null when p and v are FP32 (VT = c32, COCG only)
+template <typename VT>
+__global__ void kk_init(c64 *x, c64 *rr, c64 *rh, VT *p, VT *v, c64 *xs, c64 *ss, const c64 *b, int64_t n3,
                         double *partial, int nblk) {
   const int r = blockIdx.y;
   const size_t off = (size_t)r * n3;
@@ -74,9 +76,9 @@ __global__ void kk_init(c64 *x, c64 *rr, c64 *rh, c64 *p, c64 *v, c64 *xs, c64 *
     const c64 bv = b[off + i];
     x[off + i] = {0, 0};
     rr[off + i] = bv;
-    rh[off + i] = bv;
-    p[off + i] = {0, 0};
-    v[off + i] = {0, 0};
+    if (rh) rh[off + i] = bv;
+    vst(p + off + i, c64{0, 0});
+    vst(v + off + i, c64{0, 0});
     if (xs) {
       xs[off + i] = {0, 0};
       ss[off + i] = bv;
@@ -259,16 +261,17 @@ __global__ void kk_scalar_true(const double *partial, int nblk, c64 *scal, const
 // residual; rh = r, p = v = 0 and fresh scalars.
 // xs, ss (QMR, else null): the raw COCG iterate restarts at x, the smoothed
 // residual at r
-__global__ void kk_restart(const int *restart, const c64 *rr, c64 *rh, c64 *p, c64 *v, const c64 *x, c64 *xs,
+template <typename VT>
+__global__ void kk_restart(const int *restart, const c64 *rr, c64 *rh, VT *p, VT *v, const c64 *x, c64 *xs,
                            c64 *ss, int64_t n3, int nblk) {
   const int r = blockIdx.y;
   if (!restart[r]) return;
   const size_t off = (size_t)r * n3;
   for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT) {
     const c64 rv = rr[off + i];
-    rh[off + i] = rv;
-    p[off + i] = {0, 0};
-    v[off + i] = {0, 0};
+    if (rh) rh[off + i] = rv;
+    vst(p + off + i, c64{0, 0});
+    vst(v + off + i, c64{0, 0});
     if (xs) {
       xs[off + i] = x[off + i];
       ss[off + i] = rv;
@@ -405,7 +408,8 @@ __global__ void kk_cocg_alpha(const double *partial, int nblk, c64 *scal, const 
 // and ss the smoothed residual; the smoothing of the previous step comes first:
 //     y += eta (xs - y);  ss += eta (r - ss);  then xs += alpha p;  r -= alpha q.
 // Records: r^T r, |r|^2 and |ss|^2 (the smoothed residual just formed).
-__global__ void kk_cocg_update(const int *active, c64 *x, c64 *rr, const c64 *p, const c64 *q, c64 *xs, c64 *ss,
+template <typename VT>
+__global__ void kk_cocg_update(const int *active, c64 *x, c64 *rr, const VT *p, const VT *q, c64 *xs, c64 *ss,
                                c64 *scal, int64_t n3, const double *rec_in, int nrec_in, double *partial,
                                int nblk) {
   RHS_PREAMBLE
@@ -433,7 +437,7 @@ __global__ void kk_cocg_update(const int *active, c64 *x, c64 *rr, const c64 *p,
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT) {
     const size_t j = off + i;
-    const c64 pv = p[j], qv = q[j];
+    const c64 pv = vld(p + j), qv = vld(q + j);
     c64 rv = rr[j];
     if (xs) {
       const c64 xv = xs[j], yv = x[j], sv = ss[j];
@@ -501,6 +505,9 @@ static dim3 vgrid(const KrylovState &k) { return dim3(k.nblk, k.nrhs); }
 
 static bool bilinear_solver(int solver) { return solver == DDA_SOLVER_COCG || solver == DDA_SOLVER_QMR; }
 
+// the c32 view of a vector buffer (COCG's FP32 p and q)
+static c32 *r32(c64 *p) { return reinterpret_cast<c32 *>(p); }
+
 // Records stay inside their buffers: k.partial holds k.nrec records per value
 // and RHS (the products' x-inverse blocks and the vector kernels' blocks),
 // k.partial2 k.nblk; nrec is the count a product wrote.
@@ -512,8 +519,14 @@ static void check_records(const KrylovState &k, int nrec) {
 void k_init_state(const KrylovState &k, double tol, int max_iter, int solver, hipStream_t s) {
   check_records(k, k.nblk);
   const bool qmr = solver == DDA_SOLVER_QMR;
-  hipLaunchKernelGGL(kk_init, vgrid(k), dim3(KNT), 0, s, k.x, k.r, k.rh, k.p, k.v, qmr ? k.s : nullptr,
-                     qmr ? k.t : nullptr, k.b, k.n3, k.partial, k.nblk);
+  if (k.vec32) {
+    DDA_REQUIRE(solver == DDA_SOLVER_COCG, "FP32 search directions are built for COCG only");
+    hipLaunchKernelGGL(kk_init<c32>, vgrid(k), dim3(KNT), 0, s, k.x, k.r, nullptr, r32(k.p), r32(k.v),
+                       nullptr, nullptr, k.b, k.n3, k.partial, k.nblk);
+  } else {
+    hipLaunchKernelGGL(kk_init<c64>, vgrid(k), dim3(KNT), 0, s, k.x, k.r, k.rh, k.p, k.v, qmr ? k.s : nullptr,
+                       qmr ? k.t : nullptr, k.b, k.n3, k.partial, k.nblk);
+  }
   hipLaunchKernelGGL(kk_init_scalars, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, k.nblk, k.scal, k.active, k.status,
                      tol * tol, max_iter, bilinear_solver(solver) ? 1 : 0);
   DDA_HIP(hipGetLastError());
@@ -522,8 +535,13 @@ void k_cocg_update(const KrylovState &k, hipStream_t s, int nrec, bool fold, boo
   check_records(k, nrec);
   if (!fold)
     hipLaunchKernelGGL(kk_cocg_alpha, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, nrec, k.scal, k.active);
-  hipLaunchKernelGGL(kk_cocg_update, vgrid(k), dim3(KNT), 0, s, k.active, k.x, k.r, k.p, k.v, qmr ? k.s : nullptr,
-                     qmr ? k.t : nullptr, k.scal, k.n3, fold ? k.partial : nullptr, nrec, k.partial2, k.nblk);
+  if (k.vec32)
+    hipLaunchKernelGGL(kk_cocg_update<c32>, vgrid(k), dim3(KNT), 0, s, k.active, k.x, k.r, r32(k.p), r32(k.v),
+                       nullptr, nullptr, k.scal, k.n3, fold ? k.partial : nullptr, nrec, k.partial2, k.nblk);
+  else
+    hipLaunchKernelGGL(kk_cocg_update<c64>, vgrid(k), dim3(KNT), 0, s, k.active, k.x, k.r, k.p, k.v,
+                       qmr ? k.s : nullptr, qmr ? k.t : nullptr, k.scal, k.n3, fold ? k.partial : nullptr, nrec,
+                       k.partial2, k.nblk);
 }
 void k_cocg_scalar(const KrylovState &k, hipStream_t s, bool qmr) {
   hipLaunchKernelGGL(kk_cocg_scalar, dim3(k.nrhs), dim3(KNT), 0, s, k.partial2, k.nblk, k.scal, k.active, k.status,
@@ -565,8 +583,12 @@ void k_true_residual(const KrylovState &k, const c64 *ax, hipStream_t s) {
 void k_restart(const KrylovState &k, const int *restart, double tol, double inner_tol, int solver,
                hipStream_t s) {
   const bool qmr = solver == DDA_SOLVER_QMR;
-  hipLaunchKernelGGL(kk_restart, vgrid(k), dim3(KNT), 0, s, restart, k.r, k.rh, k.p, k.v, k.x, qmr ? k.s : nullptr,
-                     qmr ? k.t : nullptr, k.n3, k.nblk);
+  if (k.vec32)
+    hipLaunchKernelGGL(kk_restart<c32>, vgrid(k), dim3(KNT), 0, s, restart, k.r, nullptr, r32(k.p), r32(k.v),
+                       k.x, nullptr, nullptr, k.n3, k.nblk);
+  else
+    hipLaunchKernelGGL(kk_restart<c64>, vgrid(k), dim3(KNT), 0, s, restart, k.r, k.rh, k.p, k.v, k.x,
+                       qmr ? k.s : nullptr, qmr ? k.t : nullptr, k.n3, k.nblk);
   hipLaunchKernelGGL(kk_restart_scalars, dim3((k.nrhs + 63) / 64), dim3(64), 0, s, restart, k.scal, k.active,
                      k.status, k.nrhs, tol * tol, inner_tol * inner_tol, bilinear_solver(solver) ? 1 : 0);
   DDA_HIP(hipGetLastError());

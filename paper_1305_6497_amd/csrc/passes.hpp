@@ -149,33 +149,33 @@ struct RowRuns {
 
 // Element-wise work on a run of n values, element e = threadIdx.x + i kNT:
 // every load is issued before the first store.
-template <int EPT>
-__device__ __forceinline__ void runs_load(c64 (&v)[EPT], int n, const c64 *src) {
+template <int EPT, typename VT>
+__device__ __forceinline__ void runs_load(c64 (&v)[EPT], int n, const VT *src) {
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = threadIdx.x + i * kNT;
-    if (e < n) v[i] = src[e];
+    if (e < n) v[i] = vld(src + e);
   }
 }
 
-// v = d = a + c b
-template <int EPT>
-__device__ __forceinline__ void runs_axpy(c64 (&v)[EPT], int n, const c64 *a, const c64 *b, c64 *d, c64 c) {
+// v = d = a + c b (b and d of one vector type)
+template <int EPT, typename TA, typename VT>
+__device__ __forceinline__ void runs_axpy(c64 (&v)[EPT], int n, const TA *a, const VT *b, VT *d, c64 c) {
   c64 bv[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = threadIdx.x + i * kNT;
     if (e < n) {
-      v[i] = a[e];
-      bv[i] = b[e];
+      v[i] = vld(a + e);
+      bv[i] = vld(b + e);
     }
   }
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = threadIdx.x + i * kNT;
     if (e < n) {
-      v[i] = v[i] + c * bv[i];
-      d[e] = v[i];
+      v[i] = vround<VT>(v[i] + c * bv[i]);
+      vst(d + e, v[i]);
     }
   }
 }
@@ -237,19 +237,25 @@ __device__ __forceinline__ bool block_alpha(const FuseArgs &f, int r, c64 &alpha
 // f.in_mode (see FuseArgs): 0 transforms `in`; 1 and 2 first form the BiCGSTAB
 // vector p or s from r, v (and the old p) and store it, so the vector update
 // costs no pass of its own.  LC > 0: Mx = LC, known at compile time.
-template <typename T, int EPT, int LC, int V>
-__global__ __launch_bounds__(kNT) void k_xfwd(const c64 *__restrict__ in, int64_t n3, const int *__restrict__ mask,
+template <typename T, int EPT, int LC, int V, typename VT>
+__global__ __launch_bounds__(kNT) void k_xfwd(const VT *__restrict__ in, int64_t n3, const int *__restrict__ mask,
                                                const int *__restrict__ cell_site, const int4 *__restrict__ rowtab,
                                                Scaling sc, cpx<T> *__restrict__ A,
                                                size_t a_elems, const cpx<T> *__restrict__ twx, AxisPlan px,
                                                PassDims d, FuseArgs f) {
   constexpr int W = kW<T>, LOGW = kLogW<T>;
   constexpr int NE = (EPT + 2) / 3;      // nrows * Mx <= EPT * kNT / 3
+  // FP32 vectors (VT = c32: COCG's p) come only with in_mode 0 or the single
+  // update p = r + beta p (nax = 1, r in FP64)
+  constexpr bool V64 = sizeof(VT) == sizeof(c64);
   const int r = blockIdx.y;
   if (mask && !mask[r]) return;
   const int Mx = LC > 0 ? LC : px.L;
   const int nrows = LC > 0 ? xpass_rows(LC) : d.nrows;
   const int nxt = LC > 0 ? (LC + W - 1) / W : d.nxt;
+  const c64 *ua = f.ax_a[0];
+  const VT *ub = reinterpret_cast<const VT *>(f.ax_b[0]);
+  VT *ud = reinterpret_cast<VT *>(f.ax_d[0]);
   const int ne = nrows * Mx;
   cpx<T> *buf = reinterpret_cast<cpx<T> *>(dda_smem);
   cpx<T> *tw = buf + 3 * ne;
@@ -287,15 +293,16 @@ __global__ __launch_bounds__(kNT) void k_xfwd(const c64 *__restrict__ in, int64_
       c64 v[ER];
       if (f.in_mode == 0) {
         runs_load(v, n, in + j0);
-      } else if (f.in_mode == 1) {
-        runs_p(v, n, f.r + j0, f.w + j0, f.v + j0, beta, omega);
-      } else if (f.in_mode == 2) {
-        runs_axpy(v, n, f.r + j0, f.v + j0, f.w + j0, c64{-alpha.x, -alpha.y});
-      } else {
-        runs_axpy(v, n, f.ax_a[0] + j0, f.ax_b[0] + j0, f.ax_d[0] + j0, cf[0]);
-        c64 u[ER];
-        if (f.nax > 1) runs_axpy(u, n, f.ax_a[1] + j0, f.ax_b[1] + j0, f.ax_d[1] + j0, cf[1]);
-        if (f.nax > 2) runs_axpy(u, n, f.ax_a[2] + j0, f.ax_b[2] + j0, f.ax_d[2] + j0, cf[2]);
+      } else if (f.in_mode == 3) {
+        runs_axpy(v, n, ua + j0, ub + j0, ud + j0, cf[0]);
+        if constexpr (V64) {
+          c64 u[ER];
+          if (f.nax > 1) runs_axpy(u, n, f.ax_a[1] + j0, f.ax_b[1] + j0, f.ax_d[1] + j0, cf[1]);
+          if (f.nax > 2) runs_axpy(u, n, f.ax_a[2] + j0, f.ax_b[2] + j0, f.ax_d[2] + j0, cf[2]);
+        }
+      } else if constexpr (V64) {
+        if (f.in_mode == 1) runs_p(v, n, f.r + j0, f.w + j0, f.v + j0, beta, omega);
+        else runs_axpy(v, n, f.r + j0, f.v + j0, f.w + j0, c64{-alpha.x, -alpha.y});
       }
       const c64 *sr = sc.s ? sc.rhs(r) : nullptr;
 #pragma unroll
@@ -334,7 +341,7 @@ __global__ __launch_bounds__(kNT) void k_xfwd(const c64 *__restrict__ in, int64_
 #pragma unroll
       for (int i = 0; i < NE; ++i)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) v[i][c] = site[i] >= 0 ? in[off + (size_t)3 * site[i] + c] : c64{0, 0};
+        for (int c = 0; c < 3; ++c) v[i][c] = site[i] >= 0 ? vld(in + off + (size_t)3 * site[i] + c) : c64{0, 0};
     } else if (f.in_mode == 3) {
       // update list d_i = a_i + c_i b_i; d_0 is transformed
 #pragma unroll
@@ -344,14 +351,16 @@ __global__ __launch_bounds__(kNT) void k_xfwd(const c64 *__restrict__ in, int64_
           c64 val = {0, 0};
           if (site[i] >= 0) {
             const size_t j = off + (size_t)3 * site[i] + c;
-            val = f.ax_a[0][j] + cf[0] * f.ax_b[0][j];
-            f.ax_d[0][j] = val;
-            if (f.nax > 1) f.ax_d[1][j] = f.ax_a[1][j] + cf[1] * f.ax_b[1][j];
-            if (f.nax > 2) f.ax_d[2][j] = f.ax_a[2][j] + cf[2] * f.ax_b[2][j];
+            val = vround<VT>(vld(ua + j) + cf[0] * vld(ub + j));
+            vst(ud + j, val);
+            if constexpr (V64) {
+              if (f.nax > 1) f.ax_d[1][j] = f.ax_a[1][j] + cf[1] * f.ax_b[1][j];
+              if (f.nax > 2) f.ax_d[2][j] = f.ax_a[2][j] + cf[2] * f.ax_b[2][j];
+            }
           }
           v[i][c] = val;
         }
-    } else {
+    } else if constexpr (V64) {
 #pragma unroll
       for (int i = 0; i < NE; ++i)
 #pragma unroll
@@ -674,8 +683,8 @@ __global__ __launch_bounds__(kNT) void k_yinv(const int *__restrict__ mask, cons
 // --------------------------------------------------------------- x-inverse --
 // f.out_mode (see FuseArgs): 0 only writes out = ainv * in - G*in; 1 and 2 also
 // write per-block partial sums of the BiCGSTAB inner products of `out`.
-template <typename T, int EPT, int LC, int V>
-__global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *__restrict__ out, int64_t n3,
+template <typename T, int EPT, int LC, int V, typename VT>
+__global__ __launch_bounds__(kNT) void k_xinv(const VT *__restrict__ in, VT *__restrict__ out, int64_t n3,
                                                const int *__restrict__ mask, const c64 *__restrict__ ainv,
                                                int ncomp, const uint8_t *__restrict__ comp,
                                                const int *__restrict__ cell_site, const int4 *__restrict__ rowtab,
@@ -719,8 +728,8 @@ __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *_
   // out = ainv P - (G P) at one element; x is rh (out_mode 1) or r0 (out_mode 3)
   auto finish = [&](size_t j, c64 a, c64 pv, cpx<T> fv, c64 x) {
     const c64 dd = a * pv;
-    const c64 o = c64{dd.x - double(fv.x), dd.y - double(fv.y)};
-    out[j] = o;
+    const c64 o = vround<VT>(c64{dd.x - double(fv.x), dd.y - double(fv.y)});
+    vst(out + j, o);
     if (f.out_mode == 1) {
       const c64 g = cmulc(x, o);
       acc[0] += g.x;
@@ -747,7 +756,8 @@ __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *_
       acc[7] += g20.y;
     }
   };
-  const c64 *xsrc = f.out_mode == 1 ? f.rh : f.out_mode == 3 ? f.r : nullptr;
+  // BiCGSTAB's rh and BiCGstab(2)'s r0 (out modes 1 and 3) exist only as FP64 vectors
+  const c64 *xsrc = sizeof(VT) != sizeof(c64) ? nullptr : f.out_mode == 1 ? f.rh : f.out_mode == 3 ? f.r : nullptr;
   bool done = false;
   if constexpr (LC > 0) {
     constexpr int NR = xpass_rows(LC > 0 ? LC : 1);
@@ -771,7 +781,7 @@ __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *_
       for (int i = 0; i < ER; ++i) {
         const int e = threadIdx.x + i * kNT;
         if (e < n) {
-          pv[i] = in[j0 + e];
+          pv[i] = vld(in + j0 + e);
           xv[i] = xsrc ? xsrc[j0 + e] : c64{0, 0};
           const int st = e / 3;
           av[i] = ai[(comp ? 3 * comp[rr.first + st] : 0) + (e - 3 * st)];
@@ -815,7 +825,7 @@ __global__ __launch_bounds__(kNT) void k_xinv(const c64 *__restrict__ in, c64 *_
 #pragma unroll
     for (int i = 0; i < NE; ++i)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) pv[i][c] = site[i] >= 0 ? in[off + (size_t)3 * site[i] + c] : c64{0, 0};
+      for (int c = 0; c < 3; ++c) pv[i][c] = site[i] >= 0 ? vld(in + off + (size_t)3 * site[i] + c) : c64{0, 0};
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
       if (site[i] >= 0) {
@@ -909,6 +919,59 @@ static inline void allow_lds(K kernel, size_t bytes) {
   if (bytes > 65536) DDA_HIP(hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
 }
 
+// The x-forward (k = 0) or x-inverse (k = 4) pass with Krylov vectors of type
+// VT (c64, or c32 for COCG's p and q in a DDA_MIXED_V32 solve).
+template <typename T, typename VT>
+void launch_x_pass(int k, const Geometry &g, const MatvecArgs &a, const PassDims &d, hipStream_t s) {
+  const bool f32 = sizeof(T) == 4;
+  const size_t ae = g.a_elems(f32);
+  cpx<T> *A = static_cast<cpx<T> *>(a.bufA);
+  const cpx<T> *twx = static_cast<const cpx<T> *>(a.twx);
+  const int64_t n3 = 3 * g.n_sites;
+  const int nrows = xpass_rows(g.Mx);
+  const int nrowblk = (g.ny * g.nz + nrows - 1) / nrows;
+  const size_t cs = sizeof(cpx<T>);
+  const FuseArgs &f = a.fuse;
+  const VT *in = reinterpret_cast<const VT *>(a.in);
+  VT *out = reinterpret_cast<VT *>(a.out);
+  // rows-plan variants of the x-forward and x-inverse passes (forced or tuned)
+  const int xv[2] = {a.xvar[0] >= 0 ? a.xvar[0] : tuned_variant(kPassXfwd, g.Mx, f32),
+                     a.xvar[1] >= 0 ? a.xvar[1] : tuned_variant(kPassXinv, g.Mx, f32)};
+  const size_t xlds = ((size_t)3 * nrows * g.Mx + g.Mx) * cs + (size_t)3 * nrows * sizeof(int);
+  if (k == 0) {
+    with_pass<8>(g.Mx, (size_t)3 * nrows * g.Mx, [&](auto e, auto lc) {
+      constexpr int LC = decltype(lc)::value;
+      constexpr int E = LC > 0 ? pick_ept_c((size_t)3 * xpass_rows(LC) * LC, true) : decltype(e)::value;
+      auto go = [&](auto vv) {
+        hipLaunchKernelGGL((k_xfwd<T, E, LC, decltype(vv)::value, VT>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s,
+                           in, n3, a.mask, a.cell_site, a.rowtab, a.scl, A, ae, twx, a.px, d, f);
+      };
+      if constexpr (LC >= kTunedMinLen) {
+        if (xv[0] == 1) go(IC<1>{});
+        else go(IC<0>{});
+      } else {
+        go(IC<0>{});
+      }
+    });
+  } else {
+    with_pass<8>(g.Mx, (size_t)3 * nrows * g.Mx, [&](auto e, auto lc) {
+      constexpr int LC = decltype(lc)::value;
+      constexpr int E = LC > 0 ? pick_ept_c((size_t)3 * xpass_rows(LC) * LC, true) : decltype(e)::value;
+      auto go = [&](auto vv) {
+        hipLaunchKernelGGL((k_xinv<T, E, LC, decltype(vv)::value, VT>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s,
+                           in, out, n3, a.mask, a.ainv, a.ncomp, a.comp, a.cell_site, a.rowtab, a.scl, A, ae, twx,
+                           a.px, d, f);
+      };
+      if constexpr (LC >= kTunedMinLen) {
+        if (xv[1] == 1) go(IC<1>{});
+        else go(IC<0>{});
+      } else {
+        go(IC<0>{});
+      }
+    });
+  }
+}
+
 template <typename T>
 void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const hipEvent_t *ev, int only_pass,
                    int reps) {
@@ -919,10 +982,8 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
   DDA_REQUIRE(ae < (size_t(1) << 31) && be < (size_t(1) << 31), "grid too large for 32-bit tile offsets");
   cpx<T> *A = static_cast<cpx<T> *>(a.bufA);
   cpx<T> *B = static_cast<cpx<T> *>(a.bufB);
-  const cpx<T> *twx = static_cast<const cpx<T> *>(a.twx);
   const cpx<T> *twy = static_cast<const cpx<T> *>(a.twy);
   const cpx<T> *twz = static_cast<const cpx<T> *>(a.twz);
-  const int64_t n3 = 3 * g.n_sites;
   const int nrows = xpass_rows(g.Mx);
   const int nrowblk = (g.ny * g.nz + nrows - 1) / nrows;
   const size_t cs = sizeof(cpx<T>);
@@ -948,27 +1009,18 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
   // the x-inverse writes one record per block; a folding x-forward reads nrec
   DDA_REQUIRE(f.out_mode == 0 || (f.partial && nrowblk <= f.rec_cap), "product records exceed their buffer");
   DDA_REQUIRE(!f.fold_alpha || (f.nrec >= 1 && f.nrec <= f.rec_cap), "folded records exceed their buffer");
-  // rows-plan variants of the x-forward and x-inverse passes (forced or tuned)
-  const int xv[2] = {a.xvar[0] >= 0 ? a.xvar[0] : tuned_variant(kPassXfwd, g.Mx, f32),
-                     a.xvar[1] >= 0 ? a.xvar[1] : tuned_variant(kPassXinv, g.Mx, f32)};
-  const size_t xlds = ((size_t)3 * nrows * g.Mx + g.Mx) * cs + (size_t)3 * nrows * sizeof(int);
   auto pass = [&](int k) {
     switch (k) {
       case 0:
-        with_pass<8>(g.Mx, (size_t)3 * nrows * g.Mx, [&](auto e, auto lc) {
-          constexpr int LC = decltype(lc)::value;
-          constexpr int E = LC > 0 ? pick_ept_c((size_t)3 * xpass_rows(LC) * LC, true) : decltype(e)::value;
-          auto go = [&](auto vv) {
-            hipLaunchKernelGGL((k_xfwd<T, E, LC, decltype(vv)::value>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s,
-                               a.in, n3, a.mask, a.cell_site, a.rowtab, a.scl, A, ae, twx, a.px, d, f);
-          };
-          if constexpr (LC >= kTunedMinLen) {
-            if (xv[0] == 1) go(IC<1>{});
-            else go(IC<0>{});
-          } else {
-            go(IC<0>{});
+      case 4:
+        // FP32 Krylov vectors only with the FP32 product
+        if constexpr (sizeof(T) == 4) {
+          if (a.vec32) {
+            launch_x_pass<T, c32>(k, g, a, d, s);
+            break;
           }
-        });
+        }
+        launch_x_pass<T, c64>(k, g, a, d, s);
         break;
       case 1:
         with_pass<32>(g.My, (size_t)g.My * W, [&](auto e, auto lc) {
@@ -1025,23 +1077,6 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
           allow_lds(k_yinv<T, E, LC>, lds);
           hipLaunchKernelGGL((k_yinv<T, E, LC>), dim3(3 * g.nz * nxt, a.nrhs), dim3(kNT), lds, s, a.mask, B, be, A,
                              ae, twy, a.py, d);
-        });
-        break;
-      default:
-        with_pass<8>(g.Mx, (size_t)3 * nrows * g.Mx, [&](auto e, auto lc) {
-          constexpr int LC = decltype(lc)::value;
-          constexpr int E = LC > 0 ? pick_ept_c((size_t)3 * xpass_rows(LC) * LC, true) : decltype(e)::value;
-          auto go = [&](auto vv) {
-            hipLaunchKernelGGL((k_xinv<T, E, LC, decltype(vv)::value>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s,
-                               a.in, a.out, n3, a.mask, a.ainv, a.ncomp, a.comp, a.cell_site, a.rowtab, a.scl, A,
-                               ae, twx, a.px, d, f);
-          };
-          if constexpr (LC >= kTunedMinLen) {
-            if (xv[1] == 1) go(IC<1>{});
-            else go(IC<0>{});
-          } else {
-            go(IC<0>{});
-          }
         });
         break;
     }

@@ -37,6 +37,11 @@ def dda():
 SOLVERS = ["bicgstab", "bicgstab2", "cocg", "qmr"]
 
 
+def _mixed_precs(solver):
+    # "mixed32" (COCG's p and A p in FP32 too) exists for COCG only
+    return ["mixed", "mixed32"] if solver == "cocg" else ["mixed"]
+
+
 def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
@@ -289,14 +294,48 @@ def test_solve_mixed_reaches_fp64_tolerance(dda, solver):
     kd, m = 0.35, 1.5 + 0.1j
     rhs = [dda.orient_rhs(0, 0, 0, which=1)]
     t = dda.Target(sites, box, m=m, kd=kd)
-    P, st = t.solve(rhs, tol=1e-8, precision="mixed", solver=solver)
-    Pg = P.cpu().numpy()[0]
-    t.close()
-    assert st[0]["status"] == 0
     ai = _oracle_ainv(m, kd, *rhs[0])
     E = incident.incident_field(osites, kd, *rhs[0])
-    res = np.linalg.norm(E - interaction.FFTOperator(osites, kd, ai).matvec(Pg)) / np.linalg.norm(E)
-    assert res <= 1e-8
+    for prec in _mixed_precs(solver):
+        P, st = t.solve(rhs, tol=1e-8, precision=prec, solver=solver)
+        Pg = P.cpu().numpy()[0]
+        assert st[0]["status"] == 0
+        res = np.linalg.norm(E - interaction.FFTOperator(osites, kd, ai).matvec(Pg)) / np.linalg.norm(E)
+        assert res <= 1e-8, prec
+    t.close()
+
+
+@pytest.mark.parametrize("m,alpha", [(1.33 + 0.01j, "LATTDR"), (1.7 + 0.3j, "GKDLDR"), (0.9656 + 1.8628j, "LATTDR")])
+def test_mixed32_cocg_matches_dense_lu(dda, m, alpha):
+    # COCG with FP32 products and FP32 p and A p, refined in FP64:
+    # the dense-LU solution to 1e-8 at tol 1e-11, in about as many iterations
+    # as with FP64 vectors, also on a metallic target; other solvers reject the mode
+    shpar = (9.5, 8.0, 6.5)
+    sites, box = dda.make_sites("ELLIPSOID", shpar)
+    osites = targets.ellipsoid(*shpar)
+    kd = 0.5
+    b, th, ph = inputs.orientation_angles(1, seed=3)
+    rhs = [dda.orient_rhs(b[0], th[0], ph[0], which=1), dda.orient_rhs(b[0], th[0], ph[0], which=2)]
+    t = dda.Target(sites, box, m=m, kd=kd, alpha=alpha)
+    P, st = t.solve(rhs, tol=1e-11, precision="mixed32", max_iter=2000, solver="cocg")
+    _, sm = t.solve(rhs, tol=1e-11, precision="mixed", max_iter=2000, solver="cocg")
+    q = t.cross_sections(rhs, P)
+    Pg = P.cpu().numpy()
+    for other in ("bicgstab", "bicgstab2", "qmr"):
+        with pytest.raises(RuntimeError):
+            t.solve(rhs, tol=1e-5, precision="mixed32", solver=other)
+    t.close()
+    for r in range(2):
+        assert st[r]["status"] == 0 and st[r]["rel_resid"] <= 1e-11
+        assert st[r]["iters"] <= 1.15 * sm[r]["iters"] + 4, (st[r], sm[r])
+        ai = polarizability.alpha_inv(alpha, m, kd, *rhs[r])
+        E = incident.incident_field(osites, kd, *rhs[r])
+        A = interaction.dense_matrix(osites, kd, ai)
+        Po = solvers.lu_solve(A, E.ravel()).reshape(-1, 3)
+        assert _rel(Pg[r], Po) < 1e-8
+        qo = cross_sections.efficiencies(len(osites), kd, E, ai, Po)
+        for key in ("qext", "qabs", "qsca", "qpha"):
+            assert abs(q[r][key] - qo[key]) <= 1e-9 * qo["qext"], key
 
 
 @pytest.mark.parametrize("solver", SOLVERS)
@@ -306,7 +345,7 @@ def test_batched_block_equals_single_solves_bitwise(dda, solver):
     b, th, ph = inputs.orientation_angles(3, seed=4)
     rhs = [dda.orient_rhs(b[i], th[i], ph[i], which=1 + (i % 2)) for i in range(3)]
     t = dda.Target(sites, box, m=m, kd=kd)
-    for prec in ("fp64", "mixed"):
+    for prec in ["fp64"] + _mixed_precs(solver):
         Pb, sb = t.solve(rhs, tol=1e-7, precision=prec, solver=solver)
         Pb = Pb.cpu().numpy()
         for i in range(3):
@@ -416,7 +455,7 @@ def test_graph_replay_matches_eager_bitwise(dda, solver):
     t = dda.Target(sites, box, m=1.6 + 0.08j, kd=0.35)
     b, th, ph = inputs.orientation_angles(2, seed=8)
     rhs = [dda.orient_rhs(b[i], th[i], ph[i], which=1 + i) for i in range(2)]
-    for prec in ("fp64", "mixed"):
+    for prec in ["fp64"] + _mixed_precs(solver):
         ref, sr = t.solve(rhs, tol=1e-9, precision=prec, use_graph=False, check_every=3, solver=solver)
         for rep in range(3):
             got, sg = t.solve(rhs, tol=1e-9, precision=prec, use_graph=True, check_every=3, solver=solver)
@@ -435,8 +474,10 @@ def test_graph_replay_matches_eager_bitwise(dda, solver):
 # 1e-7 of Q_ext leaves a margin of two orders of magnitude.
 @pytest.mark.parametrize("solver", SOLVERS)
 @pytest.mark.parametrize("name", ["au_block_16x32x32", "block_64", "ellipsoid_96x64x48"])
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed32"])
 def test_full_size_efficiencies_against_oracle(dda, name, prec, solver):
+    if prec == "mixed32" and solver != "cocg":
+        pytest.skip("mixed32 is built for COCG only")
     import json
     import os
     with open(os.path.join(os.path.dirname(__file__), "golden", f"reference_{name}.json")) as f:
@@ -460,7 +501,7 @@ def test_full_size_efficiencies_against_oracle(dda, name, prec, solver):
 # The largest configuration (D = 133 sphere, N = 1232177, grid 270^3) as the
 # timed solve runs it: both polarizations in one batch, COCG, here to 1e-9;
 # every RHS with a stored oracle solve is compared to 1e-7 of Q_ext.
-@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+@pytest.mark.parametrize("prec", ["mixed32", "mixed", "fp64"])
 def test_sphere_d133_efficiencies_against_oracle(dda, prec):
     import json
     import os
@@ -919,6 +960,14 @@ def test_initial_guess(dda, solver):
     warm_e, swe = t.solve(rhs, tol=1e-9, precision="mixed", solver=solver, x0=loose, check_every=8)
     assert torch.equal(warm_g, warm_e)
     assert [x["iters"] for x in swg] == [x["iters"] for x in swe]
+    if solver == "cocg":
+        # FP32 p and A p: the same warm start and tolerance
+        _, s32c = t.solve(rhs, tol=1e-9, precision="mixed32", solver=solver)
+        warm32, s32 = t.solve(rhs, tol=1e-9, precision="mixed32", solver=solver, x0=loose)
+        for i in range(2):
+            assert s32[i]["status"] == 0 and s32[i]["rel_resid"] <= 1e-9
+            assert s32[i]["iters"] <= s32c[i]["iters"], (s32[i], s32c[i])
+        assert _rel(warm32.cpu().numpy(), cold.cpu().numpy()) < 1e-7
     with pytest.raises(ValueError):
         t.solve(rhs, tol=1e-5, x0=cold[:1])
     t.close()
@@ -932,13 +981,14 @@ def test_where_step_lengths_are_summed_does_not_change_results(dda, solver):
     sites, box = dda.make_sites("ELLIPSOID", (12, 9, 7))
     rhs = [dda.orient_rhs(0.3, 0.8, 1.1, which=1), dda.orient_rhs(0.3, 0.8, 1.1, which=2)]
     t = dda.Target(sites, box, m=1.8 + 0.05j, kd=0.5)
-    out = []
-    for fr in (0, -1):
-        P, st = t.solve(rhs, tol=1e-8, precision="mixed", fold_records=fr, solver=solver)
-        out.append((P.cpu().numpy(), [(x["iters"], x["outer"], x["status"]) for x in st]))
+    for prec in _mixed_precs(solver):
+        out = []
+        for fr in (0, -1):
+            P, st = t.solve(rhs, tol=1e-8, precision=prec, fold_records=fr, solver=solver)
+            out.append((P.cpu().numpy(), [(x["iters"], x["outer"], x["status"]) for x in st]))
+        assert out[1][1] == out[0][1], prec
+        assert np.array_equal(out[1][0], out[0][0]), prec
     t.close()
-    assert out[1][1] == out[0][1]
-    assert np.array_equal(out[1][0], out[0][0])
 
 
 @pytest.mark.parametrize("solver", SOLVERS)
@@ -950,11 +1000,12 @@ def test_check_interval_does_not_change_results(dda, solver):
     sites, box = dda.make_sites("ELLIPSOID", (12, 9, 7))
     rhs = [dda.orient_rhs(0.3, 0.8, 1.1, which=1), dda.orient_rhs(0.3, 0.8, 1.1, which=2)]
     t = dda.Target(sites, box, m=1.8 + 0.05j, kd=0.5)
-    out = []
-    for ce in (0, 1, 8, -3):
-        P, st = t.solve(rhs, tol=1e-8, precision="mixed", check_every=ce, solver=solver)
-        out.append((P.cpu().numpy(), [(x["iters"], x["outer"], x["status"]) for x in st]))
+    for prec in _mixed_precs(solver):
+        out = []
+        for ce in (0, 1, 8, -3):
+            P, st = t.solve(rhs, tol=1e-8, precision=prec, check_every=ce, solver=solver)
+            out.append((P.cpu().numpy(), [(x["iters"], x["outer"], x["status"]) for x in st]))
+        for P, st in out[1:]:
+            assert st == out[0][1], prec
+            assert np.array_equal(P, out[0][0]), prec
     t.close()
-    for P, st in out[1:]:
-        assert st == out[0][1]
-        assert np.array_equal(P, out[0][0])
