@@ -34,7 +34,7 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 # Sources the FFT-product kernels are compiled from: a traffic figure measured
 # on other sources no longer describes the kernel.
-KERNEL_SOURCES = ("passes.hpp", "fft_lds.hpp", "dda_internal.hpp", "reduce.hpp", "matvec_f32.hip",
+KERNEL_SOURCES = ("passes.hpp", "fft_lds.hpp", "dda_internal.hpp", "reduce.hpp", "matvec_f32.hip", "matvec_f32v.hip",
                   "matvec_f64.hip", "plan_tuned.inc")
 
 
