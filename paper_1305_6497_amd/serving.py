@@ -51,7 +51,8 @@ class Result:
 class GpuExecutor:
     """Runs one request: target setup, two-polarization solve, cross sections.
 
-    solver "auto" (the default) runs COCG (one product per iteration) with the
+    solver "auto" (the default) runs COCG (one product per iteration; with
+    precision "mixed" its p and A p are FP32 too, "mixed32") with the
     product budget of ``max_iter`` BiCGSTAB iterations and continues with
     BiCGstab(2) from COCG's iterate, for up to 2 ``max_iter`` BiCG steps, any
     RHS that COCG leaves unconverged; on the seeded mix COCG needs 13% fewer products than
@@ -99,7 +100,9 @@ class GpuExecutor:
             t = dda.Target(prep["sites"], prep["box"], m=req.m, kd=prep["kd"], device=self.device)
             try:
                 if self.solver == "auto":
-                    P, st = t.solve(rhs, tol=self.tol, precision=self.precision, max_iter=2 * self.max_iter,
+                    # COCG in mixed precision keeps its p and A p in FP32 as well ("mixed32")
+                    cocg_prec = "mixed32" if self.precision == "mixed" else self.precision
+                    P, st = t.solve(rhs, tol=self.tol, precision=cocg_prec, max_iter=2 * self.max_iter,
                                     stream=s, solver="cocg")
                     redo = [i for i, x in enumerate(st) if x["status"] != 0]
                     if redo:
