@@ -138,10 +138,11 @@ typedef struct {
                               current true residual; 0 => tol (one refinement pass) */
   int32_t max_outer;       /* cap on true-residual checks / refinement passes per RHS */
   int32_t check_every;     /* iterations between host convergence checks (>= 1); 0 => the
-                              first check after 8, then (eager launches) where the decay of the
-                              recursive residuals since the last check predicts that the slowest
-                              RHS converges (4..64); -n => the same with the first check after
-                              n (<= 64) iterations; with use_graph, 0 => 8 and -n => n */
+                              first check after 8 (after 4 on FFT grids of at most 2^18
+                              points), then (eager launches) where the decay of the recursive
+                              residuals since the last check predicts that the slowest RHS
+                              converges (4..64); -n => the same with the first check after
+                              n (<= 64) iterations; with use_graph, 0 => 8 (4) and -n => n */
   int32_t use_graph;       /* 1: the check_every iterations between host checks run as one
                               captured HIP graph on a stream of the handle (ordered after and
                               before the caller's stream); 0: kernels are launched directly */

@@ -1164,7 +1164,11 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     // that the next check falls where the slowest RHS should have converged
     // (each check costs a host round trip with the GPU idle)
     t->fold_records = opts->fold_records > 0 ? opts->fold_records : opts->fold_records < 0 ? 0 : kFoldRecords;
-    int K = opts->check_every > 0 ? opts->check_every : opts->check_every < 0 ? std::min(-opts->check_every, 64) : 8;
+    // first block: 8 iterations, or 4 on grids of at most 64^3 points, whose
+    // iterations cost less than the host round trip of a check (iterations
+    // launched after convergence still cost a launch each)
+    const int k0 = (size_t)t->g.Mx * t->g.My * t->g.Mz <= ((size_t)1 << 18) ? 4 : 8;
+    int K = opts->check_every > 0 ? opts->check_every : opts->check_every < 0 ? std::min(-opts->check_every, 64) : k0;
     const bool adaptive = opts->check_every <= 0 && opts->use_graph == 0;
     const int max_outer = opts->max_outer > 0 ? opts->max_outer : 20;
     std::vector<RhsDev> rd;
