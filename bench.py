@@ -245,7 +245,8 @@ def block64_workload(dda, inputs, torch, tol):
     out = {"config": {"n_sites": n, "box": list(info["box"]), "fft_grid": list(info["grid"]), "nrhs": 1,
                       "tol": tol}}
     for name, prec, solver in (("mixed", "mixed", "bicgstab"), ("fp64", "fp64", "bicgstab"),
-                               ("mixed_bicgstab2", "mixed", "bicgstab2"), ("mixed_cocg", "mixed", "cocg"),
+                               ("mixed32", "mixed32", "bicgstab"), ("mixed_bicgstab2", "mixed", "bicgstab2"),
+                               ("mixed_cocg", "mixed", "cocg"), ("mixed32_cocg", "mixed32", "cocg"),
                                ("mixed_qmr", "mixed", "qmr")):
         dt, P, st = _timed_solves(t, torch, rhs, 5, tol=tol, precision=prec, out=P, solver=solver)
         q = t.cross_sections(rhs, P)
@@ -338,19 +339,21 @@ def extra_workloads(dda, inputs, torch, tol, serving_alone=True):
           and ell[k]["q_err_vs_oracle"]["max_rel_err"] <= 1e-5]
     ell["at_parity"] = dict(tol=float(ok[0][4:]), solves_per_s=ell[ok[0]]["solves_per_s"],
                             max_rel_err=ell[ok[0]]["q_err_vs_oracle"]["max_rel_err"]) if ok else None
-    # the same block with COCG (FP32 p and A p) at the metric's tolerance and at the parity tolerance
-    for tl in sorted({tol, ell["at_parity"]["tol"] if ell["at_parity"] else tol}, reverse=True):
-        t.solve(rhs, tol=tl, precision="mixed32", out=P, solver="cocg")
-        torch.cuda.synchronize()
-        s0 = time.perf_counter()
-        P, st = t.solve(rhs, tol=tl, precision="mixed32", out=P, solver="cocg")
-        q = t.cross_sections(rhs, P)
-        torch.cuda.synchronize()
-        tb = time.perf_counter() - s0
-        ell[f"cocg_mixed32_tol_{tl:g}"] = {"solves_per_s": len(rhs) / tb, "block_seconds": tb,
-                                           "iters_mean": float(np.mean([x["iters"] for x in st])),
-                                           "iters_max": int(max(x["iters"] for x in st)),
-                                           "q_err_vs_oracle": _ref_errors(q, ref)}
+    # the same block with FP32 search directions (BiCGSTAB and COCG) at the metric's tolerance and at the
+    # parity tolerance
+    for slv in ("bicgstab", "cocg"):
+        for tl in sorted({tol, ell["at_parity"]["tol"] if ell["at_parity"] else tol}, reverse=True):
+            t.solve(rhs, tol=tl, precision="mixed32", out=P, solver=slv)
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            P, st = t.solve(rhs, tol=tl, precision="mixed32", out=P, solver=slv)
+            q = t.cross_sections(rhs, P)
+            torch.cuda.synchronize()
+            tb = time.perf_counter() - s0
+            ell[f"{slv}_mixed32_tol_{tl:g}"] = {"solves_per_s": len(rhs) / tb, "block_seconds": tb,
+                                                "iters_mean": float(np.mean([x["iters"] for x in st])),
+                                                "iters_max": int(max(x["iters"] for x in st)),
+                                                "q_err_vs_oracle": _ref_errors(q, ref)}
     P1 = torch.empty((1, len(sites), 3), dtype=torch.complex128, device="cuda")
     t.solve(rhs[:1], tol=tol, precision="fp64", out=P1)
     torch.cuda.synchronize()

@@ -67,14 +67,15 @@ extern "C" {
 #define DDA_FP64 0            /* complex FP64 throughout */
 #define DDA_MIXED 1           /* complex FP32 FFT product; FP64 Krylov vectors,
                                  inner products, residual refinement and sums */
-#define DDA_MIXED_V32 2       /* dda_solve with DDA_SOLVER_COCG only: the FP32 product of
-                                 DDA_MIXED, and COCG's search direction p and its product
-                                 q = A p stored in complex FP32 (arithmetic on them in FP64);
-                                 the residual r, the iterate x, every inner product, the FP64
-                                 true residual and the refinement as in DDA_MIXED (§6: single
-                                 precision where it suffices, double where accuracy is
-                                 decided; an FP32 r loses COCG's bilinear r^T r to
-                                 cancellation on metallic targets) */
+#define DDA_MIXED_V32 2       /* dda_solve with DDA_SOLVER_COCG or DDA_SOLVER_BICGSTAB: the
+                                 FP32 product of DDA_MIXED, and the search direction p and
+                                 its product (COCG's q = A p, BiCGSTAB's v = A p) stored in
+                                 complex FP32 (arithmetic on them in FP64); the residuals
+                                 (r, and BiCGSTAB's shadow rh, s and t = A s), the iterate x,
+                                 every inner product, the FP64 true residual and the
+                                 refinement as in DDA_MIXED (§6: single precision where it
+                                 suffices, double where accuracy is decided; an FP32 r loses
+                                 COCG's bilinear r^T r to cancellation on metallic targets) */
 
 /* Krylov solvers (§12, "Choice of Iterative Algorithm") */
 #define DDA_SOLVER_BICGSTAB 0   /* BiCGSTAB, van der Vorst 1992 (the guide's PBCGST) */

@@ -225,7 +225,7 @@ class Target:
         are bit-identical), see dda_solve_opts.  x0: optional initial guess,
         a contiguous complex128 [nrhs, N, 3] device tensor (default P = 0).
         precision: "fp64", "mixed" (FP32 products, FP64 vectors) or "mixed32"
-        (COCG only: also COCG's search direction p and A p stored in FP32).
+        (COCG and BiCGSTAB: also the search direction p and A p stored in FP32).
         jacobi: symmetric diagonal scaling S A S with S = diag(alpha)^(1/2)
         (tol then bounds |S(E - A P)| / |S E|, the same as |E - A P| / |E| for
         one composition with a scalar polarizability)."""

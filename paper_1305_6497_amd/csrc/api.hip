@@ -194,7 +194,8 @@ struct PassTimingScope {
   }
 };
 
-// COCG's p and q in FP32 for the duration of a DDA_MIXED_V32 solve.
+// The search direction p and its product in FP32 for the duration of a
+// DDA_MIXED_V32 solve.
 struct Vec32Scope {
   dda_target *t;
   Vec32Scope(dda_target *t_, bool on) : t(t_) { t->k.vec32 = on; }
@@ -455,7 +456,12 @@ void matvec_on(dda_target *t, int precision, const c64 *in, c64 *out, int nrhs, 
                int reps = 1, const FuseArgs *fuse = nullptr) {
   if (!ev && only_pass < 0) ev = t->pt_next(precision);
   MatvecArgs a{};
-  a.vec32 = t->k.vec32 && precision == DDA_MIXED;   // only the iterations' products run in FP32
+  // FP32 vectors only in the iterations' FP32 products: COCG's p -> q and
+  // BiCGSTAB's p -> v (in mode 3 or 1); BiCGSTAB's s -> t product (in mode 2)
+  // keeps s and t in FP64 but reads the FP32 v in its fused update
+  const bool v32 = t->k.vec32 && precision == DDA_MIXED;
+  a.vec32 = v32 && !(fuse && fuse->in_mode == 2);
+  a.vvec32 = v32;
   if (t->jacobi_active) {
     a.scl.s = t->d_scl;
     a.scl.comp = t->d_comp;
@@ -1148,9 +1154,11 @@ int dda_solve(dda_target *t, const dda_rhs *rhs, int32_t nrhs, const dda_solve_o
     DDA_REQUIRE(opts->max_iter >= 1, "max_iter must be >= 1");
     DDA_REQUIRE(opts->precision == DDA_FP64 || opts->precision == DDA_MIXED || opts->precision == DDA_MIXED_V32,
                 "unknown precision");
-    DDA_REQUIRE(opts->precision != DDA_MIXED_V32 || opts->solver == DDA_SOLVER_COCG,
-                "DDA_MIXED_V32 is built for DDA_SOLVER_COCG only");
-    // the products run in FP32 for both mixed modes; V32 also keeps COCG's p and q in FP32
+    DDA_REQUIRE(opts->precision != DDA_MIXED_V32 || opts->solver == DDA_SOLVER_COCG ||
+                    opts->solver == DDA_SOLVER_BICGSTAB,
+                "DDA_MIXED_V32 is built for DDA_SOLVER_COCG and DDA_SOLVER_BICGSTAB only");
+    // the products run in FP32 for both mixed modes; V32 also keeps the search
+    // direction p and its product in FP32
     const int prec = opts->precision == DDA_MIXED_V32 ? DDA_MIXED : opts->precision;
     DDA_REQUIRE(opts->inner_tol >= 0.0 && opts->inner_tol < 1.0, "inner_tol must be in [0, 1)");
     DDA_REQUIRE(opts->solver >= DDA_SOLVER_BICGSTAB && opts->solver <= DDA_SOLVER_QMR, "unknown solver");

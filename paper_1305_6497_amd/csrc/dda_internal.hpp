@@ -222,9 +222,12 @@ struct MatvecArgs {
   AxisPlan px, py, pz;
   FuseArgs fuse;
   Scaling scl;                    // Jacobi scaling (s = nullptr: none)
-  // in, out and the updated vector of the x-forward are c32 (COCG's p and
-  // q = A p in a DDA_MIXED_V32 solve; FP32 product only), else c64
+  // DDA_MIXED_V32 (FP32 product only): vec32, the product's input and output
+  // and the vector its fused update writes are c32 (COCG's p and q = A p,
+  // BiCGSTAB's p and v = A p); vvec32, the update's v is c32 (BiCGSTAB's
+  // s -> t product, whose s and t stay c64)
   bool vec32 = false;
+  bool vvec32 = false;
   int zvar = -1;                  // z-pass plan variant (0..3), or -1: the tuned table's choice
   int xvar[2] = {-1, -1};         // x-forward / x-inverse rows-plan variant (0..1), or -1
 };

@@ -65,7 +65,7 @@ __device__ __forceinline__ void sum_partials(const double *partial, int nblk, in
 
 // ------------------------------------------------------------- init/restart --
 // xs, ss: QMR's raw iterate (set to 0) and smoothed residual (set to b), or
-// null; rh null when p and v are FP32 (VT = c32, COCG only)
+// null; p and v FP32 (VT = c32) for a DDA_MIXED_V32 COCG or BiCGSTAB solve
 template <typename VT>
 __global__ void kk_init(c64 *x, c64 *rr, c64 *rh, VT *p, VT *v, c64 *xs, c64 *ss, const c64 *b, int64_t n3,
                         double *partial, int nblk) {
@@ -159,7 +159,8 @@ __global__ void kk_scalar_omega(const double *partial, int nblk, c64 *scal, cons
 // kk_scalar_omega computes it); block 0 stores it.  Without, it is read from
 // S_OMEGA.  Every block reading all records costs O(blocks x records), so
 // the host folds only products with few records.
-__global__ void kk_update_xr(const int *active, c64 *x, c64 *rr, const c64 *rh, const c64 *p, const c64 *s,
+template <typename VT>
+__global__ void kk_update_xr(const int *active, c64 *x, c64 *rr, const c64 *rh, const VT *p, const c64 *s,
                              const c64 *t, c64 *scal, int64_t n3, const double *rec_in, int nrec_in,
                              double *partial, int nblk) {
   RHS_PREAMBLE
@@ -182,7 +183,7 @@ __global__ void kk_update_xr(const int *active, c64 *x, c64 *rr, const c64 *rh, 
   double acc[3] = {0.0, 0.0, 0.0};
   for (int64_t i = blockIdx.x * (int64_t)KNT + threadIdx.x; i < n3; i += (int64_t)nblk * KNT) {
     const c64 sv = s[off + i];
-    x[off + i] = x[off + i] + alpha * p[off + i] + omega * sv;
+    x[off + i] = x[off + i] + alpha * vld(p + off + i) + omega * sv;
     const c64 rv = sv - omega * t[off + i];
     rr[off + i] = rv;
     const c64 d = cmulc(rh[off + i], rv);
@@ -520,8 +521,9 @@ void k_init_state(const KrylovState &k, double tol, int max_iter, int solver, hi
   check_records(k, k.nblk);
   const bool qmr = solver == DDA_SOLVER_QMR;
   if (k.vec32) {
-    DDA_REQUIRE(solver == DDA_SOLVER_COCG, "FP32 search directions are built for COCG only");
-    hipLaunchKernelGGL(kk_init<c32>, vgrid(k), dim3(KNT), 0, s, k.x, k.r, nullptr, r32(k.p), r32(k.v),
+    DDA_REQUIRE(solver == DDA_SOLVER_COCG || solver == DDA_SOLVER_BICGSTAB,
+                "FP32 search directions are built for COCG and BiCGSTAB only");
+    hipLaunchKernelGGL(kk_init<c32>, vgrid(k), dim3(KNT), 0, s, k.x, k.r, k.rh, r32(k.p), r32(k.v),
                        nullptr, nullptr, k.b, k.n3, k.partial, k.nblk);
   } else {
     hipLaunchKernelGGL(kk_init<c64>, vgrid(k), dim3(KNT), 0, s, k.x, k.r, k.rh, k.p, k.v, qmr ? k.s : nullptr,
@@ -555,8 +557,12 @@ void k_update_xr(const KrylovState &k, hipStream_t s, int nrec, bool fold) {
   check_records(k, nrec);
   if (!fold)
     hipLaunchKernelGGL(kk_scalar_omega, dim3(k.nrhs), dim3(KNT), 0, s, k.partial, nrec, k.scal, k.active);
-  hipLaunchKernelGGL(kk_update_xr, vgrid(k), dim3(KNT), 0, s, k.active, k.x, k.r, k.rh, k.p, k.s, k.t, k.scal, k.n3,
-                     fold ? k.partial : nullptr, nrec, k.partial2, k.nblk);
+  if (k.vec32)
+    hipLaunchKernelGGL(kk_update_xr<c32>, vgrid(k), dim3(KNT), 0, s, k.active, k.x, k.r, k.rh, r32(k.p), k.s, k.t,
+                       k.scal, k.n3, fold ? k.partial : nullptr, nrec, k.partial2, k.nblk);
+  else
+    hipLaunchKernelGGL(kk_update_xr<c64>, vgrid(k), dim3(KNT), 0, s, k.active, k.x, k.r, k.rh, k.p, k.s, k.t,
+                       k.scal, k.n3, fold ? k.partial : nullptr, nrec, k.partial2, k.nblk);
 }
 void k_scalar_rho(const KrylovState &k, hipStream_t s, int step, double bsign) {
   // BiCGSTAB: records of kk_update_xr (partial2); BiCGstab(2): of kk2_update_mr (partial)
@@ -584,7 +590,7 @@ void k_restart(const KrylovState &k, const int *restart, double tol, double inne
                hipStream_t s) {
   const bool qmr = solver == DDA_SOLVER_QMR;
   if (k.vec32)
-    hipLaunchKernelGGL(kk_restart<c32>, vgrid(k), dim3(KNT), 0, s, restart, k.r, nullptr, r32(k.p), r32(k.v),
+    hipLaunchKernelGGL(kk_restart<c32>, vgrid(k), dim3(KNT), 0, s, restart, k.r, k.rh, r32(k.p), r32(k.v),
                        k.x, nullptr, nullptr, k.n3, k.nblk);
   else
     hipLaunchKernelGGL(kk_restart<c64>, vgrid(k), dim3(KNT), 0, s, restart, k.r, k.rh, k.p, k.v, k.x,

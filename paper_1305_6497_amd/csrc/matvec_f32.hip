@@ -3,7 +3,11 @@
 #include "passes.hpp"
 
 namespace dda {
-extern template void launch_x_pass<float, c32>(int, const Geometry &, const MatvecArgs &, const PassDims &,
-                                               hipStream_t);
+extern template void launch_x_pass<float, c32, c32>(int, const Geometry &, const MatvecArgs &, const PassDims &,
+                                                    hipStream_t);
+extern template void launch_x_pass<float, c64, c32>(int, const Geometry &, const MatvecArgs &, const PassDims &,
+                                                    hipStream_t);
+template void launch_x_pass<float, c64, c64>(int, const Geometry &, const MatvecArgs &, const PassDims &,
+                                             hipStream_t);
 template void launch_matvec<float>(const Geometry &, const MatvecArgs &, hipStream_t, const hipEvent_t *, int, int);
 }  // namespace dda

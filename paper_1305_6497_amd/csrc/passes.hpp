@@ -158,9 +158,9 @@ __device__ __forceinline__ void runs_load(c64 (&v)[EPT], int n, const VT *src) {
   }
 }
 
-// v = d = a + c b (b and d of one vector type)
-template <int EPT, typename TA, typename VT>
-__device__ __forceinline__ void runs_axpy(c64 (&v)[EPT], int n, const TA *a, const VT *b, VT *d, c64 c) {
+// v = d = a + c b (each vector c64 or c32)
+template <int EPT, typename TA, typename TB, typename VT>
+__device__ __forceinline__ void runs_axpy(c64 (&v)[EPT], int n, const TA *a, const TB *b, VT *d, c64 c) {
   c64 bv[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
@@ -181,8 +181,8 @@ __device__ __forceinline__ void runs_axpy(c64 (&v)[EPT], int n, const TA *a, con
 }
 
 // v = p = r + beta (p - omega w)
-template <int EPT>
-__device__ __forceinline__ void runs_p(c64 (&v)[EPT], int n, const c64 *r, c64 *p, const c64 *w, c64 beta,
+template <int EPT, typename VT, typename VW>
+__device__ __forceinline__ void runs_p(c64 (&v)[EPT], int n, const c64 *r, VT *p, const VW *w, c64 beta,
                                        c64 omega) {
   c64 pv[EPT], wv[EPT];
 #pragma unroll
@@ -190,16 +190,16 @@ __device__ __forceinline__ void runs_p(c64 (&v)[EPT], int n, const c64 *r, c64 *
     const int e = threadIdx.x + i * kNT;
     if (e < n) {
       v[i] = r[e];
-      pv[i] = p[e];
-      wv[i] = w[e];
+      pv[i] = vld(p + e);
+      wv[i] = vld(w + e);
     }
   }
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = threadIdx.x + i * kNT;
     if (e < n) {
-      v[i] = v[i] + beta * (pv[i] - omega * wv[i]);
-      p[e] = v[i];
+      v[i] = vround<VT>(v[i] + beta * (pv[i] - omega * wv[i]));
+      vst(p + e, v[i]);
     }
   }
 }
@@ -237,7 +237,7 @@ __device__ __forceinline__ bool block_alpha(const FuseArgs &f, int r, c64 &alpha
 // f.in_mode (see FuseArgs): 0 transforms `in`; 1 and 2 first form the BiCGSTAB
 // vector p or s from r, v (and the old p) and store it, so the vector update
 // costs no pass of its own.  LC > 0: Mx = LC, known at compile time.
-template <typename T, int EPT, int LC, int V, typename VT>
+template <typename T, int EPT, int LC, int V, typename VT, typename VV>
 __global__ __launch_bounds__(kNT) void k_xfwd(const VT *__restrict__ in, int64_t n3, const int *__restrict__ mask,
                                                const int *__restrict__ cell_site, const int4 *__restrict__ rowtab,
                                                Scaling sc, cpx<T> *__restrict__ A,
@@ -245,9 +245,12 @@ __global__ __launch_bounds__(kNT) void k_xfwd(const VT *__restrict__ in, int64_t
                                                PassDims d, FuseArgs f) {
   constexpr int W = kW<T>, LOGW = kLogW<T>;
   constexpr int NE = (EPT + 2) / 3;      // nrows * Mx <= EPT * kNT / 3
-  // FP32 vectors (VT = c32: COCG's p) come only with in_mode 0 or the single
-  // update p = r + beta p (nax = 1, r in FP64)
-  constexpr bool V64 = sizeof(VT) == sizeof(c64);
+  // VT: the type of in (and of w, the vector an update writes); VV: of v.
+  // FP32 vectors (COCG's p; BiCGSTAB's p and v) are never part of an update
+  // list longer than one (BiCGstab(2)); r is always FP64
+  constexpr bool V64 = sizeof(VT) == sizeof(c64) && sizeof(VV) == sizeof(c64);
+  VT *uw = reinterpret_cast<VT *>(f.w);
+  const VV *uv = reinterpret_cast<const VV *>(f.v);
   const int r = blockIdx.y;
   if (mask && !mask[r]) return;
   const int Mx = LC > 0 ? LC : px.L;
@@ -300,9 +303,10 @@ __global__ __launch_bounds__(kNT) void k_xfwd(const VT *__restrict__ in, int64_t
           if (f.nax > 1) runs_axpy(u, n, f.ax_a[1] + j0, f.ax_b[1] + j0, f.ax_d[1] + j0, cf[1]);
           if (f.nax > 2) runs_axpy(u, n, f.ax_a[2] + j0, f.ax_b[2] + j0, f.ax_d[2] + j0, cf[2]);
         }
-      } else if constexpr (V64) {
-        if (f.in_mode == 1) runs_p(v, n, f.r + j0, f.w + j0, f.v + j0, beta, omega);
-        else runs_axpy(v, n, f.r + j0, f.v + j0, f.w + j0, c64{-alpha.x, -alpha.y});
+      } else if (f.in_mode == 1) {
+        runs_p(v, n, f.r + j0, uw + j0, uv + j0, beta, omega);
+      } else {
+        runs_axpy(v, n, f.r + j0, uv + j0, uw + j0, c64{-alpha.x, -alpha.y});
       }
       const c64 *sr = sc.s ? sc.rhs(r) : nullptr;
 #pragma unroll
@@ -360,7 +364,7 @@ __global__ __launch_bounds__(kNT) void k_xfwd(const VT *__restrict__ in, int64_t
           }
           v[i][c] = val;
         }
-    } else if constexpr (V64) {
+    } else {
 #pragma unroll
       for (int i = 0; i < NE; ++i)
 #pragma unroll
@@ -368,9 +372,9 @@ __global__ __launch_bounds__(kNT) void k_xfwd(const VT *__restrict__ in, int64_t
           c64 val = {0, 0};
           if (site[i] >= 0) {
             const size_t j = off + (size_t)3 * site[i] + c;
-            if (f.in_mode == 1) val = f.r[j] + beta * (f.w[j] - omega * f.v[j]);
-            else val = f.r[j] - alpha * f.v[j];
-            f.w[j] = val;
+            if (f.in_mode == 1) val = vround<VT>(f.r[j] + beta * (vld(uw + j) - omega * vld(uv + j)));
+            else val = vround<VT>(f.r[j] - alpha * vld(uv + j));
+            vst(uw + j, val);
           }
           v[i][c] = val;
         }
@@ -756,8 +760,8 @@ __global__ __launch_bounds__(kNT) void k_xinv(const VT *__restrict__ in, VT *__r
       acc[7] += g20.y;
     }
   };
-  // BiCGSTAB's rh and BiCGstab(2)'s r0 (out modes 1 and 3) exist only as FP64 vectors
-  const c64 *xsrc = sizeof(VT) != sizeof(c64) ? nullptr : f.out_mode == 1 ? f.rh : f.out_mode == 3 ? f.r : nullptr;
+  // BiCGSTAB's rh (out mode 1) and BiCGstab(2)'s r0 (out mode 3) are FP64 vectors
+  const c64 *xsrc = f.out_mode == 1 ? f.rh : f.out_mode == 3 ? f.r : nullptr;
   bool done = false;
   if constexpr (LC > 0) {
     constexpr int NR = xpass_rows(LC > 0 ? LC : 1);
@@ -919,10 +923,18 @@ static inline void allow_lds(K kernel, size_t bytes) {
   if (bytes > 65536) DDA_HIP(hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
 }
 
-// The x-forward (k = 0) or x-inverse (k = 4) pass with Krylov vectors of type
-// VT (c64, or c32 for COCG's p and q in a DDA_MIXED_V32 solve).
-template <typename T, typename VT>
+// The x-forward (k = 0) or x-inverse (k = 4) pass with the product's input and
+// output of type VT and the update's v of type VV (c64, or c32 for the search
+// directions and their products in a DDA_MIXED_V32 solve).  The x-inverse does
+// not depend on VV.
+template <typename T, typename VT, typename VV>
 void launch_x_pass(int k, const Geometry &g, const MatvecArgs &a, const PassDims &d, hipStream_t s) {
+  if constexpr (!std::is_same_v<VT, VV>) {
+    if (k != 0) {
+      launch_x_pass<T, VT, VT>(k, g, a, d, s);
+      return;
+    }
+  }
   const bool f32 = sizeof(T) == 4;
   const size_t ae = g.a_elems(f32);
   cpx<T> *A = static_cast<cpx<T> *>(a.bufA);
@@ -943,7 +955,7 @@ void launch_x_pass(int k, const Geometry &g, const MatvecArgs &a, const PassDims
       constexpr int LC = decltype(lc)::value;
       constexpr int E = LC > 0 ? pick_ept_c((size_t)3 * xpass_rows(LC) * LC, true) : decltype(e)::value;
       auto go = [&](auto vv) {
-        hipLaunchKernelGGL((k_xfwd<T, E, LC, decltype(vv)::value, VT>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s,
+        hipLaunchKernelGGL((k_xfwd<T, E, LC, decltype(vv)::value, VT, VV>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s,
                            in, n3, a.mask, a.cell_site, a.rowtab, a.scl, A, ae, twx, a.px, d, f);
       };
       if constexpr (LC >= kTunedMinLen) {
@@ -1016,11 +1028,15 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
         // FP32 Krylov vectors only with the FP32 product
         if constexpr (sizeof(T) == 4) {
           if (a.vec32) {
-            launch_x_pass<T, c32>(k, g, a, d, s);
+            launch_x_pass<T, c32, c32>(k, g, a, d, s);
+            break;
+          }
+          if (a.vvec32) {
+            launch_x_pass<T, c64, c32>(k, g, a, d, s);
             break;
           }
         }
-        launch_x_pass<T, c64>(k, g, a, d, s);
+        launch_x_pass<T, c64, c64>(k, g, a, d, s);
         break;
       case 1:
         with_pass<32>(g.My, (size_t)g.My * W, [&](auto e, auto lc) {

@@ -38,8 +38,8 @@ SOLVERS = ["bicgstab", "bicgstab2", "cocg", "qmr"]
 
 
 def _mixed_precs(solver):
-    # "mixed32" (COCG's p and A p in FP32 too) exists for COCG only
-    return ["mixed", "mixed32"] if solver == "cocg" else ["mixed"]
+    # "mixed32" (the search direction p and A p in FP32 too) exists for COCG and BiCGSTAB
+    return ["mixed", "mixed32"] if solver in ("cocg", "bicgstab") else ["mixed"]
 
 
 def _rel(a, b):
@@ -307,9 +307,10 @@ def test_solve_mixed_reaches_fp64_tolerance(dda, solver):
 
 @pytest.mark.parametrize("m,alpha", [(1.33 + 0.01j, "LATTDR"), (1.7 + 0.3j, "GKDLDR"), (0.9656 + 1.8628j, "LATTDR")])
 def test_mixed32_cocg_matches_dense_lu(dda, m, alpha):
-    # COCG with FP32 products and FP32 p and A p, refined in FP64:
-    # the dense-LU solution to 1e-8 at tol 1e-11, in about as many iterations
-    # as with FP64 vectors, also on a metallic target; other solvers reject the mode
+    # COCG and BiCGSTAB with FP32 products and FP32 p and A p, refined in
+    # FP64: the dense-LU solution to 1e-8 at tol 1e-11, in about as many
+    # iterations as with FP64 vectors, also on a metallic target; the other
+    # solvers reject the mode
     shpar = (9.5, 8.0, 6.5)
     sites, box = dda.make_sites("ELLIPSOID", shpar)
     osites = targets.ellipsoid(*shpar)
@@ -321,21 +322,26 @@ def test_mixed32_cocg_matches_dense_lu(dda, m, alpha):
     _, sm = t.solve(rhs, tol=1e-11, precision="mixed", max_iter=2000, solver="cocg")
     q = t.cross_sections(rhs, P)
     Pg = P.cpu().numpy()
-    for other in ("bicgstab", "bicgstab2", "qmr"):
+    Pb, sb = t.solve(rhs, tol=1e-11, precision="mixed32", max_iter=2000, solver="bicgstab")
+    _, sbm = t.solve(rhs, tol=1e-11, precision="mixed", max_iter=2000, solver="bicgstab")
+    qb = t.cross_sections(rhs, Pb)
+    Pbg = Pb.cpu().numpy()
+    for other in ("bicgstab2", "qmr"):
         with pytest.raises(RuntimeError):
             t.solve(rhs, tol=1e-5, precision="mixed32", solver=other)
     t.close()
     for r in range(2):
-        assert st[r]["status"] == 0 and st[r]["rel_resid"] <= 1e-11
-        assert st[r]["iters"] <= 1.15 * sm[r]["iters"] + 4, (st[r], sm[r])
         ai = polarizability.alpha_inv(alpha, m, kd, *rhs[r])
         E = incident.incident_field(osites, kd, *rhs[r])
         A = interaction.dense_matrix(osites, kd, ai)
         Po = solvers.lu_solve(A, E.ravel()).reshape(-1, 3)
-        assert _rel(Pg[r], Po) < 1e-8
         qo = cross_sections.efficiencies(len(osites), kd, E, ai, Po)
-        for key in ("qext", "qabs", "qsca", "qpha"):
-            assert abs(q[r][key] - qo[key]) <= 1e-9 * qo["qext"], key
+        for label, stats, ref_stats, Pr, qr in (("cocg", st, sm, Pg, q), ("bicgstab", sb, sbm, Pbg, qb)):
+            assert stats[r]["status"] == 0 and stats[r]["rel_resid"] <= 1e-11, (label, stats[r])
+            assert stats[r]["iters"] <= 1.15 * ref_stats[r]["iters"] + 4, (label, stats[r], ref_stats[r])
+            assert _rel(Pr[r], Po) < 1e-8, label
+            for key in ("qext", "qabs", "qsca", "qpha"):
+                assert abs(qr[r][key] - qo[key]) <= 1e-9 * qo["qext"], (label, key)
 
 
 @pytest.mark.parametrize("solver", SOLVERS)
@@ -476,8 +482,8 @@ def test_graph_replay_matches_eager_bitwise(dda, solver):
 @pytest.mark.parametrize("name", ["au_block_16x32x32", "block_64", "ellipsoid_96x64x48"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed32"])
 def test_full_size_efficiencies_against_oracle(dda, name, prec, solver):
-    if prec == "mixed32" and solver != "cocg":
-        pytest.skip("mixed32 is built for COCG only")
+    if prec == "mixed32" and solver not in ("cocg", "bicgstab"):
+        pytest.skip("mixed32 is built for COCG and BiCGSTAB only")
     import json
     import os
     with open(os.path.join(os.path.dirname(__file__), "golden", f"reference_{name}.json")) as f:
@@ -960,7 +966,7 @@ def test_initial_guess(dda, solver):
     warm_e, swe = t.solve(rhs, tol=1e-9, precision="mixed", solver=solver, x0=loose, check_every=8)
     assert torch.equal(warm_g, warm_e)
     assert [x["iters"] for x in swg] == [x["iters"] for x in swe]
-    if solver == "cocg":
+    if solver in ("cocg", "bicgstab"):
         # FP32 p and A p: the same warm start and tolerance
         _, s32c = t.solve(rhs, tol=1e-9, precision="mixed32", solver=solver)
         warm32, s32 = t.solve(rhs, tol=1e-9, precision="mixed32", solver=solver, x0=loose)
