@@ -459,8 +459,8 @@ void matvec_on(dda_target *t, int precision, const c64 *in, c64 *out, int nrhs, 
   // FP32 vectors only in the iterations' FP32 products: COCG's p -> q and
   // BiCGSTAB's p -> v (in mode 3 or 1); BiCGSTAB's s -> t product (in mode 2)
   // keeps s and t in FP64 but reads the FP32 v in its fused update
-  const bool v32 = t->k.vec32 && precision == DDA_MIXED;
-  a.vec32 = v32 && !(fuse && fuse->in_mode == 2);
+  const bool v32 = t->k.vec32 && precision == DDA_MIXED && fuse != nullptr;
+  a.vec32 = v32 && fuse->in_mode != 2;
   a.vvec32 = v32;
   if (t->jacobi_active) {
     a.scl.s = t->d_scl;
