@@ -478,12 +478,10 @@ def test_graph_replay_matches_eager_bitwise(dda, solver):
 # 1e-9, the efficiencies differ from the stored ones by O(1e-9) times the
 # conditioning of Q in P; block_64 solved to 1e-5 already agrees to 4e-6, so
 # 1e-7 of Q_ext leaves a margin of two orders of magnitude.
-@pytest.mark.parametrize("solver", SOLVERS)
+@pytest.mark.parametrize("prec,solver", [(p, s) for p in ("fp64", "mixed") for s in SOLVERS] +
+                         [("mixed32", "bicgstab"), ("mixed32", "cocg")])
 @pytest.mark.parametrize("name", ["au_block_16x32x32", "block_64", "ellipsoid_96x64x48"])
-@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed32"])
 def test_full_size_efficiencies_against_oracle(dda, name, prec, solver):
-    if prec == "mixed32" and solver not in ("cocg", "bicgstab"):
-        pytest.skip("mixed32 is built for COCG and BiCGSTAB only")
     import json
     import os
     with open(os.path.join(os.path.dirname(__file__), "golden", f"reference_{name}.json")) as f:
