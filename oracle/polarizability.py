@@ -42,8 +42,10 @@
                  + (2/(3 pi)) ln((pi - kd)/(pi + kd)) (kd)^3 + (2/3) i (kd)^3 ])
 
   Only the polarizability is modelled (the filtered Green function of the
-  full FCD method is outside this oracle).  Pinned by the kd -> 0 limit and
-  the lossless test; otherwise parity unpinned.
+  full FCD method is outside this oracle).  The bracket is the k-dependent
+  part of the field that the point dipole's field, band-limited to
+  wavenumbers below pi/d, puts on the dipole itself; a test computes that
+  integral by quadrature and pins every term of the reading with it.
 
 All functions return the inverse polarizability 1/alpha (complex128), which
 is what enters the diagonal of A in eq. (AP=E): a scalar, or for GKDLDR the

@@ -125,6 +125,31 @@ def test_radiative_reaction_sign_makes_lossless_dipole_nonabsorbing():
             assert abs(f(kd).imag + (2.0 / 3.0) * kd ** 3) < 1e-14
 
 
+def test_fcd_correction_is_the_band_limited_self_field():
+    # The filtered coupled dipole method replaces the point dipole's field by
+    # its band-limited version: wavenumbers |q| < pi / d only.  The field that
+    # this filtered field puts on the dipole itself (a plane-wave sum over the
+    # ball, isotropic, so q q -> q^2 I / 3) is
+    #   (1 / (2 pi)^3) int_{|q| < pi} 4 pi (k^2 - q^2 / 3) / (q^2 - k^2 - i0) d^3q
+    #   = (2 / pi) [PV int_0^pi q^2 (k^2 - q^2/3) / (q^2 - k^2) dq] + i (2/3) k^3,
+    # the imaginary part being the residue at q = k.  Its k-dependent part
+    # (minus its k -> 0 limit, which Clausius-Mossotti already holds) is the
+    # FCD correction 1/alpha_CM - 1/alpha_FCD: every coefficient, the (kd)^3
+    # of the log term and the radiative sign.  Computed here by quadrature.
+    from scipy import integrate
+
+    def self_field(k):
+        g = lambda q: q * q * (k * k - q * q / 3.0) / (q + k)
+        pv, _ = integrate.quad(g, 0.0, math.pi, weight="cauchy", wvar=k, epsabs=1e-14, epsrel=1e-13, limit=200)
+        return complex((2.0 / math.pi) * pv, (2.0 / math.pi) * math.pi * k ** 3 / 3.0)
+
+    static = self_field(1e-9).real
+    for m in (1.5 + 0.1j, 0.9656 + 1.8628j):
+        for kd in (0.05, 0.3, 0.7, 1.5, 2.5):
+            corr = 1.0 / pol.alpha_cm(m) - pol.alpha_inv_fcd(m, kd)
+            assert abs(corr - (self_field(kd) - static)) < 1e-12 * max(1.0, abs(corr)), (m, kd)
+
+
 def test_single_dipole_scattering_closed_form():
     # One dipole: P = alpha E, C_sca = (8 pi / 3) k^4 |alpha|^2 (Rayleigh
     # scattering of a point dipole), and extinction = absorption + scattering.
