@@ -217,7 +217,7 @@ struct MatvecArgs {
   // row), else nullptr; the x passes then move P as contiguous runs
   const int4 *rowtab;
   void *bufA, *bufB;              // workspaces (sized for nrhs in FP64)
-  const void *ghat;               // octant Green transform [6][Mzh][Myh][Mxh] (scaled by 1/M)
+  const void *ghat;               // octant Green transform [Mzh][Myh][Mxh][6] (scaled by 1/M)
   const void *twx, *twy, *twz;    // twiddles of the T precision
   AxisPlan px, py, pz;
   FuseArgs fuse;

@@ -136,13 +136,16 @@ __global__ void k_magnetic_fill(c64 *__restrict__ full, int nx, int ny, int nz, 
   for (int c = 0; c < 3; ++c) full[c * M + i] = h[c];
 }
 
+// One octant of the transformed Green tensor, scaled by 1/M, stored cell-major
+// (the six components of a cell side by side) in FP64 and FP32: the z-pass
+// reads a cell's six values as one contiguous 48-byte (FP32) record.
 __global__ void k_green_octant(const c64 *__restrict__ full, c64 *__restrict__ o64, c32 *__restrict__ o32, int Mx,
                                int My, int Mz, int Mxh, int Myh, int Mzh, double scale) {
   const int64_t moct = (int64_t)Mxh * Myh * Mzh;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= 6 * moct) return;
-  const int c = (int)(i / moct);
-  const int64_t j = i - c * moct;
+  const int64_t j = i / 6;               // cell-major: value c of cell j at 6 j + c
+  const int c = (int)(i - 6 * j);
   const int ox = (int)(j % Mxh);
   const int oy = (int)((j / Mxh) % Myh);
   const int oz = (int)(j / ((int64_t)Mxh * Myh));

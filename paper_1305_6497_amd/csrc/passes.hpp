@@ -52,7 +52,6 @@ struct PassDims {
   int nxt;                        // x tiles of W
   int nrows;                      // rows per block of the x passes
   int Mxh, Myh;                   // octant extents M/2 + 1 (Green table)
-  int64_t moct;                   // Mxh * Myh * Mzh
   int nrhs;                       // right-hand sides of the launch
   FastDiv d_mx, d_nx, d_ny, d_nxt, d_nrows, d_nrhs;
 };
@@ -469,6 +468,25 @@ __device__ __forceinline__ cpx<T> dot3(cpx<T> g0, cpx<T> p0, cpx<T> g1, cpx<T> p
   return {re, im};
 }
 
+// The six Green values of one octant cell (stored cell-major, xx yy zz xy xz
+// yz): three 16-byte loads in FP32, six in FP64.  Eight lanes of a wave read
+// 8 consecutive cells, one contiguous run of 384 (FP32) bytes.
+template <typename T>
+__device__ __forceinline__ void load_green(const cpx<T> *g, cpx<T> (&v)[6]) {
+  if constexpr (sizeof(T) == 4) {
+    const float4 *p = reinterpret_cast<const float4 *>(g);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float4 a = p[k];
+      v[2 * k] = cpx<T>{a.x, a.y};
+      v[2 * k + 1] = cpx<T>{a.z, a.w};
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = g[c];
+  }
+}
+
 // Fold a frequency index into the stored octant: k <= M/2 is kept (sign +1),
 // k > M/2 maps to M - k (sign -1 for components odd along this axis).
 __device__ __forceinline__ int fold(int k, int M, int &sgn) {
@@ -596,22 +614,45 @@ __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx
   }
   int sy;
   const int oy = fold(ky, d.My, sy);
+  // Green values of the thread's i-th cell and the x sign of its fold.  Lanes
+  // past Mx (the last x tile) hold zeros, which the x-forward pass wrote there;
+  // any Green value keeps them zero, so their index is clamped.  Slots past
+  // nq load cell 0 (in bounds, unused): the loads are unconditional, so in
+  // FP32 the next cell's loads stay in flight while the current cell is
+  // multiplied.  FP64 loads each cell's values where they are used: holding
+  // the next cell's twelve doubles costs the FP64 kernel occupancy.
+  constexpr bool kAhead = sizeof(T) == 4;
+  auto green_at = [&](int i, cpx<T>(&gv)[6], int &sx) {
+    const int q = threadIdx.x + i * kNT;
+    const int qc = q < nq ? q : 0;
+    const int kx = min((xt << LOGW) + h * NP + (qc & (NP - 1)), d.Mx - 1);
+    const int ox = fold(kx, d.Mx, sx);
+    load_green(ghat + 6 * (size_t)(mul24(mul24(qc >> LOGP, d.Myh) + oy, d.Mxh) + ox), gv);
+  };
+  cpx<T> gnext[6];
+  int sxnext = 1;
+  if constexpr (kAhead) green_at(0, gnext, sxnext);
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     const int q = threadIdx.x + i * kNT;
+    cpx<T> gv[6];
+    int sx;
+    if constexpr (kAhead) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) gv[c] = gnext[c];
+      sx = sxnext;
+      if (i + 1 < NQ) green_at(i + 1, gnext, sxnext);
+    } else {
+      green_at(i, gv, sx);
+    }
     if (q < nq) {
-      // lanes past Mx (the last x tile) hold zeros, which the x-forward pass
-      // wrote there; any Green value keeps them zero, so their index is clamped
-      const int oz = q >> LOGP, p = q & (NP - 1), kx = min((xt << LOGW) + h * NP + p, d.Mx - 1);
+      const int oz = q >> LOGP, p = q & (NP - 1);
       const bool mir = oz != 0 && 2 * oz != Mz;
       // without a mirror (oz = 0 or Mz/2) the mirror products are computed on
       // the cell itself and discarded
       const int zb = mir ? ((Mz - oz) << LOGP) + p : q;
-      int sx;
-      const int ox = fold(kx, d.Mx, sx);
-      const cpx<T> *g = ghat + (size_t)(mul24(mul24(oz, d.Myh) + oy, d.Mxh) + ox);
-      const cpx<T> gxx = g[0], gyy = g[d.moct], gzz = g[2 * d.moct];
-      const cpx<T> gxy = T(sx * sy) * g[3 * d.moct], gxz = T(sx) * g[4 * d.moct], gyz = T(sy) * g[5 * d.moct];
+      const cpx<T> gxx = gv[0], gyy = gv[1], gzz = gv[2];
+      const cpx<T> gxy = T(sx * sy) * gv[3], gxz = T(sx) * gv[4], gyz = T(sy) * gv[5];
       const cpx<T> a2 = buf[q], b2 = buf[zb];
       const cpx<T> qa0 = dot3(gxx, a0[i], gxy, a1[i], gxz, a2);
       const cpx<T> qa1 = dot3(gxy, a0[i], gyy, a1[i], gyz, a2);
@@ -1005,7 +1046,6 @@ void launch_matvec(const Geometry &g, const MatvecArgs &a, hipStream_t s, const 
   d.nxt = nxt;
   d.nrows = nrows;
   d.Mxh = g.Mxh; d.Myh = g.Myh;
-  d.moct = (int64_t)g.oct_elems();
   d.d_mx = make_fastdiv(g.Mx);
   d.d_nx = make_fastdiv(g.nx);
   d.d_ny = make_fastdiv(g.ny);
