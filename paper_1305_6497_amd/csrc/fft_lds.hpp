@@ -591,4 +591,35 @@ __device__ __forceinline__ void load_twiddles(cpx<T> *dst, const cpx<T> *src, in
   for (int i = threadIdx.x; i < L; i += kNT) dst[i] = src[i];
 }
 
+// A twiddle table copied into LDS in two steps: issue() starts the loads into
+// registers and commit() writes them to LDS, so a pass that issues its data
+// loads in between waits for one round trip to memory instead of two.  With a
+// compile-time length the loads are unconditional (indices past the table
+// are clamped, their values dropped), which lets the compiler count them
+// exactly.  FP64 tables (and run-time lengths) are copied by issue() at once:
+// staged, the FP64 x-inverse was measured slower.
+template <typename T, int LC>
+struct TwiddleStage {
+  static constexpr bool kStaged = LC > 0 && sizeof(T) == 4;
+  static constexpr int N = kStaged ? cdiv_c(LC, kNT) : 1;
+  cpx<T> v[N];
+  __device__ __forceinline__ void issue(cpx<T> *dst, const cpx<T> *src, int len) {
+    if constexpr (kStaged) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) v[k] = src[min((int)threadIdx.x + k * kNT, LC - 1)];
+    } else {
+      load_twiddles(dst, src, len);
+    }
+  }
+  __device__ __forceinline__ void commit(cpx<T> *dst) const {
+    if constexpr (kStaged) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        const int i = threadIdx.x + k * kNT;
+        if (i < LC) dst[i] = v[k];
+      }
+    }
+  }
+};
+
 }  // namespace dda

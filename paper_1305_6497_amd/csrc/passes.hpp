@@ -103,8 +103,8 @@ struct RowRuns {
   int s0[NR];                     // block-relative first site (INT_MAX past the block)
   int step[NR];                   // change of (LDS position - site) from row q-1 to q
   int lo[NR], len[NR];            // first x and count of row q
-  __device__ __forceinline__ RowRuns(const int4 *__restrict__ tab, int row0, int nrow, int L) {
-    const int *t = reinterpret_cast<const int *>(tab + row0);
+  // t: the block's row-table entries (4 ints per row, from global memory or LDS)
+  __device__ __forceinline__ RowRuns(const int *t, int nrow, int L) {
     first = t[0];
     count = 0;
     int prev = 0;
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(kNT) void k_xfwd(const VT *__restrict__ in, int64_t
     constexpr int NR = xpass_rows(LC > 0 ? LC : 1);
     constexpr int ER = (3 * NR * ((LC + 1) / 2) + kNT - 1) / kNT;
     if (rowtab && d.nx <= (LC + 1) / 2) {
-      const RowRuns<NR> rr(rowtab, row0, nrow, LC);
+      const RowRuns<NR> rr(reinterpret_cast<const int *>(rowtab + row0), nrow, LC);
       const int n = 3 * rr.count;
       const size_t j0 = off + (size_t)3 * rr.first;
       c64 v[ER];
@@ -536,7 +536,8 @@ __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx
   const int nzW = d.nz << LOGW;
   cpx<T> *buf = reinterpret_cast<cpx<T> *>(dda_smem);
   cpx<T> *tw = buf + n;
-  load_twiddles(tw, twz, Mz);
+  TwiddleStage<T, LC> tws;
+  tws.issue(tw, twz, Mz);
   const int h = li & HALF, lt = li >> HALF;
   const int iy = (int)d.d_nxt((uint32_t)lt), ix = lt - iy * d.nxt;
   const int ky = (iy & 1) ? d.My - ((iy + 1) >> 1) : (iy >> 1);
@@ -585,6 +586,7 @@ __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (c < 2) fetch(c + 1, pre[(c + 1) & 1]);
+      if (c == 0) tws.commit(tw);
       fft_pen_from_regs<T, -1, LOGP, LC, V>(buf, tw, pre[c & 1]);
       if (c < 2) park(c);
     }
@@ -599,6 +601,7 @@ __global__ __launch_bounds__(kNT) void k_zpass(const int *__restrict__ mask, cpx
       }
     };
     fetch(0, pre[0]);
+    tws.commit(tw);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
 #pragma unroll
@@ -745,10 +748,40 @@ __global__ __launch_bounds__(kNT) void k_xinv(const VT *__restrict__ in, VT *__r
   cpx<T> *buf = reinterpret_cast<cpx<T> *>(dda_smem);
   cpx<T> *tw = buf + 3 * ne;
   int *rowoff = reinterpret_cast<int *>(tw + Mx);
-  load_twiddles(tw, twx, Mx);
+  TwiddleStage<T, LC> tws;
+  tws.issue(tw, twx, Mx);
   const int row0 = blockIdx.x * nrows;
   const int nrow = min(nrows, d.ny * d.nz - row0);
   x_row_offsets<T, LC>(rowoff, d, nrows, row0, nrow);
+  // Read before the transform, so that these loads overlap those of A: the
+  // block's row runs (sites numbered row after row) and, with one
+  // composition, the three values of 1/alpha that every site of this
+  // right-hand side takes.
+  constexpr int NR = xpass_rows(LC > 0 ? LC : 1);
+  const bool runs = LC > 0 && rowtab && d.nx <= (LC + 1) / 2;
+  // The row-table entries go to LDS (a global read after the transform
+  // would delay every load of P behind it); their load is in flight with
+  // those of A.
+  int *rtab = rowoff + 3 * nrows;
+  const bool rt_lane = runs && threadIdx.x < 4 * nrow;
+  const int rt_val = rt_lane ? reinterpret_cast<const int *>(rowtab + row0)[threadIdx.x] : 0;
+  const c64 *ai = ainv + (size_t)r * ncomp * 3;      // [ncomp][3] of this RHS
+  // (three values, not an array: a select between array elements would put
+  // the array in scratch memory)
+  c64 ax{0, 0}, ay{0, 0}, az{0, 0};
+  if (!comp) {
+    ax = ai[0];
+    ay = ai[1];
+    az = ai[2];
+  }
+  // 1/alpha of component c at a site
+  auto alpha_inv = [&](int site, int c) -> c64 {
+    if (comp) return ai[3 * comp[site] + c];
+    c64 v = az;
+    if (c == 0) v = ax;
+    if (c == 1) v = ay;
+    return v;
+  };
   __syncthreads();
   const cpx<T> *Ar = A + (size_t)r * a_elems;
   const int nyW = d.ny * W;
@@ -758,10 +791,11 @@ __global__ __launch_bounds__(kNT) void k_xinv(const VT *__restrict__ in, VT *__r
     const int ro = rowoff[pq];
     return ro >= 0 ? Ar[ro + (kx >> LOGW) * nyW + (kx & (W - 1))] : cpx<T>{0, 0};
   });
+  if (rt_lane) rtab[threadIdx.x] = rt_val;
+  tws.commit(tw);
   __syncthreads();
   fft_rows<T, EPT, +1, LC, V>(buf, tw, px, 3 * nrows);
   const size_t off = (size_t)r * n3;
-  const c64 *ai = ainv + (size_t)r * ncomp * 3;      // [ncomp][3] of this RHS
   double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const c64 *sr = sc.s ? sc.rhs(r) : nullptr;
   // with scaling the field term becomes s (G s P): each thread scales the
@@ -805,10 +839,9 @@ __global__ __launch_bounds__(kNT) void k_xinv(const VT *__restrict__ in, VT *__r
   const c64 *xsrc = f.out_mode == 1 ? f.rh : f.out_mode == 3 ? f.r : nullptr;
   bool done = false;
   if constexpr (LC > 0) {
-    constexpr int NR = xpass_rows(LC > 0 ? LC : 1);
     constexpr int ER = (3 * NR * ((LC + 1) / 2) + kNT - 1) / kNT;
-    if (rowtab && d.nx <= (LC + 1) / 2) {
-      const RowRuns<NR> rr(rowtab, row0, nrow, LC);
+    if (runs) {
+      const RowRuns<NR> rr(rtab, nrow, LC);
       const int n = 3 * rr.count;
       const size_t j0 = off + (size_t)3 * rr.first;
       if (sr) {
@@ -829,7 +862,7 @@ __global__ __launch_bounds__(kNT) void k_xinv(const VT *__restrict__ in, VT *__r
           pv[i] = vld(in + j0 + e);
           xv[i] = xsrc ? xsrc[j0 + e] : c64{0, 0};
           const int st = e / 3;
-          av[i] = ai[(comp ? 3 * comp[rr.first + st] : 0) + (e - 3 * st)];
+          av[i] = alpha_inv(rr.first + st, e - 3 * st);
         }
       }
 #pragma unroll
@@ -874,11 +907,10 @@ __global__ __launch_bounds__(kNT) void k_xinv(const VT *__restrict__ in, VT *__r
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
       if (site[i] >= 0) {
-        const c64 *a = ai + (comp ? 3 * comp[site[i]] : 0);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const size_t j = off + (size_t)3 * site[i] + c;
-          finish(j, a[c], pv[i][c], buf[c * ne + bi[i]], xsrc ? xsrc[j] : c64{0, 0});
+          finish(j, alpha_inv(site[i], c), pv[i][c], buf[c * ne + bi[i]], xsrc ? xsrc[j] : c64{0, 0});
         }
       }
     }
@@ -990,7 +1022,8 @@ void launch_x_pass(int k, const Geometry &g, const MatvecArgs &a, const PassDims
   // rows-plan variants of the x-forward and x-inverse passes (forced or tuned)
   const int xv[2] = {a.xvar[0] >= 0 ? a.xvar[0] : tuned_variant(kPassXfwd, g.Mx, f32),
                      a.xvar[1] >= 0 ? a.xvar[1] : tuned_variant(kPassXinv, g.Mx, f32)};
-  const size_t xlds = ((size_t)3 * nrows * g.Mx + g.Mx) * cs + (size_t)3 * nrows * sizeof(int);
+  // rows, twiddles, the row offsets and the block's row-table entries
+  const size_t xlds = ((size_t)3 * nrows * g.Mx + g.Mx) * cs + (size_t)7 * nrows * sizeof(int);
   if (k == 0) {
     with_pass<8>(g.Mx, (size_t)3 * nrows * g.Mx, [&](auto e, auto lc) {
       constexpr int LC = decltype(lc)::value;
