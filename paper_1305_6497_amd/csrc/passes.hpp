@@ -800,8 +800,37 @@ __global__ __launch_bounds__(kNT) void k_xinv(const VT *__restrict__ in, VT *__r
   if (rt_lane) rtab[threadIdx.x] = rt_val;
   tws.commit(tw);
   __syncthreads();
-  fft_rows<T, EPT, +1, LC, V>(buf, tw, px, 3 * nrows);
   const size_t off = (size_t)r * n3;
+  // FP64 small mode with row runs: the loads of the block's run of P are
+  // issued here, so that they are in flight during the transform (FP64
+  // blocks are bound by LDS to 5 per CU, so the registers are free; in FP32
+  // they cost a resident wave and the pass was measured slower).
+  constexpr bool kPre = LC > 0 && kSmall && sizeof(T) == 8;
+  constexpr int ERP = kPre ? (3 * NR * ((LC + 1) / 2) + kNT - 1) / kNT : 1;
+  VT pin[ERP];
+  if constexpr (kPre) {
+    // Unconditional loads (no branch, so the compiler keeps them in flight
+    // across the transform): indices past the run are clamped to its first
+    // element, and a block without row runs or sites reads the first element
+    // of P.  Without row runs the row-table words read here are unused.
+    int cnt = 0;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) cnt += q < nrow ? rtab[4 * q + 2] : 0;
+    const int np = runs ? 3 * cnt : 0;
+    const VT *src = np > 0 ? in + off + (size_t)3 * rtab[0] : in;
+#pragma unroll
+    for (int i = 0; i < ERP; ++i) {
+      const int e = threadIdx.x + i * kNT;
+      pin[i] = src[e < np ? e : 0];
+    }
+  }
+  fft_rows<T, EPT, +1, LC, V>(buf, tw, px, 3 * nrows);
+  if constexpr (kPre) {
+    // keeps the compiler from converting (and so waiting for) the loaded
+    // values before the transform
+#pragma unroll
+    for (int i = 0; i < ERP; ++i) asm volatile("" : "+v"(pin[i].x), "+v"(pin[i].y));
+  }
   constexpr int NACC = kSmall ? 2 : 8;
   double acc[NACC];
 #pragma unroll
@@ -871,7 +900,8 @@ __global__ __launch_bounds__(kNT) void k_xinv(const VT *__restrict__ in, VT *__r
       for (int i = 0; i < ER; ++i) {
         const int e = threadIdx.x + i * kNT;
         if (e < n) {
-          pv[i] = vld(in + j0 + e);
+          if constexpr (kPre) pv[i] = vld(&pin[i]);
+          else pv[i] = vld(in + j0 + e);
           xv[i] = xsrc ? xsrc[j0 + e] : c64{0, 0};
           const int st = e / 3;
           av[i] = alpha_inv(rr.first + st, e - 3 * st);
