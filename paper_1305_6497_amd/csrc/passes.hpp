@@ -731,11 +731,13 @@ __global__ __launch_bounds__(kNT) void k_yinv(const int *__restrict__ mask, cons
 // --------------------------------------------------------------- x-inverse --
 // f.out_mode (see FuseArgs): 0 only writes out = ainv * in - G*in; 1 and 2 also
 // write per-block partial sums of the BiCGSTAB inner products of `out`.
-// SMALL = 1: out_mode is 0 or 4 (the plain product; the bilinear in^T out of
-// COCG and QMR), chosen when the kernel is launched, so the registers that
-// the other modes' FP64 operand and sums need are not allocated (in FP32, 70
-// instead of 92 VGPRs: 7 resident waves per SIMD instead of 5).
-template <typename T, int EPT, int LC, int V, typename VT, int SMALL>
+// MODES, chosen when the kernel is launched, names the out_modes an
+// instantiation handles, so that it holds only the registers those need:
+// 1 = {0, 4} (the plain product; the bilinear in^T out of COCG and QMR: no
+// FP64 operand, two sums; in FP32 68 instead of 92 VGPRs, 7 resident waves
+// per SIMD instead of 5), 2 = {1, 2} (BiCGSTAB: three sums), 0 = all
+// (BiCGstab(2)'s mode 3: eight sums).
+template <typename T, int EPT, int LC, int V, typename VT, int MODES>
 __global__ __launch_bounds__(kNT) void k_xinv(const VT *__restrict__ in, VT *__restrict__ out, int64_t n3,
                                                const int *__restrict__ mask, const c64 *__restrict__ ainv,
                                                int ncomp, const uint8_t *__restrict__ comp,
@@ -744,7 +746,7 @@ __global__ __launch_bounds__(kNT) void k_xinv(const VT *__restrict__ in, VT *__r
                                                const cpx<T> *__restrict__ twx, AxisPlan px, PassDims d, FuseArgs f) {
   constexpr int W = kW<T>, LOGW = kLogW<T>;
   constexpr int NE = (EPT + 2) / 3;
-  constexpr bool kSmall = SMALL == 1;
+  constexpr bool kSmall = MODES == 1, kBicg = MODES == 2;
   const int out_mode = kSmall ? (f.out_mode == 4 ? 4 : 0) : f.out_mode;
   const int r = blockIdx.y;
   if (mask && !mask[r]) return;
@@ -831,7 +833,7 @@ __global__ __launch_bounds__(kNT) void k_xinv(const VT *__restrict__ in, VT *__r
 #pragma unroll
     for (int i = 0; i < ERP; ++i) asm volatile("" : "+v"(pin[i].x), "+v"(pin[i].y));
   }
-  constexpr int NACC = kSmall ? 2 : 8;
+  constexpr int NACC = kSmall ? 2 : kBicg ? 3 : 8;
   double acc[NACC];
 #pragma unroll
   for (int k = 0; k < NACC; ++k) acc[k] = 0.0;
@@ -862,22 +864,24 @@ __global__ __launch_bounds__(kNT) void k_xinv(const VT *__restrict__ in, VT *__r
         acc[0] += g.x;
         acc[1] += g.y;
         acc[2] += o.x * o.x + o.y * o.y;
-      } else if (out_mode == 3) {
-        // in = r1, out = r2, f.r = r0
-        const c64 g12 = cmulc(pv, o), g10 = cmulc(pv, x), g20 = cmulc(o, x);
-        acc[0] += pv.x * pv.x + pv.y * pv.y;
-        acc[1] += o.x * o.x + o.y * o.y;
-        acc[2] += g12.x;
-        acc[3] += g12.y;
-        acc[4] += g10.x;
-        acc[5] += g10.y;
-        acc[6] += g20.x;
-        acc[7] += g20.y;
+      } else if constexpr (!kBicg) {
+        if (out_mode == 3) {
+          // in = r1, out = r2, f.r = r0
+          const c64 g12 = cmulc(pv, o), g10 = cmulc(pv, x), g20 = cmulc(o, x);
+          acc[0] += pv.x * pv.x + pv.y * pv.y;
+          acc[1] += o.x * o.x + o.y * o.y;
+          acc[2] += g12.x;
+          acc[3] += g12.y;
+          acc[4] += g10.x;
+          acc[5] += g10.y;
+          acc[6] += g20.x;
+          acc[7] += g20.y;
+        }
       }
     }
   };
   // BiCGSTAB's rh (out mode 1) and BiCGstab(2)'s r0 (out mode 3) are FP64 vectors
-  const c64 *xsrc = kSmall ? nullptr : out_mode == 1 ? f.rh : out_mode == 3 ? f.r : nullptr;
+  const c64 *xsrc = kSmall ? nullptr : out_mode == 1 ? f.rh : (!kBicg && out_mode == 3) ? f.r : nullptr;
   bool done = false;
   if constexpr (LC > 0) {
     constexpr int ER = (3 * NR * ((LC + 1) / 2) + kNT - 1) / kNT;
@@ -957,6 +961,7 @@ __global__ __launch_bounds__(kNT) void k_xinv(const VT *__restrict__ in, VT *__r
       }
     }
   }
+  // one partial record per block; a one-block kernel adds them in block order
   if constexpr (kSmall) {
     // COCG's and QMR's records hold the two parts of in^T out
     if (out_mode == 4) {
@@ -964,8 +969,11 @@ __global__ __launch_bounds__(kNT) void k_xinv(const VT *__restrict__ in, VT *__r
       block_sum<2, kNT>(acc, tot);
       if (threadIdx.x == 0) write_record<2>(f.partial, r, gridDim.x, blockIdx.x, tot);
     }
+  } else if constexpr (kBicg) {
+    double tot[3];
+    block_sum<3, kNT>(acc, tot);
+    if (threadIdx.x == 0) write_record<3>(f.partial, r, gridDim.x, blockIdx.x, tot);
   } else if (out_mode == 3) {
-    // one partial record per block; a one-block kernel adds them in block order
     double tot[8];
     block_sum<8, kNT>(acc, tot);
     if (threadIdx.x == 0) write_record<8>(f.partial, r, gridDim.x, blockIdx.x, tot);
@@ -1092,13 +1100,15 @@ void launch_x_pass(int k, const Geometry &g, const MatvecArgs &a, const PassDims
     with_pass<8>(g.Mx, (size_t)3 * nrows * g.Mx, [&](auto e, auto lc) {
       constexpr int LC = decltype(lc)::value;
       constexpr int E = LC > 0 ? pick_ept_c((size_t)3 * xpass_rows(LC) * LC, true) : decltype(e)::value;
-      // the plain product and the bilinear in^T out take the kernel without
-      // the other modes' registers
-      const bool small = f.out_mode == 0 || f.out_mode == 4;
+      // the instantiation that holds only the registers of this out_mode
+      const int modes = (f.out_mode == 0 || f.out_mode == 4) ? 1 : (f.out_mode == 1 || f.out_mode == 2) ? 2 : 0;
       auto go = [&](auto vv) {
         constexpr int PV = decltype(vv)::value;
-        if (small)
+        if (modes == 1)
           hipLaunchKernelGGL((k_xinv<T, E, LC, PV, VT, 1>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s, in, out, n3,
+                             a.mask, a.ainv, a.ncomp, a.comp, a.cell_site, a.rowtab, a.scl, A, ae, twx, a.px, d, f);
+        else if (modes == 2)
+          hipLaunchKernelGGL((k_xinv<T, E, LC, PV, VT, 2>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s, in, out, n3,
                              a.mask, a.ainv, a.ncomp, a.comp, a.cell_site, a.rowtab, a.scl, A, ae, twx, a.px, d, f);
         else
           hipLaunchKernelGGL((k_xinv<T, E, LC, PV, VT, 0>), dim3(nrowblk, a.nrhs), dim3(kNT), xlds, s, in, out, n3,
